@@ -1,0 +1,315 @@
+/*
+ * wo_oracle.c -- plain, sequential CPU oracle for picking-plan evaluation.
+ *
+ * TEST INFRASTRUCTURE ONLY.  Nothing in the product path may link, load or
+ * call this file; only the tests, the smoke check and the CPU-baseline leg of
+ * the benchmark do.  It shares no code, header or table with the HIP path.
+ *
+ * What it computes (arXiv 2110.13693, section 5, Subproblem 2, Eq. (2): the
+ * route objective is a sum of per-route distances d_i, and the picking
+ * frequency is a function delta = f(d) of that distance; Subproblem 3: product
+ * placement by category; section 6: clustering categories and choosing the
+ * order sequence within a time frame).  A plan is
+ *   - zone_of[c]: the zone that category c occupies (a permutation of the
+ *     categories), and
+ *   - seq[i]: the order picked i-th (a permutation of the orders).
+ * Evaluation, one plan, in the order the method states it:
+ *   1. slot map: zones are contiguous location ranges laid out in zone order;
+ *      zone z is exactly as long as the category it holds; inside a category
+ *      the SKUs sit in ascending SKU id (id = popularity rank);
+ *   2. location decode: location l lies in aisle l / (2S), at depth index
+ *      (l mod 2S) / 2 (side = l mod 2 does not change the walk), depth
+ *      coordinate y = j * pitch + pitch / 2 from the front cross aisle;
+ *   3. tours: next-fit over seq -- an order joins the open tour if the tour's
+ *      item count plus the order's stays <= capacity, otherwise it opens a new
+ *      tour; an order is never split (an order larger than the capacity is a
+ *      tour of its own);
+ *   4. S-shape route per tour (the standard heuristic of the routing
+ *      literature the paper builds on, de Koster et al. 2007): depot at the
+ *      front of aisle 0; every aisle holding a pick is traversed entirely, in
+ *      ascending order; if the number k of such aisles is odd the last one is
+ *      entered from the front and left the same way after its farthest pick;
+ *      cost = 2 * spacing * a_max + (k even ? k * L : (k - 1) * L + 2 * y_far)
+ *      with L = S * pitch;
+ *   5. D = sum of tour costs (exact in int64; the int32 output saturates at
+ *      INT32_MAX);
+ *   6. throughput over the time window (delta = f(d)):
+ *      T = D / walk_speed + seconds_per_item * items,
+ *      orders_per_window = n_orders * window / T, evaluated in double and
+ *      rounded once to float.
+ */
+#include <errno.h>
+#include <limits.h>
+#include <pthread.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define ORC_MAX_CAT 64
+#define ORC_ZONE_PAD 0xFF
+
+typedef struct {
+    int32_t n_aisles, slots_per_side, pitch_dm, spacing_dm, capacity, n_categories;
+    int32_t n_skus;
+    const int32_t *sku_category;   /* [n_skus] */
+    int32_t n_orders;
+    const int32_t *order_offsets;  /* [n_orders + 1] */
+    const int32_t *order_skus;     /* [order_offsets[n_orders]] */
+    double walk_dm_per_s, seconds_per_item, window_s;
+} orc_instance;
+
+enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_NOMEM = 3 };
+
+/* ------------------------------------------------------------------ */
+/* step 1: slot map (Subproblem 3: placement grouped by category)      */
+/* ------------------------------------------------------------------ */
+
+/* loc_of_sku[s] for every SKU under zone assignment zone_of. */
+int orc_locations(const orc_instance *w, const uint8_t *zone_of, int32_t *loc_of_sku)
+{
+    int C = w->n_categories;
+    int64_t size[ORC_MAX_CAT] = {0};
+    int64_t start[ORC_MAX_CAT];
+    int cat_in_zone[ORC_MAX_CAT];
+    int64_t next_rank[ORC_MAX_CAT] = {0};
+    int c, z;
+    int32_t s;
+
+    if (C < 1 || C > ORC_MAX_CAT) return ORC_E_INVAL;
+    for (z = 0; z < C; z++) cat_in_zone[z] = -1;
+    for (c = 0; c < C; c++) {
+        if (zone_of[c] >= C || cat_in_zone[zone_of[c]] != -1) return ORC_E_INVAL;
+        cat_in_zone[zone_of[c]] = c;
+    }
+    for (s = 0; s < w->n_skus; s++) {
+        int32_t cs = w->sku_category[s];
+        if (cs < 0 || cs >= C) return ORC_E_INVAL;
+        size[cs]++;
+    }
+    /* zones are laid out one after another in zone order */
+    {
+        int64_t acc = 0;
+        for (z = 0; z < C; z++) {
+            start[cat_in_zone[z]] = acc;
+            acc += size[cat_in_zone[z]];
+        }
+        if (acc > 2LL * w->n_aisles * w->slots_per_side) return ORC_E_INVAL;
+    }
+    /* inside a zone: ascending SKU id */
+    for (s = 0; s < w->n_skus; s++) {
+        int32_t cs = w->sku_category[s];
+        loc_of_sku[s] = (int32_t)(start[cs] + next_rank[cs]);
+        next_rank[cs]++;
+    }
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* step 2: location decode                                             */
+/* ------------------------------------------------------------------ */
+
+void orc_decode(const orc_instance *w, int32_t loc, int32_t *aisle, int32_t *y)
+{
+    int32_t per_aisle = 2 * w->slots_per_side;
+    int32_t j = (loc % per_aisle) / 2;
+    *aisle = loc / per_aisle;
+    *y = j * w->pitch_dm + w->pitch_dm / 2;
+}
+
+/* ------------------------------------------------------------------ */
+/* step 3: next-fit tours over the order sequence                      */
+/* ------------------------------------------------------------------ */
+
+/* tour_first[t] = position in seq of tour t's first order; tour_first[n_tours]
+ * = n_orders.  tour_first must hold n_orders + 1 entries. */
+int orc_tours(const orc_instance *w, const uint16_t *seq, int32_t *tour_first, int32_t *n_tours)
+{
+    int32_t i, t = 0;
+    int64_t load = 0;
+    for (i = 0; i < w->n_orders; i++) {
+        int32_t o = seq[i];
+        int64_t items;
+        if (o >= w->n_orders) return ORC_E_INVAL;
+        items = w->order_offsets[o + 1] - w->order_offsets[o];
+        if (i == 0 || load + items > w->capacity) {
+            tour_first[t++] = i;   /* open a new tour */
+            load = 0;
+        }
+        load += items;
+    }
+    tour_first[t] = w->n_orders;
+    *n_tours = t;
+    return ORC_OK;
+}
+
+/* ------------------------------------------------------------------ */
+/* step 4: S-shape cost of one tour, given its pick locations          */
+/* ------------------------------------------------------------------ */
+
+int64_t orc_sshape_cost(const orc_instance *w, const int32_t *locs, int32_t n)
+{
+    int64_t L = (int64_t)w->slots_per_side * w->pitch_dm;
+    char *visited;
+    int32_t i, k = 0, a_max = -1, y_far = 0;
+    int64_t cost;
+
+    if (n <= 0) return 0;
+    visited = (char *)calloc((size_t)w->n_aisles, 1);
+    if (!visited) return -1;
+    for (i = 0; i < n; i++) {
+        int32_t a, y;
+        orc_decode(w, locs[i], &a, &y);
+        if (!visited[a]) { visited[a] = 1; k++; }
+        if (a > a_max) { a_max = a; y_far = y; }
+        else if (a == a_max && y > y_far) y_far = y;
+    }
+    free(visited);
+    cost = 2LL * w->spacing_dm * a_max;
+    if (k % 2 == 0) cost += (int64_t)k * L;
+    else cost += (int64_t)(k - 1) * L + 2LL * y_far;
+    return cost;
+}
+
+/* ------------------------------------------------------------------ */
+/* steps 5-6: one whole plan                                           */
+/* ------------------------------------------------------------------ */
+
+static float orc_throughput(const orc_instance *w, int64_t D)
+{
+    double items = (double)w->order_offsets[w->n_orders];
+    double T = (double)D / w->walk_dm_per_s + w->seconds_per_item * items;
+    double r = ((double)w->n_orders * w->window_s) / T;
+    return (float)r;
+}
+
+/* Scratch: loc_of_sku [n_skus], tour_first [n_orders+1], picks [max tour lines]. */
+static int orc_eval_plan_ws(const orc_instance *w, const uint8_t *zone_of, const uint16_t *seq,
+                            int32_t *loc_of_sku, int32_t *tour_first, int32_t *picks,
+                            int64_t *dist_exact, int32_t *dist, float *thr)
+{
+    int32_t t, n_tours, i;
+    int64_t D = 0;
+    int rc = orc_locations(w, zone_of, loc_of_sku);
+    if (rc) return rc;
+    rc = orc_tours(w, seq, tour_first, &n_tours);
+    if (rc) return rc;
+    for (t = 0; t < n_tours; t++) {
+        int32_t n = 0;
+        for (i = tour_first[t]; i < tour_first[t + 1]; i++) {
+            int32_t o = seq[i], l;
+            for (l = w->order_offsets[o]; l < w->order_offsets[o + 1]; l++)
+                picks[n++] = loc_of_sku[w->order_skus[l]];
+        }
+        D += orc_sshape_cost(w, picks, n);
+    }
+    if (dist_exact) *dist_exact = D;
+    if (dist) *dist = D > INT32_MAX ? INT32_MAX : (int32_t)D;
+    if (thr) *thr = orc_throughput(w, D);
+    return ORC_OK;
+}
+
+static int orc_check_instance(const orc_instance *w)
+{
+    int32_t o, l;
+    if (w->n_aisles < 1 || w->slots_per_side < 1 || w->pitch_dm < 2 || (w->pitch_dm & 1) ||
+        w->spacing_dm < 0 || w->capacity < 1 || w->n_orders < 1 || w->n_orders > 65535)
+        return ORC_E_INVAL;
+    if (w->order_offsets[0] != 0) return ORC_E_INVAL;
+    for (o = 0; o < w->n_orders; o++)
+        if (w->order_offsets[o + 1] <= w->order_offsets[o]) return ORC_E_INVAL;
+    for (l = 0; l < w->order_offsets[w->n_orders]; l++)
+        if (w->order_skus[l] < 0 || w->order_skus[l] >= w->n_skus) return ORC_E_INVAL;
+    return ORC_OK;
+}
+
+static int32_t orc_max_order_lines(const orc_instance *w)
+{
+    int32_t o, m = 0;
+    for (o = 0; o < w->n_orders; o++) {
+        int32_t n = w->order_offsets[o + 1] - w->order_offsets[o];
+        if (n > m) m = n;
+    }
+    return m;
+}
+
+int orc_eval_plan(const orc_instance *w, const uint8_t *zone_of, const uint16_t *seq,
+                  int64_t *dist_exact, int32_t *dist, float *thr)
+{
+    int32_t *loc, *tf, *picks;
+    int rc = orc_check_instance(w);
+    if (rc) return rc;
+    loc = (int32_t *)malloc(sizeof(int32_t) * (size_t)w->n_skus);
+    tf = (int32_t *)malloc(sizeof(int32_t) * ((size_t)w->n_orders + 1));
+    /* a tour holds at most max(capacity, largest order) lines */
+    picks = (int32_t *)malloc(sizeof(int32_t) *
+                              (size_t)(w->capacity + orc_max_order_lines(w) + 1));
+    if (!loc || !tf || !picks) rc = ORC_E_NOMEM;
+    else rc = orc_eval_plan_ws(w, zone_of, seq, loc, tf, picks, dist_exact, dist, thr);
+    free(loc); free(tf); free(picks);
+    return rc;
+}
+
+/* ------------------------------------------------------------------ */
+/* many plans, optionally on several host threads (baseline timing)    */
+/* ------------------------------------------------------------------ */
+
+typedef struct {
+    const orc_instance *w;
+    const uint8_t *zone_of;     /* [n_plans][64] */
+    const uint16_t *seq;        /* [n_plans][n_orders] */
+    int32_t *dist;
+    float *thr;
+    int64_t n_plans;
+    int64_t next;               /* shared counter */
+    pthread_mutex_t mu;
+    int rc;
+} orc_job;
+
+static void *orc_worker(void *arg)
+{
+    orc_job *j = (orc_job *)arg;
+    const orc_instance *w = j->w;
+    int32_t *loc = (int32_t *)malloc(sizeof(int32_t) * (size_t)w->n_skus);
+    int32_t *tf = (int32_t *)malloc(sizeof(int32_t) * ((size_t)w->n_orders + 1));
+    int32_t *picks = (int32_t *)malloc(sizeof(int32_t) *
+                                       (size_t)(w->capacity + orc_max_order_lines(w) + 1));
+    if (!loc || !tf || !picks) {
+        pthread_mutex_lock(&j->mu); j->rc = ORC_E_NOMEM; pthread_mutex_unlock(&j->mu);
+    } else {
+        for (;;) {
+            int64_t p;
+            int rc;
+            pthread_mutex_lock(&j->mu);
+            p = j->next++;
+            pthread_mutex_unlock(&j->mu);
+            if (p >= j->n_plans) break;
+            rc = orc_eval_plan_ws(w, j->zone_of + 64 * p, j->seq + (size_t)w->n_orders * p,
+                                  loc, tf, picks, NULL, j->dist ? j->dist + p : NULL,
+                                  j->thr ? j->thr + p : NULL);
+            if (rc) { pthread_mutex_lock(&j->mu); j->rc = rc; pthread_mutex_unlock(&j->mu); }
+        }
+    }
+    free(loc); free(tf); free(picks);
+    return NULL;
+}
+
+int orc_eval_plans(const orc_instance *w, int64_t n_plans, const uint8_t *zone_of,
+                   const uint16_t *seq, int32_t *dist, float *thr, int n_threads)
+{
+    orc_job job;
+    pthread_t *th;
+    int t, rc = orc_check_instance(w);
+    if (rc) return rc;
+    if (n_threads < 1) n_threads = 1;
+    memset(&job, 0, sizeof job);
+    job.w = w; job.zone_of = zone_of; job.seq = seq; job.dist = dist; job.thr = thr;
+    job.n_plans = n_plans;
+    pthread_mutex_init(&job.mu, NULL);
+    th = (pthread_t *)malloc(sizeof(pthread_t) * (size_t)n_threads);
+    if (!th) return ORC_E_NOMEM;
+    for (t = 0; t < n_threads; t++) pthread_create(&th[t], NULL, orc_worker, &job);
+    for (t = 0; t < n_threads; t++) pthread_join(th[t], NULL);
+    free(th);
+    pthread_mutex_destroy(&job.mu);
+    return job.rc;
+}
