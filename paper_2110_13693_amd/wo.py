@@ -1,0 +1,190 @@
+"""Thin ctypes binding of ``libwo.so`` (names follow ``include/wo.h``).
+
+Only argument marshalling happens here: every step of plan evaluation runs in
+the library's kernels.  Tensors must already live on the GPU; the library is
+required -- there is no CPU fallback, and a missing library raises.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Sequence
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libwo.so")
+
+WO_OK, WO_E_INVAL, WO_E_RANGE, WO_E_NOMEM, WO_E_DEVICE, WO_E_STATE, WO_E_UNSUPPORTED = range(7)
+WO_MAX_CATEGORIES = 64
+WO_MAX_ORDERS = 65535
+WO_MAX_CAPACITY = 32
+WO_MAX_LOCATIONS = 1 << 22
+WO_MAX_LINES = 1 << 24
+
+# every symbol include/wo.h declares
+EXPORTS = [
+    "wo_status_str", "wo_last_error", "wo_load_warehouse", "wo_free_warehouse",
+    "wo_instance_info", "wo_eval_plans",
+]
+
+
+class WoError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__("%s: %s" % (_status_name(status), message))
+        self.status = status
+
+
+class wo_instance_desc(ctypes.Structure):
+    _fields_ = [
+        ("n_aisles", ctypes.c_int32), ("slots_per_side", ctypes.c_int32),
+        ("pitch_dm", ctypes.c_int32), ("spacing_dm", ctypes.c_int32),
+        ("capacity", ctypes.c_int32), ("n_categories", ctypes.c_int32),
+        ("n_skus", ctypes.c_int32), ("sku_category", ctypes.c_void_p),
+        ("n_orders", ctypes.c_int32), ("order_offsets", ctypes.c_void_p),
+        ("order_skus", ctypes.c_void_p),
+        ("walk_dm_per_s", ctypes.c_double), ("seconds_per_item", ctypes.c_double),
+        ("window_s", ctypes.c_double),
+    ]
+
+
+_lib = None
+
+
+def lib():
+    """Load ``libwo.so``; raise if it has not been built."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("libwo.so is not built (run __graft_entry__.build())")
+        L = ctypes.CDLL(LIB_PATH)
+        V, P, I32, I64 = ctypes.c_void_p, ctypes.POINTER, ctypes.c_int32, ctypes.c_int64
+        L.wo_status_str.argtypes = [ctypes.c_int]
+        L.wo_status_str.restype = ctypes.c_char_p
+        L.wo_last_error.argtypes = []
+        L.wo_last_error.restype = ctypes.c_char_p
+        L.wo_load_warehouse.argtypes = [P(wo_instance_desc), I32, V, P(V)]
+        L.wo_free_warehouse.argtypes = [V]
+        L.wo_instance_info.argtypes = [V, I32, P(I32), P(I32), P(I32)]
+        L.wo_eval_plans.argtypes = [V, V, I64, V, V, V, V, V]
+        for name in EXPORTS:
+            getattr(L, name).restype = getattr(L, name).restype if name in (
+                "wo_status_str", "wo_last_error") else ctypes.c_int
+        _lib = L
+    return _lib
+
+
+def _status_name(s: int) -> str:
+    try:
+        return lib().wo_status_str(int(s)).decode()
+    except ImportError:
+        return "status %d" % s
+
+
+def _check(status: int):
+    if status != WO_OK:
+        raise WoError(status, lib().wo_last_error().decode())
+
+
+def wo_status_str(s: int) -> str:
+    return lib().wo_status_str(int(s)).decode()
+
+
+def wo_last_error() -> str:
+    return lib().wo_last_error().decode()
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    return int(getattr(stream, "cuda_stream", stream))
+
+
+def _ptr(t, dtype_size: int, name: str) -> int:
+    if t is None:
+        return 0
+    if not getattr(t, "is_cuda", False):
+        raise ValueError("%s must be a GPU tensor" % name)
+    if not t.is_contiguous():
+        raise ValueError("%s must be contiguous" % name)
+    if t.element_size() != dtype_size:
+        raise ValueError("%s must have %d-byte elements" % (name, dtype_size))
+    return t.data_ptr()
+
+
+class Warehouse:
+    """Owns a ``wo_wh*`` handle (one or more loaded instances)."""
+
+    def __init__(self, handle: int, instances):
+        self.handle = ctypes.c_void_p(handle)
+        self.n_orders = [int(i.n_orders) for i in instances]
+        self.n_items = [int(i.n_items) for i in instances]
+        self.n_instances = len(self.n_orders)
+
+    def free(self):
+        if self.handle:
+            _check(lib().wo_free_warehouse(self.handle))
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def make_desc(inst, keep: list) -> wo_instance_desc:
+    """Descriptor of a :class:`synth.Instance`-like object (arrays kept alive in ``keep``)."""
+    cat = np.ascontiguousarray(inst.sku_category, dtype=np.int32)
+    off = np.ascontiguousarray(inst.order_offsets, dtype=np.int32)
+    sku = np.ascontiguousarray(inst.order_skus, dtype=np.int32)
+    keep += [cat, off, sku]
+    return wo_instance_desc(int(inst.n_aisles), int(inst.slots_per_side), int(inst.pitch_dm),
+                            int(inst.spacing_dm), int(inst.capacity), int(inst.n_categories),
+                            cat.size, cat.ctypes.data, off.size - 1, off.ctypes.data,
+                            sku.ctypes.data, float(inst.walk_dm_per_s),
+                            float(inst.seconds_per_item), float(inst.window_s))
+
+
+def wo_load_warehouse(instances: Sequence, stream=None) -> Warehouse:
+    """Load one or more instances onto the current device (synchronous)."""
+    keep: list = []
+    arr = (wo_instance_desc * len(instances))(*[make_desc(i, keep) for i in instances])
+    out = ctypes.c_void_p(0)
+    _check(lib().wo_load_warehouse(arr, len(instances), ctypes.c_void_p(_stream_handle(stream)),
+                                   ctypes.byref(out)))
+    return Warehouse(out.value, instances)
+
+
+def wo_free_warehouse(wh: Warehouse):
+    wh.free()
+
+
+def wo_eval_plans(wh: Warehouse, zone_of, order_seq, dist, orders_per_window=None,
+                  plan_offsets: Optional[Sequence[int]] = None, stream=None):
+    """Enqueue exact evaluation of ``zone_of.shape[0]`` plans (async on ``stream``).
+
+    ``zone_of``: uint8 [n, 64]; ``order_seq``: 2-byte elements, rows packed
+    instance after instance; ``dist``: int32 [n]; ``orders_per_window``:
+    float32 [n] or None.
+    """
+    n = int(zone_of.shape[0])
+    if zone_of.dim() != 2 or zone_of.shape[1] != 64:
+        raise ValueError("zone_of must be [n_plans, 64]")
+    if dist.numel() != n or (orders_per_window is not None and orders_per_window.numel() != n):
+        raise ValueError("output length must equal the number of plans")
+    offs = None
+    if plan_offsets is not None:
+        offs = np.ascontiguousarray(plan_offsets, dtype=np.int64)
+        need = int(sum((offs[i + 1] - offs[i]) * wh.n_orders[i] for i in range(wh.n_instances)))
+    else:
+        need = n * wh.n_orders[0]
+    if order_seq.numel() != need:
+        raise ValueError("order_seq holds %d entries, the plans need %d" % (order_seq.numel(), need))
+    _check(lib().wo_eval_plans(
+        wh.handle, None if offs is None else offs.ctypes.data, n,
+        _ptr(zone_of, 1, "zone_of"), _ptr(order_seq, 2, "order_seq"), _ptr(dist, 4, "dist"),
+        _ptr(orders_per_window, 4, "orders_per_window"),
+        ctypes.c_void_p(_stream_handle(stream))))
+    return dist, orders_per_window
