@@ -1,0 +1,154 @@
+"""C-ABI checks that need no GPU: the library loads, exports every function
+include/wo.h declares, and rejects malformed arguments on the host before any
+device work (status codes of include/wo.h)."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import synth
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = []
+    for h in sorted(os.listdir(os.path.join(ROOT, "include"))):
+        if h.endswith(".h"):
+            text = open(os.path.join(ROOT, "include", h)).read()
+            text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+            names += re.findall(r"\b(wo_[a-z0-9_]+)\s*\(", text)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def wo():
+    from paper_2110_13693_amd import wo as w
+    w.lib()
+    return w
+
+
+def test_every_declared_symbol_is_exported(wo):
+    decl = _declared_functions()
+    assert len(decl) >= 6
+    for name in decl:
+        assert hasattr(wo.lib(), name), name
+    assert sorted(wo.EXPORTS) == decl
+
+
+def test_status_strings(wo):
+    assert wo.wo_status_str(0) == "WO_OK"
+    assert wo.wo_status_str(2) == "WO_E_RANGE"
+    assert wo.wo_status_str(99) == "WO_E_UNKNOWN"
+
+
+def _load_status(wo, inst_or_desc, n=1):
+    keep = []
+    d = inst_or_desc if isinstance(inst_or_desc, wo.wo_instance_desc) else wo.make_desc(inst_or_desc, keep)
+    arr = (wo.wo_instance_desc * n)(*([d] * n))
+    out = ctypes.c_void_p(0)
+    st = wo.lib().wo_load_warehouse(arr, n, None, ctypes.byref(out))
+    return st, out
+
+
+@pytest.fixture
+def tiny():
+    return synth.workload("tiny", n_plans=1)[0]
+
+
+def _mod(inst, **kw):
+    d = dict(n_aisles=inst.n_aisles, slots_per_side=inst.slots_per_side, pitch_dm=inst.pitch_dm,
+             spacing_dm=inst.spacing_dm, capacity=inst.capacity, n_categories=inst.n_categories,
+             sku_category=inst.sku_category.copy(), order_offsets=inst.order_offsets.copy(),
+             order_skus=inst.order_skus.copy())
+    d.update(kw)
+    return synth.Instance(**d)
+
+
+@pytest.mark.parametrize("field,value,status", [
+    ("pitch_dm", 9, 1),             # odd pitch
+    ("pitch_dm", 0, 1),
+    ("n_aisles", 0, 1),
+    ("slots_per_side", 0, 1),
+    ("spacing_dm", -1, 1),
+    ("capacity", 0, 1),
+    ("capacity", 33, 2),            # above the supported capacity
+    ("n_categories", 65, 2),        # more than 64 categories
+    ("n_aisles", 1, 2),             # 600 SKUs no longer fit 60 locations
+])
+def test_load_rejects_descriptor(wo, tiny, field, value, status):
+    st, out = _load_status(wo, _mod(tiny, **{field: value}))
+    assert st == status, wo.wo_last_error()
+    assert out.value is None
+    assert wo.wo_last_error()
+
+
+def test_load_rejects_bad_arrays(wo, tiny):
+    cat = tiny.sku_category.copy()
+    cat[3] = 12                                         # category out of range
+    assert _load_status(wo, _mod(tiny, sku_category=cat))[0] == wo.WO_E_INVAL
+    cat = tiny.sku_category.copy()
+    cat[cat == 5] = 4                                   # empty category
+    assert _load_status(wo, _mod(tiny, sku_category=cat))[0] == wo.WO_E_INVAL
+    skus = tiny.order_skus.copy()
+    skus[0] = 600                                       # SKU out of range
+    assert _load_status(wo, _mod(tiny, order_skus=skus))[0] == wo.WO_E_INVAL
+    off = tiny.order_offsets.copy()
+    off[5] = off[4]                                     # empty order
+    assert _load_status(wo, _mod(tiny, order_offsets=off))[0] == wo.WO_E_INVAL
+
+
+def test_load_rejects_too_many_orders(wo):
+    n = 65536
+    inst = synth.make_instance(n_aisles=10, slots_per_side=30, pitch_dm=10, spacing_dm=30,
+                               capacity=20, n_categories=12, n_skus=600, category_mode="equal",
+                               n_orders=n, lines_lambda=0.0, seed=0)
+    assert _load_status(wo, inst)[0] == wo.WO_E_RANGE
+
+
+def test_load_rejects_null_and_count(wo, tiny):
+    out = ctypes.c_void_p(0)
+    L = wo.lib()
+    assert L.wo_load_warehouse(None, 1, None, ctypes.byref(out)) == wo.WO_E_INVAL
+    keep = []
+    arr = (wo.wo_instance_desc * 1)(wo.make_desc(tiny, keep))
+    assert L.wo_load_warehouse(arr, 0, None, ctypes.byref(out)) == wo.WO_E_INVAL
+    assert L.wo_load_warehouse(arr, 1, None, None) == wo.WO_E_INVAL
+    d = wo.make_desc(tiny, keep)
+    d.order_skus = None
+    assert _load_status(wo, d)[0] == wo.WO_E_INVAL
+    d = wo.make_desc(tiny, keep)
+    d.walk_dm_per_s = 0.0
+    assert _load_status(wo, d)[0] == wo.WO_E_INVAL
+
+
+def test_injected_allocation_failure(wo, tiny, monkeypatch):
+    monkeypatch.setenv("WO_FAULT_INJECT", "alloc")
+    st, out = _load_status(wo, tiny)
+    assert st == wo.WO_E_NOMEM and out.value is None
+    assert "injected" in wo.wo_last_error()
+
+
+def test_eval_rejects_null_handle(wo):
+    L = wo.lib()
+    assert L.wo_eval_plans(None, None, 1, None, None, None, None, None) == wo.WO_E_INVAL
+    assert L.wo_free_warehouse(None) == wo.WO_OK
+    n = ctypes.c_int32(0)
+    assert L.wo_instance_info(None, 0, ctypes.byref(n), None, None) == wo.WO_E_INVAL
+
+
+def test_binding_refuses_host_tensors(wo):
+    import torch
+
+    class FakeWh:
+        n_orders = [3]
+        n_instances = 1
+        handle = ctypes.c_void_p(0)
+
+    z = torch.zeros((1, 64), dtype=torch.uint8)
+    s = torch.zeros((3,), dtype=torch.int16)
+    d = torch.zeros((1,), dtype=torch.int32)
+    with pytest.raises(ValueError):
+        wo.wo_eval_plans(FakeWh(), z, s, d)
