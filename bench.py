@@ -74,6 +74,128 @@ def cpu_baseline(inst, Z, S, min_wall_s: float = 1.5):
                       % (reps, n, el, el * cores)}
 
 
+def search_comparison(args):
+    """Plain genetic search vs surrogate-screened search at equal wall time.
+
+    Paper-scale warehouse, population 16,384, tournament 4, mutation 0.02 per
+    position; the screened arm proposes 65,536 children per generation and
+    re-scores the best 3,277 exactly.  The surrogate is trained first on plans
+    the exact evaluator scores (random slottings at the identity sequence);
+    its data generation and training time are reported and counted both ways.
+    """
+    import torch
+
+    import synth
+    from paper_2110_13693_amd import wo
+
+    torch.cuda.set_device(0)
+    inst = synth.WORKLOADS["paper"]["make"](0)
+    n = inst.n_orders
+    P, K, keep = args.population, 65536, 3277
+    wh = wo.wo_load_warehouse([inst])
+    rng = np.random.default_rng([0, synth.generators.STREAM_SEARCH_INIT])
+    Z0 = torch.from_numpy(synth.generators.random_zone_perms(rng, P, inst.n_categories)).cuda()
+    S0 = torch.from_numpy(synth.generators.random_order_perms(rng, P, n).view(np.int16)).cuda().reshape(-1)
+
+    def run(sur, budget_s, max_gen, label):
+        s = wo.wo_search_create(wh, 0, Z0, S0, P, candidates=K if sur else 0, keep=keep if sur else 0,
+                                seed=11)
+        torch.cuda.synchronize()
+        trace = [(0.0, wo.wo_search_best(s)[2])]
+        t0 = time.perf_counter()
+        g = 0
+        while g < max_gen and (budget_s is None or time.perf_counter() - t0 < budget_s):
+            wo.wo_search_step(wh, s, sur, 1)
+            g += 1
+            trace.append((time.perf_counter() - t0, wo.wo_search_best(s)[2]))
+        best = wo.wo_search_best(s)
+        s.free()
+        print("%s: %d generations, %.2f s, best %d" % (label, g, trace[-1][0], best[2]),
+              file=sys.stderr, flush=True)
+        return trace, best
+
+    plain_trace, plain_best = run(None, None, args.generations, "plain")
+    wall = plain_trace[-1][0]
+
+    # surrogate: training pairs from the exact evaluator, then training
+    t0 = time.perf_counter()
+    n_train = args.train_samples
+    r_tr = np.random.default_rng([0, synth.generators.STREAM_SURROGATE_TRAIN])
+    ztr = torch.from_numpy(synth.generators.random_zone_perms(r_tr, n_train, inst.n_categories)).cuda()
+    dtr = torch.empty(n_train, dtype=torch.int32, device="cuda")
+    ident = torch.arange(n, dtype=torch.int16, device="cuda")
+    chunk = 16384
+    seq_chunk = ident.repeat(chunk)
+    for c0 in range(0, n_train, chunk):
+        m = min(chunk, n_train - c0)
+        wo.wo_eval_plans(wh, ztr[c0:c0 + m], seq_chunk[:m * n], dtr[c0:c0 + m])
+    torch.cuda.synchronize()
+    t_data = time.perf_counter() - t0
+    sur = wo.wo_sur_create(inst.n_categories, None, seed=1)
+    t1 = time.perf_counter()
+    loss = wo.wo_sur_train(sur, ztr, dtr, epochs=args.epochs, batch=1024, lr=1e-3, seed=2)
+    t_train = time.perf_counter() - t1
+    # held-out error of the surrogate against the exact evaluator
+    r_ho = np.random.default_rng([0, synth.generators.STREAM_SURROGATE_HELDOUT])
+    zho = torch.from_numpy(synth.generators.random_zone_perms(r_ho, K, inst.n_categories)).cuda()
+    dho = torch.empty(K, dtype=torch.int32, device="cuda")
+    for c0 in range(0, K, chunk):
+        wo.wo_eval_plans(wh, zho[c0:c0 + chunk], seq_chunk, dho[c0:c0 + chunk])
+    pho = torch.empty(K, dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    ts = time.perf_counter()
+    wo.wo_sur_predict(sur, zho, pho)
+    torch.cuda.synchronize()
+    t_pred = time.perf_counter() - ts
+    from scipy.stats import spearmanr   # reporting only: rank correlation, average ranks for ties
+    ex = dho.cpu().numpy().astype(np.float64)
+    pr = pho.cpu().numpy().astype(np.float64)
+    rel_mae = float(np.mean(np.abs(pr - ex) / ex))
+    rho = float(spearmanr(pr, ex).correlation)
+
+    scr_trace, scr_best = run(sur, wall, 10 ** 9, "screened")
+    target = plain_best[2] * 1.005
+
+    def time_to(trace, thr):
+        for t, b in trace:
+            if b <= thr:
+                return t
+        return None
+
+    t_hit = time_to(scr_trace, target)
+    # throughput of both best plans from the evaluator itself
+    zb = torch.from_numpy(np.stack([plain_best[0], scr_best[0]])).cuda()
+    sb = torch.from_numpy(np.concatenate([plain_best[1], scr_best[1]]).view(np.int16)).cuda()
+    db = torch.empty(2, dtype=torch.int32, device="cuda")
+    tb = torch.empty(2, dtype=torch.float32, device="cuda")
+    wo.wo_eval_plans(wh, zb, sb, db, tb)
+    torch.cuda.synchronize()
+    thr_plain, thr_scr = [float(x) for x in tb.cpu().numpy()]
+    out = {
+        "metric": "surrogate vs plain best cost at equal time",
+        "value": float(scr_best[2]) / float(plain_best[2]),
+        "unit": "screened best D / plain best D",
+        "higher_is_better": False,
+        "n_gpus": 1,
+        "config": {"workload": "paper-scale warehouse, population %d, %d generations of plain search; "
+                               "screened: %d candidates, keep %d" % (P, args.generations, K, keep)},
+        "plain": {"best_dist": plain_best[2], "orders_per_window": thr_plain,
+                  "generations": len(plain_trace) - 1, "wall_s": wall},
+        "screened": {"best_dist": scr_best[2], "orders_per_window": thr_scr,
+                     "generations": len(scr_trace) - 1, "wall_s": scr_trace[-1][0],
+                     "time_to_within_0.5pct_s": t_hit,
+                     "time_to_within_0.5pct_incl_training_s": None if t_hit is None else t_hit + t_data + t_train},
+        "surrogate": {"train_samples": n_train, "epochs": args.epochs, "last_epoch_loss": loss,
+                      "data_s": t_data, "train_s": t_train, "heldout_rel_mae": rel_mae,
+                      "heldout_spearman": rho, "predict_65536_s": t_pred},
+        "initial_best_dist": plain_trace[0][1],
+    }
+    sur.free()
+    wh.free()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -81,11 +203,20 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--search", action="store_true",
+                    help="run the plain vs surrogate-screened search comparison instead")
+    ap.add_argument("--population", type=int, default=16384)
+    ap.add_argument("--generations", type=int, default=200)
+    ap.add_argument("--train-samples", type=int, default=1 << 20)
+    ap.add_argument("--epochs", type=int, default=4)
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (the evaluator "
               "shards plans across GPUs with no exchange, see DESIGN.md)" % args.gpus, file=sys.stderr)
         return 2
+
+    if args.search:
+        return search_comparison(args)
 
     import torch
 

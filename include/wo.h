@@ -144,6 +144,146 @@ wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans,
                         const uint8_t *d_zone_of, const uint16_t *d_order_seq,
                         int32_t *d_dist, float *d_orders_per_window, void *stream);
 
+
+/* ------------------------------------------------------------------ */
+/* Learned surrogate and screening                                      */
+/* ------------------------------------------------------------------ */
+/* The paper's hybrid decision making (section 1, Figure 1) trains machine
+ * learning models on simulated scenarios and lets them decide; here the
+ * simulator is the exact evaluator above and the model predicts a plan's
+ * total distance from its slotting alone:
+ *   x = one-hot(zone_of) as a 64 x 64 matrix (row = category, column = zone;
+ *       categories >= n_categories and padding give zero rows) = 4096 inputs,
+ *   h1 = GELU(x W1 + b1) (1024), h2 = GELU(h1 W2 + b2) (256),
+ *   y = h2 W3 + b3, prediction = y * std + mean,
+ * GELU in its tanh form.  Products run on MFMA with bf16 operands (weights
+ * and activations) and fp32 accumulation; fp32 master weights; Adam.
+ *
+ * Host parameter layout (float32, WO_SUR_PARAMS values): W1 [4096][1024]
+ * (input-major: y = x W + b), b1 [1024], W2 [1024][256], b2 [256],
+ * W3 [256], b3 [1]. */
+#define WO_SUR_PARAMS 4457985
+#define WO_SCREEN_MAX_KEEP 4096
+
+typedef struct wo_sur wo_sur;
+
+/* Create a surrogate on the current device for instances with n_categories
+ * categories (zone bytes of categories >= n_categories are ignored).
+ * h_init: host parameters in the layout above, or NULL for He-uniform
+ * weights drawn from `seed` by a counter generator (zero biases).
+ * Synchronous. */
+wo_status wo_sur_create(int32_t n_categories, const float *h_init, uint64_t seed, void *stream,
+                        wo_sur **out);
+
+/* Release a surrogate (NULL is a no-op); synchronises the device first. */
+wo_status wo_sur_free(wo_sur *s);
+
+/* Target standardisation used for training and prediction.  Without a call,
+ * wo_sur_train sets it to the mean and standard deviation of its targets. */
+wo_status wo_sur_set_scale(wo_sur *s, double mean, double std);
+wo_status wo_sur_get_scale(const wo_sur *s, double *mean, double *std);
+
+/* Copy the fp32 parameters to host memory (WO_SUR_PARAMS floats, layout
+ * above).  Synchronises the device. */
+wo_status wo_sur_get_params(const wo_sur *s, float *h_out);
+
+/* Forward and backward pass of one batch without an update: gradients of
+ * L = mean_b (y_b - t_b)^2 with respect to every parameter, into host memory
+ * in the parameter layout, and the loss.  n: multiple of 128, at most 4096;
+ * d_zone_of uint8[n][64]; d_target float[n] (standardised).  Synchronous. */
+wo_status wo_sur_gradients(wo_sur *s, int32_t n, const uint8_t *d_zone_of, const float *d_target,
+                           float *h_grad, float *h_loss, void *stream);
+
+/* Train on n (plan, exact distance) pairs: d_zone_of uint8[n][64],
+ * d_dist int32[n] (e.g. from wo_eval_plans).  Mini-batch Adam (lr, beta
+ * 0.9 / 0.999, eps 1e-8) over `epochs` shuffled passes (shuffle drawn from
+ * `seed`); batch a multiple of 128 in [128, 4096]; a last partial batch is
+ * dropped.  h_last_loss (nullable) receives the mean batch loss of the last
+ * epoch.  Returns when the work is done (it synchronises the stream). */
+wo_status wo_sur_train(wo_sur *s, int64_t n, const uint8_t *d_zone_of, const int32_t *d_dist,
+                       int32_t epochs, int32_t batch, float lr, uint64_t seed, float *h_last_loss,
+                       void *stream);
+
+/* Predicted distances (de-standardised) of n plans into d_pred float[n]
+ * (async). */
+wo_status wo_sur_predict(wo_sur *s, int64_t n, const uint8_t *d_zone_of, float *d_pred, void *stream);
+
+/* Checkpoint: parameters, Adam moments, step count and standardisation to a
+ * file, and a new surrogate from such a file (bit-exact resume). */
+wo_status wo_sur_save(const wo_sur *s, const char *path);
+wo_status wo_sur_load(const char *path, void *stream, wo_sur **out);
+
+/* Screen n_plans candidate slottings of instance `inst`: predict each with
+ * the surrogate and write the indices of the `keep` smallest predictions,
+ * ordered by (prediction, index), to d_keep_idx int32[keep] (async).
+ * d_pred (nullable) receives all predictions.  keep <= WO_SCREEN_MAX_KEEP,
+ * n_plans <= 2^24.  The exact evaluator remains the judge: re-score the kept
+ * plans with wo_eval_plans. */
+wo_status wo_screen_plans(wo_wh *wh, int32_t inst, wo_sur *s, int64_t n_plans, const uint8_t *d_zone_of,
+                          float *d_pred, int64_t keep, int32_t *d_keep_idx, void *stream);
+
+/* ------------------------------------------------------------------ */
+/* Genetic plan search                                                  */
+/* ------------------------------------------------------------------ */
+/* The paper's top-level optimiser organises the subsystem searches from the
+ * CPU (section 5, Figure 10); here a genetic algorithm over whole plans runs
+ * on the device and the host only asks for generations.  Random draws come
+ * from the SplitMix64 finaliser (Steele, Lea & Flood 2014) over
+ *   h = sm(sm(sm(seed + stream) ^ (generation << 32 | child)) ^ position),
+ *   r32 = h >> 32,  streams 1 tournament, 2 zone coin, 3 zone partner,
+ *   4 insert coin, 5 insert target;
+ * a coin succeeds when r32 < mutation_threshold; a uniform integer in [0, m)
+ * is (r32 * m) >> 32.
+ *   Tournament: `tournament` draws from the population, winner = smallest
+ *   (distance, index).  Zone swap: for each category c in turn, on success
+ *   swap its zone with uniform other category.  Order insert: for each
+ *   sequence position i = 0 .. n-1 in turn, on success move the element
+ *   currently at i so that it ends at uniform position j.
+ * Plain generation (no surrogate): child 0 = the best individual unchanged;
+ * child b >= 1 = tournament winner (child id b) with both mutations; all are
+ * evaluated exactly and replace the population.
+ * Screened generation (with a surrogate): `candidates` children (child id b)
+ * take a tournament winner's zones with the zone swap; the surrogate keeps
+ * the `keep` best by (prediction, index) (wo_screen_plans); each kept
+ * candidate then takes its parent's sequence with the order insert (child id
+ * = candidate id), is evaluated exactly and replaces one of the `keep` worst
+ * individuals (largest distance, ties by smaller index), in rank order.
+ * Generations count from 0 across calls. */
+typedef struct {
+    int32_t population;            /* 2 .. 2^24 */
+    int32_t tournament;            /* 1 .. 64, e.g. 4 */
+    uint32_t mutation_threshold;   /* per-position success if r32 < this; 85899345 = 0.02 */
+    int32_t candidates;            /* screened children per generation (0: plain only) */
+    int32_t keep;                  /* survivors of the screen, <= WO_SCREEN_MAX_KEEP, < population */
+    uint64_t seed;
+} wo_search_params;
+
+typedef struct wo_search wo_search;
+
+/* Create a search over instance `inst` of wh from an initial population
+ * (d_init_zone_of uint8[population][64], d_init_seq uint16[population][n]),
+ * which is copied and evaluated exactly.  Synchronous. */
+wo_status wo_search_create(wo_wh *wh, int32_t inst, const wo_search_params *params,
+                           const uint8_t *d_init_zone_of, const uint16_t *d_init_seq, void *stream,
+                           wo_search **out);
+
+/* Release a search (NULL is a no-op); synchronises the device first. */
+wo_status wo_search_free(wo_search *s);
+
+/* Run n_generations generations (async): plain when sur is NULL, screened
+ * otherwise (the search must have been created with candidates > 0). */
+wo_status wo_search_step(wo_wh *wh, wo_search *s, wo_sur *sur, int32_t n_generations, void *stream);
+
+/* Best individual so far (each argument nullable): zone row (64 bytes),
+ * sequence (n entries), distance, generations run.  Synchronous. */
+wo_status wo_search_best(wo_search *s, uint8_t *h_zone_of, uint16_t *h_seq, int32_t *h_dist,
+                         int32_t *h_generation, void *stream);
+
+/* Copy the population (each argument nullable) to device buffers, and the
+ * candidate ids kept by the last screened generation (int32[keep]).  Async. */
+wo_status wo_search_population(wo_search *s, uint8_t *d_zone_of, uint16_t *d_seq, int32_t *d_dist,
+                               int32_t *d_last_kept, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

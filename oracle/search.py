@@ -107,3 +107,30 @@ def plain_generation(inst, zone_of, seq, dist, seed: int, gen: int):
         Sq[b] = mutate_sequence(seq[par], seed, gen, b)
     D, _ = oracle.eval_plans(inst, Z, Sq)
     return Z, Sq, D
+
+
+def worst_individuals(dist, k):
+    """The k worst individuals: largest distance first, ties by smaller index."""
+    return sorted(range(len(dist)), key=lambda i: (-int(dist[i]), i))[:k]
+
+
+def screened_generation(inst, zone_of, seq, dist, seed: int, gen: int, kept_ids):
+    """One generation of the screened arm, given the candidate ids the
+    surrogate kept (in rank order).
+
+    Candidate b is a tournament winner (child id b) with the zone swap; each
+    kept candidate takes its parent's sequence with the order insert (child
+    id = candidate id), is evaluated exactly and replaces the next of the
+    worst individuals.  Returns the new population ``(zone_of, seq, dist)``."""
+    Z, Sq, D = zone_of.copy(), seq.copy(), np.asarray(dist).copy()
+    kids_z, kids_s = [], []
+    for cid in kept_ids:
+        cid = int(cid)
+        par = tournament(dist, seed, gen, cid)
+        kids_z.append(mutate_zones(zone_of[par], inst.n_categories, seed, gen, cid))
+        kids_s.append(mutate_sequence(seq[par], seed, gen, cid))
+    kz, ks = np.stack(kids_z), np.stack(kids_s)
+    kd, _ = oracle.eval_plans(inst, kz, ks)
+    for r, slot in enumerate(worst_individuals(dist, len(kept_ids))):
+        Z[slot], Sq[slot], D[slot] = kz[r], ks[r], kd[r]
+    return Z, Sq, D

@@ -1,21 +1,33 @@
 // Exact plan evaluation on gfx950: slot map, next-fit tours, S-shape distance,
 // time-window throughput (arXiv 2110.13693, section 5, Subproblems 2 and 3,
 // Eq. (2); section 6).  One workgroup evaluates one plan at a time and walks
-// the plans with a grid stride.
+// the plans with a grid stride; several workgroups share a CU so that one's
+// latency-bound phases overlap the others' work.
 //
 // Per plan:
 //   1. zone starts: start[c] = sum of the sizes of categories placed in a
 //      lower zone; kept in LDS pre-shifted so that a line's scaled location
-//      is one add: ls = rec + zs[rec >> 24 / 4];
-//   2. the order sequence is staged in LDS with its item prefix sums P;
-//   3. next-fit: e(i) = one past the last order of a tour opened at position
-//      i = the largest m with P[m] - P[i] <= Q (at least i + 1); tours start
-//      on the orbit of 0 under e; each order gets its tour id;
-//   4. every order line (in instance order, coalesced) sets its aisle bit in
+//      is one add: ls = rec + zs[rec >> 26];
+//   2. a bitmap B over "units" of the sequence: bit P[i] is set where the
+//      i-th order of the sequence starts, P being the prefix sum of the order
+//      sizes clamped to Q + 1 (an order larger than Q is a tour of its own
+//      whatever its exact size), plus a sentinel bit at the total;
+//   3. next-fit: a tour opened at unit x ends after the last order that
+//      starts within (x, x + Q]; so the next tour opens at
+//      E(x) = highest set bit of B in (x, x + Q] (a 64-bit window of B).
+//      Tours open on the orbit of 0 under E.  The orbit is found in
+//      parallel: the unit range is cut into segments, and for each segment
+//      every order start that can be the first tour opened in it (those
+//      within Q units of its start) is chased to the segment end; the true
+//      entries are then linked segment after segment;
+//   4. tour ids: the rank of each opening position among the order starts is
+//      the sequence position of the tour's first order; a block scan over
+//      these flags gives every order its tour id;
+//   5. every order line (in instance order, coalesced) sets its aisle bit in
 //      its tour's aisle set (ds_or) and raises its tour's farthest location
 //      (ds_max) -- the largest location of a tour is, at once, the last
 //      aisle visited and the farthest depth in it;
-//   5. per tour: k = popcount of the aisle set, S-shape closed form; the
+//   6. per tour: k = popcount of the aisle set, S-shape closed form; the
 //      block sums the tours in int64.
 #include "wo_internal.h"
 
@@ -24,6 +36,11 @@ namespace wo {
 static __device__ __forceinline__ uint32_t mulhi24(uint32_t x, uint32_t m)
 {
     return (uint32_t)(((uint64_t)(x & 0xFFFFFFu) * (uint64_t)(m & 0xFFFFFFu)) >> 32);
+}
+
+static __device__ __forceinline__ uint32_t ffbh(uint32_t x)   // leading zeros, 32 for 0
+{
+    return x ? (uint32_t)__builtin_clz(x) : 32u;
 }
 
 template <int BLOCK>
@@ -73,12 +90,49 @@ static __device__ __forceinline__ float window_throughput(int64_t D, const InstD
     return __double2float_rn(r);
 }
 
+// Bits [x, x + 32) of bitmap B (B holds at least (x >> 5) + 2 words).
+static __device__ __forceinline__ uint32_t bits_at(const uint32_t *B, uint32_t x)
+{
+    const uint32_t w = x >> 5;
+    return __builtin_amdgcn_alignbit(B[w + 1], B[w], x & 31u);
+}
+
+// Next tour opening after a tour opened at unit x (no order larger than Q).
+static __device__ __forceinline__ uint32_t next_open(const uint32_t *B, uint32_t x, uint32_t maskQ)
+{
+    const uint32_t win = bits_at(B, x + 1) & maskQ;
+    return x + 32u - ffbh(win);        // x + 1 + highest set bit
+}
+
+// Number of order starts below unit x = sequence position of the order at x.
+static __device__ __forceinline__ uint32_t rank_of(const uint32_t *B, const uint32_t *prefB, uint32_t x)
+{
+    const uint32_t w = x >> 5;
+    return prefB[w] + __popc(B[w] & ((1u << (x & 31u)) - 1u));
+}
+
+// Bits [lo, hi) of bitmap F, counted.
+static __device__ __forceinline__ int count_range(const uint32_t *F, int lo, int hi)
+{
+    int c = 0;
+    while (lo < hi) {
+        const int w = lo >> 5;
+        const int lim = min(hi, (w + 1) << 5);
+        const int len = lim - lo;
+        const uint32_t m = (len == 32 ? 0xFFFFFFFFu : ((1u << len) - 1u)) << (lo & 31);
+        c += __popc(F[w] & m);
+        lo = lim;
+    }
+    return c;
+}
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     const int tid = threadIdx.x;
     const int lane = tid & 63;
+    int loaded = -1;                        // instance whose count table sits in LDS
 
     for (int64_t p = blockIdx.x; p < A.n_plans; p += gridDim.x) {
         int ii = 0;
@@ -94,120 +148,317 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
         const int n = I.n_orders;
         const int C = I.n_cat;
         const uint32_t Q = (uint32_t)I.capacity;
+        const uint32_t maskQ = Q >= 32u ? 0xFFFFFFFFu : ((1u << Q) - 1u);
+        const uint32_t n_units = (uint32_t)I.n_units;
         const int64_t row = p - (A.n_inst > 1 ? A.plan_begin[ii] : 0);
         const uint16_t *seq = A.seq + A.seq_base[ii] + row * (int64_t)n;
-        const uint32_t *rec = A.rec + I.rec_off;
-        const uint32_t *ooff = A.ooff + I.ooff_off;
-        const uint16_t *lord = A.lord + I.lord_off;
-        const EvalLayout Ly = eval_layout(n, I.words, I.t_cap);
+        const uint2 *lines = A.lines + I.line_off;
+        const EvalLayout Ly = eval_layout(n, I.n_units, I.words, I.t_cap);
         uint32_t *zs = (uint32_t *)(smem + Ly.zs);
         int64_t *red = (int64_t *)(smem + Ly.red);
-        uint32_t *P = (uint32_t *)(smem + Ly.P);
-        uint16_t *sq = (uint16_t *)(smem + Ly.sq);
-        uint16_t *e = (uint16_t *)(smem + Ly.e);
+        int *misc = (int *)(smem + Ly.misc);
+        uint32_t *lane_base = (uint32_t *)(smem + Ly.seg);
+        uint32_t *wbits = lane_base + (MAX_SEG + 1);
+        uint32_t *true_lane = wbits + (MAX_SEG + 1);
+        uint32_t *segs = true_lane + (MAX_SEG + 1);
+        uint8_t *cnt = (uint8_t *)(smem + Ly.cnt);
+        uint32_t *F = (uint32_t *)(smem + Ly.F);
         uint16_t *tour = (uint16_t *)(smem + Ly.tour);
-        uint8_t *flag = (uint8_t *)(smem + Ly.flag);
+        uint32_t *B = (uint32_t *)(smem + Ly.B);
+        uint32_t *prefB = (uint32_t *)(smem + Ly.prefB);
+        uint16_t *crec = (uint16_t *)(smem + Ly.rec);
+        uint32_t *cnrec = (uint32_t *)(smem + Ly.nrec);
+        uint32_t *cnxt = (uint32_t *)(smem + Ly.nxt);
         uint32_t *mask = (uint32_t *)(smem + Ly.mask);
         uint32_t *mx = (uint32_t *)(smem + Ly.mx);
+        const uint32_t nB = bitmap_words(I.n_units);
+        const int nF = (n + 31) / 32 + 1;
         int bad = 0;
+
+        // ---- staging: count table, cleared bitmaps ------------------------
+        if (ii != loaded) {
+            const uint4 *src = (const uint4 *)(A.cnt + I.cnt_off);
+            uint4 *dst = (uint4 *)cnt;
+            for (int k = tid; k < (n + 15) / 16; k += BLOCK) dst[k] = src[k];
+            loaded = ii;
+        }
+        for (uint32_t w = tid; w < nB; w += BLOCK) B[w] = 0;
+        for (int w = tid; w < nF; w += BLOCK) F[w] = 0;
+        if (tid < 16) misc[tid] = 0;
 
         // ---- 1. zone starts (wave 0) -------------------------------------
         if (tid < 64) {
-            uint32_t zc = (lane < C) ? (uint32_t)A.zone_of[p * 64 + lane] : 0xFFu;
+            const uint32_t zc = (lane < C) ? (uint32_t)A.zone_of[p * 64 + lane] : 0xFFu;
+            const uint32_t sz = (lane < C) ? (uint32_t)I.cat_size[lane] : 0u;
             uint32_t start = 0;
             for (int c2 = 0; c2 < C; c2++) {
-                uint32_t z2 = (uint32_t)__shfl((int)zc, c2, 64);
-                start += (z2 < zc) ? (uint32_t)I.cat_size[c2] : 0u;
+                const uint32_t z2 = (uint32_t)__builtin_amdgcn_readlane((int)zc, c2);
+                const uint32_t s2 = (uint32_t)__builtin_amdgcn_readlane((int)sz, c2);
+                start += (z2 < zc) ? s2 : 0u;
             }
             zs[lane] = (start << I.shift) - ((uint32_t)(4 * lane) << 24);
             if (A.validate) {
                 uint64_t m = (lane < C && zc < 64u) ? (1ull << zc) : 0ull;
 #pragma unroll
                 for (int d = 32; d >= 1; d >>= 1) m |= __shfl_xor(m, d, 64);
-                uint64_t want = (C == 64) ? ~0ull : ((1ull << C) - 1ull);
+                const uint64_t want = (C == 64) ? ~0ull : ((1ull << C) - 1ull);
                 if (lane == 0 && m != want) bad = 1;
             }
         }
 
-        // ---- 2. sequence, item prefix sums -------------------------------
+        // ---- 2. unit bitmap of order starts --------------------------------
         const int ch = (n + BLOCK - 1) / BLOCK;
         const int b0 = min(n, tid * ch), b1 = min(n, b0 + ch);
-        int local = 0;
-        for (int i = b0; i < b1; i++) {
-            uint32_t o = seq[i];
-            if (o >= (uint32_t)n) { bad = 1; o = (uint32_t)(n - 1); }
-            sq[i] = (uint16_t)o;
-            flag[i] = 0;
-            local += (int)(ooff[o + 1] - ooff[o]);
+        const bool one_piece = ch <= SEQ_CHUNK;          // uniform
+        uint32_t sv[SEQ_CHUNK];
+        if (one_piece) {
+#pragma unroll
+            for (int k = 0; k < SEQ_CHUNK; k++) {
+                const int i = b0 + k;
+                uint32_t o = (i < b1) ? (uint32_t)seq[i] : 0u;
+                if (o >= (uint32_t)n) { bad = 1; o = (uint32_t)(n - 1); }
+                sv[k] = o;
+            }
         }
-        int total_items;
-        int run = block_excl_scan<BLOCK>(local, (int *)red, &total_items);
-        for (int i = b0; i < b1; i++) {
-            P[i] = (uint32_t)run;
-            uint32_t o = sq[i];
-            run += (int)(ooff[o + 1] - ooff[o]);
+        __syncthreads();                                 // count table, zeroed bitmaps
+        int local = 0, big = 0;
+        if (one_piece) {
+#pragma unroll
+            for (int k = 0; k < SEQ_CHUNK; k++) {
+                if (b0 + k < b1) {
+                    const int c = cnt[sv[k]];
+                    local += c;
+                    big |= c > (int)Q;
+                }
+            }
+        } else {
+            for (int i = b0; i < b1; i++) {
+                uint32_t o = seq[i];
+                if (o >= (uint32_t)n) { bad = 1; o = (uint32_t)(n - 1); }
+                const int c = cnt[o];
+                local += c;
+                big |= c > (int)Q;
+            }
         }
-        if (tid == 0) P[n] = (uint32_t)total_items;
+        int total_units;
+        uint32_t run = (uint32_t)block_excl_scan<BLOCK>(local, (int *)red, &total_units);
+        {
+            uint32_t cur = run >> 5, acc = 0;
+            if (one_piece) {
+#pragma unroll
+                for (int k = 0; k < SEQ_CHUNK; k++) {
+                    if (b0 + k < b1) {
+                        const uint32_t w = run >> 5;
+                        if (w != cur) { atomicOr(&B[cur], acc); acc = 0; cur = w; }
+                        acc |= 1u << (run & 31u);
+                        run += cnt[sv[k]];
+                    }
+                }
+            } else {
+                for (int i = b0; i < b1; i++) {
+                    uint32_t o = seq[i];
+                    if (o >= (uint32_t)n) o = (uint32_t)(n - 1);
+                    const uint32_t w = run >> 5;
+                    if (w != cur) { atomicOr(&B[cur], acc); acc = 0; cur = w; }
+                    acc |= 1u << (run & 31u);
+                    run += cnt[o];
+                }
+            }
+            if (acc) atomicOr(&B[cur], acc);
+        }
+        if (tid == 0) atomicOr(&B[n_units >> 5], 1u << (n_units & 31u));   // sentinel
+        if (big) misc[0] = 1;
         if (A.validate) {
-            // permutation check: mark every order once (bitmap in the mask area)
-            uint32_t *seen = mask;
+            // permutation check: mark every order once (bitmap in the region)
+            uint32_t *seen = (uint32_t *)(smem + Ly.region);
             for (int w = tid; w < (n + 31) / 32; w += BLOCK) seen[w] = 0;
             __syncthreads();
             for (int i = tid; i < n; i += BLOCK) {
-                uint32_t o = sq[i];
-                uint32_t old = atomicOr(&seen[o >> 5], 1u << (o & 31));
+                const uint32_t o = seq[i];
+                if (o >= (uint32_t)n) continue;
+                const uint32_t old = atomicOr(&seen[o >> 5], 1u << (o & 31));
                 if (old & (1u << (o & 31))) bad = 1;
             }
         }
         __syncthreads();
-
-        // ---- 3. next-fit tours -------------------------------------------
-        for (int i = tid; i < n; i += BLOCK) {
-            const uint32_t target = P[i] + Q;
-            int m = i + 1;
-            if (P[i + 1] <= target) {
-                int lo = i + 1, hi = min(n, i + (int)Q);   // P[lo] <= target
-                while (lo < hi) {
-                    int mid = (lo + hi + 1) >> 1;
-                    if (P[mid] <= target) lo = mid; else hi = mid - 1;
-                }
-                m = lo;
+        {   // prefix popcounts of B (word granularity)
+            const int wch = ((int)nB + BLOCK - 1) / BLOCK;
+            const int w0 = min((int)nB, tid * wch), w1 = min((int)nB, w0 + wch);
+            int c = 0;
+            for (int w = w0; w < w1; w++) c += __popc(B[w]);
+            int tot;
+            int r = block_excl_scan<BLOCK>(c, (int *)red, &tot);
+            for (int w = w0; w < w1; w++) {
+                prefB[w] = (uint32_t)r;
+                r += __popc(B[w]);
             }
-            e[i] = (uint16_t)m;
         }
-        __syncthreads();
-        if (tid == 0) {
-            int x = 0;
-            while (x < n) { flag[x] = 1; x = e[x]; }
+
+        // ---- 3. segments and their candidate entries (wave 0) ------------
+        int G = (misc[0] || I.n_seg <= 1) ? 1 : I.n_seg;   // uniform
+        if (G > 1 && tid < 64) {
+            const int g = lane;
+            const uint32_t s_g = (uint32_t)(((uint64_t)g * n_units) / (uint32_t)G);
+            uint32_t c = 0, wb = 0;
+            if (g == 0) {
+                c = 1;
+            } else if (g < G) {
+                const uint32_t lim = n_units - s_g;   // candidates are order starts < n_units
+                wb = bits_at(B, s_g) & maskQ;
+                if (lim < 32u) wb &= (1u << lim) - 1u;
+                c = __popc(wb);
+            }
+            uint32_t inc = c;
+#pragma unroll
+            for (int d = 1; d < 64; d <<= 1) {
+                const uint32_t t = __shfl_up(inc, d, 64);
+                if (lane >= d) inc += t;
+            }
+            lane_base[g] = inc - c;
+            wbits[g] = wb;
+            segs[g] = g <= G ? s_g : n_units;
+            if (g == 63) misc[1] = (int)inc;          // total chase lanes
         }
+        if (G > 1 && tid == 0) segs[G] = n_units;
         __syncthreads();
-        int cnt = 0;
-        for (int i = b0; i < b1; i++) cnt += flag[i];
-        int n_tours;
-        int tid_run = block_excl_scan<BLOCK>(cnt, (int *)red, &n_tours) - 1;
-        for (int i = b0; i < b1; i++) {
-            tid_run += flag[i];
-            tour[sq[i]] = (uint16_t)tid_run;
+        if (G > 1 && misc[1] > CHASE_LANES) G = 1;    // uniform
+
+        // ---- 4. chase ------------------------------------------------------
+        if (G > 1) {
+            const int L_tot = misc[1];
+            for (int l = tid; l < L_tot; l += BLOCK) {
+                int lo = 0, hi = G - 1;                  // segment of lane l
+                while (lo < hi) {
+                    const int mid = (lo + hi + 1) >> 1;
+                    if ((int)lane_base[mid] <= l) lo = mid; else hi = mid - 1;
+                }
+                const int g = lo;
+                const uint32_t s_g = segs[g];
+                const uint32_t s_e = segs[g + 1];
+                uint32_t x = s_g;
+                if (g > 0) {
+                    uint32_t wb = wbits[g];
+                    for (int k = l - (int)lane_base[g]; k > 0; k--) wb &= wb - 1u;
+                    x = s_g + (uint32_t)__builtin_ctz(wb);
+                }
+                uint16_t *r = crec + l * CHASE_RECS;
+                uint32_t nr = 0;
+                r[nr++] = (uint16_t)(x - s_g);
+                for (;;) {
+                    x = next_open(B, x, maskQ);
+                    if (x >= s_e) break;
+                    if (nr == CHASE_RECS) { misc[2] = 1; break; }
+                    r[nr++] = (uint16_t)(x - s_g);
+                }
+                cnrec[l] = nr;
+                // the lane of the next segment whose candidate is this exit
+                uint32_t nx = 0xFFFFFFFFu;
+                if (g + 1 < G) {
+                    const uint32_t off = x - s_e;
+                    const uint32_t wb = wbits[g + 1];
+                    if (off < 32u && ((wb >> off) & 1u))
+                        nx = lane_base[g + 1] + __popc(wb & ((1u << off) - 1u));
+                }
+                cnxt[l] = nx;
+            }
+            __syncthreads();
+            // ---- link the true entries, segment after segment ------------
+            if (tid == 0 && !misc[2]) {
+                uint32_t l = 0;
+                for (int g = 0; g < G; g++) {
+                    true_lane[g] = l;
+                    if (g + 1 < G) {
+                        l = cnxt[l];
+                        if (l == 0xFFFFFFFFu) { misc[2] = 1; break; }
+                    }
+                }
+            }
+            __syncthreads();
+            if (!misc[2]) {
+                for (int idx = tid; idx < G * CHASE_RECS; idx += BLOCK) {
+                    const int g = idx / CHASE_RECS, k = idx % CHASE_RECS;
+                    const uint32_t l = true_lane[g];
+                    if ((uint32_t)k < cnrec[l]) {
+                        const uint32_t x = segs[g] + crec[l * CHASE_RECS + k];
+                        const uint32_t i = rank_of(B, prefB, x);
+                        atomicOr(&F[i >> 5], 1u << (i & 31u));
+                    }
+                }
+            } else {
+                G = 1;                                   // fall back to the serial chain
+            }
+        }
+        if (G == 1) {
+            // serial chain (also handles orders larger than the capacity)
+            if (tid == 0) {
+                uint32_t x = 0;
+                while (x < n_units) {
+                    const uint32_t i = rank_of(B, prefB, x);
+                    F[i >> 5] |= 1u << (i & 31u);
+                    const uint32_t win = bits_at(B, x + 1) & maskQ;
+                    if (win) {
+                        x = x + 32u - ffbh(win);
+                    } else {                             // an order larger than Q: its own tour
+                        uint32_t y = x + 1;
+                        while (!((B[y >> 5] >> (y & 31u)) & 1u)) y++;
+                        x = y;
+                    }
+                }
+            }
         }
         __syncthreads();
 
-        // ---- 4./5. aisle sets and S-shape per tour tile ------------------
+        // ---- tour id of every order --------------------------------------
+        int n_tours;
+        int trun = block_excl_scan<BLOCK>(count_range(F, b0, b1), (int *)red, &n_tours) - 1;
+        if (one_piece) {
+#pragma unroll
+            for (int k = 0; k < SEQ_CHUNK; k++) {
+                const int i = b0 + k;
+                if (i < b1) {
+                    trun += (F[i >> 5] >> (i & 31)) & 1u;
+                    tour[sv[k]] = (uint16_t)trun;
+                }
+            }
+        } else {
+            for (int i = b0; i < b1; i++) {
+                uint32_t o = seq[i];
+                if (o >= (uint32_t)n) o = (uint32_t)(n - 1);
+                trun += (F[i >> 5] >> (i & 31)) & 1u;
+                tour[o] = (uint16_t)trun;
+            }
+        }
+        __syncthreads();
+
+        // ---- 5./6. aisle sets and S-shape per tour tile ------------------
         const int W = I.words;
         const int T = I.t_cap;
         const uint32_t magic = I.magic;
+        const int n_lines = I.n_lines;
         int64_t acc = 0;
         for (int t0 = 0; t0 < n_tours; t0 += T) {
             for (int k = tid; k < W * T; k += BLOCK) mask[k] = 0;
             for (int k = tid; k < T; k += BLOCK) mx[k] = 0;
             __syncthreads();
-            for (int q = tid; q < I.n_lines; q += BLOCK) {
-                const uint32_t t = (uint32_t)tour[lord[q]] - (uint32_t)t0;
-                if (t < (uint32_t)T) {
-                    const uint32_t r = rec[q];
-                    const uint32_t ls = r + zs[r >> 26];
-                    const uint32_t a = mulhi24(ls, magic);
-                    atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
-                    atomicMax(&mx[t], ls);
+            for (int q0 = tid; q0 < n_lines; q0 += 4 * BLOCK) {
+                uint2 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    const int q = q0 + u * BLOCK;
+                    v[u] = (q < n_lines) ? lines[q] : make_uint2(0u, 0xFFFFFFFFu);
+                }
+#pragma unroll
+                for (int u = 0; u < 4; u++) {
+                    if (v[u].y != 0xFFFFFFFFu) {
+                        const uint32_t t = (uint32_t)tour[v[u].y] - (uint32_t)t0;
+                        if (t < (uint32_t)T) {
+                            const uint32_t r = v[u].x;
+                            const uint32_t ls = r + zs[r >> 26];
+                            const uint32_t a = mulhi24(ls, magic);
+                            atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
+                            atomicMax(&mx[t], ls);
+                        }
+                    }
                 }
             }
             __syncthreads();

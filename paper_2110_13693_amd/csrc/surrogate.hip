@@ -1,0 +1,542 @@
+// Surrogate network kernels for gfx950: an MLP that predicts a plan's route
+// distance from its slotting (the paper's hybrid decision making, section 1,
+// Figure 1: models trained on simulated scenarios take decisions; here the
+// simulator is the exact evaluator).
+//
+//   x   = one-hot(zone_of), 64 x 64 (row = category, column = zone) = 4096 inputs
+//   h1  = GELU(x W1 + b1)      1024
+//   h2  = GELU(h1 W2 + b2)     256
+//   y   = h2 W3 + b3           (standardised distance)
+//
+// GEMMs run on MFMA (v_mfma_f32_16x16x32_bf16: bf16 operands, fp32
+// accumulation).  Weights are kept as fp32 masters in [out][in] layout with
+// bf16 working copies; the one-hot operand is generated in registers from the
+// zone bytes and never stored.  Every GEMM here is C[M][N] = A[M][K] . B[N][K]^T
+// with both operands K-contiguous.
+#include "wo_internal.h"
+#include "wo_surrogate.h"
+
+namespace wo {
+
+typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
+typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+
+static __device__ __forceinline__ uint16_t f2bf(float f)
+{
+    uint32_t u = __float_as_uint(f);
+    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return 0x7FC0;   // NaN
+    u += 0x7FFFu + ((u >> 16) & 1u);                                           // nearest, ties to even
+    return (uint16_t)(u >> 16);
+}
+
+static __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+static __device__ __forceinline__ float gelu_f(float u)
+{
+    const float t = tanhf(0.7978845608028654f * (u + 0.044715f * u * u * u));
+    return 0.5f * u * (1.0f + t);
+}
+
+static __device__ __forceinline__ float gelu_grad_f(float u)
+{
+    const float t = tanhf(0.7978845608028654f * (u + 0.044715f * u * u * u));
+    const float dt = (1.0f - t * t) * 0.7978845608028654f * (1.0f + 3.0f * 0.044715f * u * u);
+    return 0.5f * (1.0f + t) + 0.5f * u * dt;
+}
+
+// 8 bf16 values, one of them 1.0 at position d when d < 8.
+static __device__ __forceinline__ bf16x8 one_hot8(uint32_t d)
+{
+    u32x4 w;
+    const uint32_t v = 0x3F80u << ((d & 1u) * 16u);
+    const uint32_t h = d >> 1;
+    w[0] = (h == 0u) ? v : 0u;
+    w[1] = (h == 1u) ? v : 0u;
+    w[2] = (h == 2u) ? v : 0u;
+    w[3] = (h == 3u) ? v : 0u;
+    return __builtin_bit_cast(bf16x8, w);
+}
+
+// ---------------------------------------------------------------------------
+// GEMM: C[M][N] = A[M][K] . B[N][K]^T.  Block tile 128 x 128, K step 32,
+// four waves in 2 x 2, each 64 x 64 = 4 x 4 MFMA tiles of 16 x 16.
+// M, N multiples of 128 and K a multiple of 32 (the host pads); rows of A at
+// or beyond M_real read as zero when A is generated from zone bytes.
+// ---------------------------------------------------------------------------
+constexpr int GBM = 128, GBN = 128, GBK = 32, GPAD = 8;
+
+template <int AMODE, int BMODE, int EPI>
+__global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
+{
+    __shared__ __align__(16) uint16_t As[GBM][GBK + GPAD];
+    __shared__ __align__(16) uint16_t Bs[GBN][GBK + GPAD];
+    __shared__ __align__(16) uint8_t Zs[(AMODE == A_ONEHOT) ? GBM * 64 : (BMODE == B_ONEHOT_T ? GBK * 64 : 16)];
+
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int wm = w >> 1, wn = w & 1;
+    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    const int fr = lane & 15, fk = (lane >> 4) * 8;
+
+    floatx4 acc[4][4];
+#pragma unroll
+    for (int i = 0; i < 4; i++)
+#pragma unroll
+        for (int j = 0; j < 4; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+
+    if (AMODE == A_ONEHOT) {
+        // zone bytes of the block's 128 rows (8 KB), 0xFF past the real rows
+        for (int c = tid; c < GBM * 4; c += 256) {
+            const int r = c >> 2, part = c & 3;
+            uint4 v = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+            if (m0 + r < g.M_real) v = *(const uint4 *)(g.zoneA + (int64_t)(m0 + r) * 64 + part * 16);
+            *(uint4 *)(&Zs[r * 64 + part * 16]) = v;
+        }
+    }
+
+    for (int k0 = 0; k0 < g.K; k0 += GBK) {
+        if (AMODE == A_BF16) {
+            for (int c = tid; c < GBM * 4; c += 256) {
+                const int r = c >> 2, part = c & 3;
+                *(uint4 *)(&As[r][part * 8]) =
+                    *(const uint4 *)(g.A + (int64_t)(m0 + r) * g.lda + k0 + part * 8);
+            }
+        }
+        if (BMODE == B_BF16) {
+            for (int c = tid; c < GBN * 4; c += 256) {
+                const int r = c >> 2, part = c & 3;
+                *(uint4 *)(&Bs[r][part * 8]) =
+                    *(const uint4 *)(g.B + (int64_t)(n0 + r) * g.ldb + k0 + part * 8);
+            }
+        } else {
+            // zone bytes of the 32 samples of this K step (2 KB)
+            for (int c = tid; c < GBK * 4; c += 256) {
+                const int r = c >> 2, part = c & 3;
+                uint4 v = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
+                if (k0 + r < g.K_real) v = *(const uint4 *)(g.zoneB + (int64_t)(k0 + r) * 64 + part * 16);
+                *(uint4 *)(&Zs[r * 64 + part * 16]) = v;
+            }
+        }
+        __syncthreads();
+
+        bf16x8 af[4], bfr[4];
+#pragma unroll
+        for (int ti = 0; ti < 4; ti++) {
+            const int row = wm * 64 + ti * 16 + fr;
+            if (AMODE == A_BF16) {
+                af[ti] = *(const bf16x8 *)(&As[row][fk]);
+            } else {
+                const int k = k0 + fk;                      // 8 | 64: one category per fragment
+                const uint32_t z = (k >> 6) < g.n_cat ? (uint32_t)Zs[row * 64 + (k >> 6)] : 0xFFu;
+                af[ti] = one_hot8(z - (uint32_t)(k & 63));
+            }
+        }
+#pragma unroll
+        for (int tj = 0; tj < 4; tj++) {
+            const int col = wn * 64 + tj * 16 + fr;
+            if (BMODE == B_BF16) {
+                bfr[tj] = *(const bf16x8 *)(&Bs[col][fk]);
+            } else {
+                const int n = n0 + col;                     // input feature = category*64 + zone
+                const int cc = n >> 6;
+                const uint8_t zz = cc < g.n_cat ? (uint8_t)(n & 63) : (uint8_t)0xFE;   // 0xFE matches no zone
+                u32x4 wv;
+#pragma unroll
+                for (int e = 0; e < 4; e++) {
+                    const uint32_t lo = Zs[(fk + 2 * e) * 64 + cc] == zz ? 0x3F80u : 0u;
+                    const uint32_t hi = Zs[(fk + 2 * e + 1) * 64 + cc] == zz ? 0x3F800000u : 0u;
+                    wv[e] = lo | hi;
+                }
+                bfr[tj] = __builtin_bit_cast(bf16x8, wv);
+            }
+        }
+#pragma unroll
+        for (int ti = 0; ti < 4; ti++)
+#pragma unroll
+            for (int tj = 0; tj < 4; tj++)
+                acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ti], bfr[tj], acc[ti][tj], 0, 0, 0);
+        __syncthreads();
+    }
+
+    // epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each tile
+#pragma unroll
+    for (int ti = 0; ti < 4; ti++) {
+#pragma unroll
+        for (int tj = 0; tj < 4; tj++) {
+            const int col = n0 + wn * 64 + tj * 16 + fr;
+            const int rb = m0 + wm * 64 + ti * 16 + (lane >> 4) * 4;
+            if (EPI == EPI_STORE) {
+#pragma unroll
+                for (int r = 0; r < 4; r++) g.C[(int64_t)(rb + r) * g.ldc + col] = acc[ti][tj][r];
+            } else if (EPI == EPI_BIAS_GELU) {
+                const float bias = g.bias[col];
+                uint16_t hv[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const float u = acc[ti][tj][r] + bias;
+                    if (g.U) g.U[(int64_t)(rb + r) * g.ldc + col] = u;
+                    hv[r] = f2bf(gelu_f(u));
+                    if (g.H) g.H[(int64_t)(rb + r) * g.ldc + col] = hv[r];
+                }
+                if (g.HT) {
+                    uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
+                                          (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
+                    *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pk;
+                }
+            } else {   // EPI_GELU_GRAD_T: v = acc * gelu'(U), stored transposed in bf16
+                uint16_t hv[4];
+#pragma unroll
+                for (int r = 0; r < 4; r++) {
+                    const float u = g.Uin[(int64_t)(rb + r) * g.ldc + col];
+                    hv[r] = f2bf(acc[ti][tj][r] * gelu_grad_f(u));
+                }
+                uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
+                                      (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
+                *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pk;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Layer 3 and the loss.  One wave per sample: h2 = GELU(u2) in fp32,
+// y = h2 . W3 + b3.  Training also forms dy = 2 (y - t) / n and
+// du2 = dy * W3 * GELU'(u2) (bf16, row-major and transposed).
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void layer3_kernel(L3Args a)
+{
+    const int lane = threadIdx.x & 63;
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (b >= a.n) return;
+    float u[4], h[4], s = 0.f;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int j = lane + 64 * q;
+        u[q] = a.U2[(int64_t)b * N_H2 + j];
+        h[q] = gelu_f(u[q]);
+        s += h[q] * a.W3[j];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    const float y = s + a.b3[0];
+    if (a.target == nullptr) {
+        if (lane == 0) a.pred[b] = y * a.std + a.mean;
+        return;
+    }
+    const float t = a.target[b];
+    const float dy = 2.0f * (y - t) / (float)a.n_batch;
+    if (lane == 0) {
+        a.dy[b] = dy;
+        a.sq[b] = (y - t) * (y - t);
+        if (a.pred) a.pred[b] = y;
+    }
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+        const int j = lane + 64 * q;
+        a.H2[(int64_t)b * N_H2 + j] = h[q];
+        const uint16_t v = f2bf(dy * a.W3[j] * gelu_grad_f(u[q]));
+        a.DU2[(int64_t)b * N_H2 + j] = v;
+        a.DU2T[(int64_t)j * a.ld_t + b] = v;
+    }
+}
+
+// Gradients that are sums over the batch, in a fixed order (deterministic):
+// gW3[j] = sum_b h2[b][j] dy[b], gb3 = sum_b dy[b], gb2[j] = sum_b du2[b][j],
+// gb1[i] = sum_b du1[b][i] (du from the transposed bf16 copies), loss.
+__global__ __launch_bounds__(256) void batch_sums_kernel(SumArgs a)
+{
+    const int lane = threadIdx.x & 63;
+    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per output
+    const int n_out = N_H2 + 1 + N_H2 + N_H1 + 1;
+    if (row >= n_out) return;
+    float s = 0.f;
+    if (row < N_H2) {
+        for (int b = lane; b < a.n; b += 64) s += a.H2[(int64_t)b * N_H2 + row] * a.dy[b];
+    } else if (row == N_H2) {
+        for (int b = lane; b < a.n; b += 64) s += a.dy[b];
+    } else if (row < 2 * N_H2 + 1) {
+        const int j = row - N_H2 - 1;
+        for (int b = lane; b < a.n; b += 64) s += bf2f(a.DU2T[(int64_t)j * a.ld_t + b]);
+    } else if (row < 2 * N_H2 + 1 + N_H1) {
+        const int i = row - 2 * N_H2 - 1;
+        for (int b = lane; b < a.n; b += 64) s += bf2f(a.DU1T[(int64_t)i * a.ld_t + b]);
+    } else {
+        for (int b = lane; b < a.n; b += 64) s += a.sq[b];
+    }
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+    if (lane != 0) return;
+    if (row < N_H2) a.gW3[row] = s;
+    else if (row == N_H2) a.gb3[0] = s;
+    else if (row < 2 * N_H2 + 1) a.gb2[row - N_H2 - 1] = s;
+    else if (row < 2 * N_H2 + 1 + N_H1) a.gb1[row - 2 * N_H2 - 1] = s;
+    else a.loss[0] = s / (float)a.n;
+}
+
+// Adam over the flat fp32 parameter vector (Kingma & Ba 2015, bias-corrected).
+__global__ __launch_bounds__(256) void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n,
+                                                   float lr, float beta1, float beta2, float eps, float bc1,
+                                                   float bc2)
+{
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
+        const float gi = g[i];
+        const float mi = beta1 * m[i] + (1.0f - beta1) * gi;
+        const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+    }
+}
+
+// bf16 working copies: W1 [1024][4096] and W2 [256][1024] as stored, plus W2
+// transposed to [1024][256] for the backward product.
+__global__ __launch_bounds__(256) void refresh_bf16_kernel(const float *W1t, const float *W2t, uint16_t *W1b,
+                                                           uint16_t *W2b, uint16_t *W2kn)
+{
+    const int64_t n1 = (int64_t)N_H1 * N_IN, n2 = (int64_t)N_H2 * N_H1;
+    for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n1 + n2; i += (int64_t)gridDim.x * 256) {
+        if (i < n1) {
+            W1b[i] = f2bf(W1t[i]);
+        } else {
+            const int64_t k = i - n1;               // W2t[j][i2], j < 256, i2 < 1024
+            const int64_t j = k / N_H1, i2 = k % N_H1;
+            const uint16_t v = f2bf(W2t[k]);
+            W2b[k] = v;
+            W2kn[i2 * N_H2 + j] = v;
+        }
+    }
+}
+
+// Gather a batch: zone rows and standardised targets of the given samples.
+__global__ __launch_bounds__(256) void gather_batch_kernel(const uint8_t *zone, const int32_t *dist,
+                                                           const int32_t *idx, int n, double mean, double inv_std,
+                                                           uint8_t *zb, float *tb)
+{
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (b >= n) return;
+    const int64_t s = idx[b];
+    zb[(int64_t)b * 64 + lane] = zone[s * 64 + lane];
+    if (lane == 0) tb[b] = (float)(((double)dist[s] - mean) * inv_std);
+}
+
+// Mean and standard deviation of int32 distances (two fixed-order passes,
+// one block, double accumulation).
+__global__ __launch_bounds__(1024) void moments_kernel(const int32_t *d, int64_t n, double *out)
+{
+    __shared__ double part[1024];
+    double s = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) s += (double)d[i];
+    part[threadIdx.x] = s;
+    __syncthreads();
+    for (int st = 512; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
+        __syncthreads();
+    }
+    const double mean = part[0] / (double)n;
+    __syncthreads();
+    double q = 0.0;
+    for (int64_t i = threadIdx.x; i < n; i += 1024) {
+        const double e = (double)d[i] - mean;
+        q += e * e;
+    }
+    part[threadIdx.x] = q;
+    __syncthreads();
+    for (int st = 512; st >= 1; st >>= 1) {
+        if ((int)threadIdx.x < st) part[threadIdx.x] += part[threadIdx.x + st];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        out[0] = mean;
+        out[1] = sqrt(part[0] / (double)n);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Top-k of n predictions by (value, index), one workgroup: radix selection of
+// the k-th smallest value over its order-preserving bit pattern, ties taken
+// in index order, then a bitonic sort of the k winners in LDS.
+// ---------------------------------------------------------------------------
+static __device__ __forceinline__ uint32_t order_key(float f)
+{
+    const uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+
+constexpr int TOPK_THREADS = 1024;
+
+// MODE 0: keys are float predictions (smallest first).  MODE 1: keys are int32
+// distances, largest first (the worst individuals of a population).
+template <int MODE>
+static __device__ __forceinline__ uint32_t topk_key(const void *src, int i)
+{
+    if (MODE == 0) return order_key(((const float *)src)[i]);
+    const int32_t d = ((const int32_t *)src)[i];
+    return (uint32_t)(0x7FFFFFFF - (d < 0 ? 0 : d));
+}
+
+template <int MODE>
+__global__ __launch_bounds__(TOPK_THREADS) void topk_kernel(const void *src, int n, int k, int32_t *out)
+{
+    __shared__ uint32_t hist[256];
+    __shared__ uint32_t sel[2];               // prefix found so far, remaining rank
+    __shared__ uint32_t cnt_lt[TOPK_THREADS];
+    __shared__ uint32_t cnt_eq[TOPK_THREADS];
+    __shared__ unsigned long long keys[TOPK_MAX];
+    const int tid = threadIdx.x;
+    if (tid == 0) { sel[0] = 0; sel[1] = (uint32_t)k; }
+    __syncthreads();
+    // k-th smallest key: 4 passes of 8 bits from the top
+    for (int pass = 0; pass < 4; pass++) {
+        const int shift = 24 - 8 * pass;
+        if (tid < 256) hist[tid] = 0;
+        __syncthreads();
+        const uint32_t prefix = sel[0];
+        const uint32_t hi_mask = pass == 0 ? 0u : (0xFFFFFFFFu << (shift + 8));
+        for (int i = tid; i < n; i += TOPK_THREADS) {
+            const uint32_t key = topk_key<MODE>(src, i);
+            if ((key & hi_mask) == prefix) atomicAdd(&hist[(key >> shift) & 255u], 1u);
+        }
+        __syncthreads();
+        if (tid == 0) {
+            uint32_t rem = sel[1], acc = 0;
+            int digit = 0;
+            for (; digit < 256; digit++) {
+                if (acc + hist[digit] >= rem) break;
+                acc += hist[digit];
+            }
+            sel[0] = prefix | ((uint32_t)digit << shift);
+            sel[1] = rem - acc;
+        }
+        __syncthreads();
+    }
+    const uint32_t kth = sel[0];
+    const uint32_t ties_needed = sel[1];          // how many keys equal to kth to keep
+    // keep keys < kth, and the first ties_needed keys == kth in index order
+    const int per = (n + TOPK_THREADS - 1) / TOPK_THREADS;
+    const int i0 = min(n, tid * per), i1 = min(n, i0 + per);
+    uint32_t lt = 0, eq = 0;
+    for (int i = i0; i < i1; i++) {
+        const uint32_t key = topk_key<MODE>(src, i);
+        lt += key < kth;
+        eq += key == kth;
+    }
+    // inclusive scans of lt and eq over the threads (index order)
+    cnt_lt[tid] = lt;
+    cnt_eq[tid] = eq;
+    __syncthreads();
+    for (int d = 1; d < TOPK_THREADS; d <<= 1) {
+        const uint32_t a = tid >= d ? cnt_lt[tid - d] : 0u;
+        const uint32_t b = tid >= d ? cnt_eq[tid - d] : 0u;
+        __syncthreads();
+        cnt_lt[tid] += a;
+        cnt_eq[tid] += b;
+        __syncthreads();
+    }
+    const uint32_t total_lt = cnt_lt[TOPK_THREADS - 1];
+    uint32_t pos_lt = cnt_lt[tid] - lt, pos_eq = cnt_eq[tid] - eq;
+    for (int i = i0; i < i1; i++) {
+        const uint32_t key = topk_key<MODE>(src, i);
+        if (key < kth) {
+            keys[pos_lt++] = ((unsigned long long)key << 32) | (uint32_t)i;
+        } else if (key == kth) {
+            if (pos_eq < ties_needed) keys[total_lt + pos_eq] = ((unsigned long long)key << 32) | (uint32_t)i;
+            pos_eq++;
+        }
+    }
+    int P2 = 1;
+    while (P2 < k) P2 <<= 1;
+    for (int i = k + tid; i < P2; i += TOPK_THREADS) keys[i] = ~0ull;
+    __syncthreads();
+    for (int size = 2; size <= P2; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int i = tid; i < P2; i += TOPK_THREADS) {
+                const int j = i ^ stride;
+                if (j > i) {
+                    const bool up = (i & size) == 0;
+                    const unsigned long long a = keys[i], b = keys[j];
+                    if ((a > b) == up) { keys[i] = b; keys[j] = a; }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int i = tid; i < k; i += TOPK_THREADS) out[i] = (int32_t)(keys[i] & 0xFFFFFFFFull);
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+// ---------------------------------------------------------------------------
+template <int AM, int BM, int EP>
+static hipError_t launch_gemm_t(const GemmArgs &g, hipStream_t s)
+{
+    dim3 grid(g.N / GBN, g.M / GBM);
+    hipLaunchKernelGGL((gemm_kernel<AM, BM, EP>), grid, dim3(256), 0, s, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_gemm(int amode, int bmode, int epi, const GemmArgs &g, hipStream_t s)
+{
+    if (g.M % GBM || g.N % GBN || g.K % GBK) return hipErrorInvalidValue;
+    if (amode == A_ONEHOT && bmode == B_BF16 && epi == EPI_BIAS_GELU) return launch_gemm_t<A_ONEHOT, B_BF16, EPI_BIAS_GELU>(g, s);
+    if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_BIAS_GELU) return launch_gemm_t<A_BF16, B_BF16, EPI_BIAS_GELU>(g, s);
+    if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_STORE) return launch_gemm_t<A_BF16, B_BF16, EPI_STORE>(g, s);
+    if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_GELU_GRAD_T) return launch_gemm_t<A_BF16, B_BF16, EPI_GELU_GRAD_T>(g, s);
+    if (amode == A_BF16 && bmode == B_ONEHOT_T && epi == EPI_STORE) return launch_gemm_t<A_BF16, B_ONEHOT_T, EPI_STORE>(g, s);
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_layer3(const L3Args &a, hipStream_t s)
+{
+    hipLaunchKernelGGL(layer3_kernel, dim3((a.n + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_batch_sums(const SumArgs &a, hipStream_t s)
+{
+    const int n_out = N_H2 + 1 + N_H2 + N_H1 + 1;
+    hipLaunchKernelGGL(batch_sums_kernel, dim3((n_out + 3) / 4), dim3(256), 0, s, a);
+    return hipGetLastError();
+}
+
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, int step, hipStream_t s)
+{
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float bc1 = 1.0f - powf(b1, (float)step), bc2 = 1.0f - powf(b2, (float)step);
+    hipLaunchKernelGGL(adam_kernel, dim3(2048), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, 1e-8f, bc1, bc2);
+    return hipGetLastError();
+}
+
+hipError_t launch_refresh_bf16(const float *W1t, const float *W2t, uint16_t *W1b, uint16_t *W2b, uint16_t *W2kn,
+                               hipStream_t s)
+{
+    hipLaunchKernelGGL(refresh_bf16_kernel, dim3(2048), dim3(256), 0, s, W1t, W2t, W1b, W2b, W2kn);
+    return hipGetLastError();
+}
+
+hipError_t launch_gather_batch(const uint8_t *zone, const int32_t *dist, const int32_t *idx, int n, double mean,
+                               double inv_std, uint8_t *zb, float *tb, hipStream_t s)
+{
+    hipLaunchKernelGGL(gather_batch_kernel, dim3((n + 3) / 4), dim3(256), 0, s, zone, dist, idx, n, mean, inv_std,
+                       zb, tb);
+    return hipGetLastError();
+}
+
+hipError_t launch_moments(const int32_t *d, int64_t n, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(moments_kernel, dim3(1), dim3(1024), 0, s, d, n, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_topk(const float *pred, int n, int k, int32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(topk_kernel<0>, dim3(1), dim3(TOPK_THREADS), 0, s, (const void *)pred, n, k, out);
+    return hipGetLastError();
+}
+
+hipError_t launch_worst(const int32_t *dist, int n, int k, int32_t *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(topk_kernel<1>, dim3(1), dim3(TOPK_THREADS), 0, s, (const void *)dist, n, k, out);
+    return hipGetLastError();
+}
+
+}  // namespace wo

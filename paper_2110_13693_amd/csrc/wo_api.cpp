@@ -3,6 +3,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <cmath>
 #include <atomic>
 #include <cstdarg>
 #include <cstdio>
@@ -13,6 +14,7 @@
 #include <string>
 #include <vector>
 
+#include "wo_common.h"
 #include "wo_internal.h"
 
 using namespace wo;
@@ -23,7 +25,7 @@ using namespace wo;
 
 static thread_local std::string g_err;
 
-static wo_status fail(wo_status s, const char *fmt, ...)
+wo_status wo_fail(wo_status s, const char *fmt, ...)
 {
     char buf[512];
     va_list ap;
@@ -34,12 +36,8 @@ static wo_status fail(wo_status s, const char *fmt, ...)
     return s;
 }
 
-#define HIP_TRY(call)                                                              \
-    do {                                                                           \
-        hipError_t e_ = (call);                                                    \
-        if (e_ != hipSuccess)                                                      \
-            return fail(WO_E_DEVICE, "%s failed: %s", #call, hipGetErrorString(e_)); \
-    } while (0)
+#define fail wo_fail
+#define HIP_TRY WO_HIP
 
 extern "C" const char *wo_status_str(wo_status s)
 {
@@ -63,6 +61,8 @@ static bool env_flag(const char *name, const char *value)
     return v && strcmp(v, value) == 0;
 }
 
+bool wo_fault_injected() { return env_flag("WO_FAULT_INJECT", "alloc"); }
+
 static wo_status dev_alloc(void **p, size_t bytes)
 {
     hipError_t e = hipMalloc(p, bytes ? bytes : 16);
@@ -84,7 +84,9 @@ struct wo_wh {
     std::vector<uint32_t> lds;          // LDS bytes per instance
     uint32_t lds_max = 0;
     int cu_count = 0;
-    void *d_pool = nullptr;             // rec | ooff | lord
+    void *d_pool = nullptr;             // line records | order sizes
+    const uint2 *d_lines = nullptr;
+    const uint8_t *d_cnt = nullptr;
     InstDev *d_inst = nullptr;
     int64_t *d_map = nullptr;           // plan_begin [n+1] | seq_base [n]
     int32_t *d_err = nullptr;
@@ -192,7 +194,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
 
     // allocation fault injection for tests (WO_FAULT_INJECT=alloc); it fires
     // before any HIP call so that it also runs on a host without a GPU
-    if (env_flag("WO_FAULT_INJECT", "alloc")) return fail(WO_E_NOMEM, "injected allocation failure");
+    if (wo_fault_injected()) return fail(WO_E_NOMEM, "injected allocation failure");
     wo_wh *wh = new (std::nothrow) wo_wh;
     if (!wh) return fail(WO_E_NOMEM, "host allocation failed");
     std::unique_ptr<wo_wh, wo_status (*)(wo_wh *)> guard(wh, wo_free_warehouse);
@@ -206,8 +208,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     wh->lds.resize(n_instances);
 
     // pooled host arrays
-    std::vector<uint32_t> rec, ooff;
-    std::vector<uint16_t> lord;
+    std::vector<uint2> lines;
+    std::vector<uint8_t> cnt;
     for (int32_t i = 0; i < n_instances; i++) {
         const wo_instance_desc &d = descs[i];
         InstDev &I = wh->inst[i];
@@ -240,46 +242,69 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
             I.cat_size[c]++;
         }
 
-        I.rec_off = (int64_t)rec.size();
-        I.lord_off = (int64_t)lord.size();
-        I.ooff_off = (int64_t)ooff.size();
+        I.line_off = (int64_t)lines.size();
+        I.cnt_off = (int64_t)cnt.size();
+        int64_t units = 0;
         for (int32_t o = 0; o < d.n_orders; o++) {
             for (int32_t l = d.order_offsets[o]; l < d.order_offsets[o + 1]; l++) {
                 int32_t s = d.order_skus[l];
                 uint32_t c = (uint32_t)d.sku_category[s];
-                rec.push_back(((uint32_t)rank[s] << I.shift) | ((4u * c) << 24));
-                lord.push_back((uint16_t)o);
+                lines.push_back(make_uint2(((uint32_t)rank[s] << I.shift) | ((4u * c) << 24), (uint32_t)o));
             }
+            // an order larger than the capacity is a tour of its own whatever
+            // its size, so sizes are clamped to capacity + 1 for the tour cut
+            int32_t sz = d.order_offsets[o + 1] - d.order_offsets[o];
+            int32_t u = std::min(sz, d.capacity + 1);
+            cnt.push_back((uint8_t)u);
+            units += u;
         }
-        for (int32_t o = 0; o <= d.n_orders; o++) ooff.push_back((uint32_t)d.order_offsets[o]);
+        while (cnt.size() % 16) cnt.push_back(0);
+        I.n_units = (int32_t)units;
 
-        // tours per LDS tile: fill what is left of half the LDS (two blocks per CU)
-        EvalLayout base = eval_layout(d.n_orders, I.words, 0);
-        uint32_t budget = wh->lds_max / 2;
-        int64_t per_tour = 4ll * I.words + 4;
-        int64_t t_cap = budget > base.total + 64 ? (int64_t)(budget - base.total - 64) / per_tour : 0;
-        t_cap = std::min<int64_t>(t_cap, d.n_orders);                    // never more tours than orders
-        t_cap = std::max<int64_t>(t_cap, ((d.n_orders + 31) / 32 + I.words - 1) / I.words);  // room for the check bitmap
+        // Parallel next-fit: about (Q / mean order size) order starts fall in
+        // a Q-item window, each a candidate entry of a segment; take as many
+        // segments as the chase lanes allow, no shorter than 2Q items, and long
+        // enough that a chain rarely needs more than the record slots.
+        const double items = (double)I.n_lines;
+        const double avg_len = items / d.n_orders;
+        const double cand = std::max(1.0, std::min((double)d.capacity, d.capacity / avg_len));
+        const double tour_items = std::max(1.0, d.capacity - 0.5 * (avg_len - 1.0));
+        int g_lanes = 1 + (int)((0.7 * CHASE_LANES - 1.0) / cand);
+        int g_len = (int)(items / (2.0 * d.capacity));
+        int g = std::min(std::min(g_lanes, g_len), MAX_SEG);
+        int g_recs = (int)std::ceil(items / (0.6 * CHASE_RECS * tour_items));
+        bool short_segs = (double)I.n_units / std::max(g, 1) < 65535.0;  // chase records are 16-bit offsets
+        I.n_seg = (g >= 2 && g >= g_recs && short_segs) ? g : 1;
+
+        // tours per LDS tile: the expected tour count with margin (more tours
+        // take another pass over the lines), never more than the orders
+        int64_t t_cap = (int64_t)std::ceil(1.1 * items / tour_items) + 32;
+        t_cap = std::min<int64_t>(t_cap, d.n_orders);
         t_cap = std::max<int64_t>(t_cap, 1);
+        EvalLayout ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap);
+        while (ly.total > wh->lds_max && t_cap > 1) {
+            t_cap = t_cap / 2;
+            ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap);
+        }
         I.t_cap = (int32_t)t_cap;
-        EvalLayout ly = eval_layout(d.n_orders, I.words, I.t_cap);
         if (ly.total > wh->lds_max)
             return fail(WO_E_RANGE, "instance %d: needs %u bytes of LDS, device has %u", i, ly.total, wh->lds_max);
         wh->lds[i] = ly.total;
     }
 
-    size_t b_rec = rec.size() * 4, b_ooff = ooff.size() * 4, b_lord = lord.size() * 2;
-    size_t o_ooff = (b_rec + 255) & ~size_t(255), o_lord = (o_ooff + b_ooff + 255) & ~size_t(255);
-    size_t bytes = o_lord + b_lord;
+    size_t b_lines = lines.size() * sizeof(uint2), b_cnt = cnt.size();
+    size_t o_cnt = (b_lines + 255) & ~size_t(255);
+    size_t bytes = o_cnt + b_cnt;
     wo_status st;
     if ((st = dev_alloc(&wh->d_pool, bytes))) return st;
     if ((st = dev_alloc((void **)&wh->d_inst, sizeof(InstDev) * n_instances))) return st;
     if ((st = dev_alloc((void **)&wh->d_map, sizeof(int64_t) * (2 * n_instances + 1)))) return st;
     if ((st = dev_alloc((void **)&wh->d_err, 64))) return st;
+    wh->d_lines = (const uint2 *)wh->d_pool;
+    wh->d_cnt = (const uint8_t *)wh->d_pool + o_cnt;
     hipStream_t s = (hipStream_t)stream;
-    HIP_TRY(hipMemcpyAsync(wh->d_pool, rec.data(), b_rec, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_ooff, ooff.data(), b_ooff, hipMemcpyHostToDevice, s));
-    HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_lord, lord.data(), b_lord, hipMemcpyHostToDevice, s));
+    if (b_lines) HIP_TRY(hipMemcpyAsync(wh->d_pool, lines.data(), b_lines, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_cnt, cnt.data(), b_cnt, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(wh->d_inst, wh->inst.data(), sizeof(InstDev) * n_instances, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(wh->d_err, 0, 64, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -287,21 +312,6 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     guard.release();
     *out = wh;
     return WO_OK;
-}
-
-// Pooled array bases (rec at 0, then ooff, then lord, each 256-byte aligned).
-static void pool_bases(const wo_wh *wh, const uint32_t **rec, const uint32_t **ooff, const uint16_t **lord)
-{
-    size_t n_rec = 0, n_ooff = 0;
-    for (const InstDev &I : wh->inst) {
-        n_rec += (size_t)I.n_lines;
-        n_ooff += (size_t)I.n_orders + 1;
-    }
-    size_t o_ooff = (n_rec * 4 + 255) & ~size_t(255);
-    size_t o_lord = (o_ooff + n_ooff * 4 + 255) & ~size_t(255);
-    *rec = (const uint32_t *)wh->d_pool;
-    *ooff = (const uint32_t *)((const char *)wh->d_pool + o_ooff);
-    *lord = (const uint16_t *)((const char *)wh->d_pool + o_lord);
 }
 
 extern "C" wo_status wo_free_warehouse(wo_wh *wh)
@@ -369,7 +379,8 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.n_plans = n_plans;
     a.plan_begin = wh->d_map;
     a.seq_base = wh->d_map + wh->n_inst + 1;
-    pool_bases(wh, &a.rec, &a.ooff, &a.lord);
+    a.lines = wh->d_lines;
+    a.cnt = wh->d_cnt;
     a.zone_of = d_zone_of;
     a.seq = d_order_seq;
     a.dist = d_dist;
@@ -387,3 +398,36 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     }
     return WO_OK;
 }
+
+// Evaluate n_plans plans of one instance of the handle (rows packed with that
+// instance's order count), for callers inside the library.  No argument
+// checks beyond the handle's: the caller owns the buffers.
+wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint8_t *d_zone_of,
+                            const uint16_t *d_order_seq, int32_t *d_dist, float *d_thr, hipStream_t s)
+{
+    if (n_plans <= 0) return WO_OK;
+    EvalArgs a;
+    a.inst = wh->d_inst + inst;
+    a.n_inst = 1;
+    a.n_plans = n_plans;
+    const int64_t *zero_map = (const int64_t *)((const char *)wh->d_err + 16);   // zeroed at load
+    a.plan_begin = zero_map;
+    a.seq_base = zero_map;
+    a.lines = wh->d_lines;
+    a.cnt = wh->d_cnt;
+    a.zone_of = d_zone_of;
+    a.seq = d_order_seq;
+    a.dist = d_dist;
+    a.thr = d_thr;
+    a.err = wh->d_err;
+    a.validate = 0;
+    const uint32_t lds = wh->lds[inst];
+    int per_cu = std::max(1, (int)((160u * 1024u) / std::max(1u, lds)));
+    int64_t grid = std::min<int64_t>(n_plans, (int64_t)wh->cu_count * per_cu);
+    HIP_TRY(launch_eval(a, lds, (int)grid, s));
+    return WO_OK;
+}
+
+int32_t wo::instance_orders(const wo_wh *wh, int32_t inst) { return wh->inst[inst].n_orders; }
+int32_t wo::instance_categories(const wo_wh *wh, int32_t inst) { return wh->inst[inst].n_cat; }
+int32_t wo::instance_count(const wo_wh *wh) { return wh->n_inst; }

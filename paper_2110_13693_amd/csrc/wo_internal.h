@@ -19,6 +19,7 @@ struct InstDev {
     int32_t n_cat;
     int32_t n_orders;
     int32_t n_lines;        // = items (one line = one item)
+    int32_t n_units;        // sum over orders of min(size, capacity + 1): the bitmap's span
     uint32_t magic;         // aisle = mulhi_u24(ls, magic)
     uint32_t shift;         // ls = l << shift
     uint32_t d_s;           // (2 * slots_per_side) << shift
@@ -26,10 +27,10 @@ struct InstDev {
     int32_t spacing;
     int32_t L;              // slots_per_side * pitch
     int32_t t_cap;          // tours per LDS tile
+    int32_t n_seg;          // item-space segments chased in parallel (1 = serial chain)
     int32_t pad0;
-    int64_t rec_off;        // u32 line records [n_lines]:  (rank << shift) | (4*cat) << 24
-    int64_t ooff_off;       // u32 order line offsets [n_orders + 1]
-    int64_t lord_off;       // u16 order id of each line [n_lines]
+    int64_t line_off;       // uint2 line records [n_lines]: x = (rank << shift) | (4*cat) << 24, y = order id
+    int64_t cnt_off;        // u8 per order: min(size, capacity + 1) [n_orders], padded to 16 bytes
     double walk;
     double t_item;
     double window;
@@ -42,9 +43,8 @@ struct EvalArgs {
     int64_t n_plans;
     const int64_t *plan_begin;  // device [n_inst + 1]: plan rows of instance i (unused if n_inst == 1)
     const int64_t *seq_base;    // device [n_inst]: element offset of instance i's first sequence row
-    const uint32_t *rec;    // pooled arrays
-    const uint32_t *ooff;
-    const uint16_t *lord;
+    const uint2 *lines;     // pooled arrays
+    const uint8_t *cnt;
     const uint8_t *zone_of;
     const uint16_t *seq;
     int32_t *dist;
@@ -53,32 +53,62 @@ struct EvalArgs {
     int32_t validate;
 };
 
+// Parallel next-fit: lanes that chase candidate tour chains, records per chain.
+constexpr int CHASE_LANES = 256;
+constexpr int CHASE_RECS = 32;
+constexpr int MAX_SEG = 64;
+constexpr int SEQ_CHUNK = 16;   // sequence positions per thread kept in registers
+
 // LDS layout of one evaluation block for an instance; host and device use the
-// same function so that the launch size and the kernel agree.
+// same function so that the launch size and the kernel agree.  The chase
+// records and the per-tour aisle sets are used in different phases and share
+// one region.
 struct EvalLayout {
-    uint32_t zs, red, ctr, P, sq, e, tour, flag, mask, mx, total;
+    uint32_t zs, red, misc, seg, cnt, F, tour, B, prefB, region;
+    uint32_t rec, nrec, nxt;       // chase phase (inside region)
+    uint32_t mask, mx;             // tour phase (inside region)
+    uint32_t total;
 };
 
 __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15u; }
 
-__host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t words, int32_t t_cap)
+__host__ __device__ inline uint32_t bitmap_words(int32_t n_units) { return ((uint32_t)n_units >> 5) + 3u; }
+
+__host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_units, int32_t words,
+                                                  int32_t t_cap)
 {
     EvalLayout L;
-    uint32_t n = (uint32_t)n_orders, b = 0;
-    L.zs = b;   b = align16(b + 64 * 4);
-    L.red = b;  b = align16(b + 16 * 8);
-    L.ctr = b;  b = align16(b + 16 * 4);
-    L.P = b;    b = align16(b + 4 * (n + 1));
-    L.sq = b;   b = align16(b + 2 * n);
-    L.e = b;    b = align16(b + 2 * n);
-    L.tour = b; b = align16(b + 2 * n);
-    L.flag = b; b = align16(b + n);
-    L.mask = b; b = align16(b + 4u * (uint32_t)words * (uint32_t)t_cap);
-    L.mx = b;   b = align16(b + 4u * (uint32_t)t_cap);
-    L.total = b;
+    uint32_t n = (uint32_t)n_orders, nb = bitmap_words(n_units), b = 0;
+    L.zs = b;    b = align16(b + 64 * 4);
+    L.red = b;   b = align16(b + 16 * 8);
+    L.misc = b;  b = align16(b + 16 * 4);
+    L.seg = b;   b = align16(b + 4 * 4 * (MAX_SEG + 1));   // lane_base | wbits | true_lane | seg start
+    L.cnt = b;   b = align16(b + n);
+    L.F = b;     b = align16(b + 4 * ((n + 31) / 32 + 1));
+    L.tour = b;  b = align16(b + 2 * n);
+    L.B = b;     b = align16(b + 4 * nb);
+    L.prefB = b; b = align16(b + 4 * nb);
+    L.region = b;
+    uint32_t c = b;
+    L.rec = c;   c = align16(c + 2u * CHASE_LANES * CHASE_RECS);
+    L.nrec = c;  c = align16(c + 4u * CHASE_LANES);
+    L.nxt = c;   c = align16(c + 4u * CHASE_LANES);
+    uint32_t t = b;
+    L.mask = t;  t = align16(t + 4u * (uint32_t)words * (uint32_t)t_cap);
+    L.mx = t;    t = align16(t + 4u * (uint32_t)t_cap);
+    uint32_t v = b + 4u * (uint32_t)((n + 31) / 32);   // permutation check bitmap
+    L.total = c > t ? c : t;
+    if (v > L.total) L.total = align16(v);
     return L;
 }
 
 hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s);
+
+// library-internal helpers over a loaded handle
+wo_status eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint8_t *d_zone_of,
+                        const uint16_t *d_order_seq, int32_t *d_dist, float *d_thr, hipStream_t s);
+int32_t instance_orders(const wo_wh *wh, int32_t inst);
+int32_t instance_categories(const wo_wh *wh, int32_t inst);
+int32_t instance_count(const wo_wh *wh);
 
 }  // namespace wo

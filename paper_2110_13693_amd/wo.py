@@ -23,16 +23,28 @@ WO_MAX_LOCATIONS = 1 << 22
 WO_MAX_LINES = 1 << 24
 
 # every symbol include/wo.h declares
-EXPORTS = [
+EXPORTS = sorted([
     "wo_status_str", "wo_last_error", "wo_load_warehouse", "wo_free_warehouse",
     "wo_instance_info", "wo_eval_plans",
-]
+    "wo_sur_create", "wo_sur_free", "wo_sur_set_scale", "wo_sur_get_scale", "wo_sur_get_params",
+    "wo_sur_gradients", "wo_sur_train", "wo_sur_predict", "wo_sur_save", "wo_sur_load",
+    "wo_screen_plans",
+    "wo_search_create", "wo_search_free", "wo_search_step", "wo_search_best", "wo_search_population",
+])
+WO_SUR_PARAMS = 4457985
+WO_SCREEN_MAX_KEEP = 4096
 
 
 class WoError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("%s: %s" % (_status_name(status), message))
         self.status = status
+
+
+class wo_search_params(ctypes.Structure):
+    _fields_ = [("population", ctypes.c_int32), ("tournament", ctypes.c_int32),
+                ("mutation_threshold", ctypes.c_uint32), ("candidates", ctypes.c_int32),
+                ("keep", ctypes.c_int32), ("seed", ctypes.c_uint64)]
 
 
 class wo_instance_desc(ctypes.Structure):
@@ -67,6 +79,23 @@ def lib():
         L.wo_free_warehouse.argtypes = [V]
         L.wo_instance_info.argtypes = [V, I32, P(I32), P(I32), P(I32)]
         L.wo_eval_plans.argtypes = [V, V, I64, V, V, V, V, V]
+        F32, F64, U64 = ctypes.c_float, ctypes.c_double, ctypes.c_uint64
+        L.wo_sur_create.argtypes = [I32, V, U64, V, P(V)]
+        L.wo_sur_free.argtypes = [V]
+        L.wo_sur_set_scale.argtypes = [V, F64, F64]
+        L.wo_sur_get_scale.argtypes = [V, P(F64), P(F64)]
+        L.wo_sur_get_params.argtypes = [V, V]
+        L.wo_sur_gradients.argtypes = [V, I32, V, V, V, P(F32), V]
+        L.wo_sur_train.argtypes = [V, I64, V, V, I32, I32, F32, U64, P(F32), V]
+        L.wo_sur_predict.argtypes = [V, I64, V, V, V]
+        L.wo_sur_save.argtypes = [V, ctypes.c_char_p]
+        L.wo_sur_load.argtypes = [ctypes.c_char_p, V, P(V)]
+        L.wo_screen_plans.argtypes = [V, I32, V, I64, V, V, I64, V, V]
+        L.wo_search_create.argtypes = [V, I32, P(wo_search_params), V, V, V, P(V)]
+        L.wo_search_free.argtypes = [V]
+        L.wo_search_step.argtypes = [V, V, V, I32, V]
+        L.wo_search_best.argtypes = [V, V, V, P(I32), P(I32), V]
+        L.wo_search_population.argtypes = [V, V, V, V, V, V]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype if name in (
                 "wo_status_str", "wo_last_error") else ctypes.c_int
@@ -188,3 +217,187 @@ def wo_eval_plans(wh: Warehouse, zone_of, order_seq, dist, orders_per_window=Non
         _ptr(orders_per_window, 4, "orders_per_window"),
         ctypes.c_void_p(_stream_handle(stream))))
     return dist, orders_per_window
+
+
+# ---------------------------------------------------------------------------
+# surrogate and screening
+# ---------------------------------------------------------------------------
+
+class Surrogate:
+    """Owns a ``wo_sur*`` handle."""
+
+    def __init__(self, handle: int):
+        self.handle = ctypes.c_void_p(handle)
+
+    def free(self):
+        if self.handle:
+            _check(lib().wo_sur_free(self.handle))
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def wo_sur_create(n_categories: int, init: Optional[np.ndarray] = None, seed: int = 0,
+                  stream=None) -> Surrogate:
+    """New surrogate; ``init`` float32[WO_SUR_PARAMS] in the host layout or None."""
+    buf = None
+    if init is not None:
+        buf = np.ascontiguousarray(init, dtype=np.float32).reshape(-1)
+        if buf.size != WO_SUR_PARAMS:
+            raise ValueError("init must hold %d values" % WO_SUR_PARAMS)
+    out = ctypes.c_void_p(0)
+    _check(lib().wo_sur_create(int(n_categories), None if buf is None else buf.ctypes.data,
+                               int(seed) & ((1 << 64) - 1),
+                               ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(out)))
+    return Surrogate(out.value)
+
+
+def wo_sur_free(s: Surrogate):
+    s.free()
+
+
+def wo_sur_set_scale(s: Surrogate, mean: float, std: float):
+    _check(lib().wo_sur_set_scale(s.handle, float(mean), float(std)))
+
+
+def wo_sur_get_scale(s: Surrogate):
+    m, d = ctypes.c_double(0), ctypes.c_double(0)
+    _check(lib().wo_sur_get_scale(s.handle, ctypes.byref(m), ctypes.byref(d)))
+    return m.value, d.value
+
+
+def wo_sur_get_params(s: Surrogate) -> np.ndarray:
+    out = np.empty(WO_SUR_PARAMS, dtype=np.float32)
+    _check(lib().wo_sur_get_params(s.handle, out.ctypes.data))
+    return out
+
+
+def wo_sur_gradients(s: Surrogate, zone_of, target, stream=None):
+    """``(grad float32[WO_SUR_PARAMS] host layout, loss)`` of one batch."""
+    n = int(zone_of.shape[0])
+    grad = np.empty(WO_SUR_PARAMS, dtype=np.float32)
+    loss = ctypes.c_float(0)
+    _check(lib().wo_sur_gradients(s.handle, n, _ptr(zone_of, 1, "zone_of"), _ptr(target, 4, "target"),
+                                  grad.ctypes.data, ctypes.byref(loss),
+                                  ctypes.c_void_p(_stream_handle(stream))))
+    return grad, loss.value
+
+
+def wo_sur_train(s: Surrogate, zone_of, dist, epochs: int = 1, batch: int = 1024, lr: float = 1e-3,
+                 seed: int = 0, stream=None) -> float:
+    """Train on (plan, exact distance) pairs; returns the last epoch's mean batch loss."""
+    n = int(zone_of.shape[0])
+    if dist.numel() != n:
+        raise ValueError("one distance per plan")
+    loss = ctypes.c_float(0)
+    _check(lib().wo_sur_train(s.handle, n, _ptr(zone_of, 1, "zone_of"), _ptr(dist, 4, "dist"),
+                              int(epochs), int(batch), float(lr), int(seed) & ((1 << 64) - 1),
+                              ctypes.byref(loss), ctypes.c_void_p(_stream_handle(stream))))
+    return loss.value
+
+
+def wo_sur_predict(s: Surrogate, zone_of, pred, stream=None):
+    n = int(zone_of.shape[0])
+    if pred.numel() != n:
+        raise ValueError("one prediction per plan")
+    _check(lib().wo_sur_predict(s.handle, n, _ptr(zone_of, 1, "zone_of"), _ptr(pred, 4, "pred"),
+                                ctypes.c_void_p(_stream_handle(stream))))
+    return pred
+
+
+def wo_sur_save(s: Surrogate, path: str):
+    _check(lib().wo_sur_save(s.handle, os.fsencode(path)))
+
+
+def wo_sur_load(path: str, stream=None) -> Surrogate:
+    out = ctypes.c_void_p(0)
+    _check(lib().wo_sur_load(os.fsencode(path), ctypes.c_void_p(_stream_handle(stream)),
+                             ctypes.byref(out)))
+    return Surrogate(out.value)
+
+
+def wo_screen_plans(wh: Warehouse, inst: int, s: Surrogate, zone_of, keep: int, keep_idx,
+                    pred=None, stream=None):
+    """Indices of the ``keep`` best predicted plans, ordered by (prediction, index)."""
+    n = int(zone_of.shape[0])
+    if keep_idx.numel() != keep:
+        raise ValueError("keep_idx must hold `keep` entries")
+    if pred is not None and pred.numel() != n:
+        raise ValueError("pred must hold one value per plan")
+    _check(lib().wo_screen_plans(wh.handle, int(inst), s.handle, n, _ptr(zone_of, 1, "zone_of"),
+                                 _ptr(pred, 4, "pred"), int(keep), _ptr(keep_idx, 4, "keep_idx"),
+                                 ctypes.c_void_p(_stream_handle(stream))))
+    return keep_idx
+
+
+# ---------------------------------------------------------------------------
+# genetic search
+# ---------------------------------------------------------------------------
+
+MUTATION_2PCT = 85899345   # floor(0.02 * 2^32)
+
+
+class Search:
+    """Owns a ``wo_search*`` handle."""
+
+    def __init__(self, handle: int, n_orders: int, population: int, keep: int):
+        self.handle = ctypes.c_void_p(handle)
+        self.n_orders = n_orders
+        self.population = population
+        self.keep = keep
+
+    def free(self):
+        if self.handle:
+            _check(lib().wo_search_free(self.handle))
+            self.handle = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def wo_search_create(wh: Warehouse, inst: int, init_zone_of, init_seq, population: int,
+                     tournament: int = 4, mutation_threshold: int = MUTATION_2PCT, candidates: int = 0,
+                     keep: int = 0, seed: int = 0, stream=None) -> Search:
+    prm = wo_search_params(int(population), int(tournament), int(mutation_threshold), int(candidates),
+                           int(keep), int(seed) & ((1 << 64) - 1))
+    n = wh.n_orders[inst]
+    if init_zone_of.shape[0] != population or init_seq.numel() != population * n:
+        raise ValueError("initial population has the wrong shape")
+    out = ctypes.c_void_p(0)
+    _check(lib().wo_search_create(wh.handle, int(inst), ctypes.byref(prm), _ptr(init_zone_of, 1, "zone_of"),
+                                  _ptr(init_seq, 2, "seq"), ctypes.c_void_p(_stream_handle(stream)),
+                                  ctypes.byref(out)))
+    return Search(out.value, n, population, keep)
+
+
+def wo_search_free(s: Search):
+    s.free()
+
+
+def wo_search_step(wh: Warehouse, s: Search, sur: Optional[Surrogate], n_generations: int = 1, stream=None):
+    _check(lib().wo_search_step(wh.handle, s.handle, None if sur is None else sur.handle,
+                                int(n_generations), ctypes.c_void_p(_stream_handle(stream))))
+
+
+def wo_search_best(s: Search, stream=None):
+    """``(zone_of uint8[64], seq uint16[n], dist, generation)`` of the best individual."""
+    z = np.empty(64, dtype=np.uint8)
+    q = np.empty(s.n_orders, dtype=np.uint16)
+    d = ctypes.c_int32(0)
+    g = ctypes.c_int32(0)
+    _check(lib().wo_search_best(s.handle, z.ctypes.data, q.ctypes.data, ctypes.byref(d), ctypes.byref(g),
+                                ctypes.c_void_p(_stream_handle(stream))))
+    return z, q, d.value, g.value
+
+
+def wo_search_population(s: Search, zone_of=None, seq=None, dist=None, last_kept=None, stream=None):
+    _check(lib().wo_search_population(s.handle, _ptr(zone_of, 1, "zone_of"), _ptr(seq, 2, "seq"),
+                                      _ptr(dist, 4, "dist"), _ptr(last_kept, 4, "last_kept"),
+                                      ctypes.c_void_p(_stream_handle(stream))))
