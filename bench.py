@@ -209,6 +209,8 @@ def main(argv=None):
     ap.add_argument("--generations", type=int, default=200)
     ap.add_argument("--train-samples", type=int, default=1 << 20)
     ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
+                    help="only copy a MIB-sized device buffer 10 times (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
         print("bench.py measures one GPU only; --gpus %d is not supported (the evaluator "
@@ -217,6 +219,15 @@ def main(argv=None):
 
     if args.search:
         return search_comparison(args)
+    if args.copy_probe:
+        import torch
+        a = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
+        b = torch.empty_like(a)
+        for _ in range(10):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes": a.numel(), "copies": 10}))
+        return 0
 
     import torch
 

@@ -145,6 +145,39 @@ wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans,
                         int32_t *d_dist, float *d_orders_per_window, void *stream);
 
 
+/* Launch configuration of the evaluation kernel for a handle: threads per
+ * workgroup (128, 256 or 512), workgroups per CU (0 = as many as LDS and
+ * the 32 waves of a CU allow), and the work distribution (0 = grid stride
+ * over plan rows, 1 = a ticket queue over a work list that puts the plans of
+ * the most expensive instances first -- useful for uneven batches), and the
+ * mapping of the aisle-set pass (line_pass).  `ms` is
+ * the measured time of one call when returned by the autotuner. */
+typedef struct {
+    int32_t block_threads;
+    int32_t blocks_per_cu;
+    int32_t queue;
+    int32_t line_pass;   /* 1: one order per lane (default), 0: one order line per lane */
+    float ms;
+} wo_eval_config;
+
+wo_status wo_set_eval_config(wo_wh *wh, const wo_eval_config *cfg);
+wo_status wo_get_eval_config(const wo_wh *wh, wo_eval_config *cfg);
+
+/* Autotuner: times wo_eval_plans on the given plans for every supported
+ * configuration (best of `reps` runs each, after a warm-up), keeps the
+ * fastest in the handle and returns it in best_out.  h_all (nullable)
+ * receives up to *n_all timed configurations; *n_all is set to how many
+ * were timed.  Synchronous; overwrites d_dist. */
+wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans, const uint8_t *d_zone_of,
+                           const uint16_t *d_order_seq, int32_t *d_dist, int32_t reps, void *stream,
+                           wo_eval_config *best_out, wo_eval_config *h_all, int32_t *n_all);
+
+/* Graph capture: after one call with the same plan_offsets and n_plans (which
+ * uploads the plan map and, with the queue, the work list), wo_eval_plans
+ * enqueues kernels only (a ticket reset kernel and the evaluation kernel)
+ * and may be captured into a HIP graph and replayed; WO_VALIDATE must be
+ * unset while capturing. */
+
 /* ------------------------------------------------------------------ */
 /* Learned surrogate and screening                                      */
 /* ------------------------------------------------------------------ */

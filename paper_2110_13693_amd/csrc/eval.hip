@@ -130,11 +130,22 @@ template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
+    __shared__ uint32_t s_next;
+    constexpr int SEQ_CHUNK = 4096 / BLOCK;  // sequence positions per thread kept in registers
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     int loaded = -1;                        // instance whose count table sits in LDS
 
-    for (int64_t p = blockIdx.x; p < A.n_plans; p += gridDim.x) {
+    // work items: a grid stride, or a queue (atomic ticket) over a work order
+    // that puts the most expensive plans first
+    int64_t item = blockIdx.x;
+    if (A.queue) {
+        if (tid == 0) s_next = atomicAdd(A.queue_ctr, 1u);
+        __syncthreads();
+        item = s_next;
+    }
+    while (item < A.n_plans) {
+        const int64_t p = A.work ? (int64_t)A.work[item] : item;
         int ii = 0;
         if (A.n_inst > 1) {
             int lo = 0, hi = A.n_inst - 1;   // last instance whose first row <= p
@@ -440,25 +451,64 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
             for (int k = tid; k < W * T; k += BLOCK) mask[k] = 0;
             for (int k = tid; k < T; k += BLOCK) mx[k] = 0;
             __syncthreads();
-            for (int q0 = tid; q0 < n_lines; q0 += 4 * BLOCK) {
-                uint2 v[4];
+            if (A.main_mode == 0) {
+                for (int q0 = tid; q0 < n_lines; q0 += 4 * BLOCK) {
+                    uint2 v[4];
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    const int q = q0 + u * BLOCK;
-                    v[u] = (q < n_lines) ? lines[q] : make_uint2(0u, 0xFFFFFFFFu);
-                }
+                    for (int u = 0; u < 4; u++) {
+                        const int q = q0 + u * BLOCK;
+                        v[u] = (q < n_lines) ? lines[q] : make_uint2(0u, 0xFFFFFFFFu);
+                    }
 #pragma unroll
-                for (int u = 0; u < 4; u++) {
-                    if (v[u].y != 0xFFFFFFFFu) {
-                        const uint32_t t = (uint32_t)tour[v[u].y] - (uint32_t)t0;
-                        if (t < (uint32_t)T) {
-                            const uint32_t r = v[u].x;
-                            const uint32_t ls = r + zs[r >> 26];
-                            const uint32_t a = mulhi24(ls, magic);
-                            atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
-                            atomicMax(&mx[t], ls);
+                    for (int u = 0; u < 4; u++) {
+                        if (v[u].y != 0xFFFFFFFFu) {
+                            const uint32_t t = (uint32_t)tour[v[u].y] - (uint32_t)t0;
+                            if (t < (uint32_t)T) {
+                                const uint32_t r = v[u].x;
+                                const uint32_t ls = r + zs[r >> 26];
+                                const uint32_t a = mulhi24(ls, magic);
+                                atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
+                                atomicMax(&mx[t], ls);
+                            }
                         }
                     }
+                }
+            } else {
+                // one order per lane: its tour looked up once, its farthest
+                // location kept in a register, the zone start of each line
+                // taken from the wave's copy of the table by lane permute
+                const int zsv = (int)zs[lane];
+                const uint32_t *grec = A.grec + I.grec_off;
+                const uint32_t *gbase = A.gbase + I.gbase_off;
+                const uint16_t *gord = A.gord + I.gord_off;
+                for (int g = tid >> 6; g < I.n_grp; g += BLOCK / 64) {
+                    const uint32_t o = gord[g * 64 + lane];
+                    const uint32_t t = (o != 0xFFFFu) ? (uint32_t)tour[o] - (uint32_t)t0 : 0xFFFFFFFFu;
+                    const bool active = t < (uint32_t)T;
+                    const uint32_t b0g = gbase[g], L = (gbase[g + 1] - b0g) >> 6;
+                    const uint32_t *gr = grec + b0g + lane;
+                    uint32_t far = 0;
+                    uint32_t kk = 0;
+                    for (; kk + 4 <= L; kk += 4) {
+                        uint32_t r[4];
+#pragma unroll
+                        for (int u = 0; u < 4; u++) r[u] = gr[(kk + u) * 64];
+#pragma unroll
+                        for (int u = 0; u < 4; u++) {
+                            const uint32_t ls = r[u] + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(r[u] >> 24), zsv);
+                            const uint32_t a = mulhi24(ls, magic);
+                            if (active) atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
+                            far = max(far, ls);
+                        }
+                    }
+                    for (; kk < L; kk++) {
+                        const uint32_t r = gr[kk * 64];
+                        const uint32_t ls = r + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(r >> 24), zsv);
+                        const uint32_t a = mulhi24(ls, magic);
+                        if (active) atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
+                        far = max(far, ls);
+                    }
+                    if (active) atomicMax(&mx[t], far);
                 }
             }
             __syncthreads();
@@ -483,21 +533,47 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
             if (A.thr) A.thr[p] = window_throughput(D, I);
         }
         __syncthreads();
+        if (A.queue) {
+            if (tid == 0) s_next = atomicAdd(A.queue_ctr, 1u);
+            __syncthreads();
+            item = s_next;
+        } else {
+            item += gridDim.x;
+        }
     }
 }
 
-hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
+// Reset of the work-queue ticket (a kernel, so that it can sit in a graph).
+__global__ void reset_ticket_kernel(uint32_t *ctr) { *ctr = 0u; }
+
+template <int BLOCK>
+static hipError_t launch_eval_t(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
 {
-    constexpr int BLOCK = 256;
-    static bool attr_set = false;
-    if (!attr_set) {
+    // raise the dynamic LDS limit to what this launch needs (the kernel also
+    // holds a few bytes of static LDS, so the whole 160 KB cannot be asked for)
+    static uint32_t attr_bytes = 0;
+    if (lds_bytes > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)eval_plans_kernel<BLOCK>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        attr_bytes = lds_bytes;
     }
+    if (a.queue) hipLaunchKernelGGL(reset_ticket_kernel, dim3(1), dim3(1), 0, s, a.queue_ctr);
     hipLaunchKernelGGL(eval_plans_kernel<BLOCK>, dim3(grid), dim3(BLOCK), lds_bytes, s, a);
     return hipGetLastError();
+}
+
+hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, hipStream_t s)
+{
+    switch (block) {
+    case 128: return launch_eval_t<128>(a, lds_bytes, grid, s);
+    case 256: return launch_eval_t<256>(a, lds_bytes, grid, s);
+    case 512: return launch_eval_t<512>(a, lds_bytes, grid, s);
+    }
+    return hipErrorInvalidValue;
 }
 
 }  // namespace wo

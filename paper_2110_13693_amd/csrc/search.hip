@@ -227,12 +227,16 @@ uint32_t breed_lds_bytes(int n) { return (uint32_t)(((2 * n + 15) & ~15) + 4 * (
 
 hipError_t launch_breed(const BreedArgs &a, int n_children, hipStream_t s)
 {
-    static bool attr_set = false;
-    if (!attr_set) {
+    static uint32_t attr_bytes = 0;
+    const uint32_t need = breed_lds_bytes(a.n);
+    if (need > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)breed_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
+                                           (int)need);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        attr_bytes = need;
     }
     hipLaunchKernelGGL(breed_kernel, dim3(n_children), dim3(256), breed_lds_bytes(a.n), s, a);
     return hipGetLastError();

@@ -79,7 +79,7 @@ extern "C" wo_status wo_search_create(wo_wh *wh, int32_t inst, const wo_search_p
         (prm->keep < 1 || prm->keep > prm->candidates || prm->keep > WO_SCREEN_MAX_KEEP ||
          prm->keep >= prm->population))
         return wo_fail(WO_E_RANGE, "keep must be in [1, min(candidates, %d, population - 1)]", WO_SCREEN_MAX_KEEP);
-    if (breed_lds_bytes(n) > 160u * 1024u) return wo_fail(WO_E_RANGE, "%d orders exceed the breeding LDS", n);
+    if (breed_lds_bytes(n) > 160u * 1024u - 256u) return wo_fail(WO_E_RANGE, "%d orders exceed the breeding LDS", n);
     if (wo_fault_injected()) return wo_fail(WO_E_NOMEM, "injected allocation failure");
     wo_search *s = new (std::nothrow) wo_search;
     if (!s) return wo_fail(WO_E_NOMEM, "host allocation failed");

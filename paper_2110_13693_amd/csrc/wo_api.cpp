@@ -87,10 +87,21 @@ struct wo_wh {
     void *d_pool = nullptr;             // line records | order sizes
     const uint2 *d_lines = nullptr;
     const uint8_t *d_cnt = nullptr;
+    const uint32_t *d_grec = nullptr;
+    const uint32_t *d_gbase = nullptr;
+    const uint16_t *d_gord = nullptr;
     InstDev *d_inst = nullptr;
     int64_t *d_map = nullptr;           // plan_begin [n+1] | seq_base [n]
     int32_t *d_err = nullptr;
     std::vector<int64_t> map_cached;    // what d_map holds
+    // launch configuration (wo_autotune_eval / wo_set_eval_config)
+    int block = 256;
+    int per_cu = 0;                     // 0: as many as LDS allows
+    int queue = 0;                      // 1: ticket queue over the cost-ordered work list
+    int main_mode = 1;                  // 1: one order per lane in the line pass, 0: one line per lane
+    int32_t *d_work = nullptr;          // work list for the current plan map
+    int64_t work_cap = 0;
+    std::vector<int64_t> work_map;      // plan map the work list was built for
     std::atomic<int> busy{0};
 };
 
@@ -202,7 +213,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     int lds_max = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, wh->device));
     HIP_TRY(hipDeviceGetAttribute(&wh->cu_count, hipDeviceAttributeMultiprocessorCount, wh->device));
-    wh->lds_max = (uint32_t)std::min(lds_max, 160 * 1024);
+    wh->lds_max = (uint32_t)std::min(lds_max, 160 * 1024) - 256;   // room for the kernels' static LDS
     wh->n_inst = n_instances;
     wh->inst.resize(n_instances);
     wh->lds.resize(n_instances);
@@ -210,6 +221,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     // pooled host arrays
     std::vector<uint2> lines;
     std::vector<uint8_t> cnt;
+    std::vector<uint32_t> grec, gbase;
+    std::vector<uint16_t> gord;
     for (int32_t i = 0; i < n_instances; i++) {
         const wo_instance_desc &d = descs[i];
         InstDev &I = wh->inst[i];
@@ -261,6 +274,42 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         while (cnt.size() % 16) cnt.push_back(0);
         I.n_units = (int32_t)units;
 
+        // groups of 64 orders by descending size, lines stored line-major
+        {
+            std::vector<int32_t> ord(d.n_orders);
+            for (int32_t o = 0; o < d.n_orders; o++) ord[o] = o;
+            auto len = [&](int32_t o) { return d.order_offsets[o + 1] - d.order_offsets[o]; };
+            std::stable_sort(ord.begin(), ord.end(), [&](int32_t x, int32_t y) { return len(x) > len(y); });
+            I.n_grp = (d.n_orders + 63) / 64;
+            I.grec_off = (int64_t)grec.size();
+            I.gbase_off = (int64_t)gbase.size();
+            I.gord_off = (int64_t)gord.size();
+            uint32_t off = 0;
+            for (int32_t g = 0; g < I.n_grp; g++) {
+                gbase.push_back(off);
+                const int32_t L = len(ord[64 * g]);
+                for (int32_t k = 0; k < L; k++) {
+                    for (int32_t j = 0; j < 64; j++) {
+                        const int32_t q = 64 * g + j;
+                        uint32_t r = 0;
+                        if (q < d.n_orders) {
+                            const int32_t o = ord[q];
+                            const int32_t l = d.order_offsets[o] + (k < len(o) ? k : 0);
+                            const int32_t sk = d.order_skus[l];
+                            r = ((uint32_t)rank[sk] << I.shift) | ((4u * (uint32_t)d.sku_category[sk]) << 24);
+                        }
+                        grec.push_back(r);
+                    }
+                }
+                off += (uint32_t)(64 * L);
+                for (int32_t j = 0; j < 64; j++) {
+                    const int32_t q = 64 * g + j;
+                    gord.push_back(q < d.n_orders ? (uint16_t)ord[q] : (uint16_t)0xFFFF);
+                }
+            }
+            gbase.push_back(off);
+        }
+
         // Parallel next-fit: about (Q / mean order size) order starts fall in
         // a Q-item window, each a candidate entry of a segment; take as many
         // segments as the chase lanes allow, no shorter than 2Q items, and long
@@ -294,7 +343,10 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
 
     size_t b_lines = lines.size() * sizeof(uint2), b_cnt = cnt.size();
     size_t o_cnt = (b_lines + 255) & ~size_t(255);
-    size_t bytes = o_cnt + b_cnt;
+    size_t o_grec = (o_cnt + b_cnt + 255) & ~size_t(255);
+    size_t o_gbase = (o_grec + grec.size() * 4 + 255) & ~size_t(255);
+    size_t o_gord = (o_gbase + gbase.size() * 4 + 255) & ~size_t(255);
+    size_t bytes = o_gord + gord.size() * 2;
     wo_status st;
     if ((st = dev_alloc(&wh->d_pool, bytes))) return st;
     if ((st = dev_alloc((void **)&wh->d_inst, sizeof(InstDev) * n_instances))) return st;
@@ -302,9 +354,15 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     if ((st = dev_alloc((void **)&wh->d_err, 64))) return st;
     wh->d_lines = (const uint2 *)wh->d_pool;
     wh->d_cnt = (const uint8_t *)wh->d_pool + o_cnt;
+    wh->d_grec = (const uint32_t *)((const char *)wh->d_pool + o_grec);
+    wh->d_gbase = (const uint32_t *)((const char *)wh->d_pool + o_gbase);
+    wh->d_gord = (const uint16_t *)((const char *)wh->d_pool + o_gord);
     hipStream_t s = (hipStream_t)stream;
     if (b_lines) HIP_TRY(hipMemcpyAsync(wh->d_pool, lines.data(), b_lines, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_cnt, cnt.data(), b_cnt, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_grec, grec.data(), grec.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_gbase, gbase.data(), gbase.size() * 4, hipMemcpyHostToDevice, s));
+    HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_gord, gord.data(), gord.size() * 2, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(wh->d_inst, wh->inst.data(), sizeof(InstDev) * n_instances, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(wh->d_err, 0, 64, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -322,6 +380,7 @@ extern "C" wo_status wo_free_warehouse(wo_wh *wh)
     if (wh->d_inst) (void)hipFree(wh->d_inst);
     if (wh->d_map) (void)hipFree(wh->d_map);
     if (wh->d_err) (void)hipFree(wh->d_err);
+    if (wh->d_work) (void)hipFree(wh->d_work);
     delete wh;
     return WO_OK;
 }
@@ -334,6 +393,46 @@ extern "C" wo_status wo_instance_info(const wo_wh *wh, int32_t i, int32_t *n_ord
     if (n_orders) *n_orders = wh->inst[i].n_orders;
     if (n_items) *n_items = wh->inst[i].n_lines;
     if (n_categories) *n_categories = wh->inst[i].n_cat;
+    return WO_OK;
+}
+
+// Blocks to launch: `per_cu` workgroups per CU (or as many as the LDS allows,
+// at most 32 waves per CU), never more than there are plans.
+static int launch_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
+{
+    int fit = std::max(1, (int)((160u * 1024u) / std::max(1u, lds)));
+    fit = std::min(fit, 32 / (wh->block / 64));
+    int per_cu = wh->per_cu > 0 ? std::min(wh->per_cu, fit) : fit;
+    return (int)std::min<int64_t>(n_plans, (int64_t)wh->cu_count * per_cu);
+}
+
+// Work list for the queue: plans of the most expensive instances first
+// (longest-processing-time order; cost ~ lines + 2 * orders per plan).
+static wo_status prepare_work(wo_wh *wh, const std::vector<int64_t> &map, int64_t n_plans, hipStream_t s)
+{
+    if (map == wh->work_map && wh->work_cap >= n_plans) return WO_OK;
+    if (n_plans > INT32_MAX) return fail(WO_E_RANGE, "too many plans for the work queue");
+    std::vector<int32_t> order(wh->n_inst);
+    for (int32_t i = 0; i < wh->n_inst; i++) order[i] = i;
+    std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
+        const int64_t cx = (int64_t)wh->inst[x].n_lines + 2ll * wh->inst[x].n_orders;
+        const int64_t cy = (int64_t)wh->inst[y].n_lines + 2ll * wh->inst[y].n_orders;
+        return cx > cy;
+    });
+    std::vector<int32_t> work;
+    work.reserve((size_t)n_plans);
+    for (int32_t i : order)
+        for (int64_t p = map[i]; p < map[i + 1]; p++) work.push_back((int32_t)p);
+    if (wh->work_cap < n_plans) {
+        if (wh->d_work) (void)hipFree(wh->d_work);
+        wh->d_work = nullptr;
+        wh->work_cap = 0;
+        wo_status st = dev_alloc((void **)&wh->d_work, sizeof(int32_t) * (size_t)n_plans);
+        if (st) return st;
+        wh->work_cap = n_plans;
+    }
+    HIP_TRY(hipMemcpyAsync(wh->d_work, work.data(), sizeof(int32_t) * work.size(), hipMemcpyHostToDevice, s));
+    wh->work_map = map;
     return WO_OK;
 }
 
@@ -381,15 +480,26 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.seq_base = wh->d_map + wh->n_inst + 1;
     a.lines = wh->d_lines;
     a.cnt = wh->d_cnt;
+    a.grec = wh->d_grec;
+    a.gbase = wh->d_gbase;
+    a.gord = wh->d_gord;
+    a.main_mode = wh->main_mode;
     a.zone_of = d_zone_of;
     a.seq = d_order_seq;
     a.dist = d_dist;
     a.thr = d_orders_per_window;
     a.err = wh->d_err;
     a.validate = validate ? 1 : 0;
-    int per_cu = std::max(1, (int)((160u * 1024u) / std::max(1u, wh->lds_max)));
-    int64_t grid = std::min<int64_t>(n_plans, (int64_t)wh->cu_count * per_cu);
-    HIP_TRY(launch_eval(a, wh->lds_max, (int)grid, s));
+    a.queue = 0;
+    a.queue_ctr = (uint32_t *)((char *)wh->d_err + 48);
+    a.work = nullptr;
+    if (wh->queue) {
+        wo_status st = prepare_work(wh, map, n_plans, s);
+        if (st) return st;
+        a.queue = 1;
+        a.work = wh->d_work;
+    }
+    HIP_TRY(launch_eval(a, wh->lds_max, launch_grid(wh, wh->lds_max, n_plans), wh->block, s));
     if (validate) {
         int32_t err = 0;
         HIP_TRY(hipMemcpyAsync(&err, wh->d_err, 4, hipMemcpyDeviceToHost, s));
@@ -415,19 +525,125 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.seq_base = zero_map;
     a.lines = wh->d_lines;
     a.cnt = wh->d_cnt;
+    a.grec = wh->d_grec;
+    a.gbase = wh->d_gbase;
+    a.gord = wh->d_gord;
+    a.main_mode = wh->main_mode;
     a.zone_of = d_zone_of;
     a.seq = d_order_seq;
     a.dist = d_dist;
     a.thr = d_thr;
     a.err = wh->d_err;
     a.validate = 0;
+    a.queue = 0;
+    a.queue_ctr = nullptr;
+    a.work = nullptr;
     const uint32_t lds = wh->lds[inst];
-    int per_cu = std::max(1, (int)((160u * 1024u) / std::max(1u, lds)));
-    int64_t grid = std::min<int64_t>(n_plans, (int64_t)wh->cu_count * per_cu);
-    HIP_TRY(launch_eval(a, lds, (int)grid, s));
+    HIP_TRY(launch_eval(a, lds, launch_grid(wh, lds, n_plans), wh->block, s));
     return WO_OK;
 }
 
 int32_t wo::instance_orders(const wo_wh *wh, int32_t inst) { return wh->inst[inst].n_orders; }
 int32_t wo::instance_categories(const wo_wh *wh, int32_t inst) { return wh->inst[inst].n_cat; }
 int32_t wo::instance_count(const wo_wh *wh) { return wh->n_inst; }
+
+extern "C" wo_status wo_set_eval_config(wo_wh *wh, const wo_eval_config *cfg)
+{
+    if (!wh || !cfg) return fail(WO_E_INVAL, "NULL argument");
+    if (cfg->block_threads != 128 && cfg->block_threads != 256 && cfg->block_threads != 512)
+        return fail(WO_E_INVAL, "block_threads must be 128, 256 or 512");
+    if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 32) return fail(WO_E_INVAL, "blocks_per_cu in [0, 32]");
+    if (cfg->queue != 0 && cfg->queue != 1) return fail(WO_E_INVAL, "queue must be 0 or 1");
+    if (cfg->line_pass != 0 && cfg->line_pass != 1) return fail(WO_E_INVAL, "line_pass must be 0 or 1");
+    Busy busy(&wh->busy);
+    if (!busy.ok) return fail(WO_E_STATE, "handle is in use by another thread");
+    wh->block = cfg->block_threads;
+    wh->per_cu = cfg->blocks_per_cu;
+    wh->queue = cfg->queue;
+    wh->main_mode = cfg->line_pass;
+    return WO_OK;
+}
+
+extern "C" wo_status wo_get_eval_config(const wo_wh *wh, wo_eval_config *cfg)
+{
+    if (!wh || !cfg) return fail(WO_E_INVAL, "NULL argument");
+    cfg->block_threads = wh->block;
+    cfg->blocks_per_cu = wh->per_cu;
+    cfg->queue = wh->queue;
+    cfg->line_pass = wh->main_mode;
+    cfg->ms = 0.f;
+    return WO_OK;
+}
+
+extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans,
+                                      const uint8_t *d_zone_of, const uint16_t *d_order_seq, int32_t *d_dist,
+                                      int32_t reps, void *stream, wo_eval_config *best_out,
+                                      wo_eval_config *h_all, int32_t *n_all)
+{
+    if (!wh) return fail(WO_E_INVAL, "handle is NULL");
+    if (reps < 1) return fail(WO_E_INVAL, "reps must be >= 1");
+    if (n_plans < 1) return fail(WO_E_INVAL, "need plans to time");
+    hipStream_t s = (hipStream_t)stream;
+    const int saved_block = wh->block, saved_per_cu = wh->per_cu, saved_queue = wh->queue,
+              saved_mode = wh->main_mode;
+    hipEvent_t e0, e1;
+    HIP_TRY(hipEventCreate(&e0));
+    HIP_TRY(hipEventCreate(&e1));
+    wo_eval_config best{saved_block, saved_per_cu, saved_queue, saved_mode, 3.0e38f};
+    int count = 0;
+    wo_status st = WO_OK;
+    const int blocks[3] = {128, 256, 512};
+    const int per_cus[6] = {1, 2, 3, 4, 6, 8};
+    for (int bi = 0; bi < 3 && !st; bi++) {
+        for (int pi = 0; pi < 6 && !st; pi++) {
+            const int blk = blocks[bi], pc = per_cus[pi];
+            if (pc * (blk / 64) > 32) continue;                               // waves per CU
+            if ((uint64_t)pc * wh->lds_max > 160u * 1024u) continue;          // LDS per CU
+            for (int qm = 0; qm < 4 && !st; qm++) {
+                const int q = qm & 1, mode = qm >> 1;
+                wh->block = blk;
+                wh->per_cu = pc;
+                wh->queue = q;
+                wh->main_mode = mode;
+                // warm-up (also builds the work list outside the timed region)
+                if ((st = wo_eval_plans(wh, plan_offsets, n_plans, d_zone_of, d_order_seq, d_dist, nullptr, stream)))
+                    break;
+                float ms_best = 3.0e38f;
+                for (int r = 0; r < reps && !st; r++) {
+                    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(WO_E_DEVICE, "hipEventRecord failed"); break; }
+                    if ((st = wo_eval_plans(wh, plan_offsets, n_plans, d_zone_of, d_order_seq, d_dist, nullptr,
+                                            stream)))
+                        break;
+                    float ms = 0.f;
+                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
+                        st = fail(WO_E_DEVICE, "event timing failed");
+                        break;
+                    }
+                    ms_best = std::min(ms_best, ms);
+                }
+                if (st) break;
+                wo_eval_config c{blk, pc, q, mode, ms_best};
+                if (h_all && n_all && count < *n_all) h_all[count] = c;
+                count++;
+                if (ms_best < best.ms) best = c;
+            }
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st) {
+        wh->block = saved_block;
+        wh->per_cu = saved_per_cu;
+        wh->queue = saved_queue;
+        wh->main_mode = saved_mode;
+        return st;
+    }
+    wh->block = best.block_threads;
+    wh->per_cu = best.blocks_per_cu;
+    wh->queue = best.queue;
+    wh->main_mode = best.line_pass;
+    if (best_out) *best_out = best;
+    if (n_all) *n_all = count;
+    return WO_OK;
+}

@@ -31,6 +31,15 @@ struct InstDev {
     int32_t pad0;
     int64_t line_off;       // uint2 line records [n_lines]: x = (rank << shift) | (4*cat) << 24, y = order id
     int64_t cnt_off;        // u8 per order: min(size, capacity + 1) [n_orders], padded to 16 bytes
+    // orders in groups of 64 by descending size (one order per lane): group g
+    // holds lines [gbase[g], gbase[g+1]) of grec, line k of its lane j at
+    // gbase[g] + 64 k + j (shorter orders repeat their first line); gord holds
+    // the order id of each lane (0xFFFF: none)
+    int64_t grec_off;       // u32 records, same packing as line_off's x
+    int64_t gbase_off;      // u32 [n_grp + 1], relative to grec_off
+    int64_t gord_off;       // u16 [64 * n_grp]
+    int32_t n_grp;
+    int32_t pad1;
     double walk;
     double t_item;
     double window;
@@ -45,19 +54,25 @@ struct EvalArgs {
     const int64_t *seq_base;    // device [n_inst]: element offset of instance i's first sequence row
     const uint2 *lines;     // pooled arrays
     const uint8_t *cnt;
+    const uint32_t *grec;
+    const uint32_t *gbase;
+    const uint16_t *gord;
+    int32_t main_mode;      // 0: one line per lane, 1: one order per lane (groups)
     const uint8_t *zone_of;
     const uint16_t *seq;
     int32_t *dist;
     float *thr;
     int32_t *err;           // device flag, validation mode
     int32_t validate;
+    int32_t queue;          // 1: take plans from a ticket counter
+    uint32_t *queue_ctr;
+    const int32_t *work;    // work item -> plan row (null: identity)
 };
 
 // Parallel next-fit: lanes that chase candidate tour chains, records per chain.
 constexpr int CHASE_LANES = 256;
 constexpr int CHASE_RECS = 32;
 constexpr int MAX_SEG = 64;
-constexpr int SEQ_CHUNK = 16;   // sequence positions per thread kept in registers
 
 // LDS layout of one evaluation block for an instance; host and device use the
 // same function so that the launch size and the kernel agree.  The chase
@@ -102,7 +117,7 @@ __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_un
     return L;
 }
 
-hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s);
+hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, hipStream_t s);
 
 // library-internal helpers over a loaded handle
 wo_status eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint8_t *d_zone_of,

@@ -30,6 +30,7 @@ EXPORTS = sorted([
     "wo_sur_gradients", "wo_sur_train", "wo_sur_predict", "wo_sur_save", "wo_sur_load",
     "wo_screen_plans",
     "wo_search_create", "wo_search_free", "wo_search_step", "wo_search_best", "wo_search_population",
+    "wo_set_eval_config", "wo_get_eval_config", "wo_autotune_eval",
 ])
 WO_SUR_PARAMS = 4457985
 WO_SCREEN_MAX_KEEP = 4096
@@ -39,6 +40,11 @@ class WoError(RuntimeError):
     def __init__(self, status: int, message: str):
         super().__init__("%s: %s" % (_status_name(status), message))
         self.status = status
+
+
+class wo_eval_config(ctypes.Structure):
+    _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
+                ("queue", ctypes.c_int32), ("line_pass", ctypes.c_int32), ("ms", ctypes.c_float)]
 
 
 class wo_search_params(ctypes.Structure):
@@ -91,6 +97,9 @@ def lib():
         L.wo_sur_save.argtypes = [V, ctypes.c_char_p]
         L.wo_sur_load.argtypes = [ctypes.c_char_p, V, P(V)]
         L.wo_screen_plans.argtypes = [V, I32, V, I64, V, V, I64, V, V]
+        L.wo_set_eval_config.argtypes = [V, P(wo_eval_config)]
+        L.wo_get_eval_config.argtypes = [V, P(wo_eval_config)]
+        L.wo_autotune_eval.argtypes = [V, V, I64, V, V, V, I32, V, P(wo_eval_config), V, P(I32)]
         L.wo_search_create.argtypes = [V, I32, P(wo_search_params), V, V, V, P(V)]
         L.wo_search_free.argtypes = [V]
         L.wo_search_step.argtypes = [V, V, V, I32, V]
@@ -401,3 +410,36 @@ def wo_search_population(s: Search, zone_of=None, seq=None, dist=None, last_kept
     _check(lib().wo_search_population(s.handle, _ptr(zone_of, 1, "zone_of"), _ptr(seq, 2, "seq"),
                                       _ptr(dist, 4, "dist"), _ptr(last_kept, 4, "last_kept"),
                                       ctypes.c_void_p(_stream_handle(stream))))
+
+
+# ---------------------------------------------------------------------------
+# launch configuration and autotuning
+# ---------------------------------------------------------------------------
+
+def wo_set_eval_config(wh: Warehouse, block_threads: int, blocks_per_cu: int = 0, queue: int = 0,
+                       line_pass: int = 1):
+    cfg = wo_eval_config(int(block_threads), int(blocks_per_cu), int(queue), int(line_pass), 0.0)
+    _check(lib().wo_set_eval_config(wh.handle, ctypes.byref(cfg)))
+
+
+def wo_get_eval_config(wh: Warehouse) -> dict:
+    cfg = wo_eval_config()
+    _check(lib().wo_get_eval_config(wh.handle, ctypes.byref(cfg)))
+    return {"block_threads": cfg.block_threads, "blocks_per_cu": cfg.blocks_per_cu, "queue": cfg.queue,
+            "line_pass": cfg.line_pass}
+
+
+def wo_autotune_eval(wh: Warehouse, zone_of, order_seq, dist, plan_offsets=None, reps: int = 3, stream=None):
+    """Time every launch configuration; keep and return the fastest (plus all timings)."""
+    n = int(zone_of.shape[0])
+    offs = None if plan_offsets is None else np.ascontiguousarray(plan_offsets, dtype=np.int64)
+    best = wo_eval_config()
+    allc = (wo_eval_config * 64)()
+    cnt = ctypes.c_int32(64)
+    _check(lib().wo_autotune_eval(wh.handle, None if offs is None else offs.ctypes.data, n,
+                                  _ptr(zone_of, 1, "zone_of"), _ptr(order_seq, 2, "order_seq"),
+                                  _ptr(dist, 4, "dist"), int(reps), ctypes.c_void_p(_stream_handle(stream)),
+                                  ctypes.byref(best), allc, ctypes.byref(cnt)))
+    conv = lambda c: {"block_threads": c.block_threads, "blocks_per_cu": c.blocks_per_cu, "queue": c.queue,
+                      "line_pass": c.line_pass, "ms": c.ms}
+    return conv(best), [conv(allc[i]) for i in range(min(cnt.value, 64))]

@@ -25,18 +25,21 @@ def _wo():
     return wo
 
 
-def _compare(inst, Z, S, wh=None, n_threads=8):
+def _compare(inst, Z, S, wh=None, n_threads=8, line_passes=(1, 0)):
     wo = _wo()
     own = wh is None
     if own:
         wh = wo.wo_load_warehouse([inst])
-    d_gpu, t_gpu = gpu_eval(wh, Z, S)
     d_ref, t_ref = oracle.eval_plans(inst, Z, S, n_threads=n_threads)
+    for lp in line_passes:           # both mappings of the aisle-set pass
+        wo.wo_set_eval_config(wh, 256, 0, 0, lp)
+        d_gpu, t_gpu = gpu_eval(wh, Z, S)
+        bad = np.flatnonzero(d_gpu != d_ref)
+        assert bad.size == 0, "line pass %d, plans %s: gpu %s oracle %s" % (
+            lp, bad[:5], d_gpu[bad[:5]], d_ref[bad[:5]])
+        np.testing.assert_allclose(t_gpu, t_ref, rtol=THR_RTOL, atol=0)
     if own:
         wh.free()
-    bad = np.flatnonzero(d_gpu != d_ref)
-    assert bad.size == 0, "plans %s: gpu %s oracle %s" % (bad[:5], d_gpu[bad[:5]], d_ref[bad[:5]])
-    np.testing.assert_allclose(t_gpu, t_ref, rtol=THR_RTOL, atol=0)
 
 
 def test_tiny_all_plans():
