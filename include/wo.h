@@ -146,8 +146,8 @@ wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans,
 
 
 /* Launch configuration of the evaluation kernel for a handle: threads per
- * workgroup (128, 256 or 512), workgroups per CU (0 = as many as LDS and
- * the 32 waves of a CU allow), and the work distribution (0 = grid stride
+ * workgroup (128, 256 or 512), workgroups per CU (0 = as many as registers
+ * and LDS allow), and the work distribution (0 = grid stride
  * over plan rows, 1 = a ticket queue over a work list that puts the plans of
  * the most expensive instances first -- useful for uneven batches), and the
  * mapping of the aisle-set pass (line_pass).  `ms` is
@@ -156,7 +156,7 @@ typedef struct {
     int32_t block_threads;
     int32_t blocks_per_cu;
     int32_t queue;
-    int32_t line_pass;   /* 1: one order per lane (default), 0: one order line per lane */
+    int32_t line_pass;   /* 0: one order line per lane (default), 1: one order per lane */
     float ms;
 } wo_eval_config;
 

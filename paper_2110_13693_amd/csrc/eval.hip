@@ -126,6 +126,18 @@ static __device__ __forceinline__ int count_range(const uint32_t *F, int lo, int
     return c;
 }
 
+// Instance of plan row p: the last one whose first row is <= p.
+static __device__ __forceinline__ int instance_of(const EvalArgs &A, int64_t p)
+{
+    if (A.n_inst <= 1) return 0;
+    int lo = 0, hi = A.n_inst - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (A.plan_begin[mid] <= p) lo = mid; else hi = mid - 1;
+    }
+    return lo;
+}
+
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
 {
@@ -143,18 +155,17 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
         if (tid == 0) s_next = atomicAdd(A.queue_ctr, 1u);
         __syncthreads();
         item = s_next;
+        __syncthreads();
     }
+    // the next plan's sequence chunk and zone row, loaded while the current
+    // plan's line pass runs
+    bool have_pf = false;                   // uniform
+    uint32_t sv_pf[SEQ_CHUNK / 2];          // two 16-bit order ids per register
+    uint32_t zc_pf = 0xFFu;
     while (item < A.n_plans) {
+        if (A.queue && tid == 0) s_next = atomicAdd(A.queue_ctr, 1u);   // ticket of the next plan
         const int64_t p = A.work ? (int64_t)A.work[item] : item;
-        int ii = 0;
-        if (A.n_inst > 1) {
-            int lo = 0, hi = A.n_inst - 1;   // last instance whose first row <= p
-            while (lo < hi) {
-                int mid = (lo + hi + 1) >> 1;
-                if (A.plan_begin[mid] <= p) lo = mid; else hi = mid - 1;
-            }
-            ii = lo;
-        }
+        const int ii = instance_of(A, p);
         const InstDev &I = A.inst[ii];
         const int n = I.n_orders;
         const int C = I.n_cat;
@@ -199,7 +210,7 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
 
         // ---- 1. zone starts (wave 0) -------------------------------------
         if (tid < 64) {
-            const uint32_t zc = (lane < C) ? (uint32_t)A.zone_of[p * 64 + lane] : 0xFFu;
+            const uint32_t zc = have_pf ? zc_pf : ((lane < C) ? (uint32_t)A.zone_of[p * 64 + lane] : 0xFFu);
             const uint32_t sz = (lane < C) ? (uint32_t)I.cat_size[lane] : 0u;
             uint32_t start = 0;
             for (int c2 = 0; c2 < C; c2++) {
@@ -221,23 +232,25 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
         const int ch = (n + BLOCK - 1) / BLOCK;
         const int b0 = min(n, tid * ch), b1 = min(n, b0 + ch);
         const bool one_piece = ch <= SEQ_CHUNK;          // uniform
-        uint32_t sv[SEQ_CHUNK];
+        uint32_t svp[SEQ_CHUNK / 2];                    // the chunk's order ids, two per register
         if (one_piece) {
 #pragma unroll
             for (int k = 0; k < SEQ_CHUNK; k++) {
                 const int i = b0 + k;
-                uint32_t o = (i < b1) ? (uint32_t)seq[i] : 0u;
+                uint32_t o = (i < b1) ? (have_pf ? ((sv_pf[k >> 1] >> (16 * (k & 1))) & 0xFFFFu) : (uint32_t)seq[i]) : 0u;
                 if (o >= (uint32_t)n) { bad = 1; o = (uint32_t)(n - 1); }
-                sv[k] = o;
+                if (k & 1) svp[k >> 1] |= o << 16; else svp[k >> 1] = o;
             }
         }
+#define SV(k) ((svp[(k) >> 1] >> (16 * ((k) & 1))) & 0xFFFFu)
         __syncthreads();                                 // count table, zeroed bitmaps
+        const int64_t next_item = A.queue ? (int64_t)s_next : item + (int64_t)gridDim.x;
         int local = 0, big = 0;
         if (one_piece) {
 #pragma unroll
             for (int k = 0; k < SEQ_CHUNK; k++) {
                 if (b0 + k < b1) {
-                    const int c = cnt[sv[k]];
+                    const int c = cnt[SV(k)];
                     local += c;
                     big |= c > (int)Q;
                 }
@@ -262,7 +275,7 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
                         const uint32_t w = run >> 5;
                         if (w != cur) { atomicOr(&B[cur], acc); acc = 0; cur = w; }
                         acc |= 1u << (run & 31u);
-                        run += cnt[sv[k]];
+                        run += cnt[SV(k)];
                     }
                 }
             } else {
@@ -428,7 +441,7 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
                 const int i = b0 + k;
                 if (i < b1) {
                     trun += (F[i >> 5] >> (i & 31)) & 1u;
-                    tour[sv[k]] = (uint16_t)trun;
+                    tour[SV(k)] = (uint16_t)trun;
                 }
             }
         } else {
@@ -441,6 +454,28 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
         }
         __syncthreads();
 
+        // ---- prefetch of the next plan's inputs ---------------------------
+        have_pf = false;
+        if (next_item < A.n_plans) {
+            const int64_t pn = A.work ? (int64_t)A.work[next_item] : next_item;
+            const int iin = instance_of(A, pn);
+            const InstDev &In = A.inst[iin];
+            const int nn = In.n_orders;
+            const int chn = (nn + BLOCK - 1) / BLOCK;
+            if (chn <= SEQ_CHUNK) {                      // uniform
+                const uint16_t *seqn = A.seq + A.seq_base[iin] + (pn - (A.n_inst > 1 ? A.plan_begin[iin] : 0)) * (int64_t)nn;
+                const int c0 = min(nn, tid * chn), c1 = min(nn, c0 + chn);
+#pragma unroll
+                for (int k = 0; k < SEQ_CHUNK; k += 2) {
+                    const uint32_t lo = (c0 + k < c1) ? (uint32_t)seqn[c0 + k] : 0u;
+                    const uint32_t hi = (c0 + k + 1 < c1) ? (uint32_t)seqn[c0 + k + 1] : 0u;
+                    sv_pf[k >> 1] = lo | (hi << 16);
+                }
+                zc_pf = (tid < 64 && lane < In.n_cat) ? (uint32_t)A.zone_of[pn * 64 + lane] : 0xFFu;
+                have_pf = true;
+            }
+        }
+
         // ---- 5./6. aisle sets and S-shape per tour tile ------------------
         const int W = I.words;
         const int T = I.t_cap;
@@ -452,15 +487,17 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
             for (int k = tid; k < T; k += BLOCK) mx[k] = 0;
             __syncthreads();
             if (A.main_mode == 0) {
-                for (int q0 = tid; q0 < n_lines; q0 += 4 * BLOCK) {
-                    uint2 v[4];
+                // one line per lane, 8 coalesced loads in flight per thread
+                constexpr int U = 8;
+                for (int q0 = tid; q0 < n_lines; q0 += U * BLOCK) {
+                    uint2 v[U];
 #pragma unroll
-                    for (int u = 0; u < 4; u++) {
+                    for (int u = 0; u < U; u++) {
                         const int q = q0 + u * BLOCK;
                         v[u] = (q < n_lines) ? lines[q] : make_uint2(0u, 0xFFFFFFFFu);
                     }
 #pragma unroll
-                    for (int u = 0; u < 4; u++) {
+                    for (int u = 0; u < U; u++) {
                         if (v[u].y != 0xFFFFFFFFu) {
                             const uint32_t t = (uint32_t)tour[v[u].y] - (uint32_t)t0;
                             if (t < (uint32_t)T) {
@@ -476,39 +513,58 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
             } else {
                 // one order per lane: its tour looked up once, its farthest
                 // location kept in a register, the zone start of each line
-                // taken from the wave's copy of the table by lane permute
+                // taken from the wave's copy of the table by lane permute.
+                // The next group's order ids and first 8 line records are
+                // loaded while the current group is processed.
+                constexpr int PF = 8;
                 const int zsv = (int)zs[lane];
                 const uint32_t *grec = A.grec + I.grec_off;
                 const uint32_t *gbase = A.gbase + I.gbase_off;
                 const uint16_t *gord = A.gord + I.gord_off;
-                for (int g = tid >> 6; g < I.n_grp; g += BLOCK / 64) {
-                    const uint32_t o = gord[g * 64 + lane];
+                const int gstep = BLOCK / 64;
+                int g = tid >> 6;
+                uint32_t o_n = 0xFFFFu, b_n = 0, L_n = 0, r_n[PF];
+                if (g < I.n_grp) {
+                    o_n = gord[g * 64 + lane];
+                    b_n = gbase[g];
+                    L_n = (gbase[g + 1] - b_n) >> 6;
+#pragma unroll
+                    for (int u = 0; u < PF; u++) r_n[u] = (uint32_t)u < L_n ? grec[b_n + u * 64 + lane] : 0u;
+                }
+                while (g < I.n_grp) {
+                    const uint32_t o = o_n, b0g = b_n, L = L_n;
+                    uint32_t r[PF];
+#pragma unroll
+                    for (int u = 0; u < PF; u++) r[u] = r_n[u];
+                    const int gn = g + gstep;
+                    if (gn < I.n_grp) {
+                        o_n = gord[gn * 64 + lane];
+                        b_n = gbase[gn];
+                        L_n = (gbase[gn + 1] - b_n) >> 6;
+#pragma unroll
+                        for (int u = 0; u < PF; u++) r_n[u] = (uint32_t)u < L_n ? grec[b_n + u * 64 + lane] : 0u;
+                    }
                     const uint32_t t = (o != 0xFFFFu) ? (uint32_t)tour[o] - (uint32_t)t0 : 0xFFFFFFFFu;
                     const bool active = t < (uint32_t)T;
-                    const uint32_t b0g = gbase[g], L = (gbase[g + 1] - b0g) >> 6;
-                    const uint32_t *gr = grec + b0g + lane;
                     uint32_t far = 0;
-                    uint32_t kk = 0;
-                    for (; kk + 4 <= L; kk += 4) {
-                        uint32_t r[4];
 #pragma unroll
-                        for (int u = 0; u < 4; u++) r[u] = gr[(kk + u) * 64];
-#pragma unroll
-                        for (int u = 0; u < 4; u++) {
+                    for (int u = 0; u < PF; u++) {
+                        if ((uint32_t)u < L) {
                             const uint32_t ls = r[u] + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(r[u] >> 24), zsv);
                             const uint32_t a = mulhi24(ls, magic);
                             if (active) atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
                             far = max(far, ls);
                         }
                     }
-                    for (; kk < L; kk++) {
-                        const uint32_t r = gr[kk * 64];
-                        const uint32_t ls = r + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(r >> 24), zsv);
+                    for (uint32_t kk = PF; kk < L; kk++) {     // long orders
+                        const uint32_t rr = grec[b0g + kk * 64 + lane];
+                        const uint32_t ls = rr + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(rr >> 24), zsv);
                         const uint32_t a = mulhi24(ls, magic);
                         if (active) atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
                         far = max(far, ls);
                     }
                     if (active) atomicMax(&mx[t], far);
+                    g = gn;
                 }
             }
             __syncthreads();
@@ -533,13 +589,7 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
             if (A.thr) A.thr[p] = window_throughput(D, I);
         }
         __syncthreads();
-        if (A.queue) {
-            if (tid == 0) s_next = atomicAdd(A.queue_ctr, 1u);
-            __syncthreads();
-            item = s_next;
-        } else {
-            item += gridDim.x;
-        }
+        item = next_item;
     }
 }
 
@@ -564,6 +614,27 @@ static hipError_t launch_eval_t(const EvalArgs &a, uint32_t lds_bytes, int grid,
     if (a.queue) hipLaunchKernelGGL(reset_ticket_kernel, dim3(1), dim3(1), 0, s, a.queue_ctr);
     hipLaunchKernelGGL(eval_plans_kernel<BLOCK>, dim3(grid), dim3(BLOCK), lds_bytes, s, a);
     return hipGetLastError();
+}
+
+template <int BLOCK>
+static int max_blocks_t(uint32_t lds_bytes)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, eval_plans_kernel<BLOCK>, BLOCK, lds_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
+}
+
+int eval_max_blocks_per_cu(int block, uint32_t lds_bytes)
+{
+    switch (block) {
+    case 128: return max_blocks_t<128>(lds_bytes);
+    case 256: return max_blocks_t<256>(lds_bytes);
+    case 512: return max_blocks_t<512>(lds_bytes);
+    }
+    return 1;
 }
 
 hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, hipStream_t s)

@@ -98,7 +98,7 @@ struct wo_wh {
     int block = 256;
     int per_cu = 0;                     // 0: as many as LDS allows
     int queue = 0;                      // 1: ticket queue over the cost-ordered work list
-    int main_mode = 1;                  // 1: one order per lane in the line pass, 0: one line per lane
+    int main_mode = 0;                  // 0: one line per lane in the line pass, 1: one order per lane
     int32_t *d_work = nullptr;          // work list for the current plan map
     int64_t work_cap = 0;
     std::vector<int64_t> work_map;      // plan map the work list was built for
@@ -318,10 +318,13 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         const double avg_len = items / d.n_orders;
         const double cand = std::max(1.0, std::min((double)d.capacity, d.capacity / avg_len));
         const double tour_items = std::max(1.0, d.capacity - 0.5 * (avg_len - 1.0));
-        int g_lanes = 1 + (int)((0.7 * CHASE_LANES - 1.0) / cand);
+        // fewest segments whose chains fit the record slots with margin, plus
+        // one; fewer if the expected chase lanes would not fit
+        int g_recs = (int)std::ceil(items / (0.75 * CHASE_RECS * tour_items));
+        int g = g_recs + 1;
+        int g_lanes = 1 + (int)((0.85 * CHASE_LANES - 1.0) / cand);
         int g_len = (int)(items / (2.0 * d.capacity));
-        int g = std::min(std::min(g_lanes, g_len), MAX_SEG);
-        int g_recs = (int)std::ceil(items / (0.6 * CHASE_RECS * tour_items));
+        g = std::min(std::min(g, g_lanes), std::min(g_len, MAX_SEG));
         bool short_segs = (double)I.n_units / std::max(g, 1) < 65535.0;  // chase records are 16-bit offsets
         I.n_seg = (g >= 2 && g >= g_recs && short_segs) ? g : 1;
 
@@ -400,9 +403,8 @@ extern "C" wo_status wo_instance_info(const wo_wh *wh, int32_t i, int32_t *n_ord
 // at most 32 waves per CU), never more than there are plans.
 static int launch_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
 {
-    int fit = std::max(1, (int)((160u * 1024u) / std::max(1u, lds)));
-    fit = std::min(fit, 32 / (wh->block / 64));
-    int per_cu = wh->per_cu > 0 ? std::min(wh->per_cu, fit) : fit;
+    const int fit = eval_max_blocks_per_cu(wh->block, lds);
+    const int per_cu = wh->per_cu > 0 ? std::min(wh->per_cu, fit) : fit;
     return (int)std::min<int64_t>(n_plans, (int64_t)wh->cu_count * per_cu);
 }
 
@@ -597,8 +599,7 @@ extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, in
     for (int bi = 0; bi < 3 && !st; bi++) {
         for (int pi = 0; pi < 6 && !st; pi++) {
             const int blk = blocks[bi], pc = per_cus[pi];
-            if (pc * (blk / 64) > 32) continue;                               // waves per CU
-            if ((uint64_t)pc * wh->lds_max > 160u * 1024u) continue;          // LDS per CU
+            if (pc > eval_max_blocks_per_cu(blk, wh->lds_max)) continue;      // registers and LDS
             for (int qm = 0; qm < 4 && !st; qm++) {
                 const int q = qm & 1, mode = qm >> 1;
                 wh->block = blk;

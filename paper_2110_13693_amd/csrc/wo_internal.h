@@ -118,6 +118,8 @@ __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_un
 }
 
 hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, hipStream_t s);
+// workgroups of the evaluation kernel that fit one CU (registers and LDS)
+int eval_max_blocks_per_cu(int block, uint32_t lds_bytes);
 
 // library-internal helpers over a loaded handle
 wo_status eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint8_t *d_zone_of,

@@ -417,7 +417,7 @@ def wo_search_population(s: Search, zone_of=None, seq=None, dist=None, last_kept
 # ---------------------------------------------------------------------------
 
 def wo_set_eval_config(wh: Warehouse, block_threads: int, blocks_per_cu: int = 0, queue: int = 0,
-                       line_pass: int = 1):
+                       line_pass: int = 0):
     cfg = wo_eval_config(int(block_threads), int(blocks_per_cu), int(queue), int(line_pass), 0.0)
     _check(lib().wo_set_eval_config(wh.handle, ctypes.byref(cfg)))
 
