@@ -9,7 +9,10 @@ capacity 30.  Prints one JSON line.
 The roofline object reports the evaluation kernel against the plain integer
 VALU roof; its algorithmic work per plan is 8 ops per pick + 4 per order +
 12 per tour (tour counts come from a host-side next-fit count, reporting
-only).  The cpu_baseline object times the CPU oracle on a bounded sample of
+only).  Its ``traffic`` is the kernel's HBM bytes per launch (FETCH_SIZE +
+WRITE_SIZE, each scaled by its reading on a plain copy) from the committed
+rocprofv3 summary, reported only while the kernel sources still hash to the
+profiled ones.  The cpu_baseline object times the CPU oracle on a bounded sample of
 the same plans, on the host's cores.
 """
 from __future__ import annotations
@@ -50,6 +53,29 @@ def algorithmic_ops(inst, seq: np.ndarray) -> float:
     T = tour_counts(inst, seq)
     n = seq.shape[0]
     return float(8 * inst.n_items * n + 4 * inst.n_orders * n + 12 * T.sum())
+
+
+def profiled_traffic():
+    """HBM bytes per launch of the evaluation kernel, from the committed
+    rocprofv3 FETCH_SIZE/WRITE_SIZE summary, or None when the kernel sources
+    have changed since those counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "eval_plans_kernel_paper4096_hbm.md")
+    try:
+        fields = {}
+        for line in open(path):
+            if ":" in line and not line.startswith(("|", "#", "`")):
+                k, v = line.split(":", 1)
+                fields[k.strip()] = v.strip()
+        h = hashlib.sha256()
+        for src in fields["kernel_sources"].split():
+            with open(os.path.join(ROOT, src), "rb") as f:
+                h.update(f.read())
+        if h.hexdigest() != fields["kernel_sources_sha256"]:
+            return None
+        return int(fields["traffic_bytes_per_launch"])
+    except (OSError, KeyError, ValueError):
+        return None
 
 
 def cpu_baseline(inst, Z, S, min_wall_s: float = 1.5):
@@ -269,7 +295,8 @@ def main(argv=None):
     # one launch per step: the kernel's average duration is the step time
     achieved_ops = ops / (ms_per_step / 1e3)
     roofline = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": INT_VALU_PEAK_OPS / 1e12,
-                "unit": "Tops/s", "frac": achieved_ops / INT_VALU_PEAK_OPS, "traffic": None}
+                "unit": "Tops/s", "frac": achieved_ops / INT_VALU_PEAK_OPS,
+                "traffic": profiled_traffic() if args.workload == "paper" else None}
 
     out = {
         "metric": "exact plan evals/s @4k orders",
