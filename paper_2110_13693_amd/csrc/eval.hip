@@ -1,37 +1,42 @@
 // Exact plan evaluation on gfx950: slot map, next-fit tours, S-shape distance,
 // time-window throughput (arXiv 2110.13693, section 5, Subproblems 2 and 3,
 // Eq. (2); section 6).  One workgroup evaluates one plan at a time and walks
-// the plans with a grid stride; several workgroups share a CU so that one's
-// latency-bound phases overlap the others' work.
+// the plans with a grid stride (or a ticket queue); several workgroups share a
+// CU so that one's latency-bound phases overlap the others' work.
 //
 // Per plan:
 //   1. zone starts: start[c] = sum of the sizes of categories placed in a
-//      lower zone; kept in LDS pre-shifted so that a line's scaled location
-//      is one add: ls = rec + zs[rec >> 26];
+//      lower zone -- the sizes are permuted into zone order across the lanes
+//      of one wave, scanned, and permuted back; kept in LDS pre-shifted so
+//      that a line's scaled location is one add: ls = rec + zs[rec >> 24];
 //   2. a bitmap B over "units" of the sequence: bit P[i] is set where the
 //      i-th order of the sequence starts, P being the prefix sum of the order
 //      sizes clamped to Q + 1 (an order larger than Q is a tour of its own
 //      whatever its exact size), plus a sentinel bit at the total;
 //   3. next-fit: a tour opened at unit x ends after the last order that
 //      starts within (x, x + Q]; so the next tour opens at
-//      E(x) = highest set bit of B in (x, x + Q] (a 64-bit window of B).
+//      E(x) = highest set bit of B in (x, x + Q] (a 32-bit window of B).
 //      Tours open on the orbit of 0 under E.  The orbit is found in
 //      parallel: the unit range is cut into segments, and for each segment
 //      every order start that can be the first tour opened in it (those
 //      within Q units of its start) is chased to the segment end; the true
-//      entries are then linked segment after segment;
-//   4. tour ids: the rank of each opening position among the order starts is
-//      the sequence position of the tour's first order; a block scan over
-//      these flags gives every order its tour id;
-//   5. every order line (in instance order, coalesced) sets its aisle bit in
-//      its tour's aisle set (ds_or) and raises its tour's farthest location
+//      entries are then linked segment after segment and their openings
+//      marked in a second unit bitmap F;
+//   4. tour ids: position i opens a tour iff F has bit P[i]; a block scan
+//      over these flags numbers the tours, and every order's entry in the
+//      tour table receives the byte offset of its tour's LDS row;
+//   5. every order line (instance order, coalesced) sets its aisle bit in
+//      its tour's row (ds_or) and raises the row's farthest location
 //      (ds_max) -- the largest location of a tour is, at once, the last
 //      aisle visited and the farthest depth in it;
 //   6. per tour: k = popcount of the aisle set, S-shape closed form; the
 //      block sums the tours in int64.
+// Tours beyond one tile of rows are handled in further passes over the lines.
 #include "wo_internal.h"
 
 namespace wo {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 
 static __device__ __forceinline__ uint32_t mulhi24(uint32_t x, uint32_t m)
 {
@@ -43,42 +48,58 @@ static __device__ __forceinline__ uint32_t ffbh(uint32_t x)   // leading zeros, 
     return x ? (uint32_t)__builtin_clz(x) : 32u;
 }
 
-template <int BLOCK>
-static __device__ __forceinline__ int block_excl_scan(int v, int *scratch, int *total)
+// both 16-bit halves of a limited to those of b
+static __device__ __forceinline__ uint32_t min_u16x2(uint32_t a, uint32_t b)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    int inc = v;
-#pragma unroll
-    for (int d = 1; d < 64; d <<= 1) {
-        int t = __shfl_up(inc, d, 64);
-        if (lane >= d) inc += t;
-    }
-    if (lane == 63) scratch[w] = inc;
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_elementwise_min(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
+}
+
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active): shifts
+// by 1, 2, 4, 8 inside each row of 16 lanes, then the row totals carried by
+// the row broadcasts of lanes 15 and 31.
+static __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return x;
+}
+
+// Exclusive block scan with one barrier.  `slot` holds BLOCK / 64 words and
+// must not be reused before the block has passed another barrier.
+template <int BLOCK>
+static __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t *slot, uint32_t *total)
+{
+    const uint32_t inc = wave_incl_scan(v);
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 63) slot[w] = inc;
     __syncthreads();
-    int off = 0, tot = 0;
+    uint32_t off = 0, tot = 0;
 #pragma unroll
     for (int i = 0; i < BLOCK / 64; i++) {
-        int s = scratch[i];
-        off += (i < w) ? s : 0;
+        const uint32_t s = slot[i];
+        off += (i < w) ? s : 0u;
         tot += s;
     }
-    __syncthreads();
     *total = tot;
     return off + inc - v;
 }
 
 template <int BLOCK>
-static __device__ __forceinline__ int64_t block_sum64(int64_t v, int64_t *scratch)
+static __device__ __forceinline__ int64_t block_sum64(int64_t v, int64_t *slot)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
     for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    if (lane == 0) scratch[w] = v;
+    if (lane == 0) slot[w] = v;
     __syncthreads();
     int64_t t = 0;
 #pragma unroll
-    for (int i = 0; i < BLOCK / 64; i++) t += scratch[i];
-    __syncthreads();
+    for (int i = 0; i < BLOCK / 64; i++) t += slot[i];
     return t;
 }
 
@@ -104,28 +125,6 @@ static __device__ __forceinline__ uint32_t next_open(const uint32_t *B, uint32_t
     return x + 32u - ffbh(win);        // x + 1 + highest set bit
 }
 
-// Number of order starts below unit x = sequence position of the order at x.
-static __device__ __forceinline__ uint32_t rank_of(const uint32_t *B, const uint32_t *prefB, uint32_t x)
-{
-    const uint32_t w = x >> 5;
-    return prefB[w] + __popc(B[w] & ((1u << (x & 31u)) - 1u));
-}
-
-// Bits [lo, hi) of bitmap F, counted.
-static __device__ __forceinline__ int count_range(const uint32_t *F, int lo, int hi)
-{
-    int c = 0;
-    while (lo < hi) {
-        const int w = lo >> 5;
-        const int lim = min(hi, (w + 1) << 5);
-        const int len = lim - lo;
-        const uint32_t m = (len == 32 ? 0xFFFFFFFFu : ((1u << len) - 1u)) << (lo & 31);
-        c += __popc(F[w] & m);
-        lo = lim;
-    }
-    return c;
-}
-
 // Instance of plan row p: the last one whose first row is <= p.
 static __device__ __forceinline__ int instance_of(const EvalArgs &A, int64_t p)
 {
@@ -138,15 +137,59 @@ static __device__ __forceinline__ int instance_of(const EvalArgs &A, int64_t p)
     return lo;
 }
 
+// The order ids of sequence positions [0, nv) of `s`, clamped to n - 1, two
+// per register; positions nv .. CH - 1 get the sink id n + 1 (size 0).
+template <int CH>
+static __device__ __forceinline__ void load_chunk(const uint16_t *s, int nv, uint32_t n, uint32_t *out)
+{
+    const uint32_t lim = n - 1u, sink = n + 1u;
+    if (nv == CH && (((uintptr_t)s) & 15u) == 0) {
+        const uint32_t lim2 = lim | (lim << 16);
+#pragma unroll
+        for (int j = 0; j < CH / 8; j++) {
+            const uint4 v = ((const uint4 *)s)[j];
+            out[4 * j + 0] = min_u16x2(v.x, lim2);
+            out[4 * j + 1] = min_u16x2(v.y, lim2);
+            out[4 * j + 2] = min_u16x2(v.z, lim2);
+            out[4 * j + 3] = min_u16x2(v.w, lim2);
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < CH; k += 2) {
+            const uint32_t lo = (k < nv) ? min((uint32_t)s[k], lim) : sink;
+            const uint32_t hi = (k + 1 < nv) ? min((uint32_t)s[k + 1], lim) : sink;
+            out[k >> 1] = lo | (hi << 16);
+        }
+    }
+}
+
+// LDS by absolute address.  The kernel declares no static LDS, so its dynamic
+// LDS starts at address 0 and a layout offset is the address itself; the line
+// pass uses these so that a table offset held in a register needs no base add.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+static __device__ __forceinline__ lds_u32 *lds32(uint32_t a) { return (lds_u32 *)(size_t)a; }
+static __device__ __forceinline__ lds_u16 *lds16(uint32_t a) { return (lds_u16 *)(size_t)a; }
+
+// One line of the aisle pass: `ls` is its scaled location, `tb` the byte
+// offset of its tour's row.
+static __device__ __forceinline__ void line_update(uint32_t ls, uint32_t tb, uint32_t magic)
+{
+    const uint32_t a = mulhi24(ls, magic);
+    __hip_atomic_fetch_or(lds32(LDS_REGION + 4u + tb + ((a >> 5) << 2)), 1u << (a & 31u), __ATOMIC_RELAXED,
+                          __HIP_MEMORY_SCOPE_WORKGROUP);
+    __hip_atomic_fetch_max(lds32(LDS_REGION + tb), ls, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 template <int BLOCK>
-__global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
+__global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
-    __shared__ uint32_t s_next;
+    uint32_t &s_next = *(uint32_t *)(smem + LDS_TICKET);
     constexpr int SEQ_CHUNK = 4096 / BLOCK;  // sequence positions per thread kept in registers
     const int tid = threadIdx.x;
     const int lane = tid & 63;
-    int loaded = -1;                        // instance whose count table sits in LDS
+    int loaded = -1;                        // instance whose tables sit in LDS
 
     // work items: a grid stride, or a queue (atomic ticket) over a work order
     // that puts the most expensive plans first
@@ -174,50 +217,58 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
         const uint32_t n_units = (uint32_t)I.n_units;
         const int64_t row = p - (A.n_inst > 1 ? A.plan_begin[ii] : 0);
         const uint16_t *seq = A.seq + A.seq_base[ii] + row * (int64_t)n;
-        const uint2 *lines = A.lines + I.line_off;
         const EvalLayout Ly = eval_layout(n, I.n_units, I.words, I.t_cap);
-        uint32_t *zs = (uint32_t *)(smem + Ly.zs);
-        int64_t *red = (int64_t *)(smem + Ly.red);
+        uint32_t *zs = (uint32_t *)(smem + LDS_ZS);
+        uint32_t *scan_a = (uint32_t *)(smem + Ly.red);
+        uint32_t *scan_b = scan_a + 16;
+        int64_t *sum_slot = (int64_t *)(smem + Ly.red + 128);
         int *misc = (int *)(smem + Ly.misc);
         uint32_t *lane_base = (uint32_t *)(smem + Ly.seg);
         uint32_t *wbits = lane_base + (MAX_SEG + 1);
         uint32_t *true_lane = wbits + (MAX_SEG + 1);
         uint32_t *segs = true_lane + (MAX_SEG + 1);
         uint8_t *cnt = (uint8_t *)(smem + Ly.cnt);
-        uint32_t *F = (uint32_t *)(smem + Ly.F);
         uint16_t *tour = (uint16_t *)(smem + Ly.tour);
         uint32_t *B = (uint32_t *)(smem + Ly.B);
-        uint32_t *prefB = (uint32_t *)(smem + Ly.prefB);
+        uint32_t *F = (uint32_t *)(smem + Ly.F);
         uint16_t *crec = (uint16_t *)(smem + Ly.rec);
         uint32_t *cnrec = (uint32_t *)(smem + Ly.nrec);
         uint32_t *cnxt = (uint32_t *)(smem + Ly.nxt);
-        uint32_t *mask = (uint32_t *)(smem + Ly.mask);
-        uint32_t *mx = (uint32_t *)(smem + Ly.mx);
-        const uint32_t nB = bitmap_words(I.n_units);
-        const int nF = (n + 31) / 32 + 1;
+        uint32_t *cand = (uint32_t *)(smem + Ly.cand);
+        const int T = I.t_cap;
+        const uint32_t RB = row_bytes(I.words);
+        const uint32_t dummy = (uint32_t)T * RB;          // byte offset of the dummy row
         int bad = 0;
 
-        // ---- staging: count table, cleared bitmaps ------------------------
+        // ---- staging: per-instance tables, cleared bitmaps -----------------
         if (ii != loaded) {
             const uint4 *src = (const uint4 *)(A.cnt + I.cnt_off);
             uint4 *dst = (uint4 *)cnt;
-            for (int k = tid; k < (n + 15) / 16; k += BLOCK) dst[k] = src[k];
+            for (int k = tid; k < (int)(cnt_bytes(n) / 16); k += BLOCK) dst[k] = src[k];
+            // every tour entry starts at the dummy row, so that an entry a
+            // malformed sequence leaves unwritten still points inside the tile
+            for (int k = tid; k < n + 2; k += BLOCK) tour[k] = (uint16_t)dummy;
             loaded = ii;
         }
-        for (uint32_t w = tid; w < nB; w += BLOCK) B[w] = 0;
-        for (int w = tid; w < nF; w += BLOCK) F[w] = 0;
+        {
+            uint4 *bf = (uint4 *)B;
+            const int nbf = (int)((Ly.total - Ly.B) / 16);
+            for (int k = tid; k < nbf; k += BLOCK) bf[k] = make_uint4(0u, 0u, 0u, 0u);
+        }
         if (tid < 16) misc[tid] = 0;
 
         // ---- 1. zone starts (wave 0) -------------------------------------
         if (tid < 64) {
             const uint32_t zc = have_pf ? zc_pf : ((lane < C) ? (uint32_t)A.zone_of[p * 64 + lane] : 0xFFu);
             const uint32_t sz = (lane < C) ? (uint32_t)I.cat_size[lane] : 0u;
-            uint32_t start = 0;
-            for (int c2 = 0; c2 < C; c2++) {
-                const uint32_t z2 = (uint32_t)__builtin_amdgcn_readlane((int)zc, c2);
-                const uint32_t s2 = (uint32_t)__builtin_amdgcn_readlane((int)sz, c2);
-                start += (z2 < zc) ? s2 : 0u;
-            }
+            // lanes past C send a zero size to their own lane, so a valid row
+            // fills every lane exactly once
+            const uint32_t zl = (lane < C) ? (zc & 63u) : (uint32_t)lane;
+            const uint32_t by_zone = (uint32_t)__builtin_amdgcn_ds_permute((int)(zl << 2), (int)sz);
+            const uint32_t incl = wave_incl_scan(by_zone);
+            uint32_t start = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(zl << 2), (int)(incl - by_zone));
+            // a malformed row cannot move a category off the warehouse
+            start = min(start, (uint32_t)I.n_skus - sz);
             zs[lane] = (start << I.shift) - ((uint32_t)(4 * lane) << 24);
             if (A.validate) {
                 uint64_t m = (lane < C && zc < 64u) ? (1ull << zc) : 0ull;
@@ -231,364 +282,376 @@ __global__ __launch_bounds__(BLOCK) void eval_plans_kernel(EvalArgs A)
         // ---- 2. unit bitmap of order starts --------------------------------
         const int ch = (n + BLOCK - 1) / BLOCK;
         const int b0 = min(n, tid * ch), b1 = min(n, b0 + ch);
+        const int nv = b1 - b0;
         const bool one_piece = ch <= SEQ_CHUNK;          // uniform
         uint32_t svp[SEQ_CHUNK / 2];                    // the chunk's order ids, two per register
+        uint32_t cs[SEQ_CHUNK];                         // their clamped sizes
         if (one_piece) {
+            if (have_pf) {
 #pragma unroll
-            for (int k = 0; k < SEQ_CHUNK; k++) {
-                const int i = b0 + k;
-                uint32_t o = (i < b1) ? (have_pf ? ((sv_pf[k >> 1] >> (16 * (k & 1))) & 0xFFFFu) : (uint32_t)seq[i]) : 0u;
-                if (o >= (uint32_t)n) { bad = 1; o = (uint32_t)(n - 1); }
-                if (k & 1) svp[k >> 1] |= o << 16; else svp[k >> 1] = o;
+                for (int k = 0; k < SEQ_CHUNK / 2; k++) svp[k] = sv_pf[k];
+            } else {
+                load_chunk<SEQ_CHUNK>(seq + b0, nv, (uint32_t)n, svp);
             }
         }
+        have_pf = false;
 #define SV(k) ((svp[(k) >> 1] >> (16 * ((k) & 1))) & 0xFFFFu)
-        __syncthreads();                                 // count table, zeroed bitmaps
+        __syncthreads();                                 // tables, zeroed bitmaps, zone starts
         const int64_t next_item = A.queue ? (int64_t)s_next : item + (int64_t)gridDim.x;
-        int local = 0, big = 0;
+        uint32_t local = 0, cmax = 0;
         if (one_piece) {
 #pragma unroll
             for (int k = 0; k < SEQ_CHUNK; k++) {
-                if (b0 + k < b1) {
-                    const int c = cnt[SV(k)];
-                    local += c;
-                    big |= c > (int)Q;
-                }
+                cs[k] = cnt[SV(k)];
+                local += cs[k];
+                cmax = max(cmax, cs[k]);
             }
         } else {
             for (int i = b0; i < b1; i++) {
-                uint32_t o = seq[i];
-                if (o >= (uint32_t)n) { bad = 1; o = (uint32_t)(n - 1); }
-                const int c = cnt[o];
+                const uint32_t c = cnt[min((uint32_t)seq[i], (uint32_t)(n - 1))];
                 local += c;
-                big |= c > (int)Q;
+                cmax = max(cmax, c);
             }
         }
-        int total_units;
-        uint32_t run = (uint32_t)block_excl_scan<BLOCK>(local, (int *)red, &total_units);
-        {
-            uint32_t cur = run >> 5, acc = 0;
-            if (one_piece) {
-#pragma unroll
-                for (int k = 0; k < SEQ_CHUNK; k++) {
-                    if (b0 + k < b1) {
-                        const uint32_t w = run >> 5;
-                        if (w != cur) { atomicOr(&B[cur], acc); acc = 0; cur = w; }
-                        acc |= 1u << (run & 31u);
-                        run += cnt[SV(k)];
-                    }
-                }
-            } else {
-                for (int i = b0; i < b1; i++) {
-                    uint32_t o = seq[i];
-                    if (o >= (uint32_t)n) o = (uint32_t)(n - 1);
-                    const uint32_t w = run >> 5;
-                    if (w != cur) { atomicOr(&B[cur], acc); acc = 0; cur = w; }
-                    acc |= 1u << (run & 31u);
-                    run += cnt[o];
-                }
-            }
-            if (acc) atomicOr(&B[cur], acc);
-        }
-        if (tid == 0) atomicOr(&B[n_units >> 5], 1u << (n_units & 31u));   // sentinel
-        if (big) misc[0] = 1;
+        uint32_t total_units;
+        const uint32_t run0 = block_excl_scan<BLOCK>(local, scan_a, &total_units);
+        // a malformed sequence can change the unit total; such a plan is not
+        // evaluated (its result is unspecified) and no bitmap is written
+        const bool units_ok = total_units == n_units;   // uniform
         if (A.validate) {
             // permutation check: mark every order once (bitmap in the region)
-            uint32_t *seen = (uint32_t *)(smem + Ly.region);
+            uint32_t *seen = (uint32_t *)(smem + LDS_REGION);
             for (int w = tid; w < (n + 31) / 32; w += BLOCK) seen[w] = 0;
             __syncthreads();
             for (int i = tid; i < n; i += BLOCK) {
                 const uint32_t o = seq[i];
-                if (o >= (uint32_t)n) continue;
+                if (o >= (uint32_t)n) { bad = 1; continue; }
                 const uint32_t old = atomicOr(&seen[o >> 5], 1u << (o & 31));
                 if (old & (1u << (o & 31))) bad = 1;
             }
+            if (!units_ok) bad = 1;
         }
-        __syncthreads();
-        {   // prefix popcounts of B (word granularity)
-            const int wch = ((int)nB + BLOCK - 1) / BLOCK;
-            const int w0 = min((int)nB, tid * wch), w1 = min((int)nB, w0 + wch);
-            int c = 0;
-            for (int w = w0; w < w1; w++) c += __popc(B[w]);
-            int tot;
-            int r = block_excl_scan<BLOCK>(c, (int *)red, &tot);
-            for (int w = w0; w < w1; w++) {
-                prefB[w] = (uint32_t)r;
-                r += __popc(B[w]);
-            }
-        }
-
-        // ---- 3. segments and their candidate entries (wave 0) ------------
-        int G = (misc[0] || I.n_seg <= 1) ? 1 : I.n_seg;   // uniform
-        if (G > 1 && tid < 64) {
-            const int g = lane;
-            const uint32_t s_g = (uint32_t)(((uint64_t)g * n_units) / (uint32_t)G);
-            uint32_t c = 0, wb = 0;
-            if (g == 0) {
-                c = 1;
-            } else if (g < G) {
-                const uint32_t lim = n_units - s_g;   // candidates are order starts < n_units
-                wb = bits_at(B, s_g) & maskQ;
-                if (lim < 32u) wb &= (1u << lim) - 1u;
-                c = __popc(wb);
-            }
-            uint32_t inc = c;
+        int64_t acc = 0;
+        if (units_ok) {
+            if (one_piece) {
+                // positions past the chunk have size 0 and set the next
+                // chunk's first bit (or the sentinel) again
+                uint32_t run = run0;
 #pragma unroll
-            for (int d = 1; d < 64; d <<= 1) {
-                const uint32_t t = __shfl_up(inc, d, 64);
-                if (lane >= d) inc += t;
-            }
-            lane_base[g] = inc - c;
-            wbits[g] = wb;
-            segs[g] = g <= G ? s_g : n_units;
-            if (g == 63) misc[1] = (int)inc;          // total chase lanes
-        }
-        if (G > 1 && tid == 0) segs[G] = n_units;
-        __syncthreads();
-        if (G > 1 && misc[1] > CHASE_LANES) G = 1;    // uniform
-
-        // ---- 4. chase ------------------------------------------------------
-        if (G > 1) {
-            const int L_tot = misc[1];
-            for (int l = tid; l < L_tot; l += BLOCK) {
-                int lo = 0, hi = G - 1;                  // segment of lane l
-                while (lo < hi) {
-                    const int mid = (lo + hi + 1) >> 1;
-                    if ((int)lane_base[mid] <= l) lo = mid; else hi = mid - 1;
-                }
-                const int g = lo;
-                const uint32_t s_g = segs[g];
-                const uint32_t s_e = segs[g + 1];
-                uint32_t x = s_g;
-                if (g > 0) {
-                    uint32_t wb = wbits[g];
-                    for (int k = l - (int)lane_base[g]; k > 0; k--) wb &= wb - 1u;
-                    x = s_g + (uint32_t)__builtin_ctz(wb);
-                }
-                uint16_t *r = crec + l * CHASE_RECS;
-                uint32_t nr = 0;
-                r[nr++] = (uint16_t)(x - s_g);
-                for (;;) {
-                    x = next_open(B, x, maskQ);
-                    if (x >= s_e) break;
-                    if (nr == CHASE_RECS) { misc[2] = 1; break; }
-                    r[nr++] = (uint16_t)(x - s_g);
-                }
-                cnrec[l] = nr;
-                // the lane of the next segment whose candidate is this exit
-                uint32_t nx = 0xFFFFFFFFu;
-                if (g + 1 < G) {
-                    const uint32_t off = x - s_e;
-                    const uint32_t wb = wbits[g + 1];
-                    if (off < 32u && ((wb >> off) & 1u))
-                        nx = lane_base[g + 1] + __popc(wb & ((1u << off) - 1u));
-                }
-                cnxt[l] = nx;
-            }
-            __syncthreads();
-            // ---- link the true entries, segment after segment ------------
-            if (tid == 0 && !misc[2]) {
-                uint32_t l = 0;
-                for (int g = 0; g < G; g++) {
-                    true_lane[g] = l;
-                    if (g + 1 < G) {
-                        l = cnxt[l];
-                        if (l == 0xFFFFFFFFu) { misc[2] = 1; break; }
-                    }
-                }
-            }
-            __syncthreads();
-            if (!misc[2]) {
-                for (int idx = tid; idx < G * CHASE_RECS; idx += BLOCK) {
-                    const int g = idx / CHASE_RECS, k = idx % CHASE_RECS;
-                    const uint32_t l = true_lane[g];
-                    if ((uint32_t)k < cnrec[l]) {
-                        const uint32_t x = segs[g] + crec[l * CHASE_RECS + k];
-                        const uint32_t i = rank_of(B, prefB, x);
-                        atomicOr(&F[i >> 5], 1u << (i & 31u));
-                    }
+                for (int k = 0; k < SEQ_CHUNK; k++) {
+                    atomicOr(&B[run >> 5], 1u << (run & 31u));
+                    run += cs[k];
                 }
             } else {
-                G = 1;                                   // fall back to the serial chain
-            }
-        }
-        if (G == 1) {
-            // serial chain (also handles orders larger than the capacity)
-            if (tid == 0) {
-                uint32_t x = 0;
-                while (x < n_units) {
-                    const uint32_t i = rank_of(B, prefB, x);
-                    F[i >> 5] |= 1u << (i & 31u);
-                    const uint32_t win = bits_at(B, x + 1) & maskQ;
-                    if (win) {
-                        x = x + 32u - ffbh(win);
-                    } else {                             // an order larger than Q: its own tour
-                        uint32_t y = x + 1;
-                        while (!((B[y >> 5] >> (y & 31u)) & 1u)) y++;
-                        x = y;
-                    }
+                uint32_t run = run0;
+                for (int i = b0; i < b1; i++) {
+                    atomicOr(&B[run >> 5], 1u << (run & 31u));
+                    run += cnt[min((uint32_t)seq[i], (uint32_t)(n - 1))];
                 }
             }
-        }
-        __syncthreads();
-
-        // ---- tour id of every order --------------------------------------
-        int n_tours;
-        int trun = block_excl_scan<BLOCK>(count_range(F, b0, b1), (int *)red, &n_tours) - 1;
-        if (one_piece) {
-#pragma unroll
-            for (int k = 0; k < SEQ_CHUNK; k++) {
-                const int i = b0 + k;
-                if (i < b1) {
-                    trun += (F[i >> 5] >> (i & 31)) & 1u;
-                    tour[SV(k)] = (uint16_t)trun;
-                }
-            }
-        } else {
-            for (int i = b0; i < b1; i++) {
-                uint32_t o = seq[i];
-                if (o >= (uint32_t)n) o = (uint32_t)(n - 1);
-                trun += (F[i >> 5] >> (i & 31)) & 1u;
-                tour[o] = (uint16_t)trun;
-            }
-        }
-        __syncthreads();
-
-        // ---- prefetch of the next plan's inputs ---------------------------
-        have_pf = false;
-        if (next_item < A.n_plans) {
-            const int64_t pn = A.work ? (int64_t)A.work[next_item] : next_item;
-            const int iin = instance_of(A, pn);
-            const InstDev &In = A.inst[iin];
-            const int nn = In.n_orders;
-            const int chn = (nn + BLOCK - 1) / BLOCK;
-            if (chn <= SEQ_CHUNK) {                      // uniform
-                const uint16_t *seqn = A.seq + A.seq_base[iin] + (pn - (A.n_inst > 1 ? A.plan_begin[iin] : 0)) * (int64_t)nn;
-                const int c0 = min(nn, tid * chn), c1 = min(nn, c0 + chn);
-#pragma unroll
-                for (int k = 0; k < SEQ_CHUNK; k += 2) {
-                    const uint32_t lo = (c0 + k < c1) ? (uint32_t)seqn[c0 + k] : 0u;
-                    const uint32_t hi = (c0 + k + 1 < c1) ? (uint32_t)seqn[c0 + k + 1] : 0u;
-                    sv_pf[k >> 1] = lo | (hi << 16);
-                }
-                zc_pf = (tid < 64 && lane < In.n_cat) ? (uint32_t)A.zone_of[pn * 64 + lane] : 0xFFu;
-                have_pf = true;
-            }
-        }
-
-        // ---- 5./6. aisle sets and S-shape per tour tile ------------------
-        const int W = I.words;
-        const int T = I.t_cap;
-        const uint32_t magic = I.magic;
-        const int n_lines = I.n_lines;
-        int64_t acc = 0;
-        for (int t0 = 0; t0 < n_tours; t0 += T) {
-            for (int k = tid; k < W * T; k += BLOCK) mask[k] = 0;
-            for (int k = tid; k < T; k += BLOCK) mx[k] = 0;
+            if (tid == 0) atomicOr(&B[n_units >> 5], 1u << (n_units & 31u));   // sentinel
+            if (cmax > Q) misc[0] = 1;
             __syncthreads();
-            if (A.main_mode == 0) {
-                // one line per lane, 8 coalesced loads in flight per thread
-                constexpr int U = 8;
-                for (int q0 = tid; q0 < n_lines; q0 += U * BLOCK) {
-                    uint2 v[U];
-#pragma unroll
-                    for (int u = 0; u < U; u++) {
-                        const int q = q0 + u * BLOCK;
-                        v[u] = (q < n_lines) ? lines[q] : make_uint2(0u, 0xFFFFFFFFu);
+
+            // ---- 3. segments and their candidate entries (wave 0) --------
+            int G = (misc[0] || I.n_seg <= 1) ? 1 : I.n_seg;   // uniform
+            if (G > 1 && tid < 64) {
+                const int g = lane;
+                const uint32_t s_g = (uint32_t)(((uint64_t)g * n_units) / (uint32_t)G);
+                uint32_t wb = 0;
+                if (g == 0) {
+                    wb = 1u;                          // the tour opened at unit 0
+                } else if (g < G) {
+                    const uint32_t lim = n_units - s_g;   // candidates are order starts < n_units
+                    wb = bits_at(B, s_g) & maskQ;
+                    if (lim < 32u) wb &= (1u << lim) - 1u;
+                }
+                const uint32_t c = __popc(wb);
+                const uint32_t inc = wave_incl_scan(c);
+                const uint32_t base = inc - c;
+                const uint32_t lanes = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
+                lane_base[g] = base;
+                wbits[g] = wb;
+                segs[g] = g <= G ? s_g : n_units;
+                if (lanes <= (uint32_t)CHASE_LANES) {
+                    uint32_t m = wb, idx = base;
+                    while (m) {
+                        cand[idx++] = ((uint32_t)g << 26) | (s_g + (uint32_t)__builtin_ctz(m));
+                        m &= m - 1u;
                     }
-#pragma unroll
-                    for (int u = 0; u < U; u++) {
-                        if (v[u].y != 0xFFFFFFFFu) {
-                            const uint32_t t = (uint32_t)tour[v[u].y] - (uint32_t)t0;
-                            if (t < (uint32_t)T) {
-                                const uint32_t r = v[u].x;
-                                const uint32_t ls = r + zs[r >> 26];
-                                const uint32_t a = mulhi24(ls, magic);
-                                atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
-                                atomicMax(&mx[t], ls);
-                            }
+                }
+                if (g == 0) misc[1] = (int)lanes;
+            }
+            __syncthreads();
+            if (G > 1 && misc[1] > CHASE_LANES) G = 1;    // uniform
+
+            // ---- 4. chase ---------------------------------------------------
+            if (G > 1) {
+                const int L_tot = misc[1];
+                for (int l = tid; l < L_tot; l += BLOCK) {
+                    const uint32_t cv = cand[l];
+                    const int g = (int)(cv >> 26);
+                    uint32_t x = cv & 0x3FFFFFFu;
+                    const uint32_t s_g = segs[g];
+                    const uint32_t s_e = segs[g + 1];
+                    uint16_t *r = crec + l * CHASE_RECS;
+                    uint32_t nr = 0;
+                    r[nr++] = (uint16_t)(x - s_g);
+                    for (;;) {
+                        x = next_open(B, x, maskQ);
+                        if (x >= s_e) break;
+                        if (nr == CHASE_RECS) { misc[2] = 1; break; }
+                        r[nr++] = (uint16_t)(x - s_g);
+                    }
+                    cnrec[l] = nr;
+                    // the lane of the next segment whose candidate is this exit
+                    uint32_t nx = 0xFFFFFFFFu;
+                    if (g + 1 < G) {
+                        const uint32_t off = x - s_e;
+                        const uint32_t wb = wbits[g + 1];
+                        if (off < 32u && ((wb >> off) & 1u))
+                            nx = lane_base[g + 1] + __popc(wb & ((1u << off) - 1u));
+                    }
+                    cnxt[l] = nx;
+                }
+                __syncthreads();
+                // ---- link the true entries, segment after segment --------
+                if (tid == 0 && !misc[2]) {
+                    uint32_t l = 0;
+                    for (int g = 0; g < G; g++) {
+                        true_lane[g] = l;
+                        if (g + 1 < G) {
+                            l = cnxt[l];
+                            if (l == 0xFFFFFFFFu) { misc[2] = 1; break; }
                         }
                     }
                 }
-            } else {
-                // one order per lane: its tour looked up once, its farthest
-                // location kept in a register, the zone start of each line
-                // taken from the wave's copy of the table by lane permute.
-                // The next group's order ids and first 8 line records are
-                // loaded while the current group is processed.
-                constexpr int PF = 8;
-                const int zsv = (int)zs[lane];
-                const uint32_t *grec = A.grec + I.grec_off;
-                const uint32_t *gbase = A.gbase + I.gbase_off;
-                const uint16_t *gord = A.gord + I.gord_off;
-                const int gstep = BLOCK / 64;
-                int g = tid >> 6;
-                uint32_t o_n = 0xFFFFu, b_n = 0, L_n = 0, r_n[PF];
-                if (g < I.n_grp) {
-                    o_n = gord[g * 64 + lane];
-                    b_n = gbase[g];
-                    L_n = (gbase[g + 1] - b_n) >> 6;
-#pragma unroll
-                    for (int u = 0; u < PF; u++) r_n[u] = (uint32_t)u < L_n ? grec[b_n + u * 64 + lane] : 0u;
+                __syncthreads();
+                if (!misc[2]) {
+                    for (int idx = tid; idx < G * CHASE_RECS; idx += BLOCK) {
+                        const int g = idx / CHASE_RECS, k = idx % CHASE_RECS;
+                        const uint32_t l = true_lane[g];
+                        if ((uint32_t)k < cnrec[l]) {
+                            const uint32_t x = segs[g] + crec[l * CHASE_RECS + k];
+                            atomicOr(&F[x >> 5], 1u << (x & 31u));
+                        }
+                    }
+                } else {
+                    G = 1;                               // fall back to the serial chain
                 }
-                while (g < I.n_grp) {
-                    const uint32_t o = o_n, b0g = b_n, L = L_n;
-                    uint32_t r[PF];
+            }
+            if (G == 1) {
+                // serial chain (also handles orders larger than the capacity)
+                if (tid == 0) {
+                    uint32_t x = 0;
+                    while (x < n_units) {
+                        F[x >> 5] |= 1u << (x & 31u);
+                        const uint32_t win = bits_at(B, x + 1) & maskQ;
+                        if (win) {
+                            x = x + 32u - ffbh(win);
+                        } else {                         // an order larger than Q: its own tour
+                            uint32_t y = x + 1;
+                            while (!((B[y >> 5] >> (y & 31u)) & 1u)) y++;
+                            x = y;
+                        }
+                    }
+                }
+            }
+            __syncthreads();
+
+            // ---- tour ids; tour entries for the first tile -------------------
+            uint32_t opm = 0;                            // bit k: position b0 + k opens a tour
+            uint32_t n_open = 0;
+            if (one_piece) {
+                uint32_t run = run0;
 #pragma unroll
-                    for (int u = 0; u < PF; u++) r[u] = r_n[u];
-                    const int gn = g + gstep;
-                    if (gn < I.n_grp) {
-                        o_n = gord[gn * 64 + lane];
-                        b_n = gbase[gn];
-                        L_n = (gbase[gn + 1] - b_n) >> 6;
+                for (int k = 0; k < SEQ_CHUNK; k++) {
+                    opm |= ((F[run >> 5] >> (run & 31u)) & 1u) << k;
+                    run += cs[k];
+                }
+                if (nv < 32) opm &= (1u << nv) - 1u;
+                n_open = __popc(opm);
+            } else {
+                uint32_t run = run0;
+                for (int i = b0; i < b1; i++) {
+                    n_open += (F[run >> 5] >> (run & 31u)) & 1u;
+                    run += cnt[min((uint32_t)seq[i], (uint32_t)(n - 1))];
+                }
+            }
+            // the rows of the tile are free once the flags are set
+            {
+                uint4 *rows = (uint4 *)(smem + LDS_REGION);
+                const int nr4 = (int)((RB * (uint32_t)(T + 1) + 15u) / 16u);
+                for (int k = tid; k < nr4; k += BLOCK) rows[k] = make_uint4(0u, 0u, 0u, 0u);
+            }
+            uint32_t n_tours;
+            const uint32_t first_tour = block_excl_scan<BLOCK>(n_open, scan_b, &n_tours);
+            // entry of the order at a position: its tour's row, or the dummy
+            // row for tours outside the tile [t0, t0 + T)
+            // (later tiles re-derive the tour ids from the sequence in memory)
+            auto write_entries = [&](uint32_t t0, bool from_regs) {
+                uint32_t t = first_tour - 1u;            // wraps; a store always follows an opening
+                if (from_regs) {
+#pragma unroll
+                    for (int k = 0; k < SEQ_CHUNK; k++) {
+                        t += (opm >> k) & 1u;
+                        const uint32_t rel = t - t0;
+                        tour[SV(k)] = (uint16_t)(rel < (uint32_t)T ? rel * RB : dummy);
+                    }
+                } else {
+                    uint32_t run = run0;
+                    for (int i = b0; i < b1; i++) {
+                        const uint32_t o = min((uint32_t)seq[i], (uint32_t)(n - 1));
+                        t += (F[run >> 5] >> (run & 31u)) & 1u;
+                        run += cnt[o];
+                        const uint32_t rel = t - t0;
+                        tour[o] = (uint16_t)(rel < (uint32_t)T ? rel * RB : dummy);
+                    }
+                }
+            };
+            write_entries(0u, one_piece);
+            __syncthreads();
+
+            // ---- prefetch of the next plan's inputs -----------------------
+            if (next_item < A.n_plans) {
+                const int64_t pn = A.work ? (int64_t)A.work[next_item] : next_item;
+                const int iin = instance_of(A, pn);
+                const InstDev &In = A.inst[iin];
+                const int nn = In.n_orders;
+                const int chn = (nn + BLOCK - 1) / BLOCK;
+                if (chn <= SEQ_CHUNK) {                  // uniform
+                    const uint16_t *seqn =
+                        A.seq + A.seq_base[iin] + (pn - (A.n_inst > 1 ? A.plan_begin[iin] : 0)) * (int64_t)nn;
+                    const int c0 = min(nn, tid * chn), c1 = min(nn, c0 + chn);
+                    load_chunk<SEQ_CHUNK>(seqn + c0, c1 - c0, (uint32_t)nn, sv_pf);
+                    zc_pf = (tid < 64 && lane < In.n_cat) ? (uint32_t)A.zone_of[pn * 64 + lane] : 0xFFu;
+                    have_pf = true;
+                }
+            }
+
+            // ---- 5./6. aisle sets and S-shape per tour tile ------------------
+            const uint32_t magic = I.magic;
+            for (uint32_t t0 = 0; t0 < n_tours; t0 += (uint32_t)T) {
+                if (t0 > 0) {
+                    __syncthreads();                     // the previous tile's rows are read
+                    write_entries(t0, false);
+                    uint4 *rows = (uint4 *)(smem + LDS_REGION);
+                    const int nr4 = (int)((RB * (uint32_t)(T + 1) + 15u) / 16u);
+                    for (int k = tid; k < nr4; k += BLOCK) rows[k] = make_uint4(0u, 0u, 0u, 0u);
+                    __syncthreads();
+                }
+                if (A.main_mode == 0) {
+                    // one line per lane, 8 coalesced loads in flight per thread;
+                    // the records are padded to a multiple of the block
+                    constexpr int U = 8;
+                    const uint2 *lines = A.lines + I.line_off;
+                    const int n_pad = I.n_lines_pad;
+                    int base = 0;                        // uniform
+                    for (; base + U * BLOCK <= n_pad; base += U * BLOCK) {
+                        const uint2 *lp = lines + base + tid;
+                        uint2 v[U];
+                        uint32_t tb[U], zv[U];
+#pragma unroll
+                        for (int u = 0; u < U; u++) v[u] = lp[u * BLOCK];
+                        // all table reads of the group before its atomics
+#pragma unroll
+                        for (int u = 0; u < U; u++) {
+                            tb[u] = *lds16(v[u].y);
+                            zv[u] = *lds32(LDS_ZS + (v[u].x >> 24));
+                        }
+#pragma unroll
+                        for (int u = 0; u < U; u++) line_update(v[u].x + zv[u], tb[u], magic);
+                    }
+                    for (; base < n_pad; base += BLOCK) {
+                        const uint2 v = lines[base + tid];
+                        line_update(v.x + *lds32(LDS_ZS + (v.x >> 24)), *lds16(v.y), magic);
+                    }
+                } else {
+                    // one order per lane: its row looked up once, its farthest
+                    // location kept in a register, the zone start of each line
+                    // taken from the wave's copy of the table by lane permute.
+                    // The next group's order ids and first 8 line records are
+                    // loaded while the current group is processed.
+                    constexpr int PF = 8;
+                    const int zsv = (int)zs[lane];
+                    const uint32_t *grec = A.grec + I.grec_off;
+                    const uint32_t *gbase = A.gbase + I.gbase_off;
+                    const uint16_t *gord = A.gord + I.gord_off;
+                    const int gstep = BLOCK / 64;
+                    int g = tid >> 6;
+                    uint32_t o_n = 0xFFFFu, b_n = 0, L_n = 0, r_n[PF];
+                    if (g < I.n_grp) {
+                        o_n = gord[g * 64 + lane];
+                        b_n = gbase[g];
+                        L_n = (gbase[g + 1] - b_n) >> 6;
 #pragma unroll
                         for (int u = 0; u < PF; u++) r_n[u] = (uint32_t)u < L_n ? grec[b_n + u * 64 + lane] : 0u;
                     }
-                    const uint32_t t = (o != 0xFFFFu) ? (uint32_t)tour[o] - (uint32_t)t0 : 0xFFFFFFFFu;
-                    const bool active = t < (uint32_t)T;
-                    uint32_t far = 0;
+                    while (g < I.n_grp) {
+                        const uint32_t o = o_n, b0g = b_n, L = L_n;
+                        uint32_t r[PF];
 #pragma unroll
-                    for (int u = 0; u < PF; u++) {
-                        if ((uint32_t)u < L) {
-                            const uint32_t ls = r[u] + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(r[u] >> 24), zsv);
+                        for (int u = 0; u < PF; u++) r[u] = r_n[u];
+                        const int gn = g + gstep;
+                        if (gn < I.n_grp) {
+                            o_n = gord[gn * 64 + lane];
+                            b_n = gbase[gn];
+                            L_n = (gbase[gn + 1] - b_n) >> 6;
+#pragma unroll
+                            for (int u = 0; u < PF; u++)
+                                r_n[u] = (uint32_t)u < L_n ? grec[b_n + u * 64 + lane] : 0u;
+                        }
+                        const uint32_t tb = (o != 0xFFFFu) ? (uint32_t)tour[o] : dummy;
+                        uint32_t far = 0;
+#pragma unroll
+                        for (int u = 0; u < PF; u++) {
+                            if ((uint32_t)u < L) {
+                                const uint32_t ls =
+                                    r[u] + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(r[u] >> 24), zsv);
+                                const uint32_t a = mulhi24(ls, magic);
+                                __hip_atomic_fetch_or(lds32(LDS_REGION + 4u + tb + ((a >> 5) << 2)), 1u << (a & 31u),
+                                                      __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                                far = max(far, ls);
+                            }
+                        }
+                        for (uint32_t kk = PF; kk < L; kk++) {     // long orders
+                            const uint32_t rr = grec[b0g + kk * 64 + lane];
+                            const uint32_t ls = rr + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(rr >> 24), zsv);
                             const uint32_t a = mulhi24(ls, magic);
-                            if (active) atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
+                            __hip_atomic_fetch_or(lds32(LDS_REGION + 4u + tb + ((a >> 5) << 2)), 1u << (a & 31u),
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                             far = max(far, ls);
                         }
+                        __hip_atomic_fetch_max(lds32(LDS_REGION + tb), far, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        g = gn;
                     }
-                    for (uint32_t kk = PF; kk < L; kk++) {     // long orders
-                        const uint32_t rr = grec[b0g + kk * 64 + lane];
-                        const uint32_t ls = rr + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(rr >> 24), zsv);
-                        const uint32_t a = mulhi24(ls, magic);
-                        if (active) atomicOr(&mask[(a >> 5) * T + t], 1u << (a & 31));
-                        far = max(far, ls);
-                    }
-                    if (active) atomicMax(&mx[t], far);
-                    g = gn;
+                }
+                __syncthreads();
+                const int nt = (int)min((uint32_t)T, n_tours - t0);
+                const int W = I.words;
+                for (int t = tid; t < nt; t += BLOCK) {
+                    const uint32_t *rw = (const uint32_t *)(smem + LDS_REGION + (uint32_t)t * RB);
+                    const uint32_t ls = rw[0];
+                    int k = 0;
+                    for (int w = 0; w < W; w++) k += __popc(rw[1 + w]);
+                    const uint32_t a = mulhi24(ls, magic);
+                    const uint32_t j = (ls - a * I.d_s) >> (I.shift + 1);
+                    const int64_t y = (int64_t)j * I.pitch + I.pitch / 2;
+                    int64_t cost = 2ll * I.spacing * a;
+                    cost += (k & 1) ? (int64_t)(k - 1) * I.L + 2 * y : (int64_t)k * I.L;
+                    acc += cost;
                 }
             }
-            __syncthreads();
-            const int nt = min(T, n_tours - t0);
-            for (int t = tid; t < nt; t += BLOCK) {
-                int k = 0;
-                for (int w = 0; w < W; w++) k += __popc(mask[w * T + t]);
-                const uint32_t ls = mx[t];
-                const uint32_t a = mulhi24(ls, magic);
-                const uint32_t j = (ls - a * I.d_s) >> (I.shift + 1);
-                const int64_t y = (int64_t)j * I.pitch + I.pitch / 2;
-                int64_t cost = 2ll * I.spacing * a;
-                cost += (k & 1) ? (int64_t)(k - 1) * I.L + 2 * y : (int64_t)k * I.L;
-                acc += cost;
-            }
-            __syncthreads();
         }
-        const int64_t D = block_sum64<BLOCK>(acc, red);
+#undef SV
+        const int64_t D = block_sum64<BLOCK>(acc, sum_slot);
         if (A.validate && bad) atomicOr(A.err, 1);
         if (tid == 0) {
-            A.dist[p] = D > 2147483647ll ? 2147483647 : (int32_t)D;
-            if (A.thr) A.thr[p] = window_throughput(D, I);
+            const int64_t Dv = units_ok ? D : (int64_t)2147483647;
+            A.dist[p] = Dv > 2147483647ll ? 2147483647 : (int32_t)Dv;
+            if (A.thr) A.thr[p] = window_throughput(Dv, I);
         }
-        __syncthreads();
         item = next_item;
     }
 }
@@ -599,8 +662,7 @@ __global__ void reset_ticket_kernel(uint32_t *ctr) { *ctr = 0u; }
 template <int BLOCK>
 static hipError_t launch_eval_t(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
 {
-    // raise the dynamic LDS limit to what this launch needs (the kernel also
-    // holds a few bytes of static LDS, so the whole 160 KB cannot be asked for)
+    // raise the dynamic LDS limit to what this launch needs
     static uint32_t attr_bytes = 0;
     if (lds_bytes > attr_bytes) {
         hipError_t e = hipFuncSetAttribute((const void *)eval_plans_kernel<BLOCK>,

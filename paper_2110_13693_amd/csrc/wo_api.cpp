@@ -255,24 +255,19 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
             I.cat_size[c]++;
         }
 
-        I.line_off = (int64_t)lines.size();
+        // order sizes clamped to capacity + 1: an order larger than the
+        // capacity is a tour of its own whatever its size
         I.cnt_off = (int64_t)cnt.size();
         int64_t units = 0;
         for (int32_t o = 0; o < d.n_orders; o++) {
-            for (int32_t l = d.order_offsets[o]; l < d.order_offsets[o + 1]; l++) {
-                int32_t s = d.order_skus[l];
-                uint32_t c = (uint32_t)d.sku_category[s];
-                lines.push_back(make_uint2(((uint32_t)rank[s] << I.shift) | ((4u * c) << 24), (uint32_t)o));
-            }
-            // an order larger than the capacity is a tour of its own whatever
-            // its size, so sizes are clamped to capacity + 1 for the tour cut
-            int32_t sz = d.order_offsets[o + 1] - d.order_offsets[o];
-            int32_t u = std::min(sz, d.capacity + 1);
+            const int32_t u = std::min(d.order_offsets[o + 1] - d.order_offsets[o], d.capacity + 1);
             cnt.push_back((uint8_t)u);
             units += u;
         }
-        while (cnt.size() % 16) cnt.push_back(0);
+        // zeros for the dummy entry n and the sink entry n + 1, then padding
+        while (cnt.size() < (size_t)I.cnt_off + cnt_bytes(d.n_orders)) cnt.push_back(0);
         I.n_units = (int32_t)units;
+        I.n_skus = d.n_skus;
 
         // groups of 64 orders by descending size, lines stored line-major
         {
@@ -329,9 +324,11 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         I.n_seg = (g >= 2 && g >= g_recs && short_segs) ? g : 1;
 
         // tours per LDS tile: the expected tour count with margin (more tours
-        // take another pass over the lines), never more than the orders
+        // take another pass over the lines), never more than the orders, and
+        // few enough that a row's byte offset fits the 16-bit tour entries
         int64_t t_cap = (int64_t)std::ceil(1.1 * items / tour_items) + 32;
         t_cap = std::min<int64_t>(t_cap, d.n_orders);
+        t_cap = std::min<int64_t>(t_cap, 65535 / row_bytes(I.words) - 1);
         t_cap = std::max<int64_t>(t_cap, 1);
         EvalLayout ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap);
         while (ly.total > wh->lds_max && t_cap > 1) {
@@ -341,6 +338,22 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         I.t_cap = (int32_t)t_cap;
         if (ly.total > wh->lds_max)
             return fail(WO_E_RANGE, "instance %d: needs %u bytes of LDS, device has %u", i, ly.total, wh->lds_max);
+
+        // line records in instance order; y is the LDS byte offset of the
+        // order's tour entry in this instance's layout.  Padding records sit
+        // on the dummy entry (order n), whose row is never summed.
+        I.line_off = (int64_t)lines.size();
+        for (int32_t o = 0; o < d.n_orders; o++) {
+            for (int32_t l = d.order_offsets[o]; l < d.order_offsets[o + 1]; l++) {
+                const int32_t sk = d.order_skus[l];
+                const uint32_t c = (uint32_t)d.sku_category[sk];
+                lines.push_back(make_uint2(((uint32_t)rank[sk] << I.shift) | ((4u * c) << 24),
+                                           ly.tour + 2u * (uint32_t)o));
+            }
+        }
+        while ((lines.size() - (size_t)I.line_off) % LINE_PAD)
+            lines.push_back(make_uint2(0u, ly.tour + 2u * (uint32_t)d.n_orders));
+        I.n_lines_pad = (int32_t)(lines.size() - (size_t)I.line_off);
         wh->lds[i] = ly.total;
     }
 

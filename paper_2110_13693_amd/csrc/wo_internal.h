@@ -28,9 +28,13 @@ struct InstDev {
     int32_t L;              // slots_per_side * pitch
     int32_t t_cap;          // tours per LDS tile
     int32_t n_seg;          // item-space segments chased in parallel (1 = serial chain)
-    int32_t pad0;
-    int64_t line_off;       // uint2 line records [n_lines]: x = (rank << shift) | (4*cat) << 24, y = order id
-    int64_t cnt_off;        // u8 per order: min(size, capacity + 1) [n_orders], padded to 16 bytes
+    int32_t n_lines_pad;    // line records stored: n_lines rounded up to a multiple of LINE_PAD
+    // uint2 line records [n_lines_pad]: x = (rank << shift) | (4*cat) << 24,
+    // y = LDS byte offset of the order's tour entry (2 * order + the tour
+    // table's offset); the padding records point at the dummy entry of order
+    // n_orders, whose row absorbs them
+    int64_t line_off;
+    int64_t cnt_off;        // u8 per order: min(size, capacity + 1) [n_orders], zero-padded to 16 bytes past n_orders + 2
     // orders in groups of 64 by descending size (one order per lane): group g
     // holds lines [gbase[g], gbase[g+1]) of grec, line k of its lane j at
     // gbase[g] + 64 k + j (shorter orders repeat their first line); gord holds
@@ -39,7 +43,7 @@ struct InstDev {
     int64_t gbase_off;      // u32 [n_grp + 1], relative to grec_off
     int64_t gord_off;       // u16 [64 * n_grp]
     int32_t n_grp;
-    int32_t pad1;
+    int32_t n_skus;         // sum of the category sizes: a zone start never exceeds n_skus - size
     double walk;
     double t_item;
     double window;
@@ -73,15 +77,27 @@ struct EvalArgs {
 constexpr int CHASE_LANES = 256;
 constexpr int CHASE_RECS = 32;
 constexpr int MAX_SEG = 64;
+// line records are padded to a multiple of this (the largest block size), so
+// that the line pass needs no bounds checks
+constexpr int LINE_PAD = 512;
+// fixed LDS offsets: the zone-start table, the work-queue ticket, then the
+// region shared by the chase records and the per-tour rows (the kernel holds
+// no static LDS, so these are the addresses the instructions see)
+constexpr uint32_t LDS_ZS = 0;
+constexpr uint32_t LDS_TICKET = 256;
+constexpr uint32_t LDS_REGION = 272;
 
 // LDS layout of one evaluation block for an instance; host and device use the
-// same function so that the launch size and the kernel agree.  The chase
-// records and the per-tour aisle sets are used in different phases and share
-// one region.
+// same function so that the launch size, the line records' tour offsets and
+// the kernel agree.  The zone starts (64 words) sit at offset 0 and the shared
+// region at offset 272, so that the line pass addresses both with immediate
+// offsets.  The region holds, in turn: the permutation-check bitmap
+// (validation), the chase records, and the per-tour rows of one tile.  A row
+// is 1 + words 32-bit words: the tour's farthest scaled location, then its
+// aisle set; a tile has t_cap rows plus one dummy row.
 struct EvalLayout {
-    uint32_t zs, red, misc, seg, cnt, F, tour, B, prefB, region;
-    uint32_t rec, nrec, nxt;       // chase phase (inside region)
-    uint32_t mask, mx;             // tour phase (inside region)
+    uint32_t rec, nrec, nxt, cand;     // chase phase (inside the region)
+    uint32_t red, misc, seg, cnt, tour, B, F;
     uint32_t total;
 };
 
@@ -89,31 +105,33 @@ __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15
 
 __host__ __device__ inline uint32_t bitmap_words(int32_t n_units) { return ((uint32_t)n_units >> 5) + 3u; }
 
+__host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * (uint32_t)(words + 1); }
+
+// bytes of the cnt table (order sizes, then zeros for the dummy and sink entries)
+__host__ __device__ inline uint32_t cnt_bytes(int32_t n_orders) { return align16((uint32_t)n_orders + 2u); }
+
 __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_units, int32_t words,
                                                   int32_t t_cap)
 {
     EvalLayout L;
-    uint32_t n = (uint32_t)n_orders, nb = bitmap_words(n_units), b = 0;
-    L.zs = b;    b = align16(b + 64 * 4);
-    L.red = b;   b = align16(b + 16 * 8);
-    L.misc = b;  b = align16(b + 16 * 4);
-    L.seg = b;   b = align16(b + 4 * 4 * (MAX_SEG + 1));   // lane_base | wbits | true_lane | seg start
-    L.cnt = b;   b = align16(b + n);
-    L.F = b;     b = align16(b + 4 * ((n + 31) / 32 + 1));
-    L.tour = b;  b = align16(b + 2 * n);
-    L.B = b;     b = align16(b + 4 * nb);
-    L.prefB = b; b = align16(b + 4 * nb);
-    L.region = b;
-    uint32_t c = b;
+    const uint32_t n = (uint32_t)n_orders, nb = bitmap_words(n_units);
+    uint32_t c = LDS_REGION;
     L.rec = c;   c = align16(c + 2u * CHASE_LANES * CHASE_RECS);
     L.nrec = c;  c = align16(c + 4u * CHASE_LANES);
     L.nxt = c;   c = align16(c + 4u * CHASE_LANES);
-    uint32_t t = b;
-    L.mask = t;  t = align16(t + 4u * (uint32_t)words * (uint32_t)t_cap);
-    L.mx = t;    t = align16(t + 4u * (uint32_t)t_cap);
-    uint32_t v = b + 4u * (uint32_t)((n + 31) / 32);   // permutation check bitmap
-    L.total = c > t ? c : t;
-    if (v > L.total) L.total = align16(v);
+    L.cand = c;  c = align16(c + 4u * CHASE_LANES);
+    const uint32_t rows = align16(LDS_REGION + row_bytes(words) * (uint32_t)(t_cap + 1));
+    const uint32_t seen = align16(LDS_REGION + 4u * ((n + 31) / 32));
+    uint32_t b = c > rows ? c : rows;
+    if (seen > b) b = seen;
+    L.red = b;   b = align16(b + 2 * 16 * 4 + 8 * 8);   // two scan slots, one int64 reduction slot
+    L.misc = b;  b = align16(b + 16 * 4);
+    L.seg = b;   b = align16(b + 4 * 4 * (MAX_SEG + 1));   // lane_base | wbits | true_lane | seg start
+    L.cnt = b;   b += cnt_bytes(n_orders);
+    L.tour = b;  b = align16(b + 2 * (n + 2));            // + dummy entry n, sink entry n + 1
+    L.B = b;     b = align16(b + 4 * nb);
+    L.F = b;     b = align16(b + 4 * nb);
+    L.total = b;
     return L;
 }
 
