@@ -8,7 +8,8 @@
 //   1. zone starts: start[c] = sum of the sizes of categories placed in a
 //      lower zone -- the sizes are permuted into zone order across the lanes
 //      of one wave, scanned, and permuted back; kept in LDS pre-shifted so
-//      that a line's scaled location is one add: ls = rec + zs[rec >> 24];
+//      that a line's scaled location is one add: ls = rec + zs[rec >> 24]
+//      (each wave keeps the table in registers and reads it by lane permute);
 //   2. a bitmap B over "units" of the sequence: bit P[i] is set where the
 //      i-th order of the sequence starts, P being the prefix sum of the order
 //      sizes clamped to Q + 1 (an order larger than Q is a tour of its own
@@ -89,13 +90,24 @@ static __device__ __forceinline__ uint32_t block_excl_scan(uint32_t v, uint32_t 
     return off + inc - v;
 }
 
+// Block sum of 64-bit values with one barrier (the wave sums by DPP on the
+// two halves, carried by 64-bit adds).
 template <int BLOCK>
 static __device__ __forceinline__ int64_t block_sum64(int64_t v, int64_t *slot)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v += __shfl_xor(v, d, 64);
-    if (lane == 0) slot[w] = v;
+    uint64_t x = (uint64_t)v;
+#define WO_DPP64(ctrl, rmask)                                                                                   \
+    x += ((uint64_t)(uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)(x >> 32), ctrl, rmask, 0xF, false) \
+          << 32) |                                                                                              \
+         (uint64_t)(uint32_t)__builtin_amdgcn_update_dpp(0, (int)(uint32_t)x, ctrl, rmask, 0xF, false)
+    WO_DPP64(0x111, 0xF);
+    WO_DPP64(0x112, 0xF);
+    WO_DPP64(0x114, 0xF);
+    WO_DPP64(0x118, 0xF);
+    WO_DPP64(0x142, 0xA);
+    WO_DPP64(0x143, 0xC);
+#undef WO_DPP64
+    if ((threadIdx.x & 63) == 63) slot[threadIdx.x >> 6] = (int64_t)x;
     __syncthreads();
     int64_t t = 0;
 #pragma unroll
@@ -137,30 +149,30 @@ static __device__ __forceinline__ int instance_of(const EvalArgs &A, int64_t p)
     return lo;
 }
 
-// The order ids of sequence positions [0, nv) of `s`, clamped to n - 1, two
-// per register; positions nv .. CH - 1 get the sink id n + 1 (size 0).
+// The order ids of sequence positions [0, nv) of `s`, two per 32-bit word.
+// A full, 16-byte aligned chunk is loaded as it is and the function returns
+// true: the caller clamps it to n - 1 (with min_u16x2) when it uses it, so
+// that a prefetch does not wait for its data.  Otherwise the ids are clamped
+// here and positions nv .. CH - 1 get the sink id n + 1 (size 0).
 template <int CH>
-static __device__ __forceinline__ void load_chunk(const uint16_t *s, int nv, uint32_t n, uint32_t *out)
+static __device__ __forceinline__ bool load_chunk(const uint16_t *s, int nv, uint32_t n, uint4 *out)
 {
-    const uint32_t lim = n - 1u, sink = n + 1u;
     if (nv == CH && (((uintptr_t)s) & 15u) == 0) {
-        const uint32_t lim2 = lim | (lim << 16);
 #pragma unroll
-        for (int j = 0; j < CH / 8; j++) {
-            const uint4 v = ((const uint4 *)s)[j];
-            out[4 * j + 0] = min_u16x2(v.x, lim2);
-            out[4 * j + 1] = min_u16x2(v.y, lim2);
-            out[4 * j + 2] = min_u16x2(v.z, lim2);
-            out[4 * j + 3] = min_u16x2(v.w, lim2);
-        }
-    } else {
-#pragma unroll
-        for (int k = 0; k < CH; k += 2) {
-            const uint32_t lo = (k < nv) ? min((uint32_t)s[k], lim) : sink;
-            const uint32_t hi = (k + 1 < nv) ? min((uint32_t)s[k + 1], lim) : sink;
-            out[k >> 1] = lo | (hi << 16);
-        }
+        for (int j = 0; j < CH / 8; j++) out[j] = ((const uint4 *)s)[j];
+        return true;
     }
+    const uint32_t lim = n - 1u, sink = n + 1u;
+    uint32_t w[CH / 2];
+#pragma unroll
+    for (int k = 0; k < CH; k += 2) {
+        const uint32_t lo = (k < nv) ? min((uint32_t)s[k], lim) : sink;
+        const uint32_t hi = (k + 1 < nv) ? min((uint32_t)s[k + 1], lim) : sink;
+        w[k >> 1] = lo | (hi << 16);
+    }
+#pragma unroll
+    for (int j = 0; j < CH / 8; j++) out[j] = make_uint4(w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]);
+    return false;
 }
 
 // LDS by absolute address.  The kernel declares no static LDS, so its dynamic
@@ -193,6 +205,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
 
     // work items: a grid stride, or a queue (atomic ticket) over a work order
     // that puts the most expensive plans first
+    const int64_t seq_base0 = A.seq_base[0];
     int64_t item = blockIdx.x;
     if (A.queue) {
         if (tid == 0) s_next = atomicAdd(A.queue_ctr, 1u);
@@ -203,7 +216,8 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
     // the next plan's sequence chunk and zone row, loaded while the current
     // plan's line pass runs
     bool have_pf = false;                   // uniform
-    uint32_t sv_pf[SEQ_CHUNK / 2];          // two 16-bit order ids per register
+    bool pf_raw = false;                    // sv_pf still needs clamping
+    uint4 sv_pf[SEQ_CHUNK / 8];             // two 16-bit order ids per 32-bit word
     uint32_t zc_pf = 0xFFu;
     while (item < A.n_plans) {
         if (A.queue && tid == 0) s_next = atomicAdd(A.queue_ctr, 1u);   // ticket of the next plan
@@ -287,11 +301,26 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
         uint32_t svp[SEQ_CHUNK / 2];                    // the chunk's order ids, two per register
         uint32_t cs[SEQ_CHUNK];                         // their clamped sizes
         if (one_piece) {
+            bool raw;
+            uint4 ld[SEQ_CHUNK / 8];
             if (have_pf) {
+                raw = pf_raw;
 #pragma unroll
-                for (int k = 0; k < SEQ_CHUNK / 2; k++) svp[k] = sv_pf[k];
+                for (int j = 0; j < SEQ_CHUNK / 8; j++) ld[j] = sv_pf[j];
             } else {
-                load_chunk<SEQ_CHUNK>(seq + b0, nv, (uint32_t)n, svp);
+                raw = load_chunk<SEQ_CHUNK>(seq + b0, nv, (uint32_t)n, ld);
+            }
+#pragma unroll
+            for (int j = 0; j < SEQ_CHUNK / 8; j++) {
+                svp[4 * j + 0] = ld[j].x;
+                svp[4 * j + 1] = ld[j].y;
+                svp[4 * j + 2] = ld[j].z;
+                svp[4 * j + 3] = ld[j].w;
+            }
+            if (raw) {
+                const uint32_t lim2 = (uint32_t)(n - 1) * 0x10001u;
+#pragma unroll
+                for (int k = 0; k < SEQ_CHUNK / 2; k++) svp[k] = min_u16x2(svp[k], lim2);
             }
         }
         have_pf = false;
@@ -416,15 +445,29 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                 }
                 __syncthreads();
                 // ---- link the true entries, segment after segment --------
-                if (tid == 0 && !misc[2]) {
-                    uint32_t l = 0;
+                // (wave 0 holds every chase lane's exit in registers and
+                // follows the links with lane reads)
+                if (tid < 64 && !misc[2]) {
+                    const int L_tot = misc[1];
+                    uint32_t c[CHASE_LANES / 64];
+#pragma unroll
+                    for (int j = 0; j < CHASE_LANES / 64; j++)
+                        c[j] = (lane + 64 * j < L_tot) ? cnxt[lane + 64 * j] : 0xFFFFFFFFu;
+                    uint32_t l = 0, tl = 0;
+                    bool ok = true;
                     for (int g = 0; g < G; g++) {
-                        true_lane[g] = l;
+                        if (lane == g) tl = l;
                         if (g + 1 < G) {
-                            l = cnxt[l];
-                            if (l == 0xFFFFFFFFu) { misc[2] = 1; break; }
+                            const uint32_t j = l >> 6;
+                            uint32_t v = c[0];
+#pragma unroll
+                            for (int jj = 1; jj < CHASE_LANES / 64; jj++) v = (j == (uint32_t)jj) ? c[jj] : v;
+                            l = (uint32_t)__builtin_amdgcn_readlane((int)v, (int)(l & 63u));
+                            if (l == 0xFFFFFFFFu) { ok = false; break; }
                         }
                     }
+                    if (lane < G) true_lane[lane] = tl;
+                    if (!ok && lane == 0) misc[2] = 1;
                 }
                 __syncthreads();
                 if (!misc[2]) {
@@ -515,16 +558,20 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
             // ---- prefetch of the next plan's inputs -----------------------
             if (next_item < A.n_plans) {
                 const int64_t pn = A.work ? (int64_t)A.work[next_item] : next_item;
-                const int iin = instance_of(A, pn);
+                // one instance: the next plan's row follows from this plan's
+                // sizes with no table loads
+                const bool same = A.n_inst <= 1;
+                const int iin = same ? ii : instance_of(A, pn);
                 const InstDev &In = A.inst[iin];
-                const int nn = In.n_orders;
+                const int nn = same ? n : In.n_orders;
+                const int cn = same ? C : In.n_cat;
                 const int chn = (nn + BLOCK - 1) / BLOCK;
                 if (chn <= SEQ_CHUNK) {                  // uniform
-                    const uint16_t *seqn =
-                        A.seq + A.seq_base[iin] + (pn - (A.n_inst > 1 ? A.plan_begin[iin] : 0)) * (int64_t)nn;
+                    const uint16_t *seqn = same ? A.seq + seq_base0 + pn * (int64_t)nn
+                                                : A.seq + A.seq_base[iin] + (pn - A.plan_begin[iin]) * (int64_t)nn;
                     const int c0 = min(nn, tid * chn), c1 = min(nn, c0 + chn);
-                    load_chunk<SEQ_CHUNK>(seqn + c0, c1 - c0, (uint32_t)nn, sv_pf);
-                    zc_pf = (tid < 64 && lane < In.n_cat) ? (uint32_t)A.zone_of[pn * 64 + lane] : 0xFFu;
+                    pf_raw = load_chunk<SEQ_CHUNK>(seqn + c0, c1 - c0, (uint32_t)nn, sv_pf);
+                    zc_pf = (tid < 64 && lane < cn) ? (uint32_t)A.zone_of[pn * 64 + lane] : 0xFFu;
                     have_pf = true;
                 }
             }
@@ -541,30 +588,25 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                     __syncthreads();
                 }
                 if (A.main_mode == 0) {
-                    // one line per lane, 8 coalesced loads in flight per thread;
-                    // the records are padded to a multiple of the block
-                    constexpr int U = 8;
-                    const uint2 *lines = A.lines + I.line_off;
-                    const int n_pad = I.n_lines_pad;
-                    int base = 0;                        // uniform
-                    for (; base + U * BLOCK <= n_pad; base += U * BLOCK) {
-                        const uint2 *lp = lines + base + tid;
+                    // each wave takes whole groups of 64 lanes x 8 line slots
+                    constexpr int U = LINE_SLOTS;
+                    constexpr int NW = BLOCK / 64;
+                    const int zsv = (int)zs[lane];
+                    const uint2 *lines = A.lines + I.line_off + lane;
+                    const int n_grp8 = I.n_lines_pad / LINE_PAD;
+                    for (int gi = tid >> 6; gi < n_grp8; gi += NW) {   // uniform per wave
                         uint2 v[U];
                         uint32_t tb[U], zv[U];
 #pragma unroll
-                        for (int u = 0; u < U; u++) v[u] = lp[u * BLOCK];
+                        for (int u = 0; u < U; u++) v[u] = lines[gi * LINE_PAD + u * 64];
                         // all table reads of the group before its atomics
 #pragma unroll
                         for (int u = 0; u < U; u++) {
                             tb[u] = *lds16(v[u].y);
-                            zv[u] = *lds32(LDS_ZS + (v[u].x >> 24));
+                            zv[u] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(v[u].x >> 24), zsv);
                         }
 #pragma unroll
                         for (int u = 0; u < U; u++) line_update(v[u].x + zv[u], tb[u], magic);
-                    }
-                    for (; base < n_pad; base += BLOCK) {
-                        const uint2 v = lines[base + tid];
-                        line_update(v.x + *lds32(LDS_ZS + (v.x >> 24)), *lds16(v.y), magic);
                     }
                 } else {
                     // one order per lane: its row looked up once, its farthest

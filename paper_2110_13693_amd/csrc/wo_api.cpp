@@ -326,7 +326,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         // tours per LDS tile: the expected tour count with margin (more tours
         // take another pass over the lines), never more than the orders, and
         // few enough that a row's byte offset fits the 16-bit tour entries
-        int64_t t_cap = (int64_t)std::ceil(1.1 * items / tour_items) + 32;
+        int64_t t_cap = (int64_t)std::ceil(1.04 * items / tour_items) + 8;
         t_cap = std::min<int64_t>(t_cap, d.n_orders);
         t_cap = std::min<int64_t>(t_cap, 65535 / row_bytes(I.words) - 1);
         t_cap = std::max<int64_t>(t_cap, 1);
@@ -339,20 +339,31 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         if (ly.total > wh->lds_max)
             return fail(WO_E_RANGE, "instance %d: needs %u bytes of LDS, device has %u", i, ly.total, wh->lds_max);
 
-        // line records in instance order; y is the LDS byte offset of the
-        // order's tour entry in this instance's layout.  Padding records sit
-        // on the dummy entry (order n), whose row is never summed.
+        // line records; y is the LDS byte offset of the order's tour entry in
+        // this instance's layout.  Padding records sit on the dummy entry
+        // (order n), whose row is never summed.  In instance order the lines
+        // are cut into groups of LINE_PAD = 64 lanes x 8 slots: lane j of a
+        // group takes 8 consecutive lines (mostly of one or two orders), and
+        // the group is stored slot-major so that each slot is one coalesced
+        // 512-byte load for a wave.  Lanes of one slot so hold lines of
+        // different orders and their row updates rarely share an address.
         I.line_off = (int64_t)lines.size();
-        for (int32_t o = 0; o < d.n_orders; o++) {
-            for (int32_t l = d.order_offsets[o]; l < d.order_offsets[o + 1]; l++) {
-                const int32_t sk = d.order_skus[l];
-                const uint32_t c = (uint32_t)d.sku_category[sk];
-                lines.push_back(make_uint2(((uint32_t)rank[sk] << I.shift) | ((4u * c) << 24),
-                                           ly.tour + 2u * (uint32_t)o));
+        {
+            std::vector<uint2> flat;
+            flat.reserve((size_t)I.n_lines + LINE_PAD);
+            for (int32_t o = 0; o < d.n_orders; o++) {
+                for (int32_t l = d.order_offsets[o]; l < d.order_offsets[o + 1]; l++) {
+                    const int32_t sk = d.order_skus[l];
+                    const uint32_t c = (uint32_t)d.sku_category[sk];
+                    flat.push_back(make_uint2(((uint32_t)rank[sk] << I.shift) | ((4u * c) << 24),
+                                              ly.tour + 2u * (uint32_t)o));
+                }
             }
+            while (flat.size() % LINE_PAD) flat.push_back(make_uint2(0u, ly.tour + 2u * (uint32_t)d.n_orders));
+            for (size_t g = 0; g < flat.size(); g += LINE_PAD)
+                for (int u = 0; u < LINE_SLOTS; u++)
+                    for (int j = 0; j < 64; j++) lines.push_back(flat[g + (size_t)j * LINE_SLOTS + u]);
         }
-        while ((lines.size() - (size_t)I.line_off) % LINE_PAD)
-            lines.push_back(make_uint2(0u, ly.tour + 2u * (uint32_t)d.n_orders));
         I.n_lines_pad = (int32_t)(lines.size() - (size_t)I.line_off);
         wh->lds[i] = ly.total;
     }

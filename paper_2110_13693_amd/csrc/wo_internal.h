@@ -28,11 +28,13 @@ struct InstDev {
     int32_t L;              // slots_per_side * pitch
     int32_t t_cap;          // tours per LDS tile
     int32_t n_seg;          // item-space segments chased in parallel (1 = serial chain)
-    int32_t n_lines_pad;    // line records stored: n_lines rounded up to a multiple of LINE_PAD
+    int32_t n_lines_pad;    // line records stored: n_lines rounded up to whole groups of LINE_PAD
     // uint2 line records [n_lines_pad]: x = (rank << shift) | (4*cat) << 24,
     // y = LDS byte offset of the order's tour entry (2 * order + the tour
     // table's offset); the padding records point at the dummy entry of order
-    // n_orders, whose row absorbs them
+    // n_orders, whose row absorbs them.  Stored in groups of 64 x LINE_SLOTS,
+    // slot-major (record u * 64 + j of a group is line j * LINE_SLOTS + u of
+    // it in instance order).
     int64_t line_off;
     int64_t cnt_off;        // u8 per order: min(size, capacity + 1) [n_orders], zero-padded to 16 bytes past n_orders + 2
     // orders in groups of 64 by descending size (one order per lane): group g
@@ -77,9 +79,10 @@ struct EvalArgs {
 constexpr int CHASE_LANES = 256;
 constexpr int CHASE_RECS = 32;
 constexpr int MAX_SEG = 64;
-// line records are padded to a multiple of this (the largest block size), so
-// that the line pass needs no bounds checks
-constexpr int LINE_PAD = 512;
+// line records come in groups of 64 lanes x LINE_SLOTS consecutive lines,
+// padded to whole groups, so that the line pass needs no bounds checks
+constexpr int LINE_SLOTS = 8;
+constexpr int LINE_PAD = 64 * LINE_SLOTS;
 // fixed LDS offsets: the zone-start table, the work-queue ticket, then the
 // region shared by the chase records and the per-tour rows (the kernel holds
 // no static LDS, so these are the addresses the instructions see)
@@ -94,7 +97,8 @@ constexpr uint32_t LDS_REGION = 272;
 // offsets.  The region holds, in turn: the permutation-check bitmap
 // (validation), the chase records, and the per-tour rows of one tile.  A row
 // is 1 + words 32-bit words: the tour's farthest scaled location, then its
-// aisle set; a tile has t_cap rows plus one dummy row.
+// aisle set (and a pad word when that count is even); a tile has t_cap rows
+// plus one dummy row.
 struct EvalLayout {
     uint32_t rec, nrec, nxt, cand;     // chase phase (inside the region)
     uint32_t red, misc, seg, cnt, tour, B, F;
@@ -105,7 +109,9 @@ __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15
 
 __host__ __device__ inline uint32_t bitmap_words(int32_t n_units) { return ((uint32_t)n_units >> 5) + 3u; }
 
-__host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * (uint32_t)(words + 1); }
+// a row is the farthest location plus the aisle set, padded to an odd word
+// count so that rows of random tours spread over all 32 LDS banks
+__host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * ((uint32_t)(words + 1) | 1u); }
 
 // bytes of the cnt table (order sizes, then zeros for the dummy and sink entries)
 __host__ __device__ inline uint32_t cnt_bytes(int32_t n_orders) { return align16((uint32_t)n_orders + 2u); }
