@@ -299,7 +299,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
         const int nv = b1 - b0;
         const bool one_piece = ch <= SEQ_CHUNK;          // uniform
         uint32_t svp[SEQ_CHUNK / 2];                    // the chunk's order ids, two per register
-        uint32_t cs[SEQ_CHUNK];                         // their clamped sizes
+        uint32_t csp[SEQ_CHUNK / 4];                    // their clamped sizes (<= 33), four per register
         if (one_piece) {
             bool raw;
             uint4 ld[SEQ_CHUNK / 8];
@@ -325,15 +325,17 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
         }
         have_pf = false;
 #define SV(k) ((svp[(k) >> 1] >> (16 * ((k) & 1))) & 0xFFFFu)
+#define CS(k) ((csp[(k) >> 2] >> (8 * ((k) & 3))) & 0xFFu)
         __syncthreads();                                 // tables, zeroed bitmaps, zone starts
         const int64_t next_item = A.queue ? (int64_t)s_next : item + (int64_t)gridDim.x;
         uint32_t local = 0, cmax = 0;
         if (one_piece) {
 #pragma unroll
             for (int k = 0; k < SEQ_CHUNK; k++) {
-                cs[k] = cnt[SV(k)];
-                local += cs[k];
-                cmax = max(cmax, cs[k]);
+                const uint32_t c = cnt[SV(k)];
+                if (k % 4 == 0) csp[k / 4] = c; else csp[k / 4] |= c << (8 * (k % 4));
+                local += c;
+                cmax = max(cmax, c);
             }
         } else {
             for (int i = b0; i < b1; i++) {
@@ -369,7 +371,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
 #pragma unroll
                 for (int k = 0; k < SEQ_CHUNK; k++) {
                     atomicOr(&B[run >> 5], 1u << (run & 31u));
-                    run += cs[k];
+                    run += CS(k);
                 }
             } else {
                 uint32_t run = run0;
@@ -510,7 +512,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
 #pragma unroll
                 for (int k = 0; k < SEQ_CHUNK; k++) {
                     opm |= ((F[run >> 5] >> (run & 31u)) & 1u) << k;
-                    run += cs[k];
+                    run += CS(k);
                 }
                 if (nv < 32) opm &= (1u << nv) - 1u;
                 n_open = __popc(opm);
@@ -534,12 +536,12 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
             // (later tiles re-derive the tour ids from the sequence in memory)
             auto write_entries = [&](uint32_t t0, bool from_regs) {
                 uint32_t t = first_tour - 1u;            // wraps; a store always follows an opening
-                if (from_regs) {
+                if (from_regs) {                         // first tile (t0 = 0): the row offset
+                    uint32_t tr = t * RB;                // t * RB, below dummy = T * RB iff t < T
 #pragma unroll
                     for (int k = 0; k < SEQ_CHUNK; k++) {
-                        t += (opm >> k) & 1u;
-                        const uint32_t rel = t - t0;
-                        tour[SV(k)] = (uint16_t)(rel < (uint32_t)T ? rel * RB : dummy);
+                        tr += ((opm >> k) & 1u) * RB;
+                        tour[SV(k)] = (uint16_t)min(tr, dummy);
                     }
                 } else {
                     uint32_t run = run0;
@@ -675,8 +677,10 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                 for (int t = tid; t < nt; t += BLOCK) {
                     const uint32_t *rw = (const uint32_t *)(smem + LDS_REGION + (uint32_t)t * RB);
                     const uint32_t ls = rw[0];
-                    int k = 0;
-                    for (int w = 0; w < W; w++) k += __popc(rw[1 + w]);
+                    int k = 0, w = 0;
+                    for (; w + 4 <= W; w += 4)
+                        k += __popc(rw[1 + w]) + __popc(rw[2 + w]) + __popc(rw[3 + w]) + __popc(rw[4 + w]);
+                    for (; w < W; w++) k += __popc(rw[1 + w]);
                     const uint32_t a = mulhi24(ls, magic);
                     const uint32_t j = (ls - a * I.d_s) >> (I.shift + 1);
                     const int64_t y = (int64_t)j * I.pitch + I.pitch / 2;
@@ -687,6 +691,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
             }
         }
 #undef SV
+#undef CS
         const int64_t D = block_sum64<BLOCK>(acc, sum_slot);
         if (A.validate && bad) atomicOr(A.err, 1);
         if (tid == 0) {
