@@ -222,6 +222,151 @@ def search_comparison(args):
     return 0
 
 
+def batched_bench(args):
+    """Uneven instances in one launch: 512 warehouses (aisles and orders
+    log-uniform) x 256 plans = 131,072 plans per call.  The launch
+    configuration is autotuned first; the call is then timed eagerly and as
+    a replayed graph."""
+    import torch
+
+    import synth
+    from paper_2110_13693_amd import wo
+
+    torch.cuda.set_device(0)
+    per = 256
+    insts = synth.make_batched_instances(512, seed=0)
+    Z, S, _ = synth.generators.pack_batched_plans(insts, per, seed=0)
+    offs = np.arange(len(insts) + 1, dtype=np.int64) * per
+    n_plans = Z.shape[0]
+    wh = wo.wo_load_warehouse(insts)
+    z = torch.from_numpy(Z).cuda()
+    s = torch.from_numpy(S.view(np.int16)).cuda()
+    dist = torch.empty(n_plans, dtype=torch.int32, device="cuda")
+    thr = torch.empty(n_plans, dtype=torch.float32, device="cuda")
+    best, table = wo.wo_autotune_eval(wh, z, s, dist, plan_offsets=offs, reps=3)
+    stream = torch.cuda.current_stream()
+    for _ in range(args.warmup):
+        wo.wo_eval_plans(wh, z, s, dist, thr, plan_offsets=offs, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    ev0.record(stream)
+    for _ in range(args.steps):
+        wo.wo_eval_plans(wh, z, s, dist, thr, plan_offsets=offs, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    eager_ms = ev0.elapsed_time(ev1) / args.steps
+    g = torch.cuda.CUDAGraph()
+    side = torch.cuda.Stream()
+    side.wait_stream(stream)
+    with torch.cuda.stream(side):
+        wo.wo_eval_plans(wh, z, s, dist, thr, plan_offsets=offs, stream=side)
+    stream.wait_stream(side)
+    torch.cuda.synchronize()
+    with torch.cuda.graph(g):
+        wo.wo_eval_plans(wh, z, s, dist, thr, plan_offsets=offs, stream=torch.cuda.current_stream())
+    g.replay()
+    torch.cuda.synchronize()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        g.replay()
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    graph_ms = ev0.elapsed_time(ev1) / args.steps
+    ops = 0.0
+    base = 0
+    for inst in insts:
+        seq = S[base:base + per * inst.n_orders].reshape(per, inst.n_orders)
+        ops += algorithmic_ops(inst, seq)
+        base += per * inst.n_orders
+    achieved = ops / (graph_ms / 1e3)
+    out = {
+        "metric": "exact plan evals/s, 512 uneven instances",
+        "value": n_plans / (graph_ms / 1e3),
+        "unit": "plans/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+        "ms_per_step": graph_ms, "eager_ms_per_step": eager_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "i32",
+        "data": "synthetic",
+        "config": {"workload": "512 warehouses, aisles log-uniform in [8, 400], orders log-uniform in "
+                               "[50, 4000], capacity 30, 256 plans each (131,072 plans per call)",
+                   "items": int(sum(i.n_items for i in insts)), "autotuned": best},
+        "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK_OPS / 1e12,
+                     "unit": "Tops/s", "frac": achieved / INT_VALU_PEAK_OPS, "traffic": None},
+        "autotune_table": [[c["block_threads"], c["blocks_per_cu"], c["queue"], c["line_pass"],
+                            round(c["ms"], 4)] for c in table],
+    }
+    wh.free()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
+# MFMA work of the surrogate per candidate: 2 (4096 x 1024 + 1024 x 256 + 256)
+SUR_FWD_FLOP = 2.0 * (4096 * 1024 + 1024 * 256 + 256)
+# one training sample: forward, input-gradient-free backward (two weight
+# gradients and one activation gradient for the hidden layers)
+SUR_TRAIN_FLOP = 18.35e6
+BF16_PEAK_FLOPS = 2.5e15
+
+
+def surrogate_bench(args):
+    """Surrogate throughput on the BF16 matrix cores: screening predictions
+    (65,536 candidates per call) and training (batch 1,024), on random
+    slottings of the 64-category paper warehouse."""
+    import torch
+
+    import synth
+    from paper_2110_13693_amd import wo
+
+    torch.cuda.set_device(0)
+    rng = np.random.default_rng([0, synth.generators.STREAM_SURROGATE_TRAIN])
+    K = 65536
+    z = torch.from_numpy(synth.generators.random_zone_perms(rng, K, 64)).cuda()
+    pred = torch.empty(K, dtype=torch.float32, device="cuda")
+    sur = wo.wo_sur_create(64, None, seed=1)
+    wo.wo_sur_set_scale(sur, 2.3e7, 2.0e5)
+    stream = torch.cuda.current_stream()
+    for _ in range(3):
+        wo.wo_sur_predict(sur, z, pred, stream=stream)
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = max(5, args.steps // 10)
+    ev0.record(stream)
+    for _ in range(reps):
+        wo.wo_sur_predict(sur, z, pred, stream=stream)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    pred_ms = ev0.elapsed_time(ev1) / reps
+    n_train = 1 << 18
+    zt = torch.from_numpy(synth.generators.random_zone_perms(rng, n_train, 64)).cuda()
+    dt = torch.from_numpy(rng.integers(22_000_000, 24_000_000, n_train, dtype=np.int32)).cuda()
+    wo.wo_sur_train(sur, zt[:8192], dt[:8192], epochs=1, batch=1024, lr=1e-4, seed=3)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    wo.wo_sur_train(sur, zt, dt, epochs=1, batch=1024, lr=1e-4, seed=4)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    pred_flops = SUR_FWD_FLOP * K / (pred_ms / 1e3)
+    train_flops = SUR_TRAIN_FLOP * n_train / train_s
+    out = {
+        "metric": "surrogate screening candidates/s",
+        "value": K / (pred_ms / 1e3),
+        "unit": "candidates/s",
+        "n_gpus": 1, "steps": reps, "ms_per_step": pred_ms,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "MLP 4096-1024-256-1 on one-hot(64 x 64) slottings, 65,536 candidates "
+                               "per call; training batch 1,024 over 262,144 samples"},
+        "roofline": {"bound": "mfma", "achieved": pred_flops / 1e12, "peak": BF16_PEAK_FLOPS / 1e12,
+                     "unit": "TFLOP/s", "frac": pred_flops / BF16_PEAK_FLOPS, "traffic": None},
+        "train": {"samples_per_s": n_train / train_s, "epoch_s": train_s,
+                  "achieved_tflops": train_flops / 1e12, "frac": train_flops / BF16_PEAK_FLOPS,
+                  "note": "wall time of one epoch, host shuffle included"},
+    }
+    sur.free()
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -235,6 +380,10 @@ def main(argv=None):
     ap.add_argument("--generations", type=int, default=200)
     ap.add_argument("--train-samples", type=int, default=1 << 20)
     ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--batched", action="store_true",
+                    help="time the 512-instance uneven batch (autotuned, eager and graph replay) instead")
+    ap.add_argument("--surrogate", action="store_true",
+                    help="time surrogate screening and training on the matrix cores instead")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
                     help="only copy a MIB-sized device buffer 10 times (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
@@ -245,6 +394,10 @@ def main(argv=None):
 
     if args.search:
         return search_comparison(args)
+    if args.batched:
+        return batched_bench(args)
+    if args.surrogate:
+        return surrogate_bench(args)
     if args.copy_probe:
         import torch
         a = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
