@@ -86,6 +86,9 @@ EDGE_CASES = [
     (65, 250, 1000, 30, 64, 1.5),
     (400, 250, 4000, 1, 64, 0.3),  # ~4,000 tours: several tour tiles
     (10, 30, 1, 20, 12, 1.5),    # a single order
+    (400, 250, 6000, 30, 64, 1.5),    # more orders than one block keeps in registers
+    (400, 250, 12000, 3, 64, 1.5),    # oversize orders (serial chain), several tiles, sequence in memory
+    (100, 250, 40000, 30, 8, 0.0),    # 40,000 single-line orders: near the LDS limit, tiles halved
 ]
 
 
@@ -96,6 +99,16 @@ def test_edge_cases(case):
     Z, S = synth.make_plans(inst, 37, seed=int(rng.integers(1 << 30)))
     print("case", case, flush=True)
     _compare(inst, Z, S)
+
+
+def test_instance_beyond_lds_is_rejected():
+    # 65,535 orders need more LDS than a CU has: the load fails cleanly
+    wo = _wo()
+    rng = np.random.default_rng(11)
+    inst = _random_instance(rng, 200, 250, 65535, 30, 8, lam=0.0)
+    with pytest.raises(wo.WoError) as e:
+        wo.wo_load_warehouse([inst])
+    assert "LDS" in str(e.value)
 
 
 def test_zero_plans_is_noop():
