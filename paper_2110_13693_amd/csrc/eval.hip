@@ -231,7 +231,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
         const uint32_t n_units = (uint32_t)I.n_units;
         const int64_t row = p - (A.n_inst > 1 ? A.plan_begin[ii] : 0);
         const uint16_t *seq = A.seq + A.seq_base[ii] + row * (int64_t)n;
-        const EvalLayout Ly = eval_layout(n, I.n_units, I.words, I.t_cap);
+        const EvalLayout Ly = eval_layout(n, I.n_units, I.words, I.t_cap, I.chase_log2);
         uint32_t *zs = (uint32_t *)(smem + LDS_ZS);
         uint32_t *scan_a = (uint32_t *)(smem + Ly.red);
         uint32_t *scan_b = scan_a + 16;
@@ -417,6 +417,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
             if (G > 1 && misc[1] > CHASE_LANES) G = 1;    // uniform
 
             // ---- 4. chase ---------------------------------------------------
+            const int CR2 = I.chase_log2;
             if (G > 1) {
                 const int L_tot = misc[1];
                 for (int l = tid; l < L_tot; l += BLOCK) {
@@ -425,13 +426,13 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                     uint32_t x = cv & 0x3FFFFFFu;
                     const uint32_t s_g = segs[g];
                     const uint32_t s_e = segs[g + 1];
-                    uint16_t *r = crec + l * CHASE_RECS;
+                    uint16_t *r = crec + (l << CR2);
                     uint32_t nr = 0;
                     r[nr++] = (uint16_t)(x - s_g);
                     for (;;) {
                         x = next_open(B, x, maskQ);
                         if (x >= s_e) break;
-                        if (nr == CHASE_RECS) { misc[2] = 1; break; }
+                        if (nr == (1u << CR2)) { misc[2] = 1; break; }
                         r[nr++] = (uint16_t)(x - s_g);
                     }
                     cnrec[l] = nr;
@@ -473,11 +474,11 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                 }
                 __syncthreads();
                 if (!misc[2]) {
-                    for (int idx = tid; idx < G * CHASE_RECS; idx += BLOCK) {
-                        const int g = idx / CHASE_RECS, k = idx % CHASE_RECS;
+                    for (int idx = tid; idx < (G << CR2); idx += BLOCK) {
+                        const int g = idx >> CR2, k = idx & ((1 << CR2) - 1);
                         const uint32_t l = true_lane[g];
                         if ((uint32_t)k < cnrec[l]) {
-                            const uint32_t x = segs[g] + crec[l * CHASE_RECS + k];
+                            const uint32_t x = segs[g] + crec[(l << CR2) + k];
                             atomicOr(&F[x >> 5], 1u << (x & 31u));
                         }
                     }

@@ -306,22 +306,30 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         }
 
         // Parallel next-fit: about (Q / mean order size) order starts fall in
-        // a Q-item window, each a candidate entry of a segment; take as many
-        // segments as the chase lanes allow, no shorter than 2Q items, and long
-        // enough that a chain rarely needs more than the record slots.
+        // a Q-item window, each a candidate entry of a segment.  With 2^lg
+        // opening records per chain, take the fewest segments whose chains
+        // fit the records with margin, plus one; fewer if the chase lanes or
+        // a minimum length of 2Q items do not allow them.  Longer records are
+        // tried only when 32 do not fit; without any fit, plans take the
+        // serial chain.
         const double items = (double)I.n_lines;
         const double avg_len = items / d.n_orders;
         const double cand = std::max(1.0, std::min((double)d.capacity, d.capacity / avg_len));
         const double tour_items = std::max(1.0, d.capacity - 0.5 * (avg_len - 1.0));
-        // fewest segments whose chains fit the record slots with margin, plus
-        // one; fewer if the expected chase lanes would not fit
-        int g_recs = (int)std::ceil(items / (0.75 * CHASE_RECS * tour_items));
-        int g = g_recs + 1;
-        int g_lanes = 1 + (int)((0.85 * CHASE_LANES - 1.0) / cand);
-        int g_len = (int)(items / (2.0 * d.capacity));
-        g = std::min(std::min(g, g_lanes), std::min(g_len, MAX_SEG));
-        bool short_segs = (double)I.n_units / std::max(g, 1) < 65535.0;  // chase records are 16-bit offsets
-        I.n_seg = (g >= 2 && g >= g_recs && short_segs) ? g : 1;
+        I.n_seg = 1;
+        I.chase_log2 = 5;
+        for (int lg = 5; lg <= MAX_CHASE_LOG2; lg++) {
+            const int g_recs = (int)std::ceil(items / (0.75 * (1 << lg) * tour_items));
+            const int g_lanes = 1 + (int)((0.85 * CHASE_LANES - 1.0) / cand);
+            const int g_len = (int)(items / (2.0 * d.capacity));
+            const int g = std::min(std::min(g_recs + 1, g_lanes), std::min(g_len, MAX_SEG));
+            const bool short_segs = (double)I.n_units / std::max(g, 1) < 65535.0;   // 16-bit records
+            if (g >= 2 && g >= g_recs && short_segs) {
+                I.n_seg = g;
+                I.chase_log2 = lg;
+                break;
+            }
+        }
 
         // tours per LDS tile: the expected tour count with margin (more tours
         // take another pass over the lines), never more than the orders, and
@@ -330,10 +338,10 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         t_cap = std::min<int64_t>(t_cap, d.n_orders);
         t_cap = std::min<int64_t>(t_cap, 65535 / row_bytes(I.words) - 1);
         t_cap = std::max<int64_t>(t_cap, 1);
-        EvalLayout ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap);
+        EvalLayout ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap, I.chase_log2);
         while (ly.total > wh->lds_max && t_cap > 1) {
             t_cap = t_cap / 2;
-            ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap);
+            ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap, I.chase_log2);
         }
         I.t_cap = (int32_t)t_cap;
         if (ly.total > wh->lds_max)
