@@ -59,34 +59,39 @@ static __device__ __forceinline__ bf16x8 one_hot8(uint32_t d)
 }
 
 // ---------------------------------------------------------------------------
-// GEMM: C[M][N] = A[M][K] . B[N][K]^T.  Block tile 128 x 128, K step 32,
-// four waves in 2 x 2, each 64 x 64 = 4 x 4 MFMA tiles of 16 x 16.
-// M, N multiples of 128 and K a multiple of 32 (the host pads); rows of A at
-// or beyond M_real read as zero when A is generated from zone bytes.
+// GEMM: C[M][N] = A[M][K] . B[N][K]^T.  Block tile TM x TM (128 or 64), K
+// step 64, four waves in 2 x 2, each (TM/2)^2 = (TM/32)^2 MFMA tiles of
+// 16 x 16.  The next K step's operands are loaded into registers while the
+// current one's MFMAs run from LDS.  M, N multiples of TM and K a multiple of
+// 64 (the host pads); rows of A at or beyond M_real, and samples of B at or
+// beyond K_real, read as zero when generated from zone bytes.
 // ---------------------------------------------------------------------------
-constexpr int GBM = 128, GBN = 128, GBK = 32, GPAD = 8;
+constexpr int GBK = 64, GPAD = 8, GLDK = GBK + GPAD;
 
-template <int AMODE, int BMODE, int EPI>
+template <int AMODE, int BMODE, int EPI, int TM>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 {
-    __shared__ __align__(16) uint16_t As[GBM][GBK + GPAD];
-    __shared__ __align__(16) uint16_t Bs[GBN][GBK + GPAD];
-    __shared__ __align__(16) uint8_t Zs[(AMODE == A_ONEHOT) ? GBM * 64 : (BMODE == B_ONEHOT_T ? GBK * 64 : 16)];
+    constexpr int WT = TM / 2;                 // wave tile
+    constexpr int FT = WT / 16;                // MFMA tiles per wave and dimension
+    constexpr int NLD = TM * GBK / 8 / 256;    // 16-byte loads per thread per operand tile
+    __shared__ __align__(16) uint16_t As[(AMODE == A_BF16) ? TM * GLDK : 8];
+    __shared__ __align__(16) uint16_t Bs[(BMODE == B_BF16) ? TM * GLDK : 8];
+    __shared__ __align__(16) uint8_t Zs[(AMODE == A_ONEHOT) ? TM * 64 : (BMODE == B_ONEHOT_T ? GBK * 64 : 16)];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
-    const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+    const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
 
-    floatx4 acc[4][4];
+    floatx4 acc[FT][FT];
 #pragma unroll
-    for (int i = 0; i < 4; i++)
+    for (int i = 0; i < FT; i++)
 #pragma unroll
-        for (int j = 0; j < 4; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < FT; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     if (AMODE == A_ONEHOT) {
-        // zone bytes of the block's 128 rows (8 KB), 0xFF past the real rows
-        for (int c = tid; c < GBM * 4; c += 256) {
+        // zone bytes of the block's rows, 0xFF past the real rows
+        for (int c = tid; c < TM * 4; c += 256) {
             const int r = c >> 2, part = c & 3;
             uint4 v = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
             if (m0 + r < g.M_real) v = *(const uint4 *)(g.zoneA + (int64_t)(m0 + r) * 64 + part * 16);
@@ -94,77 +99,107 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
         }
     }
 
-    for (int k0 = 0; k0 < g.K; k0 += GBK) {
-        if (AMODE == A_BF16) {
-            for (int c = tid; c < GBM * 4; c += 256) {
-                const int r = c >> 2, part = c & 3;
-                *(uint4 *)(&As[r][part * 8]) =
-                    *(const uint4 *)(g.A + (int64_t)(m0 + r) * g.lda + k0 + part * 8);
-            }
-        }
-        if (BMODE == B_BF16) {
-            for (int c = tid; c < GBN * 4; c += 256) {
-                const int r = c >> 2, part = c & 3;
-                *(uint4 *)(&Bs[r][part * 8]) =
-                    *(const uint4 *)(g.B + (int64_t)(n0 + r) * g.ldb + k0 + part * 8);
-            }
-        } else {
-            // zone bytes of the 32 samples of this K step (2 KB)
-            for (int c = tid; c < GBK * 4; c += 256) {
-                const int r = c >> 2, part = c & 3;
-                uint4 v = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
-                if (k0 + r < g.K_real) v = *(const uint4 *)(g.zoneB + (int64_t)(k0 + r) * 64 + part * 16);
-                *(uint4 *)(&Zs[r * 64 + part * 16]) = v;
-            }
-        }
-        __syncthreads();
+    u32x4 ra[NLD], rbv[NLD], rz;   // native vectors, so that they stay in registers
+#define WO_LOAD_TILE(k0_)                                                                                        \
+    do {                                                                                                         \
+        if (AMODE == A_BF16) {                                                                                   \
+            _Pragma("unroll") for (int i = 0; i < NLD; i++) {                                                    \
+                const int c = tid + i * 256, r = c >> 3, part = c & 7;                                           \
+                ra[i] = *(const u32x4 *)(g.A + (int64_t)(m0 + r) * g.lda + (k0_) + part * 8);                    \
+            }                                                                                                    \
+        }                                                                                                        \
+        if (BMODE == B_BF16) {                                                                                   \
+            _Pragma("unroll") for (int i = 0; i < NLD; i++) {                                                    \
+                const int c = tid + i * 256, r = c >> 3, part = c & 7;                                           \
+                rbv[i] = *(const u32x4 *)(g.B + (int64_t)(n0 + r) * g.ldb + (k0_) + part * 8);                   \
+            }                                                                                                    \
+        } else {                                                                                                 \
+            const int r = tid >> 2, part = tid & 3;                                                              \
+            rz = u32x4{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};                                 \
+            if ((k0_) + r < g.K_real) rz = *(const u32x4 *)(g.zoneB + (int64_t)((k0_) + r) * 64 + part * 16);    \
+        }                                                                                                        \
+    } while (0)
+#define WO_STORE_TILE()                                                                                          \
+    do {                                                                                                         \
+        if (AMODE == A_BF16) {                                                                                   \
+            _Pragma("unroll") for (int i = 0; i < NLD; i++) {                                                    \
+                const int c = tid + i * 256, r = c >> 3, part = c & 7;                                           \
+                *(u32x4 *)(&As[r * GLDK + part * 8]) = ra[i];                                                    \
+            }                                                                                                    \
+        }                                                                                                        \
+        if (BMODE == B_BF16) {                                                                                   \
+            _Pragma("unroll") for (int i = 0; i < NLD; i++) {                                                    \
+                const int c = tid + i * 256, r = c >> 3, part = c & 7;                                           \
+                *(u32x4 *)(&Bs[r * GLDK + part * 8]) = rbv[i];                                                   \
+            }                                                                                                    \
+        } else {                                                                                                 \
+            *(u32x4 *)(&Zs[(tid >> 2) * 64 + (tid & 3) * 16]) = rz;                                              \
+        }                                                                                                        \
+    } while (0)
 
-        bf16x8 af[4], bfr[4];
+    // one operand set per K step: the next one loads into registers while the
+    // current one is multiplied from LDS
+    WO_LOAD_TILE(0);
+    WO_STORE_TILE();
+    __syncthreads();
+    for (int k0 = 0; k0 < g.K; k0 += GBK) {
+        const bool more = k0 + GBK < g.K;
+        WO_LOAD_TILE(more ? k0 + GBK : k0);          // unconditional, so the operands stay in registers
 #pragma unroll
-        for (int ti = 0; ti < 4; ti++) {
-            const int row = wm * 64 + ti * 16 + fr;
-            if (AMODE == A_BF16) {
-                af[ti] = *(const bf16x8 *)(&As[row][fk]);
-            } else {
-                const int k = k0 + fk;                      // 8 | 64: one category per fragment
-                const uint32_t z = (k >> 6) < g.n_cat ? (uint32_t)Zs[row * 64 + (k >> 6)] : 0xFFu;
-                af[ti] = one_hot8(z - (uint32_t)(k & 63));
-            }
-        }
+        for (int ks = 0; ks < GBK; ks += 32) {
+            bf16x8 af[FT], bfr[FT];
 #pragma unroll
-        for (int tj = 0; tj < 4; tj++) {
-            const int col = wn * 64 + tj * 16 + fr;
-            if (BMODE == B_BF16) {
-                bfr[tj] = *(const bf16x8 *)(&Bs[col][fk]);
-            } else {
-                const int n = n0 + col;                     // input feature = category*64 + zone
-                const int cc = n >> 6;
-                const uint8_t zz = cc < g.n_cat ? (uint8_t)(n & 63) : (uint8_t)0xFE;   // 0xFE matches no zone
-                u32x4 wv;
-#pragma unroll
-                for (int e = 0; e < 4; e++) {
-                    const uint32_t lo = Zs[(fk + 2 * e) * 64 + cc] == zz ? 0x3F80u : 0u;
-                    const uint32_t hi = Zs[(fk + 2 * e + 1) * 64 + cc] == zz ? 0x3F800000u : 0u;
-                    wv[e] = lo | hi;
+            for (int ti = 0; ti < FT; ti++) {
+                const int row = wm * WT + ti * 16 + fr;
+                if (AMODE == A_BF16) {
+                    af[ti] = *(const bf16x8 *)(&As[row * GLDK + ks + fk]);
+                } else {
+                    const int k = k0 + ks + fk;             // 8 | 64: one category per fragment
+                    const uint32_t z = (k >> 6) < g.n_cat ? (uint32_t)Zs[row * 64 + (k >> 6)] : 0xFFu;
+                    af[ti] = one_hot8(z - (uint32_t)(k & 63));
                 }
-                bfr[tj] = __builtin_bit_cast(bf16x8, wv);
             }
+#pragma unroll
+            for (int tj = 0; tj < FT; tj++) {
+                const int col = wn * WT + tj * 16 + fr;
+                if (BMODE == B_BF16) {
+                    bfr[tj] = *(const bf16x8 *)(&Bs[col * GLDK + ks + fk]);
+                } else {
+                    const int n = n0 + col;                 // input feature = category*64 + zone
+                    const int cc = n >> 6;
+                    const uint8_t zz = cc < g.n_cat ? (uint8_t)(n & 63) : (uint8_t)0xFE;   // 0xFE matches no zone
+                    u32x4 wv;
+#pragma unroll
+                    for (int e = 0; e < 4; e++) {
+                        const uint32_t lo = Zs[(ks + fk + 2 * e) * 64 + cc] == zz ? 0x3F80u : 0u;
+                        const uint32_t hi = Zs[(ks + fk + 2 * e + 1) * 64 + cc] == zz ? 0x3F800000u : 0u;
+                        wv[e] = lo | hi;
+                    }
+                    bfr[tj] = __builtin_bit_cast(bf16x8, wv);
+                }
+            }
+#pragma unroll
+            for (int ti = 0; ti < FT; ti++)
+#pragma unroll
+                for (int tj = 0; tj < FT; tj++)
+                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ti], bfr[tj], acc[ti][tj], 0, 0, 0);
         }
-#pragma unroll
-        for (int ti = 0; ti < 4; ti++)
-#pragma unroll
-            for (int tj = 0; tj < 4; tj++)
-                acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ti], bfr[tj], acc[ti][tj], 0, 0, 0);
         __syncthreads();
+        if (more) {
+            WO_STORE_TILE();
+            __syncthreads();
+        }
     }
+#undef WO_LOAD_TILE
+#undef WO_STORE_TILE
 
     // epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each tile
 #pragma unroll
-    for (int ti = 0; ti < 4; ti++) {
+    for (int ti = 0; ti < FT; ti++) {
 #pragma unroll
-        for (int tj = 0; tj < 4; tj++) {
-            const int col = n0 + wn * 64 + tj * 16 + fr;
-            const int rb = m0 + wm * 64 + ti * 16 + (lane >> 4) * 4;
+        for (int tj = 0; tj < FT; tj++) {
+            const int col = n0 + wn * WT + tj * 16 + fr;
+            const int rb = m0 + wm * WT + ti * 16 + (lane >> 4) * 4;
             if (EPI == EPI_STORE) {
 #pragma unroll
                 for (int r = 0; r < 4; r++) g.C[(int64_t)(rb + r) * g.ldc + col] = acc[ti][tj][r];
@@ -466,17 +501,21 @@ __global__ __launch_bounds__(TOPK_THREADS) void topk_kernel(const void *src, int
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
+// 128 x 128 tiles when they give at least one workgroup per CU, else 64 x 64
 template <int AM, int BM, int EP>
 static hipError_t launch_gemm_t(const GemmArgs &g, hipStream_t s)
 {
-    dim3 grid(g.N / GBN, g.M / GBM);
-    hipLaunchKernelGGL((gemm_kernel<AM, BM, EP>), grid, dim3(256), 0, s, g);
+    if ((int64_t)(g.N / 128) * (g.M / 128) >= 256) {
+        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 128>), dim3(g.N / 128, g.M / 128), dim3(256), 0, s, g);
+    } else {
+        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 64>), dim3(g.N / 64, g.M / 64), dim3(256), 0, s, g);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_gemm(int amode, int bmode, int epi, const GemmArgs &g, hipStream_t s)
 {
-    if (g.M % GBM || g.N % GBN || g.K % GBK) return hipErrorInvalidValue;
+    if (g.M % 128 || g.N % 128 || g.K % GBK) return hipErrorInvalidValue;
     if (amode == A_ONEHOT && bmode == B_BF16 && epi == EPI_BIAS_GELU) return launch_gemm_t<A_ONEHOT, B_BF16, EPI_BIAS_GELU>(g, s);
     if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_BIAS_GELU) return launch_gemm_t<A_BF16, B_BF16, EPI_BIAS_GELU>(g, s);
     if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_STORE) return launch_gemm_t<A_BF16, B_BF16, EPI_STORE>(g, s);

@@ -25,7 +25,7 @@ enum { B_BF16 = 0, B_ONEHOT_T = 1 };
 enum { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_GELU_GRAD_T = 2 };
 
 struct GemmArgs {
-    int M, N, K;              // padded sizes (M, N multiples of 128, K of 32)
+    int M, N, K;              // padded sizes (M, N multiples of 128, K of 64)
     int M_real, K_real;       // rows of the zone operand that exist
     int n_cat;                // categories that exist: zone bytes of higher ones are ignored
     const uint16_t *A;        // A_BF16: [M][lda]
