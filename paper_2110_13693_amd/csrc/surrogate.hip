@@ -74,9 +74,12 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     constexpr int WT = TM / 2;                 // wave tile
     constexpr int FT = WT / 16;                // MFMA tiles per wave and dimension
     constexpr int NLD = TM * GBK / 8 / 256;    // 16-byte loads per thread per operand tile
-    __shared__ __align__(16) uint16_t As[(AMODE == A_BF16) ? TM * GLDK : 8];
-    __shared__ __align__(16) uint16_t Bs[(BMODE == B_BF16) ? TM * GLDK : 8];
-    __shared__ __align__(16) uint8_t Zs[(AMODE == A_ONEHOT) ? TM * 64 : (BMODE == B_ONEHOT_T ? GBK * 64 : 16)];
+    // operand tiles in two buffers: step k reads buffer k & 1 while the next
+    // step's operands are written to the other one
+    __shared__ __align__(16) uint16_t As[2][(AMODE == A_BF16) ? TM * GLDK : 8];
+    __shared__ __align__(16) uint16_t Bs[2][(BMODE == B_BF16) ? TM * GLDK : 8];
+    __shared__ __align__(16) uint8_t ZsA[(AMODE == A_ONEHOT) ? TM * 64 : 16];
+    __shared__ __align__(16) uint8_t ZsB[2][(BMODE == B_ONEHOT_T) ? GBK * 64 : 16];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
@@ -95,7 +98,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             const int r = c >> 2, part = c & 3;
             uint4 v = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
             if (m0 + r < g.M_real) v = *(const uint4 *)(g.zoneA + (int64_t)(m0 + r) * 64 + part * 16);
-            *(uint4 *)(&Zs[r * 64 + part * 16]) = v;
+            *(uint4 *)(&ZsA[r * 64 + part * 16]) = v;
         }
     }
 
@@ -119,30 +122,30 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             if ((k0_) + r < g.K_real) rz = *(const u32x4 *)(g.zoneB + (int64_t)((k0_) + r) * 64 + part * 16);    \
         }                                                                                                        \
     } while (0)
-#define WO_STORE_TILE()                                                                                          \
+#define WO_STORE_TILE(buf)                                                                                       \
     do {                                                                                                         \
         if (AMODE == A_BF16) {                                                                                   \
             _Pragma("unroll") for (int i = 0; i < NLD; i++) {                                                    \
                 const int c = tid + i * 256, r = c >> 3, part = c & 7;                                           \
-                *(u32x4 *)(&As[r * GLDK + part * 8]) = ra[i];                                                    \
+                *(u32x4 *)(&As[buf][r * GLDK + part * 8]) = ra[i];                                               \
             }                                                                                                    \
         }                                                                                                        \
         if (BMODE == B_BF16) {                                                                                   \
             _Pragma("unroll") for (int i = 0; i < NLD; i++) {                                                    \
                 const int c = tid + i * 256, r = c >> 3, part = c & 7;                                           \
-                *(u32x4 *)(&Bs[r * GLDK + part * 8]) = rbv[i];                                                   \
+                *(u32x4 *)(&Bs[buf][r * GLDK + part * 8]) = rbv[i];                                              \
             }                                                                                                    \
         } else {                                                                                                 \
-            *(u32x4 *)(&Zs[(tid >> 2) * 64 + (tid & 3) * 16]) = rz;                                              \
+            *(u32x4 *)(&ZsB[buf][(tid >> 2) * 64 + (tid & 3) * 16]) = rz;                                         \
         }                                                                                                        \
     } while (0)
 
     // one operand set per K step: the next one loads into registers while the
-    // current one is multiplied from LDS
+    // current one is multiplied from LDS, then goes to the other buffer
     WO_LOAD_TILE(0);
-    WO_STORE_TILE();
+    WO_STORE_TILE(0);
     __syncthreads();
-    for (int k0 = 0; k0 < g.K; k0 += GBK) {
+    for (int k0 = 0, cur = 0; k0 < g.K; k0 += GBK, cur ^= 1) {
         const bool more = k0 + GBK < g.K;
         WO_LOAD_TILE(more ? k0 + GBK : k0);          // unconditional, so the operands stay in registers
 #pragma unroll
@@ -152,10 +155,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             for (int ti = 0; ti < FT; ti++) {
                 const int row = wm * WT + ti * 16 + fr;
                 if (AMODE == A_BF16) {
-                    af[ti] = *(const bf16x8 *)(&As[row * GLDK + ks + fk]);
+                    af[ti] = *(const bf16x8 *)(&As[cur][row * GLDK + ks + fk]);
                 } else {
                     const int k = k0 + ks + fk;             // 8 | 64: one category per fragment
-                    const uint32_t z = (k >> 6) < g.n_cat ? (uint32_t)Zs[row * 64 + (k >> 6)] : 0xFFu;
+                    const uint32_t z = (k >> 6) < g.n_cat ? (uint32_t)ZsA[row * 64 + (k >> 6)] : 0xFFu;
                     af[ti] = one_hot8(z - (uint32_t)(k & 63));
                 }
             }
@@ -163,7 +166,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             for (int tj = 0; tj < FT; tj++) {
                 const int col = wn * WT + tj * 16 + fr;
                 if (BMODE == B_BF16) {
-                    bfr[tj] = *(const bf16x8 *)(&Bs[col * GLDK + ks + fk]);
+                    bfr[tj] = *(const bf16x8 *)(&Bs[cur][col * GLDK + ks + fk]);
                 } else {
                     const int n = n0 + col;                 // input feature = category*64 + zone
                     const int cc = n >> 6;
@@ -171,8 +174,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                     u32x4 wv;
 #pragma unroll
                     for (int e = 0; e < 4; e++) {
-                        const uint32_t lo = Zs[(ks + fk + 2 * e) * 64 + cc] == zz ? 0x3F80u : 0u;
-                        const uint32_t hi = Zs[(ks + fk + 2 * e + 1) * 64 + cc] == zz ? 0x3F800000u : 0u;
+                        const uint32_t lo = ZsB[cur][(ks + fk + 2 * e) * 64 + cc] == zz ? 0x3F80u : 0u;
+                        const uint32_t hi = ZsB[cur][(ks + fk + 2 * e + 1) * 64 + cc] == zz ? 0x3F800000u : 0u;
                         wv[e] = lo | hi;
                     }
                     bfr[tj] = __builtin_bit_cast(bf16x8, wv);
@@ -184,11 +187,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                 for (int tj = 0; tj < FT; tj++)
                     acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ti], bfr[tj], acc[ti][tj], 0, 0, 0);
         }
+        if (more) WO_STORE_TILE(cur ^ 1);
         __syncthreads();
-        if (more) {
-            WO_STORE_TILE();
-            __syncthreads();
-        }
     }
 #undef WO_LOAD_TILE
 #undef WO_STORE_TILE
