@@ -137,10 +137,12 @@ static __device__ __forceinline__ uint32_t next_open(const uint32_t *B, uint32_t
     return x + 32u - ffbh(win);        // x + 1 + highest set bit
 }
 
-// Instance of plan row p: the last one whose first row is <= p.
+// Instance of plan row p: from the per-plan table when there is one, else the
+// last instance whose first row is <= p.
 static __device__ __forceinline__ int instance_of(const EvalArgs &A, int64_t p)
 {
     if (A.n_inst <= 1) return 0;
+    if (A.plan_inst) return A.plan_inst[p];
     int lo = 0, hi = A.n_inst - 1;
     while (lo < hi) {
         const int mid = (lo + hi + 1) >> 1;

@@ -101,6 +101,11 @@ struct wo_wh {
     int main_mode = 0;                  // 0: one line per lane in the line pass, 1: one order per lane
     int32_t *d_work = nullptr;          // work list for the current plan map
     int64_t work_cap = 0;
+    std::vector<int32_t> work_host;     // what d_work holds (kept alive for the async upload)
+    int32_t *d_pinst = nullptr;         // instance of each plan row (several instances only)
+    int64_t pinst_cap = 0;
+    std::vector<int32_t> pinst_host;
+    std::vector<int64_t> pinst_map;     // plan map d_pinst was built for
     std::vector<int64_t> work_map;      // plan map the work list was built for
     std::atomic<int> busy{0};
 };
@@ -416,6 +421,7 @@ extern "C" wo_status wo_free_warehouse(wo_wh *wh)
     if (wh->d_map) (void)hipFree(wh->d_map);
     if (wh->d_err) (void)hipFree(wh->d_err);
     if (wh->d_work) (void)hipFree(wh->d_work);
+    if (wh->d_pinst) (void)hipFree(wh->d_pinst);
     delete wh;
     return WO_OK;
 }
@@ -453,7 +459,8 @@ static wo_status prepare_work(wo_wh *wh, const std::vector<int64_t> &map, int64_
         const int64_t cy = (int64_t)wh->inst[y].n_lines + 2ll * wh->inst[y].n_orders;
         return cx > cy;
     });
-    std::vector<int32_t> work;
+    std::vector<int32_t> &work = wh->work_host;
+    work.clear();
     work.reserve((size_t)n_plans);
     for (int32_t i : order)
         for (int64_t p = map[i]; p < map[i + 1]; p++) work.push_back((int32_t)p);
@@ -500,8 +507,27 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     if (!d_zone_of || !d_order_seq || !d_dist) return fail(WO_E_INVAL, "NULL device buffer");
     hipStream_t s = (hipStream_t)stream;
     if (map != wh->map_cached) {
-        HIP_TRY(hipMemcpyAsync(wh->d_map, map.data(), sizeof(int64_t) * map.size(), hipMemcpyHostToDevice, s));
         wh->map_cached = map;
+        HIP_TRY(hipMemcpyAsync(wh->d_map, wh->map_cached.data(), sizeof(int64_t) * map.size(),
+                               hipMemcpyHostToDevice, s));
+    }
+    // instance of every plan row, so that the kernel needs no search
+    if (wh->n_inst > 1 && (map != wh->pinst_map || wh->pinst_cap < n_plans)) {
+        if (n_plans > INT32_MAX) return fail(WO_E_RANGE, "too many plans");
+        if (wh->pinst_cap < n_plans) {
+            if (wh->d_pinst) (void)hipFree(wh->d_pinst);
+            wh->d_pinst = nullptr;
+            wh->pinst_cap = 0;
+            wo_status st = dev_alloc((void **)&wh->d_pinst, sizeof(int32_t) * (size_t)n_plans);
+            if (st) return st;
+            wh->pinst_cap = n_plans;
+        }
+        wh->pinst_host.resize((size_t)n_plans);
+        for (int32_t i = 0; i < wh->n_inst; i++)
+            for (int64_t p = map[i]; p < map[i + 1]; p++) wh->pinst_host[(size_t)p] = i;
+        HIP_TRY(hipMemcpyAsync(wh->d_pinst, wh->pinst_host.data(), sizeof(int32_t) * (size_t)n_plans,
+                               hipMemcpyHostToDevice, s));
+        wh->pinst_map = map;
     }
     const bool validate = env_flag("WO_VALIDATE", "1");
     if (validate) HIP_TRY(hipMemsetAsync(wh->d_err, 0, 4, s));
@@ -512,6 +538,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.n_plans = n_plans;
     a.plan_begin = wh->d_map;
     a.seq_base = wh->d_map + wh->n_inst + 1;
+    a.plan_inst = wh->n_inst > 1 ? wh->d_pinst : nullptr;
     a.lines = wh->d_lines;
     a.cnt = wh->d_cnt;
     a.grec = wh->d_grec;
@@ -557,6 +584,7 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     const int64_t *zero_map = (const int64_t *)((const char *)wh->d_err + 16);   // zeroed at load
     a.plan_begin = zero_map;
     a.seq_base = zero_map;
+    a.plan_inst = nullptr;
     a.lines = wh->d_lines;
     a.cnt = wh->d_cnt;
     a.grec = wh->d_grec;

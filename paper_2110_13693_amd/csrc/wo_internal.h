@@ -60,6 +60,7 @@ struct EvalArgs {
     int64_t n_plans;
     const int64_t *plan_begin;  // device [n_inst + 1]: plan rows of instance i (unused if n_inst == 1)
     const int64_t *seq_base;    // device [n_inst]: element offset of instance i's first sequence row
+    const int32_t *plan_inst;   // device [n_plans]: instance of each plan row (null: search plan_begin)
     const uint2 *lines;     // pooled arrays
     const uint8_t *cnt;
     const uint32_t *grec;
