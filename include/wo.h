@@ -145,18 +145,26 @@ wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans,
                         int32_t *d_dist, float *d_orders_per_window, void *stream);
 
 
-/* Launch configuration of the evaluation kernel for a handle: threads per
- * workgroup (128, 256 or 512), workgroups per CU (0 = as many as registers
- * and LDS allow), and the work distribution (0 = grid stride
- * over plan rows, 1 = a ticket queue over a work list that puts the plans of
- * the most expensive instances first -- useful for uneven batches), and the
- * mapping of the aisle-set pass (line_pass).  `ms` is
- * the measured time of one call when returned by the autotuner. */
+/* Launch configuration of the evaluation kernel for a handle:
+ *  - block_threads: threads per workgroup (64, 128, 256 or 512; one
+ *    workgroup evaluates one plan at a time);
+ *  - blocks_per_cu: workgroups per CU (0 = as many as registers and LDS
+ *    allow);
+ *  - queue: the work distribution (0 = grid stride over plan rows, 1 = a
+ *    ticket queue over a work list that puts the plans of the most
+ *    expensive instances first -- useful for uneven batches);
+ *  - line_pass: the mapping of the aisle-set pass;
+ *  - small_orders: plans of instances with at most this many orders (0 to
+ *    1024) are evaluated in a launch of their own with 64-thread
+ *    workgroups, sized by those instances' own LDS needs, so that many small
+ *    plans run per CU; 0 = one launch for every instance.  Default 1024.
+ * `ms` is the measured time of one call when returned by the autotuner. */
 typedef struct {
     int32_t block_threads;
     int32_t blocks_per_cu;
     int32_t queue;
     int32_t line_pass;   /* 0: one order line per lane (default), 1: one order per lane */
+    int32_t small_orders;
     float ms;
 } wo_eval_config;
 
@@ -173,10 +181,10 @@ wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, int64_t n_pla
                            wo_eval_config *best_out, wo_eval_config *h_all, int32_t *n_all);
 
 /* Graph capture: after one call with the same plan_offsets and n_plans (which
- * uploads the plan map and, with the queue, the work list), wo_eval_plans
- * enqueues kernels only (a ticket reset kernel and the evaluation kernel)
- * and may be captured into a HIP graph and replayed; WO_VALIDATE must be
- * unset while capturing. */
+ * uploads the plan map and the work lists), wo_eval_plans enqueues kernels
+ * only (ticket reset kernels and one or two evaluation launches) and may be
+ * captured into a HIP graph and replayed; WO_VALIDATE must be unset while
+ * capturing. */
 
 /* ------------------------------------------------------------------ */
 /* Learned surrogate and screening                                      */

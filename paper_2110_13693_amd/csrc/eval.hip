@@ -200,7 +200,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t &s_next = *(uint32_t *)(smem + LDS_TICKET);
-    constexpr int SEQ_CHUNK = 4096 / BLOCK;  // sequence positions per thread kept in registers
+    constexpr int SEQ_CHUNK = BLOCK >= 256 ? 4096 / BLOCK : 16;   // sequence positions per thread in registers
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     int loaded = -1;                        // instance whose tables sit in LDS
@@ -233,7 +233,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
         const uint32_t n_units = (uint32_t)I.n_units;
         const int64_t row = p - (A.n_inst > 1 ? A.plan_begin[ii] : 0);
         const uint16_t *seq = A.seq + A.seq_base[ii] + row * (int64_t)n;
-        const EvalLayout Ly = eval_layout(n, I.n_units, I.words, I.t_cap, I.chase_log2);
+        const EvalLayout Ly = eval_layout(n, I.n_units, I.words, I.t_cap, I.chase_log2, I.chase_lanes);
         uint32_t *zs = (uint32_t *)(smem + LDS_ZS);
         uint32_t *scan_a = (uint32_t *)(smem + Ly.red);
         uint32_t *scan_b = scan_a + 16;
@@ -406,7 +406,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                 lane_base[g] = base;
                 wbits[g] = wb;
                 segs[g] = g <= G ? s_g : n_units;
-                if (lanes <= (uint32_t)CHASE_LANES) {
+                if (lanes <= (uint32_t)I.chase_lanes) {
                     uint32_t m = wb, idx = base;
                     while (m) {
                         cand[idx++] = ((uint32_t)g << 26) | (s_g + (uint32_t)__builtin_ctz(m));
@@ -416,7 +416,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                 if (g == 0) misc[1] = (int)lanes;
             }
             __syncthreads();
-            if (G > 1 && misc[1] > CHASE_LANES) G = 1;    // uniform
+            if (G > 1 && misc[1] > I.chase_lanes) G = 1;  // uniform
 
             // ---- 4. chase ---------------------------------------------------
             const int CR2 = I.chase_log2;
@@ -742,6 +742,7 @@ static int max_blocks_t(uint32_t lds_bytes)
 int eval_max_blocks_per_cu(int block, uint32_t lds_bytes)
 {
     switch (block) {
+    case 64: return max_blocks_t<64>(lds_bytes);
     case 128: return max_blocks_t<128>(lds_bytes);
     case 256: return max_blocks_t<256>(lds_bytes);
     case 512: return max_blocks_t<512>(lds_bytes);
@@ -752,6 +753,7 @@ int eval_max_blocks_per_cu(int block, uint32_t lds_bytes)
 hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, hipStream_t s)
 {
     switch (block) {
+    case 64: return launch_eval_t<64>(a, lds_bytes, grid, s);
     case 128: return launch_eval_t<128>(a, lds_bytes, grid, s);
     case 256: return launch_eval_t<256>(a, lds_bytes, grid, s);
     case 512: return launch_eval_t<512>(a, lds_bytes, grid, s);

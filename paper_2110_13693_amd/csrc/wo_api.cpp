@@ -99,14 +99,23 @@ struct wo_wh {
     int per_cu = 0;                     // 0: as many as LDS allows
     int queue = 0;                      // 1: ticket queue over the cost-ordered work list
     int main_mode = 0;                  // 0: one line per lane in the line pass, 1: one order per lane
-    int32_t *d_work = nullptr;          // work list for the current plan map
-    int64_t work_cap = 0;
-    std::vector<int32_t> work_host;     // what d_work holds (kept alive for the async upload)
+    int small_orders = 1024;            // instances up to this size get a launch of 64-thread workgroups
+    // Work lists by launch class (0: the configured workgroups, 1: 64-thread
+    // workgroups for small instances): plan rows, most expensive instances
+    // first, and the LDS the class needs.
+    struct WorkClass {
+        int32_t *d_work = nullptr;
+        int64_t cap = 0;
+        std::vector<int32_t> host;      // what d_work holds (kept alive for the async upload)
+        int64_t n = 0;
+        uint32_t lds = 0;
+    } wc[2];
+    std::vector<int64_t> wc_map;        // plan map the work lists were built for
+    int wc_small = -1;                  // small_orders the work lists were built for
     int32_t *d_pinst = nullptr;         // instance of each plan row (several instances only)
     int64_t pinst_cap = 0;
     std::vector<int32_t> pinst_host;
     std::vector<int64_t> pinst_map;     // plan map d_pinst was built for
-    std::vector<int64_t> work_map;      // plan map the work list was built for
     std::atomic<int> busy{0};
 };
 
@@ -335,6 +344,12 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
                 break;
             }
         }
+        // room for the expected chase lanes with margin, in whole waves
+        {
+            const double lanes = 1.0 + (I.n_seg - 1) * cand;
+            int cl = ((int)std::ceil(1.3 * lanes + 16.0) + 63) / 64 * 64;
+            I.chase_lanes = std::min(CHASE_LANES, std::max(64, cl));
+        }
 
         // tours per LDS tile: the expected tour count with margin (more tours
         // take another pass over the lines), never more than the orders, and
@@ -343,10 +358,10 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         t_cap = std::min<int64_t>(t_cap, d.n_orders);
         t_cap = std::min<int64_t>(t_cap, 65535 / row_bytes(I.words) - 1);
         t_cap = std::max<int64_t>(t_cap, 1);
-        EvalLayout ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap, I.chase_log2);
+        EvalLayout ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap, I.chase_log2, I.chase_lanes);
         while (ly.total > wh->lds_max && t_cap > 1) {
             t_cap = t_cap / 2;
-            ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap, I.chase_log2);
+            ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap, I.chase_log2, I.chase_lanes);
         }
         I.t_cap = (int32_t)t_cap;
         if (ly.total > wh->lds_max)
@@ -420,7 +435,8 @@ extern "C" wo_status wo_free_warehouse(wo_wh *wh)
     if (wh->d_inst) (void)hipFree(wh->d_inst);
     if (wh->d_map) (void)hipFree(wh->d_map);
     if (wh->d_err) (void)hipFree(wh->d_err);
-    if (wh->d_work) (void)hipFree(wh->d_work);
+    for (auto &c : wh->wc)
+        if (c.d_work) (void)hipFree(c.d_work);
     if (wh->d_pinst) (void)hipFree(wh->d_pinst);
     delete wh;
     return WO_OK;
@@ -439,19 +455,30 @@ extern "C" wo_status wo_instance_info(const wo_wh *wh, int32_t i, int32_t *n_ord
 
 // Blocks to launch: `per_cu` workgroups per CU (or as many as the LDS allows,
 // at most 32 waves per CU), never more than there are plans.
-static int launch_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
+static int launch_grid(const wo_wh *wh, int block, int per_cu_cfg, uint32_t lds, int64_t n_plans)
 {
-    const int fit = eval_max_blocks_per_cu(wh->block, lds);
-    const int per_cu = wh->per_cu > 0 ? std::min(wh->per_cu, fit) : fit;
+    const int fit = eval_max_blocks_per_cu(block, lds);
+    const int per_cu = per_cu_cfg > 0 ? std::min(per_cu_cfg, fit) : fit;
     return (int)std::min<int64_t>(n_plans, (int64_t)wh->cu_count * per_cu);
 }
 
-// Work list for the queue: plans of the most expensive instances first
-// (longest-processing-time order; cost ~ lines + 2 * orders per plan).
+static int launch_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
+{
+    return launch_grid(wh, wh->block, wh->per_cu, lds, n_plans);
+}
+
+// Work lists by launch class, plans of the most expensive instances first
+// (longest-processing-time order; cost ~ lines + 2 * orders per plan).  With
+// small_orders > 0, instances of at most that many orders form class 1.
+static bool is_small(const wo_wh *wh, int32_t i)
+{
+    return wh->small_orders > 0 && wh->inst[i].n_orders <= wh->small_orders;
+}
+
 static wo_status prepare_work(wo_wh *wh, const std::vector<int64_t> &map, int64_t n_plans, hipStream_t s)
 {
-    if (map == wh->work_map && wh->work_cap >= n_plans) return WO_OK;
-    if (n_plans > INT32_MAX) return fail(WO_E_RANGE, "too many plans for the work queue");
+    if (map == wh->wc_map && wh->wc_small == wh->small_orders) return WO_OK;
+    if (n_plans > INT32_MAX) return fail(WO_E_RANGE, "too many plans for the work lists");
     std::vector<int32_t> order(wh->n_inst);
     for (int32_t i = 0; i < wh->n_inst; i++) order[i] = i;
     std::stable_sort(order.begin(), order.end(), [&](int32_t x, int32_t y) {
@@ -459,21 +486,29 @@ static wo_status prepare_work(wo_wh *wh, const std::vector<int64_t> &map, int64_
         const int64_t cy = (int64_t)wh->inst[y].n_lines + 2ll * wh->inst[y].n_orders;
         return cx > cy;
     });
-    std::vector<int32_t> &work = wh->work_host;
-    work.clear();
-    work.reserve((size_t)n_plans);
-    for (int32_t i : order)
-        for (int64_t p = map[i]; p < map[i + 1]; p++) work.push_back((int32_t)p);
-    if (wh->work_cap < n_plans) {
-        if (wh->d_work) (void)hipFree(wh->d_work);
-        wh->d_work = nullptr;
-        wh->work_cap = 0;
-        wo_status st = dev_alloc((void **)&wh->d_work, sizeof(int32_t) * (size_t)n_plans);
-        if (st) return st;
-        wh->work_cap = n_plans;
+    for (int c = 0; c < 2; c++) {
+        wo_wh::WorkClass &w = wh->wc[c];
+        w.host.clear();
+        w.lds = 0;
+        for (int32_t i : order) {
+            if ((int)is_small(wh, i) != c) continue;
+            for (int64_t p = map[i]; p < map[i + 1]; p++) w.host.push_back((int32_t)p);
+            if (map[i + 1] > map[i]) w.lds = std::max(w.lds, wh->lds[i]);
+        }
+        w.n = (int64_t)w.host.size();
+        if (w.n == 0) continue;
+        if (w.cap < w.n) {
+            if (w.d_work) (void)hipFree(w.d_work);
+            w.d_work = nullptr;
+            w.cap = 0;
+            wo_status st = dev_alloc((void **)&w.d_work, sizeof(int32_t) * (size_t)w.n);
+            if (st) return st;
+            w.cap = w.n;
+        }
+        HIP_TRY(hipMemcpyAsync(w.d_work, w.host.data(), sizeof(int32_t) * (size_t)w.n, hipMemcpyHostToDevice, s));
     }
-    HIP_TRY(hipMemcpyAsync(wh->d_work, work.data(), sizeof(int32_t) * work.size(), hipMemcpyHostToDevice, s));
-    wh->work_map = map;
+    wh->wc_map = map;
+    wh->wc_small = wh->small_orders;
     return WO_OK;
 }
 
@@ -554,13 +589,29 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.queue = 0;
     a.queue_ctr = (uint32_t *)((char *)wh->d_err + 48);
     a.work = nullptr;
-    if (wh->queue) {
+    bool any_small = false;
+    for (int32_t i = 0; i < wh->n_inst; i++) any_small |= is_small(wh, i) && map[i + 1] > map[i];
+    if (!any_small && !wh->queue) {
+        // one launch, grid stride over the plan rows
+        HIP_TRY(launch_eval(a, wh->lds_max, launch_grid(wh, wh->lds_max, n_plans), wh->block, s));
+    } else {
+        // one launch per class over its work list: the configured workgroups
+        // for the large instances, 64-thread ones for the small instances
         wo_status st = prepare_work(wh, map, n_plans, s);
         if (st) return st;
-        a.queue = 1;
-        a.work = wh->d_work;
+        for (int c = 0; c < 2; c++) {
+            const wo_wh::WorkClass &w = wh->wc[c];
+            if (w.n == 0) continue;
+            EvalArgs ac = a;
+            ac.n_plans = w.n;
+            ac.work = w.d_work;
+            ac.queue = wh->queue;
+            ac.queue_ctr = (uint32_t *)((char *)wh->d_err + 48 + 4 * c);
+            const int block = c ? 64 : wh->block;
+            const int per_cu = c ? 0 : wh->per_cu;
+            HIP_TRY(launch_eval(ac, w.lds, launch_grid(wh, block, per_cu, w.lds, w.n), block, s));
+        }
     }
-    HIP_TRY(launch_eval(a, wh->lds_max, launch_grid(wh, wh->lds_max, n_plans), wh->block, s));
     if (validate) {
         int32_t err = 0;
         HIP_TRY(hipMemcpyAsync(&err, wh->d_err, 4, hipMemcpyDeviceToHost, s));
@@ -612,17 +663,20 @@ int32_t wo::instance_count(const wo_wh *wh) { return wh->n_inst; }
 extern "C" wo_status wo_set_eval_config(wo_wh *wh, const wo_eval_config *cfg)
 {
     if (!wh || !cfg) return fail(WO_E_INVAL, "NULL argument");
-    if (cfg->block_threads != 128 && cfg->block_threads != 256 && cfg->block_threads != 512)
-        return fail(WO_E_INVAL, "block_threads must be 128, 256 or 512");
+    if (cfg->block_threads != 64 && cfg->block_threads != 128 && cfg->block_threads != 256 &&
+        cfg->block_threads != 512)
+        return fail(WO_E_INVAL, "block_threads must be 64, 128, 256 or 512");
     if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 32) return fail(WO_E_INVAL, "blocks_per_cu in [0, 32]");
     if (cfg->queue != 0 && cfg->queue != 1) return fail(WO_E_INVAL, "queue must be 0 or 1");
     if (cfg->line_pass != 0 && cfg->line_pass != 1) return fail(WO_E_INVAL, "line_pass must be 0 or 1");
+    if (cfg->small_orders < 0 || cfg->small_orders > 1024) return fail(WO_E_INVAL, "small_orders in [0, 1024]");
     Busy busy(&wh->busy);
     if (!busy.ok) return fail(WO_E_STATE, "handle is in use by another thread");
     wh->block = cfg->block_threads;
     wh->per_cu = cfg->blocks_per_cu;
     wh->queue = cfg->queue;
     wh->main_mode = cfg->line_pass;
+    wh->small_orders = cfg->small_orders;
     return WO_OK;
 }
 
@@ -633,6 +687,7 @@ extern "C" wo_status wo_get_eval_config(const wo_wh *wh, wo_eval_config *cfg)
     cfg->blocks_per_cu = wh->per_cu;
     cfg->queue = wh->queue;
     cfg->line_pass = wh->main_mode;
+    cfg->small_orders = wh->small_orders;
     cfg->ms = 0.f;
     return WO_OK;
 }
@@ -646,64 +701,69 @@ extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, in
     if (reps < 1) return fail(WO_E_INVAL, "reps must be >= 1");
     if (n_plans < 1) return fail(WO_E_INVAL, "need plans to time");
     hipStream_t s = (hipStream_t)stream;
-    const int saved_block = wh->block, saved_per_cu = wh->per_cu, saved_queue = wh->queue,
-              saved_mode = wh->main_mode;
+    const wo_eval_config saved{wh->block, wh->per_cu, wh->queue, wh->main_mode, wh->small_orders, 0.f};
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
-    wo_eval_config best{saved_block, saved_per_cu, saved_queue, saved_mode, 3.0e38f};
+    wo_eval_config best = saved;
+    best.ms = 3.0e38f;
     int count = 0;
     wo_status st = WO_OK;
-    const int blocks[3] = {128, 256, 512};
-    const int per_cus[6] = {1, 2, 3, 4, 6, 8};
-    for (int bi = 0; bi < 3 && !st; bi++) {
-        for (int pi = 0; pi < 6 && !st; pi++) {
+    auto apply = [&](const wo_eval_config &c) {
+        wh->block = c.block_threads;
+        wh->per_cu = c.blocks_per_cu;
+        wh->queue = c.queue;
+        wh->main_mode = c.line_pass;
+        wh->small_orders = c.small_orders;
+    };
+    // time one configuration: a warm-up call (which also builds the work
+    // lists outside the timed region), then the best of `reps`
+    auto time_cfg = [&](wo_eval_config c) -> wo_status {
+        apply(c);
+        wo_status r = wo_eval_plans(wh, plan_offsets, n_plans, d_zone_of, d_order_seq, d_dist, nullptr, stream);
+        if (r) return r;
+        float ms_best = 3.0e38f;
+        for (int k = 0; k < reps; k++) {
+            if (hipEventRecord(e0, s) != hipSuccess) return fail(WO_E_DEVICE, "hipEventRecord failed");
+            if ((r = wo_eval_plans(wh, plan_offsets, n_plans, d_zone_of, d_order_seq, d_dist, nullptr, stream)))
+                return r;
+            float ms = 0.f;
+            if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
+                hipEventElapsedTime(&ms, e0, e1) != hipSuccess)
+                return fail(WO_E_DEVICE, "event timing failed");
+            ms_best = std::min(ms_best, ms);
+        }
+        c.ms = ms_best;
+        if (h_all && n_all && count < *n_all) h_all[count] = c;
+        count++;
+        if (ms_best < best.ms) best = c;
+        return WO_OK;
+    };
+    const int blocks[4] = {64, 128, 256, 512};
+    const int per_cus[8] = {1, 2, 3, 4, 6, 8, 12, 16};
+    for (int bi = 0; bi < 4 && !st; bi++) {
+        for (int pi = 0; pi < 8 && !st; pi++) {
             const int blk = blocks[bi], pc = per_cus[pi];
             if (pc > eval_max_blocks_per_cu(blk, wh->lds_max)) continue;      // registers and LDS
-            for (int qm = 0; qm < 4 && !st; qm++) {
-                const int q = qm & 1, mode = qm >> 1;
-                wh->block = blk;
-                wh->per_cu = pc;
-                wh->queue = q;
-                wh->main_mode = mode;
-                // warm-up (also builds the work list outside the timed region)
-                if ((st = wo_eval_plans(wh, plan_offsets, n_plans, d_zone_of, d_order_seq, d_dist, nullptr, stream)))
-                    break;
-                float ms_best = 3.0e38f;
-                for (int r = 0; r < reps && !st; r++) {
-                    if (hipEventRecord(e0, s) != hipSuccess) { st = fail(WO_E_DEVICE, "hipEventRecord failed"); break; }
-                    if ((st = wo_eval_plans(wh, plan_offsets, n_plans, d_zone_of, d_order_seq, d_dist, nullptr,
-                                            stream)))
-                        break;
-                    float ms = 0.f;
-                    if (hipEventRecord(e1, s) != hipSuccess || hipEventSynchronize(e1) != hipSuccess ||
-                        hipEventElapsedTime(&ms, e0, e1) != hipSuccess) {
-                        st = fail(WO_E_DEVICE, "event timing failed");
-                        break;
-                    }
-                    ms_best = std::min(ms_best, ms);
-                }
-                if (st) break;
-                wo_eval_config c{blk, pc, q, mode, ms_best};
-                if (h_all && n_all && count < *n_all) h_all[count] = c;
-                count++;
-                if (ms_best < best.ms) best = c;
-            }
+            for (int qm = 0; qm < 4 && !st; qm++)
+                st = time_cfg(wo_eval_config{blk, pc, qm & 1, qm >> 1, saved.small_orders, 0.f});
         }
+    }
+    // the small-instance launch on and off, with the best configuration
+    bool any_small = false;
+    for (int32_t i = 0; i < wh->n_inst; i++) any_small |= wh->inst[i].n_orders <= 1024;
+    if (!st && any_small) {
+        wo_eval_config c = best;
+        c.small_orders = saved.small_orders > 0 ? 0 : 1024;
+        st = time_cfg(c);
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
     if (st) {
-        wh->block = saved_block;
-        wh->per_cu = saved_per_cu;
-        wh->queue = saved_queue;
-        wh->main_mode = saved_mode;
+        apply(saved);
         return st;
     }
-    wh->block = best.block_threads;
-    wh->per_cu = best.blocks_per_cu;
-    wh->queue = best.queue;
-    wh->main_mode = best.line_pass;
+    apply(best);
     if (best_out) *best_out = best;
     if (n_all) *n_all = count;
     return WO_OK;

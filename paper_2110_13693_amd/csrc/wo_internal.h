@@ -30,7 +30,7 @@ struct InstDev {
     int32_t n_seg;          // item-space segments chased in parallel (1 = serial chain)
     int32_t n_lines_pad;    // line records stored: n_lines rounded up to whole groups of LINE_PAD
     int32_t chase_log2;     // log2 of the opening records per chase lane
-    int32_t pad0;
+    int32_t chase_lanes;    // chase lanes the LDS layout holds (a multiple of 64, <= CHASE_LANES)
     // uint2 line records [n_lines_pad]: x = (rank << shift) | (4*cat) << 24,
     // y = LDS byte offset of the order's tour entry (2 * order + the tour
     // table's offset); the padding records point at the dummy entry of order
@@ -78,8 +78,9 @@ struct EvalArgs {
     const int32_t *work;    // work item -> plan row (null: identity)
 };
 
-// Parallel next-fit: lanes that chase candidate tour chains; each records up
-// to 2^chase_log2 openings (an instance parameter, at most 2^MAX_CHASE_LOG2).
+// Parallel next-fit: lanes that chase candidate tour chains (at most
+// CHASE_LANES; an instance holds room for chase_lanes of them); each records
+// up to 2^chase_log2 openings (at most 2^MAX_CHASE_LOG2).
 constexpr int CHASE_LANES = 256;
 constexpr int MAX_CHASE_LOG2 = 6;
 constexpr int MAX_SEG = 64;
@@ -121,15 +122,16 @@ __host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * ((uin
 __host__ __device__ inline uint32_t cnt_bytes(int32_t n_orders) { return align16((uint32_t)n_orders + 2u); }
 
 __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_units, int32_t words,
-                                                  int32_t t_cap, int32_t chase_log2)
+                                                  int32_t t_cap, int32_t chase_log2, int32_t chase_lanes)
 {
+    const uint32_t cl = (uint32_t)chase_lanes;
     EvalLayout L;
     const uint32_t n = (uint32_t)n_orders, nb = bitmap_words(n_units);
     uint32_t c = LDS_REGION;
-    L.rec = c;   c = align16(c + (2u * CHASE_LANES << chase_log2));
-    L.nrec = c;  c = align16(c + 4u * CHASE_LANES);
-    L.nxt = c;   c = align16(c + 4u * CHASE_LANES);
-    L.cand = c;  c = align16(c + 4u * CHASE_LANES);
+    L.rec = c;   c = align16(c + (2u * cl << chase_log2));
+    L.nrec = c;  c = align16(c + 4u * cl);
+    L.nxt = c;   c = align16(c + 4u * cl);
+    L.cand = c;  c = align16(c + 4u * cl);
     const uint32_t rows = align16(LDS_REGION + row_bytes(words) * (uint32_t)(t_cap + 1));
     const uint32_t seen = align16(LDS_REGION + 4u * ((n + 31) / 32));
     uint32_t b = c > rows ? c : rows;

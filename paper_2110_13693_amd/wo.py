@@ -44,7 +44,8 @@ class WoError(RuntimeError):
 
 class wo_eval_config(ctypes.Structure):
     _fields_ = [("block_threads", ctypes.c_int32), ("blocks_per_cu", ctypes.c_int32),
-                ("queue", ctypes.c_int32), ("line_pass", ctypes.c_int32), ("ms", ctypes.c_float)]
+                ("queue", ctypes.c_int32), ("line_pass", ctypes.c_int32), ("small_orders", ctypes.c_int32),
+                ("ms", ctypes.c_float)]
 
 
 class wo_search_params(ctypes.Structure):
@@ -417,8 +418,9 @@ def wo_search_population(s: Search, zone_of=None, seq=None, dist=None, last_kept
 # ---------------------------------------------------------------------------
 
 def wo_set_eval_config(wh: Warehouse, block_threads: int, blocks_per_cu: int = 0, queue: int = 0,
-                       line_pass: int = 0):
-    cfg = wo_eval_config(int(block_threads), int(blocks_per_cu), int(queue), int(line_pass), 0.0)
+                       line_pass: int = 0, small_orders: int = 1024):
+    cfg = wo_eval_config(int(block_threads), int(blocks_per_cu), int(queue), int(line_pass), int(small_orders),
+                         0.0)
     _check(lib().wo_set_eval_config(wh.handle, ctypes.byref(cfg)))
 
 
@@ -426,7 +428,7 @@ def wo_get_eval_config(wh: Warehouse) -> dict:
     cfg = wo_eval_config()
     _check(lib().wo_get_eval_config(wh.handle, ctypes.byref(cfg)))
     return {"block_threads": cfg.block_threads, "blocks_per_cu": cfg.blocks_per_cu, "queue": cfg.queue,
-            "line_pass": cfg.line_pass}
+            "line_pass": cfg.line_pass, "small_orders": cfg.small_orders}
 
 
 def wo_autotune_eval(wh: Warehouse, zone_of, order_seq, dist, plan_offsets=None, reps: int = 3, stream=None):
@@ -434,12 +436,12 @@ def wo_autotune_eval(wh: Warehouse, zone_of, order_seq, dist, plan_offsets=None,
     n = int(zone_of.shape[0])
     offs = None if plan_offsets is None else np.ascontiguousarray(plan_offsets, dtype=np.int64)
     best = wo_eval_config()
-    allc = (wo_eval_config * 64)()
-    cnt = ctypes.c_int32(64)
+    allc = (wo_eval_config * 256)()
+    cnt = ctypes.c_int32(256)
     _check(lib().wo_autotune_eval(wh.handle, None if offs is None else offs.ctypes.data, n,
                                   _ptr(zone_of, 1, "zone_of"), _ptr(order_seq, 2, "order_seq"),
                                   _ptr(dist, 4, "dist"), int(reps), ctypes.c_void_p(_stream_handle(stream)),
                                   ctypes.byref(best), allc, ctypes.byref(cnt)))
     conv = lambda c: {"block_threads": c.block_threads, "blocks_per_cu": c.blocks_per_cu, "queue": c.queue,
-                      "line_pass": c.line_pass, "ms": c.ms}
-    return conv(best), [conv(allc[i]) for i in range(min(cnt.value, 64))]
+                      "line_pass": c.line_pass, "small_orders": c.small_orders, "ms": c.ms}
+    return conv(best), [conv(allc[i]) for i in range(min(cnt.value, 256))]

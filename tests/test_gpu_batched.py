@@ -97,6 +97,39 @@ def test_block_sizes_agree(block, queue):
 
 
 @pytest.mark.parametrize("queue", [0, 1])
+def test_small_instance_launch_matches_single_launch(queue):
+    # instances of up to 1,024 orders go to a launch of 64-thread workgroups;
+    # switching that off (small_orders = 0) must not change any result
+    wo = _wo()
+    insts, Z, S, offs = _batch(40, 6, seed=6)
+    assert any(i.n_orders <= 1024 for i in insts) and any(i.n_orders > 1024 for i in insts)
+    wh = wo.wo_load_warehouse(insts)
+    z, s = _dev(Z, S)
+    wo.wo_set_eval_config(wh, 256, 0, queue, 0, 1024)
+    d_split, t_split = _run(wo, wh, z, s, offs)
+    wo.wo_set_eval_config(wh, 256, 0, queue, 0, 0)
+    d_one, t_one = _run(wo, wh, z, s, offs)
+    assert np.array_equal(d_split, d_one) and np.array_equal(t_split, t_one)
+    _check_sample(insts, Z, S, offs, d_split, t_split, 6, range(0, len(d_split), 5))
+    wh.free()
+
+
+def test_64_thread_workgroups_all_instances():
+    # every instance in 64-thread workgroups, including those with more orders
+    # than one wave keeps in registers
+    wo = _wo()
+    insts, Z, S, offs = _batch(24, 6, seed=7)
+    wh = wo.wo_load_warehouse(insts)
+    z, s = _dev(Z, S)
+    d_ref, t_ref = _run(wo, wh, z, s, offs)
+    wo.wo_set_eval_config(wh, 64, 0, 1, 0, 0)
+    d, t = _run(wo, wh, z, s, offs)
+    assert np.array_equal(d, d_ref) and np.array_equal(t, t_ref)
+    _check_sample(insts, Z, S, offs, d, t, 6, range(0, len(d), 7))
+    wh.free()
+
+
+@pytest.mark.parametrize("queue", [0, 1])
 def test_graph_capture_replays(queue):
     import torch
     wo = _wo()
