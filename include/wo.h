@@ -156,8 +156,10 @@ wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans,
  *  - line_pass: the mapping of the aisle-set pass;
  *  - small_orders: plans of instances with at most this many orders (0 to
  *    1024) are evaluated in a launch of their own with 64-thread
- *    workgroups, sized by those instances' own LDS needs, so that many small
- *    plans run per CU; 0 = one launch for every instance.  Default 1024.
+ *    workgroups, and those with at most twice as many in one with
+ *    128-thread workgroups, each sized by its instances' own LDS needs, so
+ *    that many small plans run per CU; 0 = one launch for every instance.
+ *    Default 1024.
  * `ms` is the measured time of one call when returned by the autotuner. */
 typedef struct {
     int32_t block_threads;

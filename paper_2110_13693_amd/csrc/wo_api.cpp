@@ -101,15 +101,16 @@ struct wo_wh {
     int main_mode = 0;                  // 0: one line per lane in the line pass, 1: one order per lane
     int small_orders = 1024;            // instances up to this size get a launch of 64-thread workgroups
     // Work lists by launch class (0: the configured workgroups, 1: 64-thread
-    // workgroups for small instances): plan rows, most expensive instances
-    // first, and the LDS the class needs.
+    // workgroups for instances of at most small_orders orders, 2: 128-thread
+    // workgroups for instances of at most twice that): plan rows, most
+    // expensive instances first, and the LDS the class needs.
     struct WorkClass {
         int32_t *d_work = nullptr;
         int64_t cap = 0;
         std::vector<int32_t> host;      // what d_work holds (kept alive for the async upload)
         int64_t n = 0;
         uint32_t lds = 0;
-    } wc[2];
+    } wc[3];
     std::vector<int64_t> wc_map;        // plan map the work lists were built for
     int wc_small = -1;                  // small_orders the work lists were built for
     int32_t *d_pinst = nullptr;         // instance of each plan row (several instances only)
@@ -469,11 +470,15 @@ static int launch_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
 
 // Work lists by launch class, plans of the most expensive instances first
 // (longest-processing-time order; cost ~ lines + 2 * orders per plan).  With
-// small_orders > 0, instances of at most that many orders form class 1.
-static bool is_small(const wo_wh *wh, int32_t i)
+// small_orders > 0, instances of at most that many orders form class 1 and
+// those of at most twice as many class 2.
+static int class_of(const wo_wh *wh, int32_t i)
 {
-    return wh->small_orders > 0 && wh->inst[i].n_orders <= wh->small_orders;
+    const int n = wh->inst[i].n_orders, s = wh->small_orders;
+    if (s <= 0) return 0;
+    return n <= s ? 1 : (n <= 2 * s ? 2 : 0);
 }
+static const int class_block[3] = {0, 64, 128};   // 0: the configured block size
 
 static wo_status prepare_work(wo_wh *wh, const std::vector<int64_t> &map, int64_t n_plans, hipStream_t s)
 {
@@ -486,12 +491,12 @@ static wo_status prepare_work(wo_wh *wh, const std::vector<int64_t> &map, int64_
         const int64_t cy = (int64_t)wh->inst[y].n_lines + 2ll * wh->inst[y].n_orders;
         return cx > cy;
     });
-    for (int c = 0; c < 2; c++) {
+    for (int c = 0; c < 3; c++) {
         wo_wh::WorkClass &w = wh->wc[c];
         w.host.clear();
         w.lds = 0;
         for (int32_t i : order) {
-            if ((int)is_small(wh, i) != c) continue;
+            if (class_of(wh, i) != c) continue;
             for (int64_t p = map[i]; p < map[i + 1]; p++) w.host.push_back((int32_t)p);
             if (map[i + 1] > map[i]) w.lds = std::max(w.lds, wh->lds[i]);
         }
@@ -590,16 +595,16 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.queue_ctr = (uint32_t *)((char *)wh->d_err + 48);
     a.work = nullptr;
     bool any_small = false;
-    for (int32_t i = 0; i < wh->n_inst; i++) any_small |= is_small(wh, i) && map[i + 1] > map[i];
+    for (int32_t i = 0; i < wh->n_inst; i++) any_small |= class_of(wh, i) != 0 && map[i + 1] > map[i];
     if (!any_small && !wh->queue) {
         // one launch, grid stride over the plan rows
         HIP_TRY(launch_eval(a, wh->lds_max, launch_grid(wh, wh->lds_max, n_plans), wh->block, s));
     } else {
         // one launch per class over its work list: the configured workgroups
-        // for the large instances, 64-thread ones for the small instances
+        // for the large instances, 64- and 128-thread ones for the small ones
         wo_status st = prepare_work(wh, map, n_plans, s);
         if (st) return st;
-        for (int c = 0; c < 2; c++) {
+        for (int c = 0; c < 3; c++) {
             const wo_wh::WorkClass &w = wh->wc[c];
             if (w.n == 0) continue;
             EvalArgs ac = a;
@@ -607,7 +612,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
             ac.work = w.d_work;
             ac.queue = wh->queue;
             ac.queue_ctr = (uint32_t *)((char *)wh->d_err + 48 + 4 * c);
-            const int block = c ? 64 : wh->block;
+            const int block = c ? class_block[c] : wh->block;
             const int per_cu = c ? 0 : wh->per_cu;
             HIP_TRY(launch_eval(ac, w.lds, launch_grid(wh, block, per_cu, w.lds, w.n), block, s));
         }
