@@ -246,7 +246,8 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
         uint8_t *cnt = (uint8_t *)(smem + Ly.cnt);
         uint16_t *tour = (uint16_t *)(smem + Ly.tour);
         uint32_t *B = (uint32_t *)(smem + Ly.B);
-        uint32_t *F = (uint32_t *)(smem + Ly.F);
+        uint32_t *P = (uint32_t *)(smem + Ly.P);
+        uint32_t *pref = (uint32_t *)(smem + Ly.pref);
         uint16_t *crec = (uint16_t *)(smem + Ly.rec);
         uint32_t *cnrec = (uint32_t *)(smem + Ly.nrec);
         uint32_t *cnxt = (uint32_t *)(smem + Ly.nxt);
@@ -386,6 +387,13 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
             if (cmax > Q) misc[0] = 1;
             __syncthreads();
 
+            // order starts per unit word, for the position of an opening unit
+            const uint32_t nbw = bitmap_words((int32_t)n_units);
+            const uint32_t wpt = (nbw + BLOCK - 1) / BLOCK;
+            const uint32_t w0 = min(nbw, (uint32_t)tid * wpt), w1 = min(nbw, w0 + wpt);
+            uint32_t pc = 0;
+            for (uint32_t w = w0; w < w1; w++) pc += __popc(B[w]);
+
             // ---- 3. segments and their candidate entries (wave 0) --------
             int G = (misc[0] || I.n_seg <= 1) ? 1 : I.n_seg;   // uniform
             if (G > 1 && tid < 64) {
@@ -415,7 +423,20 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                 }
                 if (g == 0) misc[1] = (int)lanes;
             }
-            __syncthreads();
+            {
+                // the scan's barrier also publishes the segment tables
+                uint32_t n_starts;
+                uint32_t base = block_excl_scan<BLOCK>(pc, scan_a, &n_starts);
+                for (uint32_t w = w0; w < w1; w++) {
+                    pref[w] = base;
+                    base += __popc(B[w]);
+                }
+            }
+            // position in the sequence of the order that starts at unit x
+            auto pos_of = [&](uint32_t x) -> uint32_t {
+                const uint32_t w = x >> 5;
+                return pref[w] + __popc(B[w] & ~(0xFFFFFFFFu << (x & 31u)));
+            };
             if (G > 1 && misc[1] > I.chase_lanes) G = 1;  // uniform
 
             // ---- 4. chase ---------------------------------------------------
@@ -480,8 +501,8 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                         const int g = idx >> CR2, k = idx & ((1 << CR2) - 1);
                         const uint32_t l = true_lane[g];
                         if ((uint32_t)k < cnrec[l]) {
-                            const uint32_t x = segs[g] + crec[(l << CR2) + k];
-                            atomicOr(&F[x >> 5], 1u << (x & 31u));
+                            const uint32_t r = pos_of(segs[g] + crec[(l << CR2) + k]);
+                            atomicOr(&P[r >> 5], 1u << (r & 31u));
                         }
                     }
                 } else {
@@ -490,10 +511,12 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
             }
             if (G == 1) {
                 // serial chain (also handles orders larger than the capacity)
+                __syncthreads();                         // the start counts
                 if (tid == 0) {
                     uint32_t x = 0;
                     while (x < n_units) {
-                        F[x >> 5] |= 1u << (x & 31u);
+                        const uint32_t r = pos_of(x);
+                        P[r >> 5] |= 1u << (r & 31u);
                         const uint32_t win = bits_at(B, x + 1) & maskQ;
                         if (win) {
                             x = x + 32u - ffbh(win);
@@ -511,19 +534,13 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
             uint32_t opm = 0;                            // bit k: position b0 + k opens a tour
             uint32_t n_open = 0;
             if (one_piece) {
-                uint32_t run = run0;
-#pragma unroll
-                for (int k = 0; k < SEQ_CHUNK; k++) {
-                    opm |= ((F[run >> 5] >> (run & 31u)) & 1u) << k;
-                    run += CS(k);
-                }
-                if (nv < 32) opm &= (1u << nv) - 1u;
+                opm = bits_at(P, (uint32_t)b0) & ~(0xFFFFFFFFu << nv);   // nv <= 16
                 n_open = __popc(opm);
             } else {
-                uint32_t run = run0;
-                for (int i = b0; i < b1; i++) {
-                    n_open += (F[run >> 5] >> (run & 31u)) & 1u;
-                    run += cnt[min((uint32_t)seq[i], (uint32_t)(n - 1))];
+                for (int i = b0; i < b1; i += 32) {
+                    const int m = min(32, b1 - i);
+                    const uint32_t bits = bits_at(P, (uint32_t)i);
+                    n_open += __popc(m == 32 ? bits : bits & ~(0xFFFFFFFFu << m));
                 }
             }
             // the rows of the tile are free once the flags are set
@@ -547,11 +564,9 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                         tour[SV(k)] = (uint16_t)min(tr, dummy);
                     }
                 } else {
-                    uint32_t run = run0;
                     for (int i = b0; i < b1; i++) {
                         const uint32_t o = min((uint32_t)seq[i], (uint32_t)(n - 1));
-                        t += (F[run >> 5] >> (run & 31u)) & 1u;
-                        run += cnt[o];
+                        t += (P[i >> 5] >> (i & 31)) & 1u;
                         const uint32_t rel = t - t0;
                         tour[o] = (uint16_t)(rel < (uint32_t)T ? rel * RB : dummy);
                     }

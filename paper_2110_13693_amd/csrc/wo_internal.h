@@ -106,7 +106,7 @@ constexpr uint32_t LDS_REGION = 272;
 // plus one dummy row.
 struct EvalLayout {
     uint32_t rec, nrec, nxt, cand;     // chase phase (inside the region)
-    uint32_t red, misc, seg, cnt, tour, B, F;
+    uint32_t red, misc, seg, cnt, tour, pref, B, P;
     uint32_t total;
 };
 
@@ -141,8 +141,9 @@ __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_un
     L.seg = b;   b = align16(b + 4 * 4 * (MAX_SEG + 1));   // lane_base | wbits | true_lane | seg start
     L.cnt = b;   b += cnt_bytes(n_orders);
     L.tour = b;  b = align16(b + 2 * (n + 2));            // + dummy entry n, sink entry n + 1
+    L.pref = b;  b = align16(b + 4 * nb);               // order starts below each unit word
     L.B = b;     b = align16(b + 4 * nb);
-    L.F = b;     b = align16(b + 4 * nb);
+    L.P = b;     b = align16(b + 4 * (n / 32 + 3));      // tour openings by sequence position
     L.total = b;
     return L;
 }
