@@ -185,16 +185,6 @@ typedef __attribute__((address_space(3))) uint16_t lds_u16;
 static __device__ __forceinline__ lds_u32 *lds32(uint32_t a) { return (lds_u32 *)(size_t)a; }
 static __device__ __forceinline__ lds_u16 *lds16(uint32_t a) { return (lds_u16 *)(size_t)a; }
 
-// One line of the aisle pass: `ls` is its scaled location, `tb` the byte
-// offset of its tour's row.
-static __device__ __forceinline__ void line_update(uint32_t ls, uint32_t tb, uint32_t magic)
-{
-    const uint32_t a = mulhi24(ls, magic);
-    __hip_atomic_fetch_or(lds32(LDS_REGION + 4u + tb + ((a >> 5) << 2)), 1u << (a & 31u), __ATOMIC_RELAXED,
-                          __HIP_MEMORY_SCOPE_WORKGROUP);
-    __hip_atomic_fetch_max(lds32(LDS_REGION + tb), ls, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-}
-
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
 {
@@ -619,14 +609,34 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                         uint32_t tb[U], zv[U];
 #pragma unroll
                         for (int u = 0; u < U; u++) v[u] = lines[gi * LINE_PAD + u * 64];
-                        // all table reads of the group before its atomics
+                        // all table reads of the group before its atomics; a
+                        // lane's slots hold consecutive lines, so an order's
+                        // tour entry is read once and its farthest location
+                        // is raised once per run of its lines
 #pragma unroll
                         for (int u = 0; u < U; u++) {
-                            tb[u] = *lds16(v[u].y);
+                            uint32_t t = 0;
+                            if (u == 0 || v[u].y != v[u - 1].y) t = *lds16(v[u].y);
+                            tb[u] = t;
                             zv[u] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(v[u].x >> 24), zsv);
                         }
 #pragma unroll
-                        for (int u = 0; u < U; u++) line_update(v[u].x + zv[u], tb[u], magic);
+                        for (int u = 1; u < U; u++)
+                            if (v[u].y == v[u - 1].y) tb[u] = tb[u - 1];
+                        uint32_t far = 0;
+#pragma unroll
+                        for (int u = 0; u < U; u++) {
+                            const uint32_t ls = v[u].x + zv[u];
+                            const uint32_t a = mulhi24(ls, magic);
+                            __hip_atomic_fetch_or(lds32(LDS_REGION + 4u + tb[u] + ((a >> 5) << 2)), 1u << (a & 31u),
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                            far = max(far, ls);
+                            if (u == U - 1 || v[u + 1].y != v[u].y) {
+                                __hip_atomic_fetch_max(lds32(LDS_REGION + tb[u]), far, __ATOMIC_RELAXED,
+                                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                                far = 0;
+                            }
+                        }
                     }
                 } else {
                     // one order per lane: its row looked up once, its farthest
