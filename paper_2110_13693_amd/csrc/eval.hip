@@ -130,11 +130,21 @@ static __device__ __forceinline__ uint32_t bits_at(const uint32_t *B, uint32_t x
     return __builtin_amdgcn_alignbit(B[w + 1], B[w], x & 31u);
 }
 
-// Next tour opening after a tour opened at unit x (no order larger than Q).
+// Leading zeros of a word by v_ffbh_u32, which gives all ones for 0.
+static __device__ __forceinline__ uint32_t ffbh_raw(uint32_t x)
+{
+    uint32_t r;
+    asm("v_ffbh_u32 %0, %1" : "=v"(r) : "v"(x));
+    return r;
+}
+
+// Next tour opening after a tour opened at unit x.  With no order larger
+// than Q the window (x, x + Q] holds the next order start (or the sentinel);
+// an empty window would move x by 33, never back.
 static __device__ __forceinline__ uint32_t next_open(const uint32_t *B, uint32_t x, uint32_t maskQ)
 {
     const uint32_t win = bits_at(B, x + 1) & maskQ;
-    return x + 32u - ffbh(win);        // x + 1 + highest set bit
+    return x + 32u - ffbh_raw(win);    // x + 1 + highest set bit
 }
 
 // Instance of plan row p: from the per-plan table when there is one, else the
@@ -439,15 +449,18 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                     uint32_t x = cv & 0x3FFFFFFu;
                     const uint32_t s_g = segs[g];
                     const uint32_t s_e = segs[g + 1];
-                    uint16_t *r = crec + (l << CR2);
-                    uint32_t nr = 0;
-                    r[nr++] = (uint16_t)(x - s_g);
-                    for (;;) {
+                    // one loop exit; records past the last slot overwrite it
+                    // and send the plan to the serial chain
+                    const uint32_t rb = Ly.rec + ((uint32_t)l << (CR2 + 1));
+                    const uint32_t rl = rb + (2u << CR2) - 2u;
+                    uint32_t ra = rb;
+                    do {
+                        *lds16(min(ra, rl)) = (uint16_t)(x - s_g);
+                        ra += 2u;
                         x = next_open(B, x, maskQ);
-                        if (x >= s_e) break;
-                        if (nr == (1u << CR2)) { misc[2] = 1; break; }
-                        r[nr++] = (uint16_t)(x - s_g);
-                    }
+                    } while (x < s_e);
+                    const uint32_t nr = (ra - rb) >> 1;
+                    if (nr > (1u << CR2)) misc[2] = 1;
                     cnrec[l] = nr;
                     // the lane of the next segment whose candidate is this exit
                     uint32_t nx = 0xFFFFFFFFu;
