@@ -624,18 +624,21 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                         for (int u = 0; u < U; u++) v[u] = lines[gi * LINE_PAD + u * 64];
                         // all table reads of the group before its atomics; a
                         // lane's slots hold consecutive lines, so an order's
-                        // tour entry is read once and its farthest location
-                        // is raised once per run of its lines
+                        // tour entry is read once (bit 31 of y marks the first
+                        // slot of its run) and its farthest location is raised
+                        // once per run
+                        bool first[U];
 #pragma unroll
                         for (int u = 0; u < U; u++) {
+                            first[u] = u == 0 || (int32_t)v[u].y < 0;
                             uint32_t t = 0;
-                            if (u == 0 || v[u].y != v[u - 1].y) t = *lds16(v[u].y);
+                            if (first[u]) t = *lds16(v[u].y & 0x7FFFFFFFu);
                             tb[u] = t;
                             zv[u] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(v[u].x >> 24), zsv);
                         }
 #pragma unroll
                         for (int u = 1; u < U; u++)
-                            if (v[u].y == v[u - 1].y) tb[u] = tb[u - 1];
+                            if (!first[u]) tb[u] = tb[u - 1];
                         uint32_t far = 0;
 #pragma unroll
                         for (int u = 0; u < U; u++) {
@@ -644,7 +647,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                             __hip_atomic_fetch_or(lds32(LDS_REGION + 4u + tb[u] + ((a >> 5) << 2)), 1u << (a & 31u),
                                                   __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
                             far = max(far, ls);
-                            if (u == U - 1 || v[u + 1].y != v[u].y) {
+                            if (u == U - 1 || first[u + 1]) {
                                 __hip_atomic_fetch_max(lds32(LDS_REGION + tb[u]), far, __ATOMIC_RELAXED,
                                                        __HIP_MEMORY_SCOPE_WORKGROUP);
                                 far = 0;

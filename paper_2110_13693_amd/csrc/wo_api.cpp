@@ -389,9 +389,16 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
                 }
             }
             while (flat.size() % LINE_PAD) flat.push_back(make_uint2(0u, ly.tour + 2u * (uint32_t)d.n_orders));
+            // bit 31 of y marks the first slot of a run of one order's lines
+            // in a lane (the slot that reads the tour entry)
             for (size_t g = 0; g < flat.size(); g += LINE_PAD)
                 for (int u = 0; u < LINE_SLOTS; u++)
-                    for (int j = 0; j < 64; j++) lines.push_back(flat[g + (size_t)j * LINE_SLOTS + u]);
+                    for (int j = 0; j < 64; j++) {
+                        const size_t k = g + (size_t)j * LINE_SLOTS + u;
+                        uint2 r = flat[k];
+                        if (u == 0 || flat[k - 1].y != r.y) r.y |= 0x80000000u;
+                        lines.push_back(r);
+                    }
         }
         I.n_lines_pad = (int32_t)(lines.size() - (size_t)I.line_off);
         wh->lds[i] = ly.total;

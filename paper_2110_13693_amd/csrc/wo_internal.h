@@ -33,8 +33,10 @@ struct InstDev {
     int32_t chase_lanes;    // chase lanes the LDS layout holds (a multiple of 64, <= CHASE_LANES)
     // uint2 line records [n_lines_pad]: x = (rank << shift) | (4*cat) << 24,
     // y = LDS byte offset of the order's tour entry (2 * order + the tour
-    // table's offset); the padding records point at the dummy entry of order
-    // n_orders, whose row absorbs them.  Stored in groups of 64 x LINE_SLOTS,
+    // table's offset), with bit 31 set on the first of a lane's consecutive
+    // slots that hold lines of one order; the padding records point at the
+    // dummy entry of order n_orders, whose row absorbs them.  Stored in
+    // groups of 64 x LINE_SLOTS,
     // slot-major (record u * 64 + j of a group is line j * LINE_SLOTS + u of
     // it in instance order).
     int64_t line_off;
