@@ -265,6 +265,14 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
             // every tour entry starts at the dummy row, so that an entry a
             // malformed sequence leaves unwritten still points inside the tile
             for (int k = tid; k < n + 2; k += BLOCK) tour[k] = (uint16_t)dummy;
+            if (tid < 64) {
+                // segment starts, fixed by the instance's unit total (a plan
+                // whose total differs is not evaluated); 32-bit products since
+                // the total is below 2^22
+                const uint32_t G0 = (uint32_t)max(I.n_seg, 1), nu = n_units;
+                segs[lane] = (uint32_t)lane < G0 ? (uint32_t)lane * nu / G0 : nu;
+                if (lane == 0) segs[MAX_SEG] = nu;
+            }
             loaded = ii;
         }
         {
@@ -398,7 +406,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
             int G = (misc[0] || I.n_seg <= 1) ? 1 : I.n_seg;   // uniform
             if (G > 1 && tid < 64) {
                 const int g = lane;
-                const uint32_t s_g = (uint32_t)(((uint64_t)g * n_units) / (uint32_t)G);
+                const uint32_t s_g = segs[g];
                 uint32_t wb = 0;
                 if (g == 0) {
                     wb = 1u;                          // the tour opened at unit 0
@@ -413,7 +421,6 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                 const uint32_t lanes = (uint32_t)__builtin_amdgcn_readlane((int)inc, 63);
                 lane_base[g] = base;
                 wbits[g] = wb;
-                segs[g] = g <= G ? s_g : n_units;
                 if (lanes <= (uint32_t)I.chase_lanes) {
                     uint32_t m = wb, idx = base;
                     while (m) {

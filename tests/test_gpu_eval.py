@@ -89,6 +89,7 @@ EDGE_CASES = [
     (400, 250, 6000, 30, 64, 1.5),    # more orders than one block keeps in registers
     (400, 250, 12000, 3, 64, 1.5),    # oversize orders (serial chain), several tiles, sequence in memory
     (100, 250, 40000, 30, 8, 0.0),    # 40,000 single-line orders: near the LDS limit, tiles halved
+    (100, 250, 6000, 2, 8, 0.0),      # single-line orders at capacity 2: 64 chase segments
 ]
 
 
