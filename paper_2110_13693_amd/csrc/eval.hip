@@ -123,6 +123,24 @@ static __device__ __forceinline__ float window_throughput(int64_t D, const InstD
     return __double2float_rn(r);
 }
 
+// LDS by absolute address.  The kernel declares no static LDS, so its dynamic
+// LDS starts at address 0 and a layout offset is the address itself; the line
+// pass uses these so that a table offset held in a register needs no base add.
+typedef __attribute__((address_space(3))) uint32_t lds_u32;
+typedef __attribute__((address_space(3))) uint16_t lds_u16;
+static __device__ __forceinline__ lds_u32 *lds32(uint32_t a) { return (lds_u32 *)(size_t)a; }
+static __device__ __forceinline__ lds_u16 *lds16(uint32_t a) { return (lds_u16 *)(size_t)a; }
+
+// Byte address of the word holding bit x of a bitmap at LDS address base
+// (uniform): a shift and one shift-add, which the compiler would otherwise
+// turn into shift, mask and add.
+static __device__ __forceinline__ uint32_t word_addr(uint32_t base, uint32_t x)
+{
+    uint32_t r;
+    asm("v_lshl_add_u32 %0, %1, 2, %2" : "=v"(r) : "v"(x >> 5), "s"(base));
+    return r;
+}
+
 // Bits [x, x + 32) of bitmap B (B holds at least (x >> 5) + 2 words).
 static __device__ __forceinline__ uint32_t bits_at(const uint32_t *B, uint32_t x)
 {
@@ -138,13 +156,16 @@ static __device__ __forceinline__ uint32_t ffbh_raw(uint32_t x)
     return r;
 }
 
-// Next tour opening after a tour opened at unit x.  With no order larger
-// than Q the window (x, x + Q] holds the next order start (or the sentinel);
-// an empty window would move x by 33, never back.
-static __device__ __forceinline__ uint32_t next_open(const uint32_t *B, uint32_t x, uint32_t maskQ)
+// One chase step in terms of y = x + 1, for a tour opened at unit x: the
+// next opening E(x) is x + 1 + the highest set bit of the window (x, x + Q]
+// of the bitmap at LDS address B, and the result is E(x) + 1.  With no order
+// larger than Q the window holds the next order start (or the sentinel); an
+// empty window would move y by 33, never back.
+static __device__ __forceinline__ uint32_t next_open1(uint32_t B, uint32_t y, uint32_t maskQ)
 {
-    const uint32_t win = bits_at(B, x + 1) & maskQ;
-    return x + 32u - ffbh_raw(win);    // x + 1 + highest set bit
+    const uint32_t a = word_addr(B, y);
+    const uint32_t win = __builtin_amdgcn_alignbit(*lds32(a + 4u), *lds32(a), y) & maskQ;
+    return y + 32u - ffbh_raw(win);
 }
 
 // Instance of plan row p: from the per-plan table when there is one, else the
@@ -186,14 +207,6 @@ static __device__ __forceinline__ bool load_chunk(const uint16_t *s, int nv, uin
     for (int j = 0; j < CH / 8; j++) out[j] = make_uint4(w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]);
     return false;
 }
-
-// LDS by absolute address.  The kernel declares no static LDS, so its dynamic
-// LDS starts at address 0 and a layout offset is the address itself; the line
-// pass uses these so that a table offset held in a register needs no base add.
-typedef __attribute__((address_space(3))) uint32_t lds_u32;
-typedef __attribute__((address_space(3))) uint16_t lds_u16;
-static __device__ __forceinline__ lds_u32 *lds32(uint32_t a) { return (lds_u32 *)(size_t)a; }
-static __device__ __forceinline__ lds_u16 *lds16(uint32_t a) { return (lds_u16 *)(size_t)a; }
 
 template <int BLOCK>
 __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
@@ -381,7 +394,8 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                 uint32_t run = run0;
 #pragma unroll
                 for (int k = 0; k < SEQ_CHUNK; k++) {
-                    atomicOr(&B[run >> 5], 1u << (run & 31u));
+                    __hip_atomic_fetch_or(lds32(word_addr(Ly.B, run)), 1u << (run & 31u), __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_WORKGROUP);
                     run += CS(k);
                 }
             } else {
@@ -460,12 +474,14 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                     // and send the plan to the serial chain
                     const uint32_t rb = Ly.rec + ((uint32_t)l << (CR2 + 1));
                     const uint32_t rl = rb + (2u << CR2) - 2u;
-                    uint32_t ra = rb;
+                    const uint32_t s_g1 = s_g + 1u, s_e1 = s_e + 1u;
+                    uint32_t ra = rb, y = x + 1u;
                     do {
-                        *lds16(min(ra, rl)) = (uint16_t)(x - s_g);
+                        *lds16(min(ra, rl)) = (uint16_t)(y - s_g1);
                         ra += 2u;
-                        x = next_open(B, x, maskQ);
-                    } while (x < s_e);
+                        y = next_open1(Ly.B, y, maskQ);
+                    } while (y < s_e1);
+                    x = y - 1u;
                     const uint32_t nr = (ra - rb) >> 1;
                     if (nr > (1u << CR2)) misc[2] = 1;
                     cnrec[l] = nr;
