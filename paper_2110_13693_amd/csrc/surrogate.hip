@@ -32,30 +32,26 @@ static __device__ __forceinline__ uint16_t f2bf(float f)
 
 static __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
 
+// tanh(a) = sign(a) (1 - 2 / (e^{2|a|} + 1)) with the hardware exp and
+// reciprocal: absolute error near 1e-7, far below the bf16 rounding of the
+// activations it feeds
+static __device__ __forceinline__ float tanh_fast(float a)
+{
+    const float e = __expf(2.0f * fabsf(a));
+    return copysignf(1.0f - __fdividef(2.0f, e + 1.0f), a);
+}
+
 static __device__ __forceinline__ float gelu_f(float u)
 {
-    const float t = tanhf(0.7978845608028654f * (u + 0.044715f * u * u * u));
+    const float t = tanh_fast(0.7978845608028654f * (u + 0.044715f * u * u * u));
     return 0.5f * u * (1.0f + t);
 }
 
 static __device__ __forceinline__ float gelu_grad_f(float u)
 {
-    const float t = tanhf(0.7978845608028654f * (u + 0.044715f * u * u * u));
+    const float t = tanh_fast(0.7978845608028654f * (u + 0.044715f * u * u * u));
     const float dt = (1.0f - t * t) * 0.7978845608028654f * (1.0f + 3.0f * 0.044715f * u * u);
     return 0.5f * (1.0f + t) + 0.5f * u * dt;
-}
-
-// 8 bf16 values, one of them 1.0 at position d when d < 8.
-static __device__ __forceinline__ bf16x8 one_hot8(uint32_t d)
-{
-    u32x4 w;
-    const uint32_t v = 0x3F80u << ((d & 1u) * 16u);
-    const uint32_t h = d >> 1;
-    w[0] = (h == 0u) ? v : 0u;
-    w[1] = (h == 1u) ? v : 0u;
-    w[2] = (h == 2u) ? v : 0u;
-    w[3] = (h == 3u) ? v : 0u;
-    return __builtin_bit_cast(bf16x8, w);
 }
 
 // ---------------------------------------------------------------------------
@@ -80,6 +76,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     __shared__ __align__(16) uint16_t Bs[2][(BMODE == B_BF16) ? TM * GLDK : 8];
     __shared__ __align__(16) uint8_t ZsA[(AMODE == A_ONEHOT) ? TM * 64 : 16];
     __shared__ __align__(16) uint8_t ZsB[2][(BMODE == B_ONEHOT_T) ? GBK * 64 : 16];
+    // one-hot fragments: pattern d < 8 holds bf16 1.0 at element d, pattern 8
+    // is all zeros
+    __shared__ __align__(16) uint32_t OneHot[(AMODE == A_ONEHOT) ? 9 * 4 : 4];
 
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
@@ -93,6 +92,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
         for (int j = 0; j < FT; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
     if (AMODE == A_ONEHOT) {
+        if (tid < 36) {
+            const uint32_t d = (uint32_t)tid >> 2, e = (uint32_t)tid & 3u;
+            OneHot[tid] = (d < 8u && (d >> 1) == e) ? (0x3F80u << ((d & 1u) * 16u)) : 0u;
+        }
         // zone bytes of the block's rows, 0xFF past the real rows
         for (int c = tid; c < TM * 4; c += 256) {
             const int r = c >> 2, part = c & 3;
@@ -159,7 +162,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                 } else {
                     const int k = k0 + ks + fk;             // 8 | 64: one category per fragment
                     const uint32_t z = (k >> 6) < g.n_cat ? (uint32_t)ZsA[row * 64 + (k >> 6)] : 0xFFu;
-                    af[ti] = one_hot8(z - (uint32_t)(k & 63));
+                    af[ti] = *(const bf16x8 *)(&OneHot[4u * min(z - (uint32_t)(k & 63), 8u)]);
                 }
             }
 #pragma unroll
@@ -210,7 +213,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                 for (int r = 0; r < 4; r++) {
                     const float u = acc[ti][tj][r] + bias;
                     if (g.U) g.U[(int64_t)(rb + r) * g.ldc + col] = u;
-                    hv[r] = f2bf(gelu_f(u));
+                    if (g.H || g.HT) hv[r] = f2bf(gelu_f(u));
                     if (g.H) g.H[(int64_t)(rb + r) * g.ldc + col] = hv[r];
                 }
                 if (g.HT) {

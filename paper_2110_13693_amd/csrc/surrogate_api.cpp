@@ -20,7 +20,7 @@ using namespace wo;
 
 namespace {
 
-constexpr int PRED_CHUNK = 8192;     // rows per inference pass
+constexpr int PRED_CHUNK = 65536;    // rows per inference pass (enough workgroups to fill the GPU)
 constexpr int MAX_BATCH = 4096;      // training rows per step
 constexpr int WORK_ROWS = PRED_CHUNK > MAX_BATCH ? PRED_CHUNK : MAX_BATCH;
 
