@@ -63,6 +63,9 @@ static __device__ __forceinline__ float gelu_grad_f(float u)
 // beyond K_real, read as zero when generated from zone bytes.
 // ---------------------------------------------------------------------------
 constexpr int GBK = 64, GPAD = 8, GLDK = GBK + GPAD;
+// zone bytes of A rows at a 68-byte stride: the 16 rows of an MFMA tile then
+// read one category's bytes from 16 different LDS banks
+constexpr int ZLD = 68;
 
 template <int AMODE, int BMODE, int EPI, int TM>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
@@ -74,7 +77,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     // step's operands are written to the other one
     __shared__ __align__(16) uint16_t As[2][(AMODE == A_BF16) ? TM * GLDK : 8];
     __shared__ __align__(16) uint16_t Bs[2][(BMODE == B_BF16) ? TM * GLDK : 8];
-    __shared__ __align__(16) uint8_t ZsA[(AMODE == A_ONEHOT) ? TM * 64 : 16];
+    __shared__ __align__(16) uint8_t ZsA[(AMODE == A_ONEHOT) ? TM * ZLD : 16];
     __shared__ __align__(16) uint8_t ZsB[2][(BMODE == B_ONEHOT_T) ? GBK * 64 : 16];
     // one-hot fragments: pattern d < 8 holds bf16 1.0 at element d, pattern 8
     // is all zeros
@@ -101,7 +104,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             const int r = c >> 2, part = c & 3;
             uint4 v = make_uint4(0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu);
             if (m0 + r < g.M_real) v = *(const uint4 *)(g.zoneA + (int64_t)(m0 + r) * 64 + part * 16);
-            *(uint4 *)(&ZsA[r * 64 + part * 16]) = v;
+            uint32_t *zw = (uint32_t *)(&ZsA[r * ZLD + part * 16]);
+            zw[0] = v.x;
+            zw[1] = v.y;
+            zw[2] = v.z;
+            zw[3] = v.w;
         }
     }
 
@@ -151,6 +158,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     for (int k0 = 0, cur = 0; k0 < g.K; k0 += GBK, cur ^= 1) {
         const bool more = k0 + GBK < g.K;
         WO_LOAD_TILE(more ? k0 + GBK : k0);          // unconditional, so the operands stay in registers
+        // a K step of 64 is one category: the zone of each of the wave's rows
+        uint32_t zrow[FT];
+        if (AMODE == A_ONEHOT) {
+            const int cat = k0 >> 6;
+#pragma unroll
+            for (int ti = 0; ti < FT; ti++)
+                zrow[ti] = cat < g.n_cat ? (uint32_t)ZsA[(wm * WT + ti * 16 + fr) * ZLD + cat] : 0xFFu;
+        }
 #pragma unroll
         for (int ks = 0; ks < GBK; ks += 32) {
             bf16x8 af[FT], bfr[FT];
@@ -160,9 +175,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                 if (AMODE == A_BF16) {
                     af[ti] = *(const bf16x8 *)(&As[cur][row * GLDK + ks + fk]);
                 } else {
-                    const int k = k0 + ks + fk;             // 8 | 64: one category per fragment
-                    const uint32_t z = (k >> 6) < g.n_cat ? (uint32_t)ZsA[row * 64 + (k >> 6)] : 0xFFu;
-                    af[ti] = *(const bf16x8 *)(&OneHot[4u * min(z - (uint32_t)(k & 63), 8u)]);
+                    af[ti] = *(const bf16x8 *)(&OneHot[4u * min(zrow[ti] - (uint32_t)(ks + fk), 8u)]);
                 }
             }
 #pragma unroll
