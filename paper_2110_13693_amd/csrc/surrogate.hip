@@ -22,12 +22,10 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
 
+// fp32 -> bf16, nearest with ties to even (the hardware conversion)
 static __device__ __forceinline__ uint16_t f2bf(float f)
 {
-    uint32_t u = __float_as_uint(f);
-    if ((u & 0x7F800000u) == 0x7F800000u && (u & 0x7FFFFFu)) return 0x7FC0;   // NaN
-    u += 0x7FFFu + ((u >> 16) & 1u);                                           // nearest, ties to even
-    return (uint16_t)(u >> 16);
+    return __builtin_bit_cast(uint16_t, (__bf16)f);
 }
 
 static __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
@@ -38,7 +36,7 @@ static __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_floa
 static __device__ __forceinline__ float tanh_fast(float a)
 {
     const float e = __expf(2.0f * fabsf(a));
-    return copysignf(1.0f - __fdividef(2.0f, e + 1.0f), a);
+    return copysignf(1.0f - 2.0f * __builtin_amdgcn_rcpf(e + 1.0f), a);
 }
 
 static __device__ __forceinline__ float gelu_f(float u)
@@ -218,16 +216,16 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             const int rb = m0 + wm * WT + ti * 16 + (lane >> 4) * 4;
             if (EPI == EPI_STORE) {
 #pragma unroll
-                for (int r = 0; r < 4; r++) g.C[(int64_t)(rb + r) * g.ldc + col] = acc[ti][tj][r];
+                for (int r = 0; r < 4; r++) g.C[(uint32_t)((rb + r) * g.ldc + col)] = acc[ti][tj][r];
             } else if (EPI == EPI_BIAS_GELU) {
                 const float bias = g.bias[col];
                 uint16_t hv[4];
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
                     const float u = acc[ti][tj][r] + bias;
-                    if (g.U) g.U[(int64_t)(rb + r) * g.ldc + col] = u;
+                    if (g.U) g.U[(uint32_t)((rb + r) * g.ldc + col)] = u;
                     if (g.H || g.HT) hv[r] = f2bf(gelu_f(u));
-                    if (g.H) g.H[(int64_t)(rb + r) * g.ldc + col] = hv[r];
+                    if (g.H) g.H[(uint32_t)((rb + r) * g.ldc + col)] = hv[r];
                 }
                 if (g.HT) {
                     uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
@@ -238,7 +236,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                 uint16_t hv[4];
 #pragma unroll
                 for (int r = 0; r < 4; r++) {
-                    const float u = g.Uin[(int64_t)(rb + r) * g.ldc + col];
+                    const float u = g.Uin[(uint32_t)((rb + r) * g.ldc + col)];
                     hv[r] = f2bf(acc[ti][tj][r] * gelu_grad_f(u));
                 }
                 uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
@@ -532,6 +530,7 @@ static hipError_t launch_gemm_t(const GemmArgs &g, hipStream_t s)
 hipError_t launch_gemm(int amode, int bmode, int epi, const GemmArgs &g, hipStream_t s)
 {
     if (g.M % 128 || g.N % 128 || g.K % GBK) return hipErrorInvalidValue;
+    if ((int64_t)g.M * g.ldc >= (int64_t)1 << 31) return hipErrorInvalidValue;   // 32-bit output offsets
     if (amode == A_ONEHOT && bmode == B_BF16 && epi == EPI_BIAS_GELU) return launch_gemm_t<A_ONEHOT, B_BF16, EPI_BIAS_GELU>(g, s);
     if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_BIAS_GELU) return launch_gemm_t<A_BF16, B_BF16, EPI_BIAS_GELU>(g, s);
     if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_STORE) return launch_gemm_t<A_BF16, B_BF16, EPI_STORE>(g, s);
