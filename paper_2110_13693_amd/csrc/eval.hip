@@ -482,9 +482,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                         y = next_open1(Ly.B, y, maskQ);
                     } while (y < s_e1);
                     x = y - 1u;
-                    const uint32_t nr = (ra - rb) >> 1;
-                    if (nr > (1u << CR2)) misc[2] = 1;
-                    cnrec[l] = nr;
+                    cnrec[l] = (ra - rb) >> 1;            // more than 2^CR2: records lost
                     // the lane of the next segment whose candidate is this exit
                     uint32_t nx = 0xFFFFFFFFu;
                     if (g + 1 < G) {
@@ -519,7 +517,9 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                         }
                     }
                     if (lane < G) true_lane[lane] = tl;
-                    if (!ok && lane == 0) misc[2] = 1;
+                    // only a true chain's lost records matter
+                    const bool lost = lane < G && cnrec[tl] > (1u << CR2);
+                    if ((!ok || __ballot(lost) != 0) && lane == 0) misc[2] = 1;
                 }
                 __syncthreads();
                 if (!misc[2]) {

@@ -283,6 +283,22 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         while (cnt.size() < (size_t)I.cnt_off + cnt_bytes(d.n_orders)) cnt.push_back(0);
         I.n_units = (int32_t)units;
         I.n_skus = d.n_skus;
+        // tours of next-fit over the orders in instance order: the orders are
+        // exchangeable, so this is the tour count of a typical plan, whatever
+        // the spread of order sizes
+        int64_t tours_est = 0;
+        {
+            int64_t load = 0;
+            for (int32_t o = 0; o < d.n_orders; o++) {
+                const int64_t u = cnt[(size_t)I.cnt_off + o];
+                if (tours_est == 0 || load + u > d.capacity) {
+                    tours_est++;
+                    load = u;
+                } else {
+                    load += u;
+                }
+            }
+        }
 
         // groups of 64 orders by descending size, lines stored line-major
         {
@@ -321,22 +337,20 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         }
 
         // Parallel next-fit: about (Q / mean order size) order starts fall in
-        // a Q-item window, each a candidate entry of a segment.  With 2^lg
+        // a Q-unit window, each a candidate entry of a segment.  With 2^lg
         // opening records per chain, take the fewest segments whose chains
-        // fit the records with margin, plus one; fewer if the chase lanes or
-        // a minimum length of 2Q items do not allow them.  Longer records are
-        // tried only when 32 do not fit; without any fit, plans take the
-        // serial chain.
-        const double items = (double)I.n_lines;
-        const double avg_len = items / d.n_orders;
+        // fit the estimated tours with margin, plus one; fewer if the chase
+        // lanes or a minimum length of 2Q units do not allow them.  Longer
+        // records are tried only when 32 do not fit; without any fit, plans
+        // take the serial chain.
+        const double avg_len = (double)units / d.n_orders;
         const double cand = std::max(1.0, std::min((double)d.capacity, d.capacity / avg_len));
-        const double tour_items = std::max(1.0, d.capacity - 0.5 * (avg_len - 1.0));
         I.n_seg = 1;
         I.chase_log2 = 5;
         for (int lg = 5; lg <= MAX_CHASE_LOG2; lg++) {
-            const int g_recs = (int)std::ceil(items / (0.75 * (1 << lg) * tour_items));
+            const int g_recs = (int)std::ceil((double)tours_est / (0.75 * (1 << lg)));
             const int g_lanes = 1 + (int)((0.85 * CHASE_LANES - 1.0) / cand);
-            const int g_len = (int)(items / (2.0 * d.capacity));
+            const int g_len = (int)((double)units / (2.0 * d.capacity));
             const int g = std::min(std::min(g_recs + 1, g_lanes), std::min(g_len, MAX_SEG));
             const bool short_segs = (double)I.n_units / std::max(g, 1) < 65535.0;   // 16-bit records
             if (g >= 2 && g >= g_recs && short_segs) {
@@ -355,7 +369,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         // tours per LDS tile: the expected tour count with margin (more tours
         // take another pass over the lines), never more than the orders, and
         // few enough that a row's byte offset fits the 16-bit tour entries
-        int64_t t_cap = (int64_t)std::ceil(1.04 * items / tour_items) + 8;
+        int64_t t_cap = (int64_t)std::ceil(1.04 * (double)tours_est) + 8;
         t_cap = std::min<int64_t>(t_cap, d.n_orders);
         t_cap = std::min<int64_t>(t_cap, 65535 / row_bytes(I.words) - 1);
         t_cap = std::max<int64_t>(t_cap, 1);

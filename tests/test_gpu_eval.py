@@ -102,6 +102,54 @@ def test_edge_cases(case):
     _compare(inst, Z, S)
 
 
+def _structured_sequences(inst, rng):
+    """Order sequences that defeat the sizing of the parallel next-fit: runs
+    of small orders put more candidate entries in a segment than its chase
+    lanes hold, and runs of large ones more openings than a chase record list
+    holds, so such plans fall back to the serial chain."""
+    sizes = np.diff(inst.order_offsets)
+    asc = np.argsort(sizes, kind="stable")
+    half = len(asc) // 2
+    small, large = asc[:half], asc[half:][::-1]
+    blocks = []
+    for i in range(0, half, 100):
+        blocks += [small[i:i + 100], large[i:i + 100]]
+    blocked = np.concatenate(blocks + [asc[2 * half:]])
+    middle = np.concatenate([large[: half // 2], small, large[half // 2:], asc[2 * half:]])
+    seqs = [asc, asc[::-1], blocked, middle, rng.permutation(len(asc))]
+    for s in seqs:
+        assert np.array_equal(np.sort(s), np.arange(len(asc)))
+    return np.stack(seqs).astype(np.uint16)
+
+
+def _bimodal_instance(rng, n_orders, capacity, small, large, p_small=0.5):
+    """Orders of `small` lines (fraction p_small) or `large` lines on a
+    400-aisle warehouse."""
+    import dataclasses
+    base = _random_instance(rng, 400, 250, n_orders, capacity, 64, lam=0.0)
+    sizes = np.where(rng.random(n_orders) < p_small, small, large).astype(np.int32)
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    skus = rng.integers(0, base.n_skus, size=int(offs[-1]), dtype=np.int32)
+    return dataclasses.replace(base, order_offsets=offs, order_skus=skus)
+
+
+@pytest.mark.parametrize("kind", ["paper", "bimodal", "skewed", "oversize"])
+def test_structured_sequences(kind):
+    rng = np.random.default_rng(23)
+    if kind == "paper":
+        inst = _random_instance(rng, 400, 250, 4000, 30, 64, lam=1.5)
+    elif kind == "bimodal":
+        inst = _bimodal_instance(rng, 2000, 30, 1, 16)
+    elif kind == "skewed":       # sorted runs of the rare 16-line orders overflow the chase records
+        inst = _bimodal_instance(rng, 4000, 30, 1, 16, p_small=0.9)
+    else:                        # orders larger than the capacity: the serial chain
+        inst = _random_instance(rng, 400, 250, 2000, 8, 64, lam=1.5)
+    S = _structured_sequences(inst, rng)
+    Z = synth.generators.random_zone_perms(rng, S.shape[0], inst.n_categories)
+    print("structured sequences", kind, flush=True)
+    _compare(inst, Z, S)
+
+
 def test_instance_beyond_lds_is_rejected():
     # 65,535 orders need more LDS than a CU has: the load fails cleanly
     wo = _wo()
