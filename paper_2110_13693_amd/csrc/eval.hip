@@ -22,14 +22,16 @@
 //      every order start that can be the first tour opened in it (those
 //      within Q units of its start) is chased to the segment end; the true
 //      entries are then linked segment after segment and their openings
-//      marked in a second unit bitmap F;
-//   4. tour ids: position i opens a tour iff F has bit P[i]; a block scan
-//      over these flags numbers the tours, and every order's entry in the
-//      tour table receives the byte offset of its tour's LDS row;
+//      marked, by sequence position, in a bitmap P (the position of the
+//      order starting at unit x is the count of set bits of B below x);
+//   4. tour ids: a thread's opening flags are P at its positions; a block
+//      scan over their counts numbers the tours, and every order's entry in
+//      the tour table receives the byte offset of its tour's LDS row;
 //   5. every order line (instance order, coalesced) sets its aisle bit in
 //      its tour's row (ds_or) and raises the row's farthest location
-//      (ds_max) -- the largest location of a tour is, at once, the last
-//      aisle visited and the farthest depth in it;
+//      (ds_max, once per run of an order's lines) -- the largest location
+//      of a tour is, at once, the last aisle visited and the farthest depth
+//      in it;
 //   6. per tour: k = popcount of the aisle set, S-shape closed form; the
 //      block sums the tours in int64.
 // Tours beyond one tile of rows are handled in further passes over the lines.
