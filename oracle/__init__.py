@@ -5,7 +5,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 its binding) never does, and this package never imports the product path.
 
 ``wo_oracle.c`` is the plain sequential evaluator (slot map, next-fit tours,
-S-shape distance, time-window throughput); ``surrogate.py`` is the float64
+S-shape, return or largest-gap route distance, time-window throughput); ``surrogate.py`` is the float64
 reference of the surrogate network; ``search.py`` re-implements one step of the
 genetic search on the CPU.  Each cites the passage of arXiv 2110.13693 it
 follows.
@@ -36,8 +36,10 @@ class _Inst(ctypes.Structure):
         ("n_orders", ctypes.c_int32), ("order_offsets", ctypes.c_void_p),
         ("order_skus", ctypes.c_void_p),
         ("walk_dm_per_s", ctypes.c_double), ("seconds_per_item", ctypes.c_double),
-        ("window_s", ctypes.c_double),
+        ("window_s", ctypes.c_double), ("routing", ctypes.c_int32),
     ]
+
+ROUTE_SSHAPE, ROUTE_RETURN, ROUTE_LARGEST_GAP = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -63,6 +65,9 @@ def _load():
         lib.orc_tours.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_sshape_cost.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_int32]
         lib.orc_sshape_cost.restype = ctypes.c_int64
+        for f in (lib.orc_return_cost, lib.orc_largest_gap_cost, lib.orc_tour_cost):
+            f.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_int32]
+            f.restype = ctypes.c_int64
         lib.orc_eval_plan.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_eval_plans.argtypes = [P(_Inst), ctypes.c_int64, ctypes.c_void_p,
@@ -87,7 +92,8 @@ class _Bound:
                        inst.capacity, inst.n_categories, self.cat.size,
                        self.cat.ctypes.data, self.off.size - 1, self.off.ctypes.data,
                        self.sku.ctypes.data, float(inst.walk_dm_per_s),
-                       float(inst.seconds_per_item), float(inst.window_s))
+                       float(inst.seconds_per_item), float(inst.window_s),
+                       int(getattr(inst, "routing", ROUTE_SSHAPE)))
         self.n_orders = self.off.size - 1
 
     def ref(self):
@@ -123,6 +129,27 @@ def sshape_cost(inst, locs) -> int:
     b = _Bound(inst)
     l = _c(locs, np.int32)
     return int(_load().orc_sshape_cost(b.ref(), l.ctypes.data, l.size))
+
+
+def return_cost(inst, locs) -> int:
+    """Return-route length (dm) of one tour given its pick locations."""
+    b = _Bound(inst)
+    l = _c(locs, np.int32)
+    return int(_load().orc_return_cost(b.ref(), l.ctypes.data, l.size))
+
+
+def largest_gap_cost(inst, locs) -> int:
+    """Largest-gap route length (dm) of one tour given its pick locations."""
+    b = _Bound(inst)
+    l = _c(locs, np.int32)
+    return int(_load().orc_largest_gap_cost(b.ref(), l.ctypes.data, l.size))
+
+
+def tour_cost(inst, locs) -> int:
+    """Route length (dm) of one tour under the instance's routing policy."""
+    b = _Bound(inst)
+    l = _c(locs, np.int32)
+    return int(_load().orc_tour_cost(b.ref(), l.ctypes.data, l.size))
 
 
 def eval_plan(inst, zone_of, seq) -> Tuple[int, int, float]:

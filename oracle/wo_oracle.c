@@ -24,13 +24,24 @@
  *      item count plus the order's stays <= capacity, otherwise it opens a new
  *      tour; an order is never split (an order larger than the capacity is a
  *      tour of its own);
- *   4. S-shape route per tour (the standard heuristic of the routing
- *      literature the paper builds on, de Koster et al. 2007): depot at the
- *      front of aisle 0; every aisle holding a pick is traversed entirely, in
- *      ascending order; if the number k of such aisles is odd the last one is
- *      entered from the front and left the same way after its farthest pick;
- *      cost = 2 * spacing * a_max + (k even ? k * L : (k - 1) * L + 2 * y_far)
- *      with L = S * pitch;
+ *   4. route per tour, by one of the standard heuristics of the routing
+ *      literature the paper builds on (de Koster et al. 2007), depot at the
+ *      front of aisle 0, L = S * pitch:
+ *      - S-shape (the default): every aisle holding a pick is traversed
+ *        entirely, in ascending order; if the number k of such aisles is odd
+ *        the last one is entered from the front and left the same way after
+ *        its farthest pick;
+ *        cost = 2 * spacing * a_max + (k even ? k * L : (k - 1) * L + 2 * y_far);
+ *      - return: every aisle holding a pick is entered from the front up to
+ *        its farthest pick and left the same way;
+ *        cost = 2 * spacing * a_max + sum over those aisles of 2 * y_max;
+ *      - largest gap: the first and the last aisle holding picks are
+ *        traversed entirely (front to back, then back to front); every other
+ *        such aisle is entered from the front and from the back, each time up
+ *        to its largest gap and back, the largest gap being the longest of:
+ *        front to first pick, between adjacent picks, last pick to back;
+ *        cost = 2 * spacing * a_max + 2 * L + sum over the inner aisles of
+ *        2 * (L - gap); with a single aisle it is the return route;
  *   5. D = sum of tour costs (exact in int64; the int32 output saturates at
  *      INT32_MAX);
  *   6. throughput over the time window (delta = f(d)):
@@ -56,7 +67,10 @@ typedef struct {
     const int32_t *order_offsets;  /* [n_orders + 1] */
     const int32_t *order_skus;     /* [order_offsets[n_orders]] */
     double walk_dm_per_s, seconds_per_item, window_s;
+    int32_t routing;               /* ORC_ROUTE_* */
 } orc_instance;
+
+enum { ORC_ROUTE_SSHAPE = 0, ORC_ROUTE_RETURN = 1, ORC_ROUTE_LARGEST_GAP = 2 };
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_NOMEM = 3 };
 
@@ -170,6 +184,85 @@ int64_t orc_sshape_cost(const orc_instance *w, const int32_t *locs, int32_t n)
     return cost;
 }
 
+/* Return and largest gap need every pick's depth per aisle: the picks are
+ * decoded and sorted by (aisle, depth), then each aisle is one run. */
+typedef struct { int32_t a, y; } orc_pick;
+
+static int orc_pick_cmp(const void *p, const void *q)
+{
+    const orc_pick *x = (const orc_pick *)p, *z = (const orc_pick *)q;
+    if (x->a != z->a) return x->a < z->a ? -1 : 1;
+    return x->y < z->y ? -1 : (x->y > z->y);
+}
+
+static orc_pick *orc_sorted_picks(const orc_instance *w, const int32_t *locs, int32_t n)
+{
+    int32_t i;
+    orc_pick *pk = (orc_pick *)malloc(sizeof(orc_pick) * (size_t)n);
+    if (!pk) return NULL;
+    for (i = 0; i < n; i++) orc_decode(w, locs[i], &pk[i].a, &pk[i].y);
+    qsort(pk, (size_t)n, sizeof(orc_pick), orc_pick_cmp);
+    return pk;
+}
+
+int64_t orc_return_cost(const orc_instance *w, const int32_t *locs, int32_t n)
+{
+    int32_t i;
+    int64_t cost;
+    orc_pick *pk;
+    if (n <= 0) return 0;
+    pk = orc_sorted_picks(w, locs, n);
+    if (!pk) return -1;
+    cost = 2LL * w->spacing_dm * pk[n - 1].a;
+    for (i = 0; i < n; i++)
+        if (i == n - 1 || pk[i + 1].a != pk[i].a) cost += 2LL * pk[i].y;   /* farthest pick of its aisle */
+    free(pk);
+    return cost;
+}
+
+int64_t orc_largest_gap_cost(const orc_instance *w, const int32_t *locs, int32_t n)
+{
+    int64_t L = (int64_t)w->slots_per_side * w->pitch_dm;
+    int32_t i, first, a_lo, a_hi;
+    int64_t cost;
+    orc_pick *pk;
+    if (n <= 0) return 0;
+    pk = orc_sorted_picks(w, locs, n);
+    if (!pk) return -1;
+    a_lo = pk[0].a;
+    a_hi = pk[n - 1].a;
+    if (a_lo == a_hi) {
+        cost = 2LL * w->spacing_dm * a_hi + 2LL * pk[n - 1].y;
+        free(pk);
+        return cost;
+    }
+    cost = 2LL * w->spacing_dm * a_hi + 2 * L;
+    for (first = 0; first < n; first = i) {
+        int64_t gap;
+        for (i = first; i < n && pk[i].a == pk[first].a; i++) {}
+        if (pk[first].a == a_lo || pk[first].a == a_hi) continue;
+        gap = pk[first].y;                                   /* front to first pick */
+        if (L - pk[i - 1].y > gap) gap = L - pk[i - 1].y;    /* last pick to back */
+        {
+            int32_t j;
+            for (j = first; j + 1 < i; j++)
+                if (pk[j + 1].y - pk[j].y > gap) gap = pk[j + 1].y - pk[j].y;
+        }
+        cost += 2 * (L - gap);
+    }
+    free(pk);
+    return cost;
+}
+
+int64_t orc_tour_cost(const orc_instance *w, const int32_t *locs, int32_t n)
+{
+    switch (w->routing) {
+    case ORC_ROUTE_RETURN: return orc_return_cost(w, locs, n);
+    case ORC_ROUTE_LARGEST_GAP: return orc_largest_gap_cost(w, locs, n);
+    default: return orc_sshape_cost(w, locs, n);
+    }
+}
+
 /* ------------------------------------------------------------------ */
 /* steps 5-6: one whole plan                                           */
 /* ------------------------------------------------------------------ */
@@ -200,7 +293,11 @@ static int orc_eval_plan_ws(const orc_instance *w, const uint8_t *zone_of, const
             for (l = w->order_offsets[o]; l < w->order_offsets[o + 1]; l++)
                 picks[n++] = loc_of_sku[w->order_skus[l]];
         }
-        D += orc_sshape_cost(w, picks, n);
+        {
+            int64_t c = orc_tour_cost(w, picks, n);
+            if (c < 0) return ORC_E_NOMEM;
+            D += c;
+        }
     }
     if (dist_exact) *dist_exact = D;
     if (dist) *dist = D > INT32_MAX ? INT32_MAX : (int32_t)D;
@@ -212,7 +309,8 @@ static int orc_check_instance(const orc_instance *w)
 {
     int32_t o, l;
     if (w->n_aisles < 1 || w->slots_per_side < 1 || w->pitch_dm < 2 || (w->pitch_dm & 1) ||
-        w->spacing_dm < 0 || w->capacity < 1 || w->n_orders < 1 || w->n_orders > 65535)
+        w->spacing_dm < 0 || w->capacity < 1 || w->n_orders < 1 || w->n_orders > 65535 ||
+        w->routing < ORC_ROUTE_SSHAPE || w->routing > ORC_ROUTE_LARGEST_GAP)
         return ORC_E_INVAL;
     if (w->order_offsets[0] != 0) return ORC_E_INVAL;
     for (o = 0; o < w->n_orders; o++)

@@ -141,3 +141,70 @@ def sshape_walk(inst, points):
     if k:
         assert y == 0, "route must end on the front cross aisle"
     return length, covered
+
+
+# ------------------------------------------- return and largest-gap walks
+def return_walk(inst, points):
+    """Walk the return route and return (length, visited): along the front
+    cross aisle to each aisle holding a pick (ascending), up that aisle to its
+    farthest pick and back down, and finally back to the depot."""
+    w = inst.spacing_dm
+    x, length = 0, 0
+    covered = [False] * len(points)
+    for a in sorted({a for a, _ in points}):
+        length += abs(a * w - x)
+        x = a * w
+        far = max(py for pa, py in points if pa == a)
+        length += 2 * far
+        for i, (pa, py) in enumerate(points):
+            if pa == a and py <= far:
+                covered[i] = True
+    return length + x, covered
+
+
+def largest_gap_walk(inst, points):
+    """Walk the largest-gap route and return (length, visited).
+
+    One aisle with picks: the return route.  Otherwise the picker goes along
+    the front to the first such aisle, crosses it to the back, goes along the
+    back to the last one (dipping into every aisle in between from the back
+    down to the upper end of its largest gap and back up), crosses the last
+    aisle to the front and returns along the front (dipping into every aisle
+    in between from the front up to the lower end of its largest gap)."""
+    L = inst.slots_per_side * inst.pitch_dm
+    w = inst.spacing_dm
+    aisles = sorted({a for a, _ in points})
+    if len(aisles) <= 1:
+        return return_walk(inst, points)
+    covered = [False] * len(points)
+
+    def gap(a):
+        ys = [0] + sorted(py for pa, py in points if pa == a) + [L]
+        best = max(range(len(ys) - 1), key=lambda i: ys[i + 1] - ys[i])
+        return ys[best], ys[best + 1]          # lower and upper end
+
+    def cover(a, lo, hi):
+        for i, (pa, py) in enumerate(points):
+            if pa == a and lo <= py <= hi:
+                covered[i] = True
+
+    a_lo, a_hi = aisles[0], aisles[-1]
+    length = a_lo * w + L                      # depot -> first aisle, across it
+    cover(a_lo, 0, L)
+    x = a_lo
+    for a in aisles[1:-1]:                     # along the back
+        length += (a - x) * w
+        x = a
+        _, up = gap(a)
+        length += 2 * (L - up)
+        cover(a, up, L)
+    length += (a_hi - x) * w + L               # to the last aisle, across it
+    cover(a_hi, 0, L)
+    x = a_hi
+    for a in reversed(aisles[1:-1]):           # along the front, back to the depot
+        length += (x - a) * w
+        x = a
+        lo, _ = gap(a)
+        length += 2 * lo
+        cover(a, 0, lo)
+    return length + x * w, covered
