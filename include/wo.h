@@ -97,7 +97,28 @@ typedef struct {
     double walk_dm_per_s;      /* walking speed, dm/s (> 0), e.g. 12.0 */
     double seconds_per_item;   /* picking time per item (>= 0), e.g. 10.0 */
     double window_s;           /* time window (> 0), e.g. 28800.0 */
+    int32_t routing;           /* WO_ROUTE_*: route of every tour (0 = S-shape);
+                                  the same for all instances of one load */
 } wo_instance_desc;
+
+/* Route of a tour (section 5, Subproblem 2 leaves the routing method open;
+ * these are the standard heuristics of the order-picking literature, depot
+ * at the front of aisle 0, L = slots_per_side * pitch_dm):
+ *   WO_ROUTE_SSHAPE      every aisle with a pick is crossed entirely; with an
+ *                        odd count the last one is entered and left from the
+ *                        front;
+ *   WO_ROUTE_RETURN      every aisle with a pick is entered from the front up
+ *                        to its farthest pick and left the same way;
+ *   WO_ROUTE_LARGEST_GAP the first and last aisles with picks are crossed;
+ *                        every other one is entered from both cross aisles,
+ *                        each time up to its largest gap (front to first pick,
+ *                        between picks, last pick to back) and back; a single
+ *                        aisle is a return route.
+ * Return and largest gap keep every pick of a tour in LDS: a tour may hold at
+ * most WO_MAX_PICK_SLOTS lines (capacity, and any single order), else
+ * wo_load_warehouse fails with WO_E_UNSUPPORTED. */
+enum { WO_ROUTE_SSHAPE = 0, WO_ROUTE_RETURN = 1, WO_ROUTE_LARGEST_GAP = 2 };
+#define WO_MAX_PICK_SLOTS 32
 
 typedef struct wo_wh wo_wh;
 

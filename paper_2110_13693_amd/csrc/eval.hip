@@ -210,8 +210,65 @@ static __device__ __forceinline__ bool load_chunk(const uint16_t *s, int nv, uin
     return false;
 }
 
-template <int BLOCK>
-__global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
+// Ascending bitonic sort of 32 words held in registers (straight-line min/max).
+static __device__ __forceinline__ void sort32(uint32_t (&v)[MAX_PICK_SLOTS])
+{
+#pragma unroll
+    for (int k = 2; k <= MAX_PICK_SLOTS; k <<= 1)
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1)
+#pragma unroll
+            for (int i = 0; i < MAX_PICK_SLOTS; i++) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const uint32_t a = v[i], b = v[l];
+                    const bool up = (i & k) == 0;
+                    v[i] = up ? min(a, b) : max(a, b);
+                    v[l] = up ? max(a, b) : min(a, b);
+                }
+            }
+}
+
+// Return or largest-gap route of one tour from its np >= 1 picks, sorted by
+// scaled location, i.e. by aisle and then depth (section 5, Subproblem 2).
+template <int ROUTE>
+static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MAX_PICK_SLOTS], uint32_t np,
+                                                          const InstDev &I, uint32_t magic)
+{
+    const int32_t L = I.L;
+    uint32_t ca = mulhi24(v[0], magic);               // current aisle
+    const uint32_t a_lo = ca;
+    int32_t py = 0;                                   // previous depth in the aisle (front: 0)
+    int32_t g = 0;                                    // largest gap so far in the aisle
+    int64_t sum = 0;                                  // return: farthest depths; gap: inner L - gap
+#pragma unroll
+    for (int i = 0; i < MAX_PICK_SLOTS; i++) {
+        if ((uint32_t)i < np) {
+            const uint32_t a = mulhi24(v[i], magic);
+            const int32_t y = (int32_t)((v[i] - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
+            if (a != ca) {                            // close aisle ca
+                if (ROUTE == WO_ROUTE_RETURN) {
+                    sum += py;
+                } else {
+                    g = max(g, L - py);
+                    if (ca != a_lo) sum += L - g;
+                }
+                ca = a;
+                py = 0;
+                g = 0;
+            }
+            g = max(g, y - py);
+            py = y;
+        }
+    }
+    const int64_t horiz = 2ll * I.spacing * ca;       // ca is the farthest aisle now
+    if (ROUTE == WO_ROUTE_RETURN) return horiz + 2 * (sum + py);
+    if (ca == a_lo) return horiz + 2ll * py;           // one aisle: the return route
+    return horiz + 2ll * L + 2 * sum;
+}
+
+template <int BLOCK, int ROUTE>
+__global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_plans_kernel(EvalArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
     uint32_t &s_next = *(uint32_t *)(smem + LDS_TICKET);
@@ -248,7 +305,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
         const uint32_t n_units = (uint32_t)I.n_units;
         const int64_t row = p - (A.n_inst > 1 ? A.plan_begin[ii] : 0);
         const uint16_t *seq = A.seq + A.seq_base[ii] + row * (int64_t)n;
-        const EvalLayout Ly = eval_layout(n, I.n_units, I.words, I.t_cap, I.chase_log2, I.chase_lanes);
+        const EvalLayout Ly = eval_layout(n, I.n_units, (uint32_t)I.row_b, I.t_cap, I.chase_log2, I.chase_lanes);
         uint32_t *zs = (uint32_t *)(smem + LDS_ZS);
         uint32_t *scan_a = (uint32_t *)(smem + Ly.red);
         uint32_t *scan_b = scan_a + 16;
@@ -268,7 +325,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
         uint32_t *cnxt = (uint32_t *)(smem + Ly.nxt);
         uint32_t *cand = (uint32_t *)(smem + Ly.cand);
         const int T = I.t_cap;
-        const uint32_t RB = row_bytes(I.words);
+        const uint32_t RB = (uint32_t)I.row_b;
         const uint32_t dummy = (uint32_t)T * RB;          // byte offset of the dummy row
         int bad = 0;
 
@@ -635,7 +692,7 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                     for (int k = tid; k < nr4; k += BLOCK) rows[k] = make_uint4(0u, 0u, 0u, 0u);
                     __syncthreads();
                 }
-                if (A.main_mode == 0) {
+                if (ROUTE != WO_ROUTE_SSHAPE || A.main_mode == 0) {
                     // each wave takes whole groups of 64 lanes x 8 line slots
                     constexpr int U = LINE_SLOTS;
                     constexpr int NW = BLOCK / 64;
@@ -664,6 +721,19 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
 #pragma unroll
                         for (int u = 1; u < U; u++)
                             if (!first[u]) tb[u] = tb[u - 1];
+                        if (ROUTE != WO_ROUTE_SSHAPE) {
+                            // pick rows: take the next entry of the tour's row
+                            // (the dummy row's count runs past its entries,
+                            // which then share its last one)
+                            const uint32_t last = (uint32_t)I.pick_slots - 1u;
+#pragma unroll
+                            for (int u = 0; u < U; u++) {
+                                const uint32_t e = __hip_atomic_fetch_add(lds32(LDS_REGION + tb[u]), 1u, __ATOMIC_RELAXED,
+                                                                          __HIP_MEMORY_SCOPE_WORKGROUP);
+                                *lds32(LDS_REGION + 4u + tb[u] + (min(e, last) << 2)) = v[u].x + zv[u];
+                            }
+                            continue;
+                        }
                         uint32_t far = 0;
 #pragma unroll
                         for (int u = 0; u < U; u++) {
@@ -742,6 +812,18 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
                 }
                 __syncthreads();
                 const int nt = (int)min((uint32_t)T, n_tours - t0);
+                if (ROUTE != WO_ROUTE_SSHAPE) {
+                    for (int t = tid; t < nt; t += BLOCK) {
+                        const uint32_t *rw = (const uint32_t *)(smem + LDS_REGION + (uint32_t)t * RB);
+                        const uint32_t np = min(rw[0], (uint32_t)I.pick_slots);   // >= 1: a tour has picks
+                        uint32_t v[MAX_PICK_SLOTS];
+#pragma unroll
+                        for (int i = 0; i < MAX_PICK_SLOTS; i++) v[i] = (uint32_t)i < np ? rw[1 + i] : 0xFFFFFFFFu;
+                        sort32(v);
+                        acc += pick_route_cost<ROUTE>(v, np, I, magic);
+                    }
+                    continue;
+                }
                 const int W = I.words;
                 for (int t = tid; t < nt; t += BLOCK) {
                     const uint32_t *rw = (const uint32_t *)(smem + LDS_REGION + (uint32_t)t * RB);
@@ -775,13 +857,13 @@ __global__ __launch_bounds__(BLOCK, 4) void eval_plans_kernel(EvalArgs A)
 // Reset of the work-queue ticket (a kernel, so that it can sit in a graph).
 __global__ void reset_ticket_kernel(uint32_t *ctr) { *ctr = 0u; }
 
-template <int BLOCK>
+template <int BLOCK, int ROUTE>
 static hipError_t launch_eval_t(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
 {
     // raise the dynamic LDS limit to what this launch needs
     static uint32_t attr_bytes = 0;
     if (lds_bytes > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)eval_plans_kernel<BLOCK>,
+        hipError_t e = hipFuncSetAttribute((const void *)eval_plans_kernel<BLOCK, ROUTE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -790,39 +872,61 @@ static hipError_t launch_eval_t(const EvalArgs &a, uint32_t lds_bytes, int grid,
         attr_bytes = lds_bytes;
     }
     if (a.queue) hipLaunchKernelGGL(reset_ticket_kernel, dim3(1), dim3(1), 0, s, a.queue_ctr);
-    hipLaunchKernelGGL(eval_plans_kernel<BLOCK>, dim3(grid), dim3(BLOCK), lds_bytes, s, a);
+    hipLaunchKernelGGL((eval_plans_kernel<BLOCK, ROUTE>), dim3(grid), dim3(BLOCK), lds_bytes, s, a);
     return hipGetLastError();
 }
 
-template <int BLOCK>
+template <int BLOCK, int ROUTE>
 static int max_blocks_t(uint32_t lds_bytes)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, eval_plans_kernel<BLOCK>, BLOCK, lds_bytes) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, eval_plans_kernel<BLOCK, ROUTE>, BLOCK, lds_bytes) !=
+        hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
     return n > 0 ? n : 1;
 }
 
-int eval_max_blocks_per_cu(int block, uint32_t lds_bytes)
+template <int ROUTE>
+static int max_blocks_r(int block, uint32_t lds_bytes)
 {
     switch (block) {
-    case 64: return max_blocks_t<64>(lds_bytes);
-    case 128: return max_blocks_t<128>(lds_bytes);
-    case 256: return max_blocks_t<256>(lds_bytes);
-    case 512: return max_blocks_t<512>(lds_bytes);
+    case 64: return max_blocks_t<64, ROUTE>(lds_bytes);
+    case 128: return max_blocks_t<128, ROUTE>(lds_bytes);
+    case 256: return max_blocks_t<256, ROUTE>(lds_bytes);
+    case 512: return max_blocks_t<512, ROUTE>(lds_bytes);
     }
     return 1;
 }
 
-hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, hipStream_t s)
+int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes)
+{
+    switch (route) {
+    case WO_ROUTE_RETURN: return max_blocks_r<WO_ROUTE_RETURN>(block, lds_bytes);
+    case WO_ROUTE_LARGEST_GAP: return max_blocks_r<WO_ROUTE_LARGEST_GAP>(block, lds_bytes);
+    }
+    return max_blocks_r<WO_ROUTE_SSHAPE>(block, lds_bytes);
+}
+
+template <int ROUTE>
+static hipError_t launch_eval_r(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, hipStream_t s)
 {
     switch (block) {
-    case 64: return launch_eval_t<64>(a, lds_bytes, grid, s);
-    case 128: return launch_eval_t<128>(a, lds_bytes, grid, s);
-    case 256: return launch_eval_t<256>(a, lds_bytes, grid, s);
-    case 512: return launch_eval_t<512>(a, lds_bytes, grid, s);
+    case 64: return launch_eval_t<64, ROUTE>(a, lds_bytes, grid, s);
+    case 128: return launch_eval_t<128, ROUTE>(a, lds_bytes, grid, s);
+    case 256: return launch_eval_t<256, ROUTE>(a, lds_bytes, grid, s);
+    case 512: return launch_eval_t<512, ROUTE>(a, lds_bytes, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, int route, hipStream_t s)
+{
+    switch (route) {
+    case WO_ROUTE_SSHAPE: return launch_eval_r<WO_ROUTE_SSHAPE>(a, lds_bytes, grid, block, s);
+    case WO_ROUTE_RETURN: return launch_eval_r<WO_ROUTE_RETURN>(a, lds_bytes, grid, block, s);
+    case WO_ROUTE_LARGEST_GAP: return launch_eval_r<WO_ROUTE_LARGEST_GAP>(a, lds_bytes, grid, block, s);
     }
     return hipErrorInvalidValue;
 }

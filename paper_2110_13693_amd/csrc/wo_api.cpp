@@ -99,6 +99,7 @@ struct wo_wh {
     int per_cu = 0;                     // 0: as many as LDS allows
     int queue = 0;                      // 1: ticket queue over the cost-ordered work list
     int main_mode = 0;                  // 0: one line per lane in the line pass, 1: one order per lane
+    int route = WO_ROUTE_SSHAPE;        // the route of every instance of the handle
     int small_orders = 1024;            // instances up to this size get a launch of 64-thread workgroups
     // Work lists by launch class (0: the configured workgroups, 1: 64-thread
     // workgroups for instances of at most small_orders orders, 2: 128-thread
@@ -165,6 +166,8 @@ static wo_status check_desc(const wo_instance_desc &d, int idx)
         return fail(WO_E_INVAL, "instance %d: slot pitch must be even and >= 2 (got %d)", idx, d.pitch_dm);
     if (d.spacing_dm < 0) return fail(WO_E_INVAL, "instance %d: negative aisle spacing", idx);
     if (d.capacity < 1) return fail(WO_E_INVAL, "instance %d: capacity must be >= 1", idx);
+    if (d.routing < WO_ROUTE_SSHAPE || d.routing > WO_ROUTE_LARGEST_GAP)
+        return fail(WO_E_INVAL, "instance %d: unknown routing %d", idx, d.routing);
     if (d.capacity > WO_MAX_CAPACITY)
         return fail(WO_E_RANGE, "instance %d: capacity %d > %d", idx, d.capacity, WO_MAX_CAPACITY);
     if (d.n_categories < 1) return fail(WO_E_INVAL, "instance %d: need >= 1 category", idx);
@@ -216,6 +219,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     for (int32_t i = 0; i < n_instances; i++) {
         wo_status s = check_desc(descs[i], i);
         if (s) return s;
+        if (descs[i].routing != descs[0].routing)
+            return fail(WO_E_UNSUPPORTED, "instance %d: routing differs from instance 0's (one route per load)", i);
     }
 
     // allocation fault injection for tests (WO_FAULT_INJECT=alloc); it fires
@@ -230,6 +235,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     HIP_TRY(hipDeviceGetAttribute(&wh->cu_count, hipDeviceAttributeMultiprocessorCount, wh->device));
     wh->lds_max = (uint32_t)std::min(lds_max, 160 * 1024) - 256;   // room for the kernels' static LDS
     wh->n_inst = n_instances;
+    wh->route = descs[0].routing;
     wh->inst.resize(n_instances);
     wh->lds.resize(n_instances);
 
@@ -249,6 +255,18 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
                         per_aisle);
         I.n_aisles = d.n_aisles;
         I.words = (d.n_aisles + 31) / 32;
+        I.route = d.routing;
+        {
+            // a tour holds at most max(capacity, largest order) lines
+            int32_t max_lines = 0;
+            for (int32_t o = 0; o < d.n_orders; o++)
+                max_lines = std::max(max_lines, d.order_offsets[o + 1] - d.order_offsets[o]);
+            I.pick_slots = std::max(d.capacity, max_lines);
+            if (d.routing != WO_ROUTE_SSHAPE && I.pick_slots > MAX_PICK_SLOTS)
+                return fail(WO_E_UNSUPPORTED, "instance %d: a tour may hold %d lines, more than the %d a "
+                            "return or largest-gap row keeps", i, I.pick_slots, MAX_PICK_SLOTS);
+            I.row_b = (int32_t)(d.routing == WO_ROUTE_SSHAPE ? row_bytes(I.words) : pick_row_bytes(I.pick_slots));
+        }
         I.capacity = d.capacity;
         I.n_cat = d.n_categories;
         I.n_orders = d.n_orders;
@@ -371,12 +389,12 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         // few enough that a row's byte offset fits the 16-bit tour entries
         int64_t t_cap = (int64_t)std::ceil(1.04 * (double)tours_est) + 8;
         t_cap = std::min<int64_t>(t_cap, d.n_orders);
-        t_cap = std::min<int64_t>(t_cap, 65535 / row_bytes(I.words) - 1);
+        t_cap = std::min<int64_t>(t_cap, 65535 / I.row_b - 1);
         t_cap = std::max<int64_t>(t_cap, 1);
-        EvalLayout ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap, I.chase_log2, I.chase_lanes);
+        EvalLayout ly = eval_layout(d.n_orders, I.n_units, (uint32_t)I.row_b, (int32_t)t_cap, I.chase_log2, I.chase_lanes);
         while (ly.total > wh->lds_max && t_cap > 1) {
             t_cap = t_cap / 2;
-            ly = eval_layout(d.n_orders, I.n_units, I.words, (int32_t)t_cap, I.chase_log2, I.chase_lanes);
+            ly = eval_layout(d.n_orders, I.n_units, (uint32_t)I.row_b, (int32_t)t_cap, I.chase_log2, I.chase_lanes);
         }
         I.t_cap = (int32_t)t_cap;
         if (ly.total > wh->lds_max)
@@ -479,7 +497,7 @@ extern "C" wo_status wo_instance_info(const wo_wh *wh, int32_t i, int32_t *n_ord
 // at most 32 waves per CU), never more than there are plans.
 static int launch_grid(const wo_wh *wh, int block, int per_cu_cfg, uint32_t lds, int64_t n_plans)
 {
-    const int fit = eval_max_blocks_per_cu(block, lds);
+    const int fit = eval_max_blocks_per_cu(block, wh->route, lds);
     const int per_cu = per_cu_cfg > 0 ? std::min(per_cu_cfg, fit) : fit;
     return (int)std::min<int64_t>(n_plans, (int64_t)wh->cu_count * per_cu);
 }
@@ -605,7 +623,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.grec = wh->d_grec;
     a.gbase = wh->d_gbase;
     a.gord = wh->d_gord;
-    a.main_mode = wh->main_mode;
+    a.main_mode = wh->route == WO_ROUTE_SSHAPE ? wh->main_mode : 0;   // pick rows: line per lane only
     a.zone_of = d_zone_of;
     a.seq = d_order_seq;
     a.dist = d_dist;
@@ -619,7 +637,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     for (int32_t i = 0; i < wh->n_inst; i++) any_small |= class_of(wh, i) != 0 && map[i + 1] > map[i];
     if (!any_small && !wh->queue) {
         // one launch, grid stride over the plan rows
-        HIP_TRY(launch_eval(a, wh->lds_max, launch_grid(wh, wh->lds_max, n_plans), wh->block, s));
+        HIP_TRY(launch_eval(a, wh->lds_max, launch_grid(wh, wh->lds_max, n_plans), wh->block, wh->route, s));
     } else {
         // one launch per class over its work list: the configured workgroups
         // for the large instances, 64- and 128-thread ones for the small ones
@@ -635,7 +653,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
             ac.queue_ctr = (uint32_t *)((char *)wh->d_err + 48 + 4 * c);
             const int block = c ? class_block[c] : wh->block;
             const int per_cu = c ? 0 : wh->per_cu;
-            HIP_TRY(launch_eval(ac, w.lds, launch_grid(wh, block, per_cu, w.lds, w.n), block, s));
+            HIP_TRY(launch_eval(ac, w.lds, launch_grid(wh, block, per_cu, w.lds, w.n), block, wh->route, s));
         }
     }
     if (validate) {
@@ -667,7 +685,7 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.grec = wh->d_grec;
     a.gbase = wh->d_gbase;
     a.gord = wh->d_gord;
-    a.main_mode = wh->main_mode;
+    a.main_mode = wh->route == WO_ROUTE_SSHAPE ? wh->main_mode : 0;   // pick rows: line per lane only
     a.zone_of = d_zone_of;
     a.seq = d_order_seq;
     a.dist = d_dist;
@@ -678,7 +696,7 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.queue_ctr = nullptr;
     a.work = nullptr;
     const uint32_t lds = wh->lds[inst];
-    HIP_TRY(launch_eval(a, lds, launch_grid(wh, lds, n_plans), wh->block, s));
+    HIP_TRY(launch_eval(a, lds, launch_grid(wh, lds, n_plans), wh->block, wh->route, s));
     return WO_OK;
 }
 
@@ -770,9 +788,11 @@ extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, in
     for (int bi = 0; bi < 4 && !st; bi++) {
         for (int pi = 0; pi < 8 && !st; pi++) {
             const int blk = blocks[bi], pc = per_cus[pi];
-            if (pc > eval_max_blocks_per_cu(blk, wh->lds_max)) continue;      // registers and LDS
-            for (int qm = 0; qm < 4 && !st; qm++)
+            if (pc > eval_max_blocks_per_cu(blk, wh->route, wh->lds_max)) continue;      // registers and LDS
+            for (int qm = 0; qm < 4 && !st; qm++) {
+                if (wh->route != WO_ROUTE_SSHAPE && (qm >> 1)) continue;   // pick rows: line per lane only
                 st = time_cfg(wo_eval_config{blk, pc, qm & 1, qm >> 1, saved.small_orders, 0.f});
+            }
         }
     }
     // the small-instance launch on and off, with the best configuration

@@ -31,6 +31,9 @@ struct InstDev {
     int32_t n_lines_pad;    // line records stored: n_lines rounded up to whole groups of LINE_PAD
     int32_t chase_log2;     // log2 of the opening records per chase lane
     int32_t chase_lanes;    // chase lanes the LDS layout holds (a multiple of 64, <= CHASE_LANES)
+    int32_t route;          // WO_ROUTE_*
+    int32_t pick_slots;     // return / largest gap: pick entries per tour row (<= MAX_PICK_SLOTS)
+    int32_t row_b;          // bytes of one tour row in LDS
     // uint2 line records [n_lines_pad]: x = (rank << shift) | (4*cat) << 24,
     // y = LDS byte offset of the order's tour entry (2 * order + the tour
     // table's offset), with bit 31 set on the first of a lane's consecutive
@@ -116,14 +119,18 @@ __host__ __device__ inline uint32_t align16(uint32_t x) { return (x + 15u) & ~15
 
 __host__ __device__ inline uint32_t bitmap_words(int32_t n_units) { return ((uint32_t)n_units >> 5) + 3u; }
 
-// a row is the farthest location plus the aisle set, padded to an odd word
-// count so that rows of random tours spread over all 32 LDS banks
+// An S-shape row is the farthest location plus the aisle set; a return or
+// largest-gap row is a pick count plus up to pick_slots scaled locations.
+// Rows are padded to an odd word count so that rows of random tours spread
+// over all 32 LDS banks.
+constexpr int MAX_PICK_SLOTS = 32;
 __host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * ((uint32_t)(words + 1) | 1u); }
+__host__ __device__ inline uint32_t pick_row_bytes(int32_t slots) { return 4u * ((uint32_t)(slots + 1) | 1u); }
 
 // bytes of the cnt table (order sizes, then zeros for the dummy and sink entries)
 __host__ __device__ inline uint32_t cnt_bytes(int32_t n_orders) { return align16((uint32_t)n_orders + 2u); }
 
-__host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_units, int32_t words,
+__host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_units, uint32_t rb,
                                                   int32_t t_cap, int32_t chase_log2, int32_t chase_lanes)
 {
     const uint32_t cl = (uint32_t)chase_lanes;
@@ -134,7 +141,7 @@ __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_un
     L.nrec = c;  c = align16(c + 4u * cl);
     L.nxt = c;   c = align16(c + 4u * cl);
     L.cand = c;  c = align16(c + 4u * cl);
-    const uint32_t rows = align16(LDS_REGION + row_bytes(words) * (uint32_t)(t_cap + 1));
+    const uint32_t rows = align16(LDS_REGION + rb * (uint32_t)(t_cap + 1));
     const uint32_t seen = align16(LDS_REGION + 4u * ((n + 31) / 32));
     uint32_t b = c > rows ? c : rows;
     if (seen > b) b = seen;
@@ -150,9 +157,9 @@ __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_un
     return L;
 }
 
-hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, hipStream_t s);
+hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, int route, hipStream_t s);
 // workgroups of the evaluation kernel that fit one CU (registers and LDS)
-int eval_max_blocks_per_cu(int block, uint32_t lds_bytes);
+int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes);
 
 // library-internal helpers over a loaded handle
 wo_status eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint8_t *d_zone_of,

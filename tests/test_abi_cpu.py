@@ -77,6 +77,8 @@ def _mod(inst, **kw):
     ("capacity", 33, 2),            # above the supported capacity
     ("n_categories", 65, 2),        # more than 64 categories
     ("n_aisles", 1, 2),             # 600 SKUs no longer fit 60 locations
+    ("routing", 3, 1),              # unknown route
+    ("routing", -1, 1),
 ])
 def test_load_rejects_descriptor(wo, tiny, field, value, status):
     st, out = _load_status(wo, _mod(tiny, **{field: value}))
@@ -152,3 +154,15 @@ def test_binding_refuses_host_tensors(wo):
     d = torch.zeros((1,), dtype=torch.int32)
     with pytest.raises(ValueError):
         wo.wo_eval_plans(FakeWh(), z, s, d)
+
+
+def test_load_rejects_mixed_routing(wo, tiny):
+    # one route per load: instances that differ are refused before any device work
+    keep = []
+    d0 = wo.make_desc(tiny, keep)
+    d1 = wo.make_desc(_mod(tiny, routing=1), keep)
+    arr = (wo.wo_instance_desc * 2)(d0, d1)
+    out = ctypes.c_void_p(0)
+    assert wo.lib().wo_load_warehouse(arr, 2, None, ctypes.byref(out)) == wo.WO_E_UNSUPPORTED
+    assert "routing" in wo.wo_last_error()
+    assert out.value is None

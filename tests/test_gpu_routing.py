@@ -1,0 +1,103 @@
+"""GPU parity of the return and largest-gap routes against the CPU oracle
+(through the C ABI).  Distances must match bit-exactly; the throughput to
+1e-6 relative, as for the S-shape route."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.test_gpu_eval import _compare, _random_instance, _structured_sequences, _wo
+
+pytestmark = pytest.mark.gpu
+
+ROUTES = [1, 2]          # return, largest gap
+
+
+def _routed(inst, routing):
+    return dataclasses.replace(inst, routing=routing)
+
+
+@pytest.mark.parametrize("routing", ROUTES)
+def test_tiny_all_plans(routing):
+    inst, Z, S = synth.workload("tiny")
+    print("tiny", routing, flush=True)
+    _compare(_routed(inst, routing), Z, S)
+
+
+@pytest.mark.parametrize("routing", ROUTES)
+def test_paper_scale_sample(routing):
+    inst, Z, S = synth.workload("paper", n_plans=64)
+    print("paper", routing, flush=True)
+    _compare(_routed(inst, routing), Z, S)
+
+
+ROUTE_CASES = [
+    # (aisles, slots, orders, capacity, categories, lambda)
+    (1, 5, 7, 3, 3, 2.0),          # one aisle: every tour is a return route
+    (3, 4, 50, 2, 5, 3.0),         # oversize orders, their own tours
+    (33, 7, 300, 32, 64, 1.5),     # capacity 32: rows of 32 picks
+    (400, 250, 4000, 1, 64, 0.3),  # ~4,000 tours: several tour tiles
+    (400, 250, 6000, 30, 64, 1.5), # sequence in memory
+]
+
+
+@pytest.mark.parametrize("routing", ROUTES)
+@pytest.mark.parametrize("case", ROUTE_CASES, ids=lambda c: "N%d_S%d_n%d_Q%d_C%d" % c[:5])
+def test_route_edge_cases(case, routing):
+    rng = np.random.default_rng(abs(hash(case)) % (1 << 31))
+    inst = _routed(_random_instance(rng, *case), routing)
+    Z, S = synth.make_plans(inst, 23, seed=int(rng.integers(1 << 30)))
+    print("case", case, routing, flush=True)
+    _compare(inst, Z, S)
+
+
+@pytest.mark.parametrize("routing", ROUTES)
+def test_structured_sequences_routed(routing):
+    rng = np.random.default_rng(29)
+    inst = _routed(_random_instance(rng, 400, 250, 4000, 30, 64, lam=1.5), routing)
+    S = _structured_sequences(inst, rng)
+    Z = synth.generators.random_zone_perms(rng, S.shape[0], inst.n_categories)
+    _compare(inst, Z, S)
+
+
+def test_batched_routed_instances_match_single():
+    import torch
+    wo = _wo()
+    rng = np.random.default_rng(31)
+    insts = [_routed(_random_instance(rng, n_a, 40, n_o, 20, 16), 2)
+             for n_a, n_o in ((8, 60), (30, 500), (12, 200))]
+    plans = [synth.make_plans(i, 16, seed=k) for k, i in enumerate(insts)]
+    wh = wo.wo_load_warehouse(insts)
+    Z = np.concatenate([p[0] for p in plans])
+    S = np.concatenate([p[1].reshape(-1) for p in plans])
+    offs = np.array([0, 16, 32, 48], dtype=np.int64)
+    z = torch.from_numpy(Z).cuda()
+    s = torch.from_numpy(S.view(np.int16)).cuda()
+    d = torch.empty(48, dtype=torch.int32, device="cuda")
+    t = torch.empty(48, dtype=torch.float32, device="cuda")
+    wo.wo_eval_plans(wh, z, s, d, t, plan_offsets=offs)
+    torch.cuda.synchronize()
+    for k, (inst, (Zi, Si)) in enumerate(zip(insts, plans)):
+        d_ref, _ = oracle.eval_plans(inst, Zi, Si)
+        assert np.array_equal(d.cpu().numpy()[16 * k:16 * (k + 1)], d_ref)
+    wh.free()
+
+
+def test_too_many_picks_per_tour_is_rejected():
+    # an order of 40 lines cannot sit in a 32-pick row
+    wo = _wo()
+    rng = np.random.default_rng(37)
+    base = _random_instance(rng, 20, 30, 50, 20, 8, lam=1.0)
+    sizes = np.diff(base.order_offsets).copy()
+    sizes[7] = 40
+    offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
+    skus = rng.integers(0, base.n_skus, size=int(offs[-1]), dtype=np.int32)
+    inst = dataclasses.replace(base, order_offsets=offs, order_skus=skus, routing=1)
+    with pytest.raises(wo.WoError) as e:
+        wo.wo_load_warehouse([inst])
+    assert "lines" in str(e.value)
+    # the S-shape route has no such limit
+    wh = wo.wo_load_warehouse([dataclasses.replace(inst, routing=0)])
+    wh.free()
