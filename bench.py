@@ -18,6 +18,7 @@ the same plans, on the host's cores.
 from __future__ import annotations
 
 import argparse
+import dataclasses
 import json
 import os
 import sys
@@ -31,6 +32,8 @@ if ROOT not in sys.path:
 
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz, one 32-bit integer op per lane per clock
 INT_VALU_PEAK_OPS = 256 * 64 * 2.4e9
+# route of every tour: S-shape (the headline), return, largest gap
+ROUTES = {"sshape": 0, "return": 1, "largest-gap": 2}
 HBM_PEAK_BYTES = 8.0e12
 
 
@@ -374,6 +377,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--route", default="sshape", choices=list(ROUTES),
+                    help="route of every tour (the default S-shape is the headline)")
     ap.add_argument("--search", action="store_true",
                     help="run the plain vs surrogate-screened search comparison instead")
     ap.add_argument("--population", type=int, default=16384)
@@ -415,6 +420,7 @@ def main(argv=None):
 
     torch.cuda.set_device(0)
     inst, Z, S = synth.workload(args.workload)
+    inst = dataclasses.replace(inst, routing=ROUTES[args.route])
     n_plans = Z.shape[0]
     wh = wo.wo_load_warehouse([inst])
     z = torch.from_numpy(Z).cuda()
@@ -449,7 +455,7 @@ def main(argv=None):
     achieved_ops = ops / (ms_per_step / 1e3)
     roofline = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": INT_VALU_PEAK_OPS / 1e12,
                 "unit": "Tops/s", "frac": achieved_ops / INT_VALU_PEAK_OPS,
-                "traffic": profiled_traffic() if args.workload == "paper" else None}
+                "traffic": profiled_traffic() if args.workload == "paper" and args.route == "sshape" else None}
 
     out = {
         "metric": "exact plan evals/s @4k orders",
@@ -467,6 +473,7 @@ def main(argv=None):
         "config": {"workload": "paper-scale warehouse: 400 aisles x 2 x 250 slots, 150k SKUs in "
                                "64 categories, 4,000 orders (~10k items), capacity 30, 4,096 "
                                "plans per call" if args.workload == "paper" else "tiny warehouse",
+                   "route": args.route,
                    "plans_per_step": n_plans, "orders": inst.n_orders, "items": inst.n_items,
                    "parallelism": "1 GPU"},
         "roofline": roofline,
