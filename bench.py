@@ -146,11 +146,21 @@ def search_comparison(args):
     plain_trace, plain_best = run(None, None, args.generations, "plain")
     wall = plain_trace[-1][0]
 
-    # surrogate: training pairs from the exact evaluator, then training
+    # surrogate: training pairs from the exact evaluator, then training; the
+    # random slottings are drawn on the device (argsort of seeded uniform keys)
+    def draw_slottings(gen, n):
+        keys = torch.rand(n, inst.n_categories, generator=gen, device="cuda")
+        z = torch.full((n, 64), 0xFF, dtype=torch.uint8, device="cuda")
+        z[:, :inst.n_categories] = keys.argsort(dim=1).to(torch.uint8)
+        return z
+
+    draw_slottings(torch.Generator(device="cuda"), 4096)   # first-use set-up of these ops, untimed
+    torch.cuda.synchronize()
     t0 = time.perf_counter()
     n_train = args.train_samples
-    r_tr = np.random.default_rng([0, synth.generators.STREAM_SURROGATE_TRAIN])
-    ztr = torch.from_numpy(synth.generators.random_zone_perms(r_tr, n_train, inst.n_categories)).cuda()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(int(synth.generators.STREAM_SURROGATE_TRAIN))
+    ztr = draw_slottings(gen, n_train)
     dtr = torch.empty(n_train, dtype=torch.int32, device="cuda")
     ident = torch.arange(n, dtype=torch.int16, device="cuda")
     chunk = 16384
@@ -162,7 +172,7 @@ def search_comparison(args):
     t_data = time.perf_counter() - t0
     sur = wo.wo_sur_create(inst.n_categories, None, seed=1)
     t1 = time.perf_counter()
-    loss = wo.wo_sur_train(sur, ztr, dtr, epochs=args.epochs, batch=1024, lr=1e-3, seed=2)
+    loss = wo.wo_sur_train(sur, ztr, dtr, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=2)
     t_train = time.perf_counter() - t1
     # held-out error of the surrogate against the exact evaluator
     r_ho = np.random.default_rng([0, synth.generators.STREAM_SURROGATE_HELDOUT])
@@ -214,7 +224,8 @@ def search_comparison(args):
                      "generations": len(scr_trace) - 1, "wall_s": scr_trace[-1][0],
                      "time_to_within_0.5pct_s": t_hit,
                      "time_to_within_0.5pct_incl_training_s": None if t_hit is None else t_hit + t_data + t_train},
-        "surrogate": {"train_samples": n_train, "epochs": args.epochs, "last_epoch_loss": loss,
+        "surrogate": {"train_samples": n_train, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
+                      "last_epoch_loss": loss,
                       "data_s": t_data, "train_s": t_train, "heldout_rel_mae": rel_mae,
                       "heldout_spearman": rho, "predict_65536_s": t_pred},
         "initial_best_dist": plain_trace[0][1],
@@ -384,7 +395,9 @@ def main(argv=None):
     ap.add_argument("--population", type=int, default=16384)
     ap.add_argument("--generations", type=int, default=200)
     ap.add_argument("--train-samples", type=int, default=1 << 20)
-    ap.add_argument("--epochs", type=int, default=4)
+    ap.add_argument("--epochs", type=int, default=1, help="surrogate training epochs (search comparison)")
+    ap.add_argument("--batch", type=int, default=4096, help="surrogate training batch (search comparison)")
+    ap.add_argument("--lr", type=float, default=2e-3, help="surrogate learning rate (search comparison)")
     ap.add_argument("--batched", action="store_true",
                     help="time the 512-instance uneven batch (autotuned, eager and graph replay) instead")
     ap.add_argument("--surrogate", action="store_true",
