@@ -324,7 +324,7 @@ BF16_PEAK_FLOPS = 2.5e15
 
 def surrogate_bench(args):
     """Surrogate throughput on the BF16 matrix cores: screening predictions
-    (65,536 candidates per call) and training (batch 1,024), on random
+    (65,536 candidates per call) and training (batch 4,096), on random
     slottings of the 64-category paper warehouse."""
     import torch
 
@@ -353,10 +353,10 @@ def surrogate_bench(args):
     n_train = 1 << 18
     zt = torch.from_numpy(synth.generators.random_zone_perms(rng, n_train, 64)).cuda()
     dt = torch.from_numpy(rng.integers(22_000_000, 24_000_000, n_train, dtype=np.int32)).cuda()
-    wo.wo_sur_train(sur, zt[:8192], dt[:8192], epochs=1, batch=1024, lr=1e-4, seed=3)
+    wo.wo_sur_train(sur, zt[:8192], dt[:8192], epochs=1, batch=4096, lr=1e-4, seed=3)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    wo.wo_sur_train(sur, zt, dt, epochs=1, batch=1024, lr=1e-4, seed=4)
+    wo.wo_sur_train(sur, zt, dt, epochs=1, batch=4096, lr=1e-4, seed=4)
     torch.cuda.synchronize()
     train_s = time.perf_counter() - t0
     pred_flops = SUR_FWD_FLOP * K / (pred_ms / 1e3)
@@ -369,7 +369,7 @@ def surrogate_bench(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "MLP 4096-1024-256-1 on one-hot(64 x 64) slottings, 65,536 candidates "
-                               "per call; training batch 1,024 over 262,144 samples"},
+                               "per call; training batch 4,096 over 262,144 samples"},
         "roofline": {"bound": "mfma", "achieved": pred_flops / 1e12, "peak": BF16_PEAK_FLOPS / 1e12,
                      "unit": "TFLOP/s", "frac": pred_flops / BF16_PEAK_FLOPS, "traffic": None},
         "train": {"samples_per_s": n_train / train_s, "epoch_s": train_s,

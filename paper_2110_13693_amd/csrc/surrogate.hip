@@ -323,9 +323,11 @@ __global__ __launch_bounds__(256) void batch_sums_kernel(SumArgs a)
 }
 
 // Adam over the flat fp32 parameter vector (Kingma & Ba 2015, bias-corrected).
+// Adam over the fp32 masters; the updated W1 and W2 also go straight to
+// their bf16 working copies (W2 in both layouts), as refresh_bf16_kernel does.
 __global__ __launch_bounds__(256) void adam_kernel(float *p, const float *g, float *m, float *v, int64_t n,
                                                    float lr, float beta1, float beta2, float eps, float bc1,
-                                                   float bc2)
+                                                   float bc2, uint16_t *W1b, uint16_t *W2b, uint16_t *W2kn)
 {
     for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256) {
         const float gi = g[i];
@@ -333,7 +335,16 @@ __global__ __launch_bounds__(256) void adam_kernel(float *p, const float *g, flo
         const float vi = beta2 * v[i] + (1.0f - beta2) * gi * gi;
         m[i] = mi;
         v[i] = vi;
-        p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+        const float pi = p[i] - lr * (mi / bc1) / (sqrtf(vi / bc2) + eps);
+        p[i] = pi;
+        if (W1b && i < P_W1 + (int64_t)N_H1 * N_IN) {
+            W1b[i - P_W1] = f2bf(pi);
+        } else if (W1b && i >= P_W2 && i < P_W2 + (int64_t)N_H2 * N_H1) {
+            const int64_t k = i - P_W2;                 // W2 [j][i2], j < 256, i2 < 1024
+            const uint16_t h = f2bf(pi);
+            W2b[k] = h;
+            W2kn[(k % N_H1) * N_H2 + k / N_H1] = h;
+        }
     }
 }
 
@@ -552,11 +563,13 @@ hipError_t launch_batch_sums(const SumArgs &a, hipStream_t s)
     return hipGetLastError();
 }
 
-hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, int step, hipStream_t s)
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, int step,
+                       uint16_t *W1b, uint16_t *W2b, uint16_t *W2kn, hipStream_t s)
 {
     const float b1 = 0.9f, b2 = 0.999f;
     const float bc1 = 1.0f - powf(b1, (float)step), bc2 = 1.0f - powf(b2, (float)step);
-    hipLaunchKernelGGL(adam_kernel, dim3(2048), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, 1e-8f, bc1, bc2);
+    hipLaunchKernelGGL(adam_kernel, dim3(2048), dim3(256), 0, s, p, g, m, v, n, lr, b1, b2, 1e-8f, bc1, bc2, W1b,
+                       W2b, W2kn);
     return hipGetLastError();
 }
 

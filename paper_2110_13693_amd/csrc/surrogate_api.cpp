@@ -439,8 +439,8 @@ extern "C" wo_status wo_sur_train(wo_sur *s, int64_t n, const uint8_t *d_zone_of
             wo_status r = gradients(s, batch, st);
             if (r) return r;
             s->step++;
-            WO_HIP(launch_adam(s->d_p, s->d_g, s->d_m, s->d_v, P_TOTAL, lr, s->step, st));
-            WO_HIP(launch_refresh_bf16(s->d_p + P_W1, s->d_p + P_W2, s->d_W1b, s->d_W2b, s->d_W2kn, st));
+            WO_HIP(launch_adam(s->d_p, s->d_g, s->d_m, s->d_v, P_TOTAL, lr, s->step, s->d_W1b, s->d_W2b, s->d_W2kn,
+                               st));
             if (last && h_last_loss)
                 WO_HIP(hipMemcpyAsync(&losses[b], s->d_loss, sizeof(float), hipMemcpyDeviceToHost, st));
         }

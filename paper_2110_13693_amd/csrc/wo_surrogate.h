@@ -69,7 +69,10 @@ struct SumArgs {
 hipError_t launch_gemm(int amode, int bmode, int epi, const GemmArgs &g, hipStream_t s);
 hipError_t launch_layer3(const L3Args &a, hipStream_t s);
 hipError_t launch_batch_sums(const SumArgs &a, hipStream_t s);
-hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, int step, hipStream_t s);
+// Adam step; when W1b is non-null the updated W1 and W2 are also written to
+// their bf16 copies (W2 as stored and transposed), as launch_refresh_bf16 does
+hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, float lr, int step,
+                       uint16_t *W1b, uint16_t *W2b, uint16_t *W2kn, hipStream_t s);
 hipError_t launch_refresh_bf16(const float *W1t, const float *W2t, uint16_t *W1b, uint16_t *W2b, uint16_t *W2kn,
                                hipStream_t s);
 hipError_t launch_gather_batch(const uint8_t *zone, const int32_t *dist, const int32_t *idx, int n, double mean,
