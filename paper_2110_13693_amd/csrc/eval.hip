@@ -35,6 +35,9 @@
 //   6. per tour: k = popcount of the aisle set, S-shape closed form; the
 //      block sums the tours in int64.
 // Tours beyond one tile of rows are handled in further passes over the lines.
+// The return and largest-gap routes (ROUTE = 1, 2) share steps 1-4; their rows
+// hold each tour's picks instead (step 5 appends the line's scaled location),
+// and step 6 sorts a tour's picks by (aisle, depth) and walks them once.
 #include "wo_internal.h"
 
 namespace wo {
