@@ -87,6 +87,26 @@ def test_forward_matches_reference(n_cat):
     s.free()
 
 
+def test_large_screen_matches_reference_on_samples():
+    # 70,000 candidates: one full 65,536-row pass and a ragged second one;
+    # sampled rows of both against the reference forward
+    import torch
+    wo = _wo()
+    p = _params(6)
+    s = wo.wo_sur_create(64, flat(p))
+    wo.wo_sur_set_scale(s, 0.0, 1.0)
+    n = 70000
+    Z = _zones(n, 7)
+    z = torch.from_numpy(Z).cuda()
+    pred = torch.empty(n, dtype=torch.float32, device="cuda")
+    wo.wo_sur_predict(s, z, pred)
+    torch.cuda.synchronize()
+    rows = np.concatenate([np.arange(0, 64), np.arange(65472, 65600), np.arange(n - 64, n)])
+    y, _ = S.forward(_ref_params(p), S.one_hot(Z[rows], 64))
+    assert _rel_l2(pred.cpu().numpy()[rows], y) <= 1e-2
+    s.free()
+
+
 def test_padding_bytes_are_ignored():
     import torch
     wo = _wo()
