@@ -406,8 +406,8 @@ def main(argv=None):
                     help="only copy a MIB-sized device buffer 10 times (calibrates HBM byte counters)")
     args = ap.parse_args(argv)
     if args.gpus != 1:
-        print("bench.py measures one GPU only; --gpus %d is not supported (the evaluator "
-              "shards plans across GPUs with no exchange, see DESIGN.md)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only; --gpus %d is not supported (on several GPUs the "
+              "evaluator would shard the plans, with no exchange between GPUs)" % args.gpus, file=sys.stderr)
         return 2
 
     if args.search:

@@ -281,7 +281,7 @@ wo_status wo_sur_load(const char *path, void *stream, wo_sur **out);
  * the surrogate and write the indices of the `keep` smallest predictions,
  * ordered by (prediction, index), to d_keep_idx int32[keep] (async).
  * d_pred (nullable) receives all predictions.  keep <= WO_SCREEN_MAX_KEEP,
- * n_plans <= 2^24.  The exact evaluator remains the judge: re-score the kept
+ * n_plans <= 2^24.  The exact evaluator has the last word: re-score the kept
  * plans with wo_eval_plans. */
 wo_status wo_screen_plans(wo_wh *wh, int32_t inst, wo_sur *s, int64_t n_plans, const uint8_t *d_zone_of,
                           float *d_pred, int64_t keep, int32_t *d_keep_idx, void *stream);

@@ -11,7 +11,7 @@ stream])`` so each kind of draw has its own stream:
     2  candidate plans                    5  surrogate held-out plans
                                           6  search initial population
 
-Recipe (the readings are listed in the design doc):
+Recipe:
 
 * Category sizes are equal (``n_skus / C`` each) or Dirichlet(alpha) scaled to
   ``n_skus`` by largest remainder with every size >= 1.
