@@ -66,17 +66,19 @@ def test_batched_routed_instances_match_single():
     import torch
     wo = _wo()
     rng = np.random.default_rng(31)
+    # orders up to 1,024, up to 2,048 and beyond: all three launch classes
     insts = [_routed(_random_instance(rng, n_a, 40, n_o, 20, 16), 2)
-             for n_a, n_o in ((8, 60), (30, 500), (12, 200))]
+             for n_a, n_o in ((8, 60), (30, 500), (12, 200), (60, 1500), (100, 3000))]
     plans = [synth.make_plans(i, 16, seed=k) for k, i in enumerate(insts)]
     wh = wo.wo_load_warehouse(insts)
     Z = np.concatenate([p[0] for p in plans])
     S = np.concatenate([p[1].reshape(-1) for p in plans])
-    offs = np.array([0, 16, 32, 48], dtype=np.int64)
+    n = 16 * len(insts)
+    offs = np.arange(0, n + 1, 16, dtype=np.int64)
     z = torch.from_numpy(Z).cuda()
     s = torch.from_numpy(S.view(np.int16)).cuda()
-    d = torch.empty(48, dtype=torch.int32, device="cuda")
-    t = torch.empty(48, dtype=torch.float32, device="cuda")
+    d = torch.empty(n, dtype=torch.int32, device="cuda")
+    t = torch.empty(n, dtype=torch.float32, device="cuda")
     wo.wo_eval_plans(wh, z, s, d, t, plan_offsets=offs)
     torch.cuda.synchronize()
     for k, (inst, (Zi, Si)) in enumerate(zip(insts, plans)):
