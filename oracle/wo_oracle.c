@@ -24,7 +24,7 @@
  *      item count plus the order's stays <= capacity, otherwise it opens a new
  *      tour; an order is never split (an order larger than the capacity is a
  *      tour of its own);
- *   4. route per tour, by one of the standard heuristics of the routing
+ *   4. route per tour, by one of the standard policies of the routing
  *      literature the paper builds on (de Koster et al. 2007), depot at the
  *      front of aisle 0, L = S * pitch:
  *      - S-shape (the default): every aisle holding a pick is traversed
@@ -42,6 +42,9 @@
  *        front to first pick, between adjacent picks, last pick to back;
  *        cost = 2 * spacing * a_max + 2 * L + sum over the inner aisles of
  *        2 * (L - gap); with a single aisle it is the return route;
+ *      - optimal: the shortest closed walk from the depot through every pick
+ *        (the paper's minimum route distance), by a dynamic programme over the
+ *        aisles (orc_optimal_cost below states it);
  *   5. D = sum of tour costs (exact in int64; the int32 output saturates at
  *      INT32_MAX);
  *   6. throughput over the time window (delta = f(d)):
@@ -70,7 +73,7 @@ typedef struct {
     int32_t routing;               /* ORC_ROUTE_* */
 } orc_instance;
 
-enum { ORC_ROUTE_SSHAPE = 0, ORC_ROUTE_RETURN = 1, ORC_ROUTE_LARGEST_GAP = 2 };
+enum { ORC_ROUTE_SSHAPE = 0, ORC_ROUTE_RETURN = 1, ORC_ROUTE_LARGEST_GAP = 2, ORC_ROUTE_OPTIMAL = 3 };
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_NOMEM = 3 };
 
@@ -254,11 +257,162 @@ int64_t orc_largest_gap_cost(const orc_instance *w, const int32_t *locs, int32_t
     return cost;
 }
 
+/* Optimal route (the paper's minimum route distance, section 5, Subproblem 2,
+ * found there by trying visiting orders).  In a single-block warehouse the
+ * shortest closed walk from the depot through every pick is found exactly by
+ * a dynamic programme over the aisles from left to right, in the manner of
+ * Ratliff and Rosenthal (1983).  It is stated here from first principles:
+ *
+ *   A closed walk is a connected multigraph on the aisle graph in which every
+ *   vertex has even degree; an edge is never needed more than twice.  The
+ *   vertices are the two ends of every aisle (front f_j at y = 0, back b_j at
+ *   y = L), the picks, and the depot (= f_0).  The programme decides, column
+ *   by column, first the vertical edges inside aisle j, then the horizontal
+ *   edges f_j-f_{j+1} and b_j-b_{j+1} (0, 1 or 2 copies each).  After a column
+ *   only f_j and b_j can still gain edges, so a partial solution is described
+ *   by: for each of f_j, b_j whether it is absent (no edge, not the depot),
+ *   of even or of odd degree; whether the two lie in one component; and
+ *   whether a component has been closed off (it can touch nothing to the
+ *   right, so it must be the whole walk: the state DONE).
+ *
+ *   Inside an aisle with picks y_1 <= ... <= y_m, every pick needs even
+ *   degree > 0, so the m + 1 segments (front-y_1, ..., y_m-back) all have the
+ *   same multiplicity parity: either all are used once (a traversal, cost L,
+ *   joining f_j and b_j) or each is used 0 or 2 times.  In the second case the
+ *   doubled segments must reach the front or the back (a doubled run touching
+ *   neither is a component that can never join the rest), so exactly one
+ *   segment is left out (cost 2 (L - that segment), picks below it hang on
+ *   f_j, picks above it on b_j) or none (cost 2 L, joining f_j and b_j).  An
+ *   aisle without picks may also be left empty.
+ *
+ *   A horizontal edge from an absent vertex would be a dead end that can be
+ *   removed, so it is not generated.  The walk never needs a column right of
+ *   the last aisle with picks, nor left of the depot's aisle 0. */
+enum { ORC_ABSENT = 0, ORC_EVEN = 1, ORC_ODD = 2 };
+#define ORC_NSTATE 19            /* (front, back, joined) + DONE */
+#define ORC_DONE 18
+#define ORC_INF ((int64_t)1 << 60)
+
+static int orc_state(int f, int b, int joined) { return (f * 3 + b) * 2 + (f && b ? joined : 0); }
+
+static int orc_add_degree(int st, int d)
+{
+    if (d == 0) return st;
+    if (st == ORC_ABSENT) return (d & 1) ? ORC_ODD : ORC_EVEN;
+    if (d & 1) return st == ORC_ODD ? ORC_EVEN : ORC_ODD;
+    return st;
+}
+
+static void orc_relax(int64_t *cost, int s, int64_t c)
+{
+    if (c < cost[s]) cost[s] = c;
+}
+
+/* One vertical pattern of aisle j applied to state s (not DONE).
+ * df, db: degree added at the front and back end; join: the pattern links
+ * front and back; lo_f / hi_b: some picks hang on the front / back end only. */
+static void orc_vertical(int64_t *out, int s, int64_t c, int df, int db, int join, int lo_f, int hi_b)
+{
+    int f = s / 6, b = (s / 2) % 3, joined = s & 1;
+    int nf = orc_add_degree(f, df), nb = orc_add_degree(b, db);
+    if (join) {
+        joined = 1;                          /* the pattern is a path from f_j to b_j */
+    } else {
+        /* an end that was absent and gains edges starts a new component:
+         * it is not joined to the other end */
+        if ((lo_f && f == ORC_ABSENT) || (hi_b && b == ORC_ABSENT)) joined = 0;
+    }
+    orc_relax(out, orc_state(nf, nb, joined), c);
+}
+
+int64_t orc_optimal_cost(const orc_instance *w, const int32_t *locs, int32_t n)
+{
+    const int64_t L = (int64_t)w->slots_per_side * w->pitch_dm;
+    const int64_t sp = w->spacing_dm;
+    int64_t cur[ORC_NSTATE], nxt[ORC_NSTATE], best;
+    int32_t i, j, first, a_max;
+    orc_pick *pk;
+    if (n <= 0) return 0;
+    pk = orc_sorted_picks(w, locs, n);
+    if (!pk) return -1;
+    a_max = pk[n - 1].a;
+
+    for (i = 0; i < ORC_NSTATE; i++) cur[i] = ORC_INF;
+    cur[orc_state(ORC_EVEN, ORC_ABSENT, 0)] = 0;        /* the depot at f_0, no edge yet */
+    first = 0;
+    for (j = 0; j <= a_max; j++) {
+        int32_t last = first, s, g;
+        while (last < n && pk[last].a == j) last++;   /* picks of aisle j: [first, last) */
+        /* vertical edges inside aisle j */
+        for (i = 0; i < ORC_NSTATE; i++) nxt[i] = ORC_INF;
+        for (s = 0; s < ORC_NSTATE; s++) {
+            int64_t c = cur[s];
+            if (c >= ORC_INF) continue;
+            if (s == ORC_DONE) {                     /* nothing may be added any more */
+                if (last == first) orc_relax(nxt, ORC_DONE, c);
+                continue;
+            }
+            if (last == first) orc_vertical(nxt, s, c, 0, 0, 0, 0, 0);      /* left empty */
+            orc_vertical(nxt, s, c + L, 1, 1, 1, 0, 0);                      /* traversed once */
+            orc_vertical(nxt, s, c + 2 * L, 2, 2, 1, 0, 0);                  /* traversed twice */
+            for (g = first; g <= last && last > first; g++) {
+                /* leave out segment g: from y_{g-1} (front if g = first) to
+                 * y_g (back if g = last); everything else doubled */
+                int64_t lo = g == first ? 0 : pk[g - 1].y;
+                int64_t hi = g == last ? L : pk[g].y;
+                int has_lo = g > first, has_hi = g < last;
+                orc_vertical(nxt, s, c + 2 * (L - (hi - lo)), has_lo ? 2 : 0, has_hi ? 2 : 0, 0,
+                             has_lo, has_hi);
+            }
+        }
+        memcpy(cur, nxt, sizeof cur);
+        first = last;
+        if (j == a_max) break;
+        /* horizontal edges to column j + 1 */
+        for (i = 0; i < ORC_NSTATE; i++) nxt[i] = ORC_INF;
+        for (s = 0; s < ORC_NSTATE; s++) {
+            int hf, hb, f = s / 6, b = (s / 2) % 3, joined = s & 1;
+            int64_t c = cur[s];
+            if (c >= ORC_INF) continue;
+            if (s == ORC_DONE) { orc_relax(nxt, ORC_DONE, c); continue; }
+            for (hf = 0; hf <= 2; hf++)
+                for (hb = 0; hb <= 2; hb++) {
+                    if ((f == ORC_ABSENT && hf) || (b == ORC_ABSENT && hb)) continue;
+                    /* f_j and b_j are final now: even degree */
+                    if (f != ORC_ABSENT && orc_add_degree(f, hf) != ORC_EVEN) continue;
+                    if (b != ORC_ABSENT && orc_add_degree(b, hb) != ORC_EVEN) continue;
+                    if (f && b && !joined) {
+                        /* two components: each must continue to the right */
+                        if (!hf || !hb) continue;
+                    } else if (!hf && !hb) {
+                        orc_relax(nxt, ORC_DONE, c);      /* the one component closes */
+                        continue;
+                    }
+                    orc_relax(nxt, orc_state(orc_add_degree(ORC_ABSENT, hf), orc_add_degree(ORC_ABSENT, hb),
+                                             joined || !(f && b)),
+                              c + sp * (hf + hb));
+                }
+        }
+        memcpy(cur, nxt, sizeof cur);
+    }
+    free(pk);
+    /* the walk ends after aisle a_max: even ends, one component */
+    best = cur[ORC_DONE];
+    for (i = 0; i < ORC_NSTATE; i++) {
+        int f = i / 6, b = (i / 2) % 3;
+        if (i == ORC_DONE || f == ORC_ODD || b == ORC_ODD || (f == ORC_ABSENT && b == ORC_ABSENT)) continue;
+        if (f && b && !(i & 1)) continue;
+        if (cur[i] < best) best = cur[i];
+    }
+    return best;
+}
+
 int64_t orc_tour_cost(const orc_instance *w, const int32_t *locs, int32_t n)
 {
     switch (w->routing) {
     case ORC_ROUTE_RETURN: return orc_return_cost(w, locs, n);
     case ORC_ROUTE_LARGEST_GAP: return orc_largest_gap_cost(w, locs, n);
+    case ORC_ROUTE_OPTIMAL: return orc_optimal_cost(w, locs, n);
     default: return orc_sshape_cost(w, locs, n);
     }
 }
@@ -310,7 +464,7 @@ static int orc_check_instance(const orc_instance *w)
     int32_t o, l;
     if (w->n_aisles < 1 || w->slots_per_side < 1 || w->pitch_dm < 2 || (w->pitch_dm & 1) ||
         w->spacing_dm < 0 || w->capacity < 1 || w->n_orders < 1 || w->n_orders > 65535 ||
-        w->routing < ORC_ROUTE_SSHAPE || w->routing > ORC_ROUTE_LARGEST_GAP)
+        w->routing < ORC_ROUTE_SSHAPE || w->routing > ORC_ROUTE_OPTIMAL)
         return ORC_E_INVAL;
     if (w->order_offsets[0] != 0) return ORC_E_INVAL;
     for (o = 0; o < w->n_orders; o++)

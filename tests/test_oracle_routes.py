@@ -1,5 +1,5 @@
-"""Pins of the oracle's route distances (S-shape, return, largest gap)
-against independent route geometry.
+"""Pins of the oracle's route distances (S-shape, return, largest gap,
+optimal) against independent route geometry.
 
 * Dijkstra on the explicit aisle graph (the paper computes distances between
   pick positions with Dijkstra's algorithm, section 5, Subproblem 2) equals
@@ -8,6 +8,8 @@ against independent route geometry.
   sequences", same passage) gives the optimal tour; S-shape is never shorter.
 * An explicit waypoint walk of the S-shape route reproduces the oracle's cost
   and passes every pick.
+* The optimal route's dynamic programme equals that brute-force optimum
+  exactly, and is never longer than any of the heuristic routes.
 """
 import numpy as np
 import pytest
@@ -166,6 +168,78 @@ def test_routing_field_selects_the_tour_cost():
     import dataclasses
     base = tiny_geometry([[0]], n_aisles=10)
     locs = [0, 130, 599]
-    for routing, f in ((0, oracle.sshape_cost), (1, oracle.return_cost), (2, oracle.largest_gap_cost)):
+    for routing, f in ((0, oracle.sshape_cost), (1, oracle.return_cost), (2, oracle.largest_gap_cost),
+                       (3, oracle.optimal_cost)):
         inst = dataclasses.replace(base, routing=routing)
         assert oracle.tour_cost(inst, locs) == f(base, locs)
+
+
+# ------------------------------------------------------------ optimal route
+OPT_GEOMETRIES = [
+    dict(n_aisles=10),                         # L = 300 dm, aisles 30 dm apart
+    dict(n_aisles=7, slots=3, spacing=30),     # short aisles: L = 30 dm, as long as a step across
+    dict(n_aisles=8, slots=2, spacing=50),     # aisles shorter than a step across
+    dict(n_aisles=5, slots=30, spacing=4),     # long aisles close together
+    dict(n_aisles=12, slots=5, pitch=4, spacing=9),
+]
+
+
+@pytest.mark.parametrize("geom", range(len(OPT_GEOMETRIES)))
+@pytest.mark.parametrize("seed", range(12))
+def test_optimal_equals_brute_force(geom, seed):
+    # the dynamic programme against Dijkstra distances and every visiting order
+    inst = tiny_geometry([[0]], **OPT_GEOMETRIES[geom])
+    rng = np.random.default_rng(7000 + 100 * geom + seed)
+    for _ in range(6):
+        locs = _random_tour(rng, inst, int(rng.integers(1, 8)))
+        pts = sorted({point(inst, l) for l in locs})
+        assert oracle.optimal_cost(inst, locs) == optimal_tour_length(aisle_graph_dijkstra(inst, pts)), locs
+
+
+def test_optimal_hand_examples():
+    inst = tiny_geometry([[0]], n_aisles=10)
+    assert oracle.optimal_cost(inst, [60, 120]) == 140       # the return route
+    assert oracle.optimal_cost(inst, [0, 130, 599]) == 1150
+    # picks at y = 5 and y = 295 in aisle 5 only: in from the front to the deep
+    # pick and back (2*5*30 + 2*295 = 890) beats the loop up the empty aisle 0,
+    # along the back and down aisle 5 (2*300 + 2*5*30 = 900)
+    assert oracle.optimal_cost(inst, [5 * 60, 5 * 60 + 59]) == 890
+    # aisles 30 dm long and 50 dm apart, picks at y = 25 in aisles 2 and 5:
+    # front to aisle 2, across it, along the back to aisle 5, down it and back
+    # along the front: 2*50 + 30 + 3*50 + 30 + 5*50 = 560, against 600 for
+    # going in from the front twice
+    short = tiny_geometry([[0]], n_aisles=8, slots=3, spacing=50)
+    locs = [2 * 6 + 4, 5 * 6 + 4]
+    pts = sorted({point(short, l) for l in locs})
+    assert oracle.optimal_cost(short, locs) == optimal_tour_length(aisle_graph_dijkstra(short, pts)) == 560
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_optimal_not_above_heuristics(seed):
+    # paper-like aisles (250 slots, 400 aisles) and tours of up to 30 picks
+    rng = np.random.default_rng(8000 + seed)
+    inst = tiny_geometry([[0]], n_aisles=400, slots=250, n_cat=1, cat_size=1)
+    locs = _random_tour(rng, inst, int(rng.integers(1, 31)))
+    opt = oracle.optimal_cost(inst, locs)
+    assert opt <= min(oracle.sshape_cost(inst, locs), oracle.return_cost(inst, locs),
+                      oracle.largest_gap_cost(inst, locs))
+    pts = [point(inst, l) for l in locs]
+    a_max = max(a for a, _ in pts)
+    # at least the walk to the farthest aisle and back, and twice the
+    # depot distance of any pick
+    L = inst.slots_per_side * inst.pitch_dm
+    assert opt >= 2 * inst.spacing_dm * a_max
+    assert opt >= max(2 * (inst.spacing_dm * a + min(y, 2 * L - y)) for a, y in pts)
+
+
+@pytest.mark.parametrize("seed", range(10))
+def test_optimal_invariant_under_pick_order_and_duplicates(seed):
+    rng = np.random.default_rng(9000 + seed)
+    inst = tiny_geometry([[0]], n_aisles=40, slots=50)
+    locs = _random_tour(rng, inst, 20)
+    base = oracle.optimal_cost(inst, locs)
+    assert oracle.optimal_cost(inst, list(rng.permutation(locs))) == base
+    assert oracle.optimal_cost(inst, locs + locs[:5]) == base
+    # a pick on the other side of the same aisle position is the same point
+    twin = [l ^ 1 for l in locs]
+    assert oracle.optimal_cost(inst, twin) == base
