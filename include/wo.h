@@ -102,8 +102,8 @@ typedef struct {
 } wo_instance_desc;
 
 /* Route of a tour (section 5, Subproblem 2 leaves the routing method open;
- * these are the standard heuristics of the order-picking literature, depot
- * at the front of aisle 0, L = slots_per_side * pitch_dm):
+ * these are the standard policies of the order-picking literature, depot at
+ * the front of aisle 0, L = slots_per_side * pitch_dm):
  *   WO_ROUTE_SSHAPE      every aisle with a pick is crossed entirely; with an
  *                        odd count the last one is entered and left from the
  *                        front;
@@ -113,11 +113,16 @@ typedef struct {
  *                        every other one is entered from both cross aisles,
  *                        each time up to its largest gap (front to first pick,
  *                        between picks, last pick to back) and back; a single
- *                        aisle is a return route.
- * Return and largest gap keep every pick of a tour in LDS: a tour may hold at
- * most WO_MAX_PICK_SLOTS lines (capacity, and any single order), else
- * wo_load_warehouse fails with WO_E_UNSUPPORTED. */
-enum { WO_ROUTE_SSHAPE = 0, WO_ROUTE_RETURN = 1, WO_ROUTE_LARGEST_GAP = 2 };
+ *                        aisle is a return route;
+ *   WO_ROUTE_OPTIMAL     the shortest closed walk from the depot through every
+ *                        pick (the minimum route distance of the same passage),
+ *                        exact for the single-block layout.
+ * Return, largest gap and optimal keep every pick of a tour in LDS: a tour may
+ * hold at most WO_MAX_PICK_SLOTS lines (capacity, and any single order), else
+ * wo_load_warehouse fails with WO_E_UNSUPPORTED.  The optimal route computes
+ * in 32-bit integers: 4 * spacing * (n_aisles + 2) + 4 * L * (n_aisles + 1)
+ * must stay below 2^30 dm, else the load fails with WO_E_RANGE. */
+enum { WO_ROUTE_SSHAPE = 0, WO_ROUTE_RETURN = 1, WO_ROUTE_LARGEST_GAP = 2, WO_ROUTE_OPTIMAL = 3 };
 #define WO_MAX_PICK_SLOTS 32
 
 typedef struct wo_wh wo_wh;

@@ -166,7 +166,7 @@ static wo_status check_desc(const wo_instance_desc &d, int idx)
         return fail(WO_E_INVAL, "instance %d: slot pitch must be even and >= 2 (got %d)", idx, d.pitch_dm);
     if (d.spacing_dm < 0) return fail(WO_E_INVAL, "instance %d: negative aisle spacing", idx);
     if (d.capacity < 1) return fail(WO_E_INVAL, "instance %d: capacity must be >= 1", idx);
-    if (d.routing < WO_ROUTE_SSHAPE || d.routing > WO_ROUTE_LARGEST_GAP)
+    if (d.routing < WO_ROUTE_SSHAPE || d.routing > WO_ROUTE_OPTIMAL)
         return fail(WO_E_INVAL, "instance %d: unknown routing %d", idx, d.routing);
     if (d.capacity > WO_MAX_CAPACITY)
         return fail(WO_E_RANGE, "instance %d: capacity %d > %d", idx, d.capacity, WO_MAX_CAPACITY);
@@ -176,6 +176,15 @@ static wo_status check_desc(const wo_instance_desc &d, int idx)
     int64_t n_loc = 2ll * d.n_aisles * d.slots_per_side;
     if (n_loc > WO_MAX_LOCATIONS)
         return fail(WO_E_RANGE, "instance %d: %lld locations > %d", idx, (long long)n_loc, WO_MAX_LOCATIONS);
+    if (d.routing == WO_ROUTE_OPTIMAL) {
+        // every class cost of the optimal route's programme, plus its
+        // unreachable marker 2^30, must fit a signed 32-bit integer
+        const int64_t L = (int64_t)d.slots_per_side * d.pitch_dm;
+        const int64_t bound = 4ll * d.spacing_dm * (d.n_aisles + 2) + 4ll * L * (d.n_aisles + 1);
+        if (bound >= (1ll << 30))
+            return fail(WO_E_RANGE, "instance %d: warehouse too large for the optimal route's 32-bit "
+                        "distances (%lld dm)", idx, (long long)bound);
+    }
     if (d.n_orders < 1) return fail(WO_E_INVAL, "instance %d: need >= 1 order", idx);
     if (d.n_orders > WO_MAX_ORDERS)
         return fail(WO_E_RANGE, "instance %d: %d orders > %d", idx, d.n_orders, WO_MAX_ORDERS);
@@ -264,7 +273,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
             I.pick_slots = std::max(d.capacity, max_lines);
             if (d.routing != WO_ROUTE_SSHAPE && I.pick_slots > MAX_PICK_SLOTS)
                 return fail(WO_E_UNSUPPORTED, "instance %d: a tour may hold %d lines, more than the %d a "
-                            "return or largest-gap row keeps", i, I.pick_slots, MAX_PICK_SLOTS);
+                            "route's pick row keeps", i, I.pick_slots, MAX_PICK_SLOTS);
             I.row_b = (int32_t)(d.routing == WO_ROUTE_SSHAPE ? row_bytes(I.words) : pick_row_bytes(I.pick_slots));
         }
         I.capacity = d.capacity;

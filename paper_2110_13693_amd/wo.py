@@ -67,7 +67,7 @@ class wo_instance_desc(ctypes.Structure):
     ]
 
 
-WO_ROUTE_SSHAPE, WO_ROUTE_RETURN, WO_ROUTE_LARGEST_GAP = 0, 1, 2
+WO_ROUTE_SSHAPE, WO_ROUTE_RETURN, WO_ROUTE_LARGEST_GAP, WO_ROUTE_OPTIMAL = 0, 1, 2, 3
 
 _lib = None
 

@@ -77,7 +77,7 @@ def _mod(inst, **kw):
     ("capacity", 33, 2),            # above the supported capacity
     ("n_categories", 65, 2),        # more than 64 categories
     ("n_aisles", 1, 2),             # 600 SKUs no longer fit 60 locations
-    ("routing", 3, 1),              # unknown route
+    ("routing", 4, 1),              # unknown route
     ("routing", -1, 1),
 ])
 def test_load_rejects_descriptor(wo, tiny, field, value, status):
@@ -154,6 +154,15 @@ def test_binding_refuses_host_tensors(wo):
     d = torch.zeros((1,), dtype=torch.int32)
     with pytest.raises(ValueError):
         wo.wo_eval_plans(FakeWh(), z, s, d)
+
+
+def test_load_rejects_optimal_route_beyond_32_bits(wo, tiny):
+    # the optimal route's programme computes in 32-bit integers: 30 slots of
+    # 1,000,000 dm make 4 * L * (10 + 1) = 1.32e9 dm, beyond 2^30
+    st, out = _load_status(wo, _mod(tiny, routing=3, pitch_dm=1000000))
+    assert st == wo.WO_E_RANGE, wo.wo_last_error()
+    assert "optimal" in wo.wo_last_error()
+    assert out.value is None
 
 
 def test_load_rejects_mixed_routing(wo, tiny):

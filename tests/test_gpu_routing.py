@@ -1,5 +1,5 @@
-"""GPU parity of the return and largest-gap routes against the CPU oracle
-(through the C ABI).  Distances must match bit-exactly; the throughput to
+"""GPU parity of the return, largest-gap and optimal routes against the CPU
+oracle (through the C ABI).  Distances must match bit-exactly; the throughput to
 1e-6 relative, as for the S-shape route."""
 import dataclasses
 
@@ -12,7 +12,7 @@ from tests.test_gpu_eval import _compare, _random_instance, _structured_sequence
 
 pytestmark = pytest.mark.gpu
 
-ROUTES = [1, 2]          # return, largest gap
+ROUTES = [1, 2, 3]       # return, largest gap, optimal
 
 
 def _routed(inst, routing):
@@ -40,6 +40,8 @@ ROUTE_CASES = [
     (33, 7, 300, 32, 64, 1.5),     # capacity 32: rows of 32 picks
     (400, 250, 4000, 1, 64, 0.3),  # ~4,000 tours: several tour tiles
     (400, 250, 6000, 30, 64, 1.5), # sequence in memory
+    (60, 2, 500, 12, 16, 1.5),     # aisles 20 dm long, 30 dm apart: loops over empty aisles pay
+    (300, 1, 400, 8, 8, 1.0),      # aisles 10 dm long, long runs without picks
 ]
 
 
@@ -62,12 +64,13 @@ def test_structured_sequences_routed(routing):
     _compare(inst, Z, S)
 
 
-def test_batched_routed_instances_match_single():
+@pytest.mark.parametrize("routing", [2, 3])
+def test_batched_routed_instances_match_single(routing):
     import torch
     wo = _wo()
     rng = np.random.default_rng(31)
     # orders up to 1,024, up to 2,048 and beyond: all three launch classes
-    insts = [_routed(_random_instance(rng, n_a, 40, n_o, 20, 16), 2)
+    insts = [_routed(_random_instance(rng, n_a, 40, n_o, 20, 16), routing)
              for n_a, n_o in ((8, 60), (30, 500), (12, 200), (60, 1500), (100, 3000))]
     plans = [synth.make_plans(i, 16, seed=k) for k, i in enumerate(insts)]
     wh = wo.wo_load_warehouse(insts)
