@@ -37,10 +37,11 @@ class _Inst(ctypes.Structure):
         ("n_orders", ctypes.c_int32), ("order_offsets", ctypes.c_void_p),
         ("order_skus", ctypes.c_void_p),
         ("walk_dm_per_s", ctypes.c_double), ("seconds_per_item", ctypes.c_double),
-        ("window_s", ctypes.c_double), ("routing", ctypes.c_int32),
+        ("window_s", ctypes.c_double), ("routing", ctypes.c_int32), ("batching", ctypes.c_int32),
     ]
 
 ROUTE_SSHAPE, ROUTE_RETURN, ROUTE_LARGEST_GAP, ROUTE_OPTIMAL = 0, 1, 2, 3
+BATCH_NEXT_FIT, BATCH_FIRST_FIT = 0, 1
 
 
 def build(force: bool = True) -> str:
@@ -64,6 +65,7 @@ def _load():
         P = ctypes.POINTER
         lib.orc_locations.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_tours.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.orc_tours_first_fit.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_sshape_cost.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_int32]
         lib.orc_sshape_cost.restype = ctypes.c_int64
         for f in (lib.orc_return_cost, lib.orc_largest_gap_cost, lib.orc_optimal_cost, lib.orc_tour_cost):
@@ -94,7 +96,8 @@ class _Bound:
                        self.cat.ctypes.data, self.off.size - 1, self.off.ctypes.data,
                        self.sku.ctypes.data, float(inst.walk_dm_per_s),
                        float(inst.seconds_per_item), float(inst.window_s),
-                       int(getattr(inst, "routing", ROUTE_SSHAPE)))
+                       int(getattr(inst, "routing", ROUTE_SSHAPE)),
+                       int(getattr(inst, "batching", BATCH_NEXT_FIT)))
         self.n_orders = self.off.size - 1
 
     def ref(self):
@@ -123,6 +126,17 @@ def tours(inst, seq) -> np.ndarray:
     n = ctypes.c_int32(0)
     _check(_load().orc_tours(b.ref(), s.ctypes.data, out.ctypes.data, ctypes.byref(n)))
     return out[: n.value + 1].copy()
+
+
+def tours_first_fit(inst, seq) -> np.ndarray:
+    """First-fit tour of every sequence position, tours numbered in opening order."""
+    b = _Bound(inst)
+    s = _c(seq, np.uint16)
+    out = np.empty(b.n_orders, dtype=np.int32)
+    n = ctypes.c_int32(0)
+    _check(_load().orc_tours_first_fit(b.ref(), s.ctypes.data, out.ctypes.data, ctypes.byref(n)))
+    assert n.value == int(out.max()) + 1
+    return out
 
 
 def sshape_cost(inst, locs) -> int:

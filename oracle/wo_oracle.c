@@ -23,7 +23,8 @@
  *   3. tours: next-fit over seq -- an order joins the open tour if the tour's
  *      item count plus the order's stays <= capacity, otherwise it opens a new
  *      tour; an order is never split (an order larger than the capacity is a
- *      tour of its own);
+ *      tour of its own); or, when the instance asks for it, first fit
+ *      (orc_tours_first_fit below);
  *   4. route per tour, by one of the standard policies of the routing
  *      literature the paper builds on (de Koster et al. 2007), depot at the
  *      front of aisle 0, L = S * pitch:
@@ -71,9 +72,11 @@ typedef struct {
     const int32_t *order_skus;     /* [order_offsets[n_orders]] */
     double walk_dm_per_s, seconds_per_item, window_s;
     int32_t routing;               /* ORC_ROUTE_* */
+    int32_t batching;              /* ORC_BATCH_* */
 } orc_instance;
 
 enum { ORC_ROUTE_SSHAPE = 0, ORC_ROUTE_RETURN = 1, ORC_ROUTE_LARGEST_GAP = 2, ORC_ROUTE_OPTIMAL = 3 };
+enum { ORC_BATCH_NEXT_FIT = 0, ORC_BATCH_FIRST_FIT = 1 };
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_NOMEM = 3 };
 
@@ -156,6 +159,33 @@ int orc_tours(const orc_instance *w, const uint16_t *seq, int32_t *tour_first, i
     }
     tour_first[t] = w->n_orders;
     *n_tours = t;
+    return ORC_OK;
+}
+
+/* First fit, the other greedy order-batching rule of the literature: each
+ * order, in sequence, joins the earliest-opened tour whose item count plus
+ * the order's stays <= capacity; when no open tour has room it opens a new
+ * one.  An order larger than the capacity therefore gets a tour of its own,
+ * which nothing joins later.  tour_of[i] = tour of the order at position i,
+ * tours numbered in opening order. */
+int orc_tours_first_fit(const orc_instance *w, const uint16_t *seq, int32_t *tour_of, int32_t *n_tours)
+{
+    int32_t i, t, T = 0;
+    int64_t *load = (int64_t *)malloc(sizeof(int64_t) * (size_t)w->n_orders);
+    if (!load) return ORC_E_NOMEM;
+    for (i = 0; i < w->n_orders; i++) {
+        int32_t o = seq[i];
+        int64_t items;
+        if (o >= w->n_orders) { free(load); return ORC_E_INVAL; }
+        items = w->order_offsets[o + 1] - w->order_offsets[o];
+        for (t = 0; t < T; t++)
+            if (load[t] + items <= w->capacity) break;
+        if (t == T) load[T++] = 0;   /* open a new tour */
+        load[t] += items;
+        tour_of[i] = t;
+    }
+    free(load);
+    *n_tours = T;
     return ORC_OK;
 }
 
@@ -438,6 +468,26 @@ static int orc_eval_plan_ws(const orc_instance *w, const uint8_t *zone_of, const
     int64_t D = 0;
     int rc = orc_locations(w, zone_of, loc_of_sku);
     if (rc) return rc;
+    if (w->batching == ORC_BATCH_FIRST_FIT) {
+        /* tour_first holds the tour of every position here; a tour's picks
+         * are the lines of its orders */
+        rc = orc_tours_first_fit(w, seq, tour_first, &n_tours);
+        if (rc) return rc;
+        for (t = 0; t < n_tours; t++) {
+            int32_t n = 0;
+            int64_t c;
+            for (i = 0; i < w->n_orders; i++) {
+                int32_t o = seq[i], l;
+                if (tour_first[i] != t) continue;
+                for (l = w->order_offsets[o]; l < w->order_offsets[o + 1]; l++)
+                    picks[n++] = loc_of_sku[w->order_skus[l]];
+            }
+            c = orc_tour_cost(w, picks, n);
+            if (c < 0) return ORC_E_NOMEM;
+            D += c;
+        }
+        goto done;
+    }
     rc = orc_tours(w, seq, tour_first, &n_tours);
     if (rc) return rc;
     for (t = 0; t < n_tours; t++) {
@@ -453,6 +503,7 @@ static int orc_eval_plan_ws(const orc_instance *w, const uint8_t *zone_of, const
             D += c;
         }
     }
+done:
     if (dist_exact) *dist_exact = D;
     if (dist) *dist = D > INT32_MAX ? INT32_MAX : (int32_t)D;
     if (thr) *thr = orc_throughput(w, D);
@@ -464,7 +515,8 @@ static int orc_check_instance(const orc_instance *w)
     int32_t o, l;
     if (w->n_aisles < 1 || w->slots_per_side < 1 || w->pitch_dm < 2 || (w->pitch_dm & 1) ||
         w->spacing_dm < 0 || w->capacity < 1 || w->n_orders < 1 || w->n_orders > 65535 ||
-        w->routing < ORC_ROUTE_SSHAPE || w->routing > ORC_ROUTE_OPTIMAL)
+        w->routing < ORC_ROUTE_SSHAPE || w->routing > ORC_ROUTE_OPTIMAL ||
+        w->batching < ORC_BATCH_NEXT_FIT || w->batching > ORC_BATCH_FIRST_FIT)
         return ORC_E_INVAL;
     if (w->order_offsets[0] != 0) return ORC_E_INVAL;
     for (o = 0; o < w->n_orders; o++)
