@@ -99,6 +99,8 @@ typedef struct {
     double window_s;           /* time window (> 0), e.g. 28800.0 */
     int32_t routing;           /* WO_ROUTE_*: route of every tour (0 = S-shape);
                                   the same for all instances of one load */
+    int32_t batching;          /* WO_BATCH_*: how orders form tours (0 = next fit);
+                                  the same for all instances of one load */
 } wo_instance_desc;
 
 /* Route of a tour (section 5, Subproblem 2 leaves the routing method open;
@@ -123,6 +125,19 @@ typedef struct {
  * in 32-bit integers: 4 * spacing * (n_aisles + 2) + 4 * L * (n_aisles + 1)
  * must stay below 2^30 dm, else the load fails with WO_E_RANGE. */
 enum { WO_ROUTE_SSHAPE = 0, WO_ROUTE_RETURN = 1, WO_ROUTE_LARGEST_GAP = 2, WO_ROUTE_OPTIMAL = 3 };
+
+/* Batching of orders into tours (the paper cuts the order sequence greedily
+ * into capacity-bounded tours, section 5, Subproblem 2 and section 6; these
+ * are the two greedy rules of the order-batching literature):
+ *   WO_BATCH_NEXT_FIT   an order joins the open tour if the items fit, else
+ *                       it opens a new tour (tours are runs of the sequence);
+ *   WO_BATCH_FIRST_FIT  an order joins the earliest-opened tour with room for
+ *                       it, else it opens a new tour.
+ * An order larger than the capacity is a tour of its own under both.  First
+ * fit is built for the S-shape route and instances of at most 4,096 orders;
+ * other combinations fail at load with WO_E_UNSUPPORTED, and the launch
+ * configuration (wo_set_eval_config, wo_autotune_eval) does not apply to it. */
+enum { WO_BATCH_NEXT_FIT = 0, WO_BATCH_FIRST_FIT = 1 };
 #define WO_MAX_PICK_SLOTS 32
 
 typedef struct wo_wh wo_wh;

@@ -948,6 +948,169 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
 // Reset of the work-queue ticket (a kernel, so that it can sit in a graph).
 __global__ void reset_ticket_kernel(uint32_t *ctr) { *ctr = 0u; }
 
+static __device__ __forceinline__ int32_t wave_max_i32(int32_t v)
+{
+#pragma unroll
+    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+// Plans under first-fit order batching (the other greedy batching rule of the
+// order-picking literature beside next fit; section 5, Subproblem 2 leaves
+// the batching of orders into tours open) and the S-shape route.  One
+// wavefront evaluates one plan:
+//   1. zone starts: each category's start is the total size of the
+//      categories in lower zones (one pass over the categories per lane);
+//   2. first fit, order by order in sequence: the free room of every tour
+//      sits in LDS, and lane c keeps the largest room among tours
+//      64c .. 64c + 63, so the first tour with room for an order is one ballot
+//      over the lanes, one read of that group of 64 tours and a second ballot;
+//   3. tiles of FF_TILE tours: every line record whose order belongs to the
+//      tile sets its aisle bit and raises its tour's farthest location in the
+//      tour's LDS row; then one lane per tour takes the S-shape closed form;
+//   4. the wave's sum, saturated to int32, and the rate over the window.
+__global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
+{
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x;
+    for (int64_t p = blockIdx.x; p < A.n_plans; p += gridDim.x) {
+        const int ii = instance_of(A, p);
+        const InstDev &I = A.inst[ii];
+        const int n = I.n_orders;
+        const int C = I.n_cat;
+        const int32_t Q = I.capacity;
+        const int64_t row = p - (A.n_inst > 1 ? A.plan_begin[ii] : 0);
+        const uint16_t *seq = A.seq + A.seq_base[ii] + row * (int64_t)n;
+        const uint8_t *cnt = A.cnt + I.cnt_off;
+        // the line records name their order by its entry in the next-fit
+        // kernel's tour table
+        const uint32_t nf_tour = eval_layout(n, I.n_units, (uint32_t)I.row_b, I.t_cap, I.chase_log2,
+                                             I.chase_lanes).tour;
+        uint32_t *zs = (uint32_t *)smem;
+        uint16_t *tour_of = (uint16_t *)(smem + ff_tour_off());
+        uint8_t *room = smem + ff_room_off(n);
+        uint32_t *rows = (uint32_t *)(smem + ff_rows_off(n));
+        const uint32_t RW = row_bytes(I.words) / 4u;
+        int bad = 0;
+
+        // ---- 1. zone starts ---------------------------------------------
+        {
+            const uint32_t zc = lane < C ? (uint32_t)A.zone_of[p * 64 + lane] : 0xFFu;
+            const uint32_t sz = lane < C ? (uint32_t)I.cat_size[lane] : 0u;
+            uint32_t start = 0;
+            for (int c = 0; c < C; c++) {
+                const uint32_t zo = (uint32_t)__shfl((int)zc, c, 64);
+                start += zo < zc ? (uint32_t)I.cat_size[c] : 0u;
+            }
+            // a malformed row cannot move a category off the warehouse
+            start = min(start, (uint32_t)I.n_skus - sz);
+            zs[lane] = (start << I.shift) - ((uint32_t)(4 * lane) << 24);
+            if (A.validate) {
+                uint64_t m = (lane < C && zc < 64u) ? (1ull << zc) : 0ull;
+#pragma unroll
+                for (int d = 32; d >= 1; d >>= 1) m |= __shfl_xor(m, d, 64);
+                const uint64_t want = (C == 64) ? ~0ull : ((1ull << C) - 1ull);
+                if (m != want) bad = 1;
+            }
+        }
+        for (int o = lane; o <= n; o += 64) tour_of[o] = 0xFFFFu;   // no tour yet; entry n: padding
+        if (A.validate) {
+            // every order exactly once: mark them in the room table, which
+            // first fit then overwrites
+            for (int o = lane; o < n; o += 64) room[o] = 0;
+            __syncthreads();
+            for (int i = lane; i < n; i += 64) {
+                const uint32_t o = seq[i];
+                if (o < (uint32_t)n) room[o] = 1; else bad = 1;
+            }
+            __syncthreads();
+            for (int o = lane; o < n; o += 64) bad |= room[o] != 1;
+        }
+        __syncthreads();
+
+        // ---- 2. first fit -------------------------------------------------
+        int T = 0;                         // tours opened (uniform)
+        int32_t gmax = -1;                 // lane c: largest room in tours 64c..64c+63 (-1: none open)
+        for (int i0 = 0; i0 < n; i0 += 64) {
+            const int i = i0 + lane;
+            const uint32_t o_l = i < n ? min((uint32_t)seq[i], (uint32_t)n) : (uint32_t)n;
+            const uint32_t s_l = cnt[o_l];             // min(size, Q + 1)
+            const int m = min(64, n - i0);
+            for (int j = 0; j < m; j++) {
+                const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)o_l, j);
+                const int32_t sz = __builtin_amdgcn_readlane((int)s_l, j);
+                if (o >= (uint32_t)n) continue;        // malformed row: the order is left out
+                int t = T;
+                if (sz <= Q) {
+                    const uint64_t g = __ballot(gmax >= sz);
+                    if (g) {
+                        const int c = __builtin_ctzll(g);
+                        const int u = 64 * c + lane;
+                        const int32_t r = u < T ? (int32_t)room[u] : -1;
+                        const uint64_t f = __ballot(r >= sz);
+                        if (f) {                       // always, as gmax is exact
+                            const int k = __builtin_ctzll(f);
+                            t = 64 * c + k;
+                            const int32_t r2 = lane == k ? r - sz : r;
+                            if (lane == k) room[u] = (uint8_t)r2;
+                            const int32_t mx = wave_max_i32(r2);
+                            if (lane == c) gmax = mx;
+                        }
+                    }
+                }
+                if (t == T) {                          // no open tour has room
+                    const int32_t r0 = sz <= Q ? Q - sz : 0;   // a larger order rides alone
+                    if (lane == 0) room[T] = (uint8_t)r0;
+                    if (lane == (T >> 6)) gmax = max(gmax, r0);
+                    T++;
+                }
+                // one wavefront: its LDS accesses take effect in program order
+                if (lane == 0) tour_of[o] = (uint16_t)t;
+            }
+        }
+
+        // ---- 3. tiles of tours: aisle sets, farthest locations, S-shape ---
+        int64_t acc = 0;
+        const uint2 *lines = A.lines + I.line_off;
+        for (int t0 = 0; t0 < T; t0 += FF_TILE) {
+            for (uint32_t k = lane; k < FF_TILE * RW; k += 64) rows[k] = 0u;
+            __syncthreads();
+            for (int r = lane; r < I.n_lines_pad; r += 64) {
+                const uint2 rec = lines[r];
+                const uint32_t o = ((rec.y & 0x7FFFFFFFu) - nf_tour) >> 1;   // padding: order n
+                if (o >= (uint32_t)n) continue;
+                const uint32_t t = (uint32_t)tour_of[o] - (uint32_t)t0;
+                if (t >= (uint32_t)FF_TILE) continue;
+                const uint32_t ls = rec.x + zs[rec.x >> 26];
+                const uint32_t a = mulhi24(ls, I.magic);
+                atomicOr(&rows[t * RW + 1u + (a >> 5)], 1u << (a & 31u));
+                atomicMax(&rows[t * RW], ls);
+            }
+            __syncthreads();
+            if (t0 + lane < T) {
+                const uint32_t *rw = rows + (uint32_t)lane * RW;
+                const uint32_t ls = rw[0];
+                int k = 0;
+                for (int w = 0; w < I.words; w++) k += __popc(rw[1 + w]);
+                const uint32_t a = mulhi24(ls, I.magic);
+                const int64_t y = (int64_t)((ls - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
+                acc += 2ll * I.spacing * a + ((k & 1) ? (int64_t)(k - 1) * I.L + 2 * y : (int64_t)k * I.L);
+            }
+            __syncthreads();
+        }
+
+        // ---- 4. sum and rate -----------------------------------------------
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
+        if (A.validate && bad) atomicOr(A.err, 1);
+        if (lane == 0) {
+            A.dist[p] = acc > 2147483647ll ? 2147483647 : (int32_t)acc;
+            if (A.thr) A.thr[p] = window_throughput(acc, I);
+        }
+        __syncthreads();
+    }
+}
+
 template <int BLOCK, int ROUTE>
 static hipError_t launch_eval_t(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
 {
@@ -989,6 +1152,32 @@ static int max_blocks_r(int block, uint32_t lds_bytes)
     case 512: return max_blocks_t<512, ROUTE>(lds_bytes);
     }
     return 1;
+}
+
+hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
+{
+    static uint32_t attr_bytes = 0;
+    if (lds_bytes > attr_bytes) {
+        hipError_t e = hipFuncSetAttribute((const void *)eval_ff_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           (int)lds_bytes);
+        if (e != hipSuccess) {
+            (void)hipGetLastError();
+            return e;
+        }
+        attr_bytes = lds_bytes;
+    }
+    hipLaunchKernelGGL(eval_ff_kernel, dim3(grid), dim3(64), lds_bytes, s, a);
+    return hipGetLastError();
+}
+
+int eval_ff_max_blocks_per_cu(uint32_t lds_bytes)
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, eval_ff_kernel, 64, lds_bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1;
+    }
+    return n > 0 ? n : 1;
 }
 
 int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes)

@@ -100,6 +100,9 @@ struct wo_wh {
     int queue = 0;                      // 1: ticket queue over the cost-ordered work list
     int main_mode = 0;                  // 0: one line per lane in the line pass, 1: one order per lane
     int route = WO_ROUTE_SSHAPE;        // the route of every instance of the handle
+    int batching = WO_BATCH_NEXT_FIT;   // the order batching of every instance of the handle
+    std::vector<uint32_t> ff_lds;       // first fit: LDS of one plan of each instance
+    uint32_t ff_lds_max = 0;
     int small_orders = 1024;            // instances up to this size get a launch of 64-thread workgroups
     // Work lists by launch class (0: the configured workgroups, 1: 64-thread
     // workgroups for instances of at most small_orders orders, 2: 128-thread
@@ -168,6 +171,13 @@ static wo_status check_desc(const wo_instance_desc &d, int idx)
     if (d.capacity < 1) return fail(WO_E_INVAL, "instance %d: capacity must be >= 1", idx);
     if (d.routing < WO_ROUTE_SSHAPE || d.routing > WO_ROUTE_OPTIMAL)
         return fail(WO_E_INVAL, "instance %d: unknown routing %d", idx, d.routing);
+    if (d.batching < WO_BATCH_NEXT_FIT || d.batching > WO_BATCH_FIRST_FIT)
+        return fail(WO_E_INVAL, "instance %d: unknown batching %d", idx, d.batching);
+    if (d.batching == WO_BATCH_FIRST_FIT && d.routing != WO_ROUTE_SSHAPE)
+        return fail(WO_E_UNSUPPORTED, "instance %d: first-fit batching is built for the S-shape route only", idx);
+    if (d.batching == WO_BATCH_FIRST_FIT && d.n_orders > FF_MAX_ORDERS)
+        return fail(WO_E_UNSUPPORTED, "instance %d: first-fit batching takes at most %d orders (got %d)", idx,
+                    FF_MAX_ORDERS, d.n_orders);
     if (d.capacity > WO_MAX_CAPACITY)
         return fail(WO_E_RANGE, "instance %d: capacity %d > %d", idx, d.capacity, WO_MAX_CAPACITY);
     if (d.n_categories < 1) return fail(WO_E_INVAL, "instance %d: need >= 1 category", idx);
@@ -230,6 +240,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         if (s) return s;
         if (descs[i].routing != descs[0].routing)
             return fail(WO_E_UNSUPPORTED, "instance %d: routing differs from instance 0's (one route per load)", i);
+        if (descs[i].batching != descs[0].batching)
+            return fail(WO_E_UNSUPPORTED, "instance %d: batching differs from instance 0's (one rule per load)", i);
     }
 
     // allocation fault injection for tests (WO_FAULT_INJECT=alloc); it fires
@@ -245,8 +257,10 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     wh->lds_max = (uint32_t)std::min(lds_max, 160 * 1024) - 256;   // room for the kernels' static LDS
     wh->n_inst = n_instances;
     wh->route = descs[0].routing;
+    wh->batching = descs[0].batching;
     wh->inst.resize(n_instances);
     wh->lds.resize(n_instances);
+    wh->ff_lds.resize(n_instances);
 
     // pooled host arrays
     std::vector<uint2> lines;
@@ -443,6 +457,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         }
         I.n_lines_pad = (int32_t)(lines.size() - (size_t)I.line_off);
         wh->lds[i] = ly.total;
+        wh->ff_lds[i] = ff_lds_bytes(d.n_orders, I.words);
     }
 
     size_t b_lines = lines.size() * sizeof(uint2), b_cnt = cnt.size();
@@ -471,6 +486,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     HIP_TRY(hipMemsetAsync(wh->d_err, 0, 64, s));
     HIP_TRY(hipStreamSynchronize(s));
     wh->lds_max = *std::max_element(wh->lds.begin(), wh->lds.end());
+    wh->ff_lds_max = *std::max_element(wh->ff_lds.begin(), wh->ff_lds.end());
     guard.release();
     *out = wh;
     return WO_OK;
@@ -509,6 +525,11 @@ static int launch_grid(const wo_wh *wh, int block, int per_cu_cfg, uint32_t lds,
     const int fit = eval_max_blocks_per_cu(block, wh->route, lds);
     const int per_cu = per_cu_cfg > 0 ? std::min(per_cu_cfg, fit) : fit;
     return (int)std::min<int64_t>(n_plans, (int64_t)wh->cu_count * per_cu);
+}
+
+static int ff_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
+{
+    return (int)std::min<int64_t>(n_plans, (int64_t)wh->cu_count * eval_ff_max_blocks_per_cu(lds));
 }
 
 static int launch_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
@@ -644,7 +665,11 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.work = nullptr;
     bool any_small = false;
     for (int32_t i = 0; i < wh->n_inst; i++) any_small |= class_of(wh, i) != 0 && map[i + 1] > map[i];
-    if (!any_small && !wh->queue) {
+    if (wh->batching == WO_BATCH_FIRST_FIT) {
+        // first fit has a kernel of its own, one wavefront per plan; the
+        // launch configuration above applies to next fit only
+        HIP_TRY(launch_eval_ff(a, wh->ff_lds_max, ff_grid(wh, wh->ff_lds_max, n_plans), s));
+    } else if (!any_small && !wh->queue) {
         // one launch, grid stride over the plan rows
         HIP_TRY(launch_eval(a, wh->lds_max, launch_grid(wh, wh->lds_max, n_plans), wh->block, wh->route, s));
     } else {
@@ -704,6 +729,11 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.queue = 0;
     a.queue_ctr = nullptr;
     a.work = nullptr;
+    if (wh->batching == WO_BATCH_FIRST_FIT) {
+        const uint32_t lds = wh->ff_lds[inst];
+        HIP_TRY(launch_eval_ff(a, lds, ff_grid(wh, lds, n_plans), s));
+        return WO_OK;
+    }
     const uint32_t lds = wh->lds[inst];
     HIP_TRY(launch_eval(a, lds, launch_grid(wh, lds, n_plans), wh->block, wh->route, s));
     return WO_OK;

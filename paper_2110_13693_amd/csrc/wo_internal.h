@@ -127,8 +127,23 @@ constexpr int MAX_PICK_SLOTS = 32;
 __host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * ((uint32_t)(words + 1) | 1u); }
 __host__ __device__ inline uint32_t pick_row_bytes(int32_t slots) { return 4u * ((uint32_t)(slots + 1) | 1u); }
 
+// First-fit batching runs in a kernel of its own, one wavefront per plan:
+// the zone starts (64 words), the tour of every order (u16, plus the entry of
+// the padding records' order), the free room of every tour (u8), then one
+// tile of FF_TILE S-shape rows.  Tours never outnumber orders, and at most
+// FF_MAX_ORDERS orders keep the room summary in one register per lane.
+constexpr int FF_TILE = 64;
+constexpr int FF_MAX_ORDERS = 4096;
+__host__ __device__ inline uint32_t ff_tour_off() { return 256u; }
+__host__ __device__ inline uint32_t ff_room_off(int32_t n_orders) { return 256u + align16(2u * ((uint32_t)n_orders + 1u)); }
+__host__ __device__ inline uint32_t ff_rows_off(int32_t n_orders) { return ff_room_off(n_orders) + align16((uint32_t)n_orders); }
+
 // bytes of the cnt table (order sizes, then zeros for the dummy and sink entries)
 __host__ __device__ inline uint32_t cnt_bytes(int32_t n_orders) { return align16((uint32_t)n_orders + 2u); }
+__host__ __device__ inline uint32_t ff_lds_bytes(int32_t n_orders, int32_t words)
+{
+    return ff_rows_off(n_orders) + (uint32_t)FF_TILE * row_bytes(words);
+}
 
 __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_units, uint32_t rb,
                                                   int32_t t_cap, int32_t chase_log2, int32_t chase_lanes)
@@ -160,6 +175,9 @@ __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_un
 hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, int route, hipStream_t s);
 // workgroups of the evaluation kernel that fit one CU (registers and LDS)
 int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes);
+// First-fit batching with the S-shape route: one 64-thread workgroup per plan.
+hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s);
+int eval_ff_max_blocks_per_cu(uint32_t lds_bytes);
 
 // library-internal helpers over a loaded handle
 wo_status eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint8_t *d_zone_of,

@@ -63,11 +63,12 @@ class wo_instance_desc(ctypes.Structure):
         ("n_orders", ctypes.c_int32), ("order_offsets", ctypes.c_void_p),
         ("order_skus", ctypes.c_void_p),
         ("walk_dm_per_s", ctypes.c_double), ("seconds_per_item", ctypes.c_double),
-        ("window_s", ctypes.c_double), ("routing", ctypes.c_int32),
+        ("window_s", ctypes.c_double), ("routing", ctypes.c_int32), ("batching", ctypes.c_int32),
     ]
 
 
 WO_ROUTE_SSHAPE, WO_ROUTE_RETURN, WO_ROUTE_LARGEST_GAP, WO_ROUTE_OPTIMAL = 0, 1, 2, 3
+WO_BATCH_NEXT_FIT, WO_BATCH_FIRST_FIT = 0, 1
 
 _lib = None
 
@@ -186,7 +187,8 @@ def make_desc(inst, keep: list) -> wo_instance_desc:
                             cat.size, cat.ctypes.data, off.size - 1, off.ctypes.data,
                             sku.ctypes.data, float(inst.walk_dm_per_s),
                             float(inst.seconds_per_item), float(inst.window_s),
-                            int(getattr(inst, "routing", WO_ROUTE_SSHAPE)))
+                            int(getattr(inst, "routing", WO_ROUTE_SSHAPE)),
+                            int(getattr(inst, "batching", WO_BATCH_NEXT_FIT)))
 
 
 def wo_load_warehouse(instances: Sequence, stream=None) -> Warehouse:

@@ -79,6 +79,8 @@ def _mod(inst, **kw):
     ("n_aisles", 1, 2),             # 600 SKUs no longer fit 60 locations
     ("routing", 4, 1),              # unknown route
     ("routing", -1, 1),
+    ("batching", 2, 1),             # unknown batching rule
+    ("batching", -1, 1),
 ])
 def test_load_rejects_descriptor(wo, tiny, field, value, status):
     st, out = _load_status(wo, _mod(tiny, **{field: value}))
@@ -162,6 +164,33 @@ def test_load_rejects_optimal_route_beyond_32_bits(wo, tiny):
     st, out = _load_status(wo, _mod(tiny, routing=3, pitch_dm=1000000))
     assert st == wo.WO_E_RANGE, wo.wo_last_error()
     assert "optimal" in wo.wo_last_error()
+    assert out.value is None
+
+
+@pytest.mark.parametrize("routing", [1, 2, 3])
+def test_load_rejects_first_fit_with_other_routes(wo, tiny, routing):
+    st, out = _load_status(wo, _mod(tiny, batching=1, routing=routing))
+    assert st == wo.WO_E_UNSUPPORTED, wo.wo_last_error()
+    assert "first-fit" in wo.wo_last_error()
+    assert out.value is None
+
+
+def test_load_rejects_first_fit_beyond_4096_orders(wo):
+    inst = synth.make_instance(n_aisles=40, slots_per_side=50, pitch_dm=10, spacing_dm=30, capacity=20,
+                               n_categories=8, n_skus=3000, category_mode="dirichlet", n_orders=4097,
+                               lines_lambda=1.0, zipf_s=1.0, seed=3)
+    st, out = _load_status(wo, _mod(inst, batching=1))
+    assert st == wo.WO_E_UNSUPPORTED, wo.wo_last_error()
+    assert "4096" in wo.wo_last_error()
+    assert out.value is None
+
+
+def test_load_rejects_mixed_batching(wo, tiny):
+    keep = []
+    arr = (wo.wo_instance_desc * 2)(wo.make_desc(tiny, keep), wo.make_desc(_mod(tiny, batching=1), keep))
+    out = ctypes.c_void_p(0)
+    assert wo.lib().wo_load_warehouse(arr, 2, None, ctypes.byref(out)) == wo.WO_E_UNSUPPORTED
+    assert "batching" in wo.wo_last_error()
     assert out.value is None
 
 

@@ -1,0 +1,146 @@
+"""GPU parity of first-fit order batching against the CPU oracle (through the
+C ABI).  Distances must match bit-exactly; the throughput to 1e-6 relative,
+as for next fit."""
+import dataclasses
+
+import numpy as np
+import pytest
+
+import oracle
+import synth
+from tests.gpu_util import gpu_eval
+from tests.test_gpu_eval import THR_RTOL, _random_instance, _structured_sequences, _wo
+
+pytestmark = pytest.mark.gpu
+
+
+def _ff(inst):
+    return dataclasses.replace(inst, batching=1)
+
+
+def _compare(inst, Z, S):
+    wo = _wo()
+    wh = wo.wo_load_warehouse([inst])
+    d_ref, t_ref = oracle.eval_plans(inst, Z, S, n_threads=8)
+    d_gpu, t_gpu = gpu_eval(wh, Z, S)
+    wh.free()
+    bad = np.flatnonzero(d_gpu != d_ref)
+    assert bad.size == 0, "plans %s: gpu %s oracle %s" % (bad[:5], d_gpu[bad[:5]], d_ref[bad[:5]])
+    np.testing.assert_allclose(t_gpu, t_ref, rtol=THR_RTOL, atol=0)
+    return d_gpu
+
+
+def test_tiny_all_plans():
+    inst, Z, S = synth.workload("tiny")
+    print("tiny first fit", flush=True)
+    d_ff = _compare(_ff(inst), Z, S)
+    d_nf, _ = oracle.eval_plans(inst, Z, S)
+    assert (d_ff != d_nf).any()          # the rule changes the tours
+
+
+def test_paper_scale_sample():
+    inst, Z, S = synth.workload("paper", n_plans=64)
+    print("paper first fit", flush=True)
+    _compare(_ff(inst), Z, S)
+
+
+def test_worked_plan_on_gpu():
+    # A = {61, 62}, B = {598, 599}, C = {0}, capacity 3: first fit [A, C], [B]
+    from tests.whelpers import identity_zones, tiny_geometry
+    inst = _ff(tiny_geometry([[61, 62], [598, 599], [0]], capacity=3))
+    Z = identity_zones(12)[None, :]
+    S = np.arange(3, dtype=np.uint16)[None, :]
+    wo = _wo()
+    wh = wo.wo_load_warehouse([inst])
+    d, _ = gpu_eval(wh, Z, S)
+    wh.free()
+    assert d.tolist() == [660 + 1130]
+
+
+FF_CASES = [
+    # (aisles, slots, orders, capacity, categories, lambda)
+    (1, 1, 1, 1, 1, 0.0),          # one location, one order
+    (1, 5, 7, 1, 3, 2.0),          # capacity 1: every order a tour, most oversize
+    (3, 4, 50, 2, 5, 3.0),         # many oversize orders
+    (33, 7, 300, 32, 64, 1.5),     # capacity 32, two aisle words
+    (64, 3, 129, 5, 17, 0.5),      # a multiple of 32 aisles
+    (400, 250, 4096, 1, 64, 0.0),  # 4,096 single-item orders at capacity 1: 4,096 tours, 64 tiles
+    (400, 250, 4096, 30, 64, 1.5), # the largest instance first fit takes
+    (100, 250, 4000, 3, 8, 1.5),   # oversize orders among small ones
+    (10, 30, 1, 20, 12, 1.5),      # a single order
+    (400, 250, 3000, 7, 64, 4.0),  # large orders, capacity 7
+]
+
+
+@pytest.mark.parametrize("case", FF_CASES, ids=lambda c: "N%d_S%d_n%d_Q%d_C%d" % c[:5])
+def test_edge_cases(case):
+    rng = np.random.default_rng(abs(hash(case)) % (1 << 31))
+    inst = _ff(_random_instance(rng, *case))
+    Z, S = synth.make_plans(inst, 29, seed=int(rng.integers(1 << 30)))
+    print("case", case, flush=True)
+    _compare(inst, Z, S)
+
+
+def test_structured_sequences():
+    # sequences sorted by order size, both ways, and blocked: first fit packs
+    # the small orders of a run into the room the large ones left
+    rng = np.random.default_rng(41)
+    inst = _ff(_random_instance(rng, 400, 250, 4000, 30, 64, lam=1.5))
+    S = _structured_sequences(inst, rng)
+    Z = synth.generators.random_zone_perms(rng, S.shape[0], inst.n_categories)
+    _compare(inst, Z, S)
+
+
+def test_batched_instances_match_single():
+    import torch
+    wo = _wo()
+    rng = np.random.default_rng(43)
+    insts = [_ff(_random_instance(rng, a, 250, o, 30, 64)) for a, o in [(8, 50), (400, 4000), (37, 700), (120, 61)]]
+    per = [5, 3, 8, 2]
+    Zs, Ss, offs = [], [], [0]
+    for inst, k in zip(insts, per):
+        Z, S = synth.make_plans(inst, k, seed=int(rng.integers(1 << 30)))
+        Zs.append(Z)
+        Ss.append(S.reshape(-1))
+        offs.append(offs[-1] + k)
+    wh = wo.wo_load_warehouse(insts)
+    d, t = gpu_eval(wh, np.concatenate(Zs), np.concatenate(Ss), plan_offsets=offs)
+    wh.free()
+    for i, inst in enumerate(insts):
+        dr, tr = oracle.eval_plans(inst, Zs[i], Ss[i].reshape(per[i], -1))
+        assert np.array_equal(d[offs[i]:offs[i + 1]], dr)
+        np.testing.assert_allclose(t[offs[i]:offs[i + 1]], tr, rtol=THR_RTOL)
+    del torch
+
+
+def test_validation_mode(monkeypatch):
+    wo = _wo()
+    inst, Z, S = synth.workload("tiny", n_plans=8)
+    wh = wo.wo_load_warehouse([_ff(inst)])
+    monkeypatch.setenv("WO_VALIDATE", "1")
+    gpu_eval(wh, Z, S)                  # valid plans pass
+    S2 = S.copy()
+    S2[3, 5] = S2[3, 6]                 # duplicate order id
+    with pytest.raises(wo.WoError) as ei:
+        gpu_eval(wh, Z, S2)
+    assert ei.value.status == wo.WO_E_INVAL
+    Z2 = Z.copy()
+    Z2[1, 0] = Z2[1, 1]                 # duplicate zone
+    with pytest.raises(wo.WoError):
+        gpu_eval(wh, Z2, S)
+    monkeypatch.delenv("WO_VALIDATE")
+    S3 = S.copy()
+    S3[0, 0] = 60000                    # out of range id without validation: defined, in bounds
+    d, _ = gpu_eval(wh, Z, S3)
+    assert d.shape == (8,)
+    wh.free()
+
+
+def test_repeat_calls_deterministic():
+    wo = _wo()
+    inst, Z, S = synth.workload("paper", n_plans=256)
+    wh = wo.wo_load_warehouse([_ff(inst)])
+    d1, t1 = gpu_eval(wh, Z, S)
+    d2, t2 = gpu_eval(wh, Z, S)
+    wh.free()
+    assert np.array_equal(d1, d2) and np.array_equal(t1, t2)
