@@ -948,11 +948,17 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
 // Reset of the work-queue ticket (a kernel, so that it can sit in a graph).
 __global__ void reset_ticket_kernel(uint32_t *ctr) { *ctr = 0u; }
 
+// Largest value over the wavefront (DPP row shifts and broadcasts, as in
+// wave_incl_scan; lanes without a source keep their own value).
 static __device__ __forceinline__ int32_t wave_max_i32(int32_t v)
 {
-#pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) v = max(v, __shfl_xor(v, d, 64));
-    return v;
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false));   // row_shr:1
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xF, 0xF, false));   // row_shr:2
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false));   // row_shr:4
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false));   // row_shr:8
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));   // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
 }
 
 // Plans under first-fit order batching (the other greedy batching rule of the
@@ -961,10 +967,12 @@ static __device__ __forceinline__ int32_t wave_max_i32(int32_t v)
 // wavefront evaluates one plan:
 //   1. zone starts: each category's start is the total size of the
 //      categories in lower zones (one pass over the categories per lane);
-//   2. first fit, order by order in sequence: the free room of every tour
-//      sits in LDS, and lane c keeps the largest room among tours
-//      64c .. 64c + 63, so the first tour with room for an order is one ballot
-//      over the lanes, one read of that group of 64 tours and a second ballot;
+//   2. first fit, order by order in sequence: lane l keeps the free room of
+//      tours l, 64 + l, 128 + l, ... in registers (a byte each), and lane c
+//      the largest room among tours 64c .. 64c + 63, so the first tour with
+//      room for an order is one ballot over the groups, one register of that
+//      group and a second ballot (every order has an item, so an empty room
+//      never fits);
 //   3. tiles of FF_TILE tours: every line record whose order belongs to the
 //      tile sets its aisle bit and raises its tour's farthest location in the
 //      tour's LDS row; then one lane per tour takes the S-shape closed form;
@@ -988,7 +996,6 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
                                              I.chase_lanes).tour;
         uint32_t *zs = (uint32_t *)smem;
         uint16_t *tour_of = (uint16_t *)(smem + ff_tour_off());
-        uint8_t *room = smem + ff_room_off(n);
         uint32_t *rows = (uint32_t *)(smem + ff_rows_off(n));
         const uint32_t RW = row_bytes(I.words) / 4u;
         int bad = 0;
@@ -1015,22 +1022,27 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
         }
         for (int o = lane; o <= n; o += 64) tour_of[o] = 0xFFFFu;   // no tour yet; entry n: padding
         if (A.validate) {
-            // every order exactly once: mark them in the room table, which
-            // first fit then overwrites
-            for (int o = lane; o < n; o += 64) room[o] = 0;
+            // every order exactly once: mark them in the tour table, which
+            // is then reset
             __syncthreads();
             for (int i = lane; i < n; i += 64) {
                 const uint32_t o = seq[i];
-                if (o < (uint32_t)n) room[o] = 1; else bad = 1;
+                if (o < (uint32_t)n) tour_of[o] = 0; else bad = 1;
             }
             __syncthreads();
-            for (int o = lane; o < n; o += 64) bad |= room[o] != 1;
+            for (int o = lane; o < n; o += 64) {
+                bad |= tour_of[o] != 0;
+                tour_of[o] = 0xFFFFu;
+            }
         }
         __syncthreads();
 
         // ---- 2. first fit -------------------------------------------------
         int T = 0;                         // tours opened (uniform)
-        int32_t gmax = -1;                 // lane c: largest room in tours 64c..64c+63 (-1: none open)
+        int32_t gmax = 0;                  // lane c: largest room in tours 64c..64c+63
+        uint32_t R[FF_MAX_ORDERS / 256];   // byte b of R[q]: room of tour 64 (4q + b) + lane
+#pragma unroll
+        for (int q = 0; q < FF_MAX_ORDERS / 256; q++) R[q] = 0u;
         for (int i0 = 0; i0 < n; i0 += 64) {
             const int i = i0 + lane;
             const uint32_t o_l = i < n ? min((uint32_t)seq[i], (uint32_t)n) : (uint32_t)n;
@@ -1044,15 +1056,16 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
                 if (sz <= Q) {
                     const uint64_t g = __ballot(gmax >= sz);
                     if (g) {
-                        const int c = __builtin_ctzll(g);
-                        const int u = 64 * c + lane;
-                        const int32_t r = u < T ? (int32_t)room[u] : -1;
+                        const int c = __builtin_ctzll(g);          // uniform
+                        const uint32_t sh = 8u * (uint32_t)(c & 3);
+                        const uint32_t w = R[c >> 2];
+                        const int32_t r = (int32_t)((w >> sh) & 0xFFu);
                         const uint64_t f = __ballot(r >= sz);
                         if (f) {                       // always, as gmax is exact
                             const int k = __builtin_ctzll(f);
                             t = 64 * c + k;
                             const int32_t r2 = lane == k ? r - sz : r;
-                            if (lane == k) room[u] = (uint8_t)r2;
+                            R[c >> 2] = (w & ~(0xFFu << sh)) | ((uint32_t)r2 << sh);
                             const int32_t mx = wave_max_i32(r2);
                             if (lane == c) gmax = mx;
                         }
@@ -1060,8 +1073,10 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
                 }
                 if (t == T) {                          // no open tour has room
                     const int32_t r0 = sz <= Q ? Q - sz : 0;   // a larger order rides alone
-                    if (lane == 0) room[T] = (uint8_t)r0;
-                    if (lane == (T >> 6)) gmax = max(gmax, r0);
+                    const int c = T >> 6;
+                    const uint32_t sh = 8u * (uint32_t)(c & 3);
+                    if (lane == (T & 63)) R[c >> 2] |= (uint32_t)r0 << sh;
+                    if (lane == c) gmax = max(gmax, r0);
                     T++;
                 }
                 // one wavefront: its LDS accesses take effect in program order

@@ -127,16 +127,15 @@ constexpr int MAX_PICK_SLOTS = 32;
 __host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * ((uint32_t)(words + 1) | 1u); }
 __host__ __device__ inline uint32_t pick_row_bytes(int32_t slots) { return 4u * ((uint32_t)(slots + 1) | 1u); }
 
-// First-fit batching runs in a kernel of its own, one wavefront per plan:
-// the zone starts (64 words), the tour of every order (u16, plus the entry of
-// the padding records' order), the free room of every tour (u8), then one
-// tile of FF_TILE S-shape rows.  Tours never outnumber orders, and at most
-// FF_MAX_ORDERS orders keep the room summary in one register per lane.
+// First-fit batching runs in a kernel of its own, one wavefront per plan.
+// LDS: the zone starts (64 words), the tour of every order (u16, plus the
+// entry of the padding records' order), then one tile of FF_TILE S-shape
+// rows.  Tours never outnumber orders; at most FF_MAX_ORDERS orders keep every
+// tour's free room in 16 registers per lane and the group maxima in one.
 constexpr int FF_TILE = 64;
 constexpr int FF_MAX_ORDERS = 4096;
 __host__ __device__ inline uint32_t ff_tour_off() { return 256u; }
-__host__ __device__ inline uint32_t ff_room_off(int32_t n_orders) { return 256u + align16(2u * ((uint32_t)n_orders + 1u)); }
-__host__ __device__ inline uint32_t ff_rows_off(int32_t n_orders) { return ff_room_off(n_orders) + align16((uint32_t)n_orders); }
+__host__ __device__ inline uint32_t ff_rows_off(int32_t n_orders) { return 256u + align16(2u * ((uint32_t)n_orders + 1u)); }
 
 // bytes of the cnt table (order sizes, then zeros for the dummy and sink entries)
 __host__ __device__ inline uint32_t cnt_bytes(int32_t n_orders) { return align16((uint32_t)n_orders + 2u); }
