@@ -969,13 +969,15 @@ static __device__ __forceinline__ int32_t wave_max_i32(int32_t v)
 //      categories in lower zones (one pass over the categories per lane);
 //   2. first fit, order by order in sequence: lane l keeps the free room of
 //      tours l, 64 + l, 128 + l, ... in registers (a byte each), and lane c
-//      the largest room among tours 64c .. 64c + 63, so the first tour with
-//      room for an order is one ballot over the groups, one register of that
-//      group and a second ballot (every order has an item, so an empty room
-//      never fits);
-//   3. tiles of FF_TILE tours: every line record whose order belongs to the
-//      tile sets its aisle bit and raises its tour's farthest location in the
-//      tour's LDS row; then one lane per tour takes the S-shape closed form;
+//      an upper bound of the largest room among tours 64c .. 64c + 63.  The
+//      groups whose bound admits the order are tried in turn: one register
+//      of the group and a ballot find its first tour with room; a group
+//      without one gets its exact largest room as its new bound.  Every order
+//      has an item, so an empty room never fits;
+//   3. tiles of FF_TILE tours: every line of an order in the tile sets its
+//      aisle bit in the tour's LDS row, and the order raises the tour's
+//      farthest location; then one lane per tour takes the S-shape closed
+//      form;
 //   4. the wave's sum, saturated to int32, and the rate over the window.
 __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
 {
@@ -990,13 +992,9 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
         const int64_t row = p - (A.n_inst > 1 ? A.plan_begin[ii] : 0);
         const uint16_t *seq = A.seq + A.seq_base[ii] + row * (int64_t)n;
         const uint8_t *cnt = A.cnt + I.cnt_off;
-        // the line records name their order by its entry in the next-fit
-        // kernel's tour table
-        const uint32_t nf_tour = eval_layout(n, I.n_units, (uint32_t)I.row_b, I.t_cap, I.chase_log2,
-                                             I.chase_lanes).tour;
         uint32_t *zs = (uint32_t *)smem;
-        uint16_t *tour_of = (uint16_t *)(smem + ff_tour_off());
-        uint32_t *rows = (uint32_t *)(smem + ff_rows_off(n));
+        uint16_t *tour_of = A.ff_tour + (int64_t)blockIdx.x * A.ff_stride;   // this workgroup's slice
+        uint32_t *rows = (uint32_t *)(smem + ff_rows_off());
         const uint32_t RW = row_bytes(I.words) / 4u;
         int bad = 0;
 
@@ -1039,71 +1037,89 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
 
         // ---- 2. first fit -------------------------------------------------
         int T = 0;                         // tours opened (uniform)
-        int32_t gmax = 0;                  // lane c: largest room in tours 64c..64c+63
+        int32_t gmax = 0;                  // lane c: >= the largest room in tours 64c..64c+63
         uint32_t R[FF_MAX_ORDERS / 256];   // byte b of R[q]: room of tour 64 (4q + b) + lane
 #pragma unroll
         for (int q = 0; q < FF_MAX_ORDERS / 256; q++) R[q] = 0u;
         for (int i0 = 0; i0 < n; i0 += 64) {
             const int i = i0 + lane;
             const uint32_t o_l = i < n ? min((uint32_t)seq[i], (uint32_t)n) : (uint32_t)n;
-            const uint32_t s_l = cnt[o_l];             // min(size, Q + 1)
+            // min(size, Q + 1); 0 for an id out of range, which then joins
+            // some tour without taking room and is left out below
+            const uint32_t s_l = cnt[o_l];
             const int m = min(64, n - i0);
+            int t_l = 0;                               // lane j: tour of position i0 + j
             for (int j = 0; j < m; j++) {
-                const uint32_t o = (uint32_t)__builtin_amdgcn_readlane((int)o_l, j);
                 const int32_t sz = __builtin_amdgcn_readlane((int)s_l, j);
-                if (o >= (uint32_t)n) continue;        // malformed row: the order is left out
-                int t = T;
-                if (sz <= Q) {
-                    const uint64_t g = __ballot(gmax >= sz);
-                    if (g) {
-                        const int c = __builtin_ctzll(g);          // uniform
-                        const uint32_t sh = 8u * (uint32_t)(c & 3);
-                        const uint32_t w = R[c >> 2];
-                        const int32_t r = (int32_t)((w >> sh) & 0xFFu);
-                        const uint64_t f = __ballot(r >= sz);
-                        if (f) {                       // always, as gmax is exact
-                            const int k = __builtin_ctzll(f);
-                            t = 64 * c + k;
-                            const int32_t r2 = lane == k ? r - sz : r;
-                            R[c >> 2] = (w & ~(0xFFu << sh)) | ((uint32_t)r2 << sh);
-                            const int32_t mx = wave_max_i32(r2);
-                            if (lane == c) gmax = mx;
-                        }
+                int c = -1, k = 0;                     // group and lane of the tour found
+                uint64_t g = __ballot(gmax >= sz);     // none for an order larger than Q
+                while (g) {                            // uniform
+                    const int cg = __builtin_ctzll(g);
+                    const int32_t r = (int32_t)((R[cg >> 2] >> (8u * (uint32_t)(cg & 3))) & 0xFFu);
+                    const uint64_t f = __ballot(r >= sz);
+                    if (f) {
+                        c = cg;
+                        k = __builtin_ctzll(f);
+                        break;
                     }
+                    const int32_t mx = wave_max_i32(r);        // the bound was stale
+                    if (lane == cg) gmax = mx;
+                    g &= g - 1;
                 }
-                if (t == T) {                          // no open tour has room
+                int t;
+                if (c >= 0) {                          // the order joins tour 64c + k
+                    t = 64 * c + k;
+                    // every lane takes part (no divergent update of the register array)
+                    R[c >> 2] -= lane == k ? (uint32_t)sz << (8u * (uint32_t)(c & 3)) : 0u;
+                } else {                               // no open tour has room
+                    t = T;
                     const int32_t r0 = sz <= Q ? Q - sz : 0;   // a larger order rides alone
-                    const int c = T >> 6;
-                    const uint32_t sh = 8u * (uint32_t)(c & 3);
-                    if (lane == (T & 63)) R[c >> 2] |= (uint32_t)r0 << sh;
-                    if (lane == c) gmax = max(gmax, r0);
+                    const int cn = T >> 6;
+                    R[cn >> 2] |= lane == (T & 63) ? (uint32_t)r0 << (8u * (uint32_t)(cn & 3)) : 0u;
+                    if (lane == cn) gmax = max(gmax, r0);
                     T++;
                 }
-                // one wavefront: its LDS accesses take effect in program order
-                if (lane == 0) tour_of[o] = (uint16_t)t;
+                t_l = lane == j ? t : t_l;
             }
+            // read after the tile loop's barrier
+            if (i < n && o_l < (uint32_t)n) tour_of[o_l] = (uint16_t)t_l;
         }
 
         // ---- 3. tiles of tours: aisle sets, farthest locations, S-shape ---
+        // One order per lane, from the groups of 64 orders of like size: an
+        // order outside the tile loads none of its lines.
         int64_t acc = 0;
-        const uint2 *lines = A.lines + I.line_off;
+        const uint32_t *grec = A.grec + I.grec_off;
+        const uint32_t *gbase = A.gbase + I.gbase_off;
+        const uint16_t *gord = A.gord + I.gord_off;
         for (int t0 = 0; t0 < T; t0 += FF_TILE) {
             for (uint32_t k = lane; k < FF_TILE * RW; k += 64) rows[k] = 0u;
             __syncthreads();
-            for (int r = lane; r < I.n_lines_pad; r += 64) {
-                const uint2 rec = lines[r];
-                const uint32_t o = ((rec.y & 0x7FFFFFFFu) - nf_tour) >> 1;   // padding: order n
-                if (o >= (uint32_t)n) continue;
-                const uint32_t t = (uint32_t)tour_of[o] - (uint32_t)t0;
+            for (int g = 0; g < I.n_grp; g++) {
+                const uint32_t o = gord[64 * g + lane];            // 0xFFFF: no order
+                const uint32_t b0 = gbase[g];
+                const uint32_t len = (gbase[g + 1] - b0) >> 6;     // lines of the group's longest order
+                const uint32_t t = (o < (uint32_t)n ? (uint32_t)tour_of[o] : 0xFFFFu) - (uint32_t)t0;
                 if (t >= (uint32_t)FF_TILE) continue;
-                const uint32_t ls = rec.x + zs[rec.x >> 26];
-                const uint32_t a = mulhi24(ls, I.magic);
-                atomicOr(&rows[t * RW + 1u + (a >> 5)], 1u << (a & 31u));
-                atomicMax(&rows[t * RW], ls);
+                uint32_t far = 0;
+                for (uint32_t k = 0; k < len; k += 4) {
+                    uint32_t x[4];
+#pragma unroll
+                    for (int q = 0; q < 4; q++)                     // shorter orders repeat their first line
+                        x[q] = grec[b0 + 64u * min(k + (uint32_t)q, len - 1u) + (uint32_t)lane];
+#pragma unroll
+                    for (int q = 0; q < 4; q++) {
+                        const uint32_t ls = x[q] + zs[x[q] >> 26];
+                        const uint32_t a = mulhi24(ls, I.magic);
+                        atomicOr(&rows[t * RW + 1u + (a >> 5)], 1u << (a & 31u));
+                        far = max(far, ls);
+                    }
+                }
+                atomicMax(&rows[t * RW], far);
             }
             __syncthreads();
-            if (t0 + lane < T) {
-                const uint32_t *rw = rows + (uint32_t)lane * RW;
+            for (int tt = lane; tt < FF_TILE && t0 + tt < T; tt += 64) {
+                const uint32_t *rw = rows + (uint32_t)tt * RW;
                 const uint32_t ls = rw[0];
                 int k = 0;
                 for (int w = 0; w < I.words; w++) k += __popc(rw[1 + w]);

@@ -103,6 +103,9 @@ struct wo_wh {
     int batching = WO_BATCH_NEXT_FIT;   // the order batching of every instance of the handle
     std::vector<uint32_t> ff_lds;       // first fit: LDS of one plan of each instance
     uint32_t ff_lds_max = 0;
+    uint16_t *d_ff_tour = nullptr;      // first fit: tour of every order, one slice per workgroup
+    int64_t ff_stride = 0;              // entries per slice (largest order count + 1, rounded up)
+    int ff_slots = 0;                   // slices: the most workgroups a first-fit launch may have
     int small_orders = 1024;            // instances up to this size get a launch of 64-thread workgroups
     // Work lists by launch class (0: the configured workgroups, 1: 64-thread
     // workgroups for instances of at most small_orders orders, 2: 128-thread
@@ -457,7 +460,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         }
         I.n_lines_pad = (int32_t)(lines.size() - (size_t)I.line_off);
         wh->lds[i] = ly.total;
-        wh->ff_lds[i] = ff_lds_bytes(d.n_orders, I.words);
+        wh->ff_lds[i] = ff_lds_bytes(I.words);
     }
 
     size_t b_lines = lines.size() * sizeof(uint2), b_cnt = cnt.size();
@@ -487,6 +490,14 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     HIP_TRY(hipStreamSynchronize(s));
     wh->lds_max = *std::max_element(wh->lds.begin(), wh->lds.end());
     wh->ff_lds_max = *std::max_element(wh->ff_lds.begin(), wh->ff_lds.end());
+    if (wh->batching == WO_BATCH_FIRST_FIT) {
+        int32_t n_max = 0;
+        for (int32_t i = 0; i < n_instances; i++) n_max = std::max(n_max, descs[i].n_orders);
+        wh->ff_stride = ((int64_t)n_max + 1 + 63) & ~(int64_t)63;
+        wh->ff_slots = wh->cu_count * eval_ff_max_blocks_per_cu(*std::min_element(wh->ff_lds.begin(), wh->ff_lds.end()));
+        if ((st = dev_alloc((void **)&wh->d_ff_tour, sizeof(uint16_t) * (size_t)wh->ff_stride * wh->ff_slots)))
+            return st;
+    }
     guard.release();
     *out = wh;
     return WO_OK;
@@ -495,7 +506,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
 extern "C" wo_status wo_free_warehouse(wo_wh *wh)
 {
     if (!wh) return WO_OK;
-    if (wh->d_pool || wh->d_inst || wh->d_map || wh->d_err) (void)hipDeviceSynchronize();
+    if (wh->d_pool || wh->d_inst || wh->d_map || wh->d_err || wh->d_ff_tour) (void)hipDeviceSynchronize();
     if (wh->d_pool) (void)hipFree(wh->d_pool);
     if (wh->d_inst) (void)hipFree(wh->d_inst);
     if (wh->d_map) (void)hipFree(wh->d_map);
@@ -503,6 +514,7 @@ extern "C" wo_status wo_free_warehouse(wo_wh *wh)
     for (auto &c : wh->wc)
         if (c.d_work) (void)hipFree(c.d_work);
     if (wh->d_pinst) (void)hipFree(wh->d_pinst);
+    if (wh->d_ff_tour) (void)hipFree(wh->d_ff_tour);
     delete wh;
     return WO_OK;
 }
@@ -529,7 +541,8 @@ static int launch_grid(const wo_wh *wh, int block, int per_cu_cfg, uint32_t lds,
 
 static int ff_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
 {
-    return (int)std::min<int64_t>(n_plans, (int64_t)wh->cu_count * eval_ff_max_blocks_per_cu(lds));
+    const int64_t fit = (int64_t)wh->cu_count * eval_ff_max_blocks_per_cu(lds);
+    return (int)std::min<int64_t>(n_plans, std::min<int64_t>(fit, wh->ff_slots));   // one tour table slice each
 }
 
 static int launch_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
@@ -663,6 +676,8 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.queue = 0;
     a.queue_ctr = (uint32_t *)((char *)wh->d_err + 48);
     a.work = nullptr;
+    a.ff_tour = wh->d_ff_tour;
+    a.ff_stride = wh->ff_stride;
     bool any_small = false;
     for (int32_t i = 0; i < wh->n_inst; i++) any_small |= class_of(wh, i) != 0 && map[i + 1] > map[i];
     if (wh->batching == WO_BATCH_FIRST_FIT) {
@@ -729,6 +744,8 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.queue = 0;
     a.queue_ctr = nullptr;
     a.work = nullptr;
+    a.ff_tour = wh->d_ff_tour;
+    a.ff_stride = wh->ff_stride;
     if (wh->batching == WO_BATCH_FIRST_FIT) {
         const uint32_t lds = wh->ff_lds[inst];
         HIP_TRY(launch_eval_ff(a, lds, ff_grid(wh, lds, n_plans), s));

@@ -81,6 +81,8 @@ struct EvalArgs {
     int32_t queue;          // 1: take plans from a ticket counter
     uint32_t *queue_ctr;
     const int32_t *work;    // work item -> plan row (null: identity)
+    uint16_t *ff_tour;      // first fit: tour of every order, ff_stride entries per workgroup
+    int64_t ff_stride;
 };
 
 // Parallel next-fit: lanes that chase candidate tour chains (at most
@@ -128,20 +130,20 @@ __host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * ((uin
 __host__ __device__ inline uint32_t pick_row_bytes(int32_t slots) { return 4u * ((uint32_t)(slots + 1) | 1u); }
 
 // First-fit batching runs in a kernel of its own, one wavefront per plan.
-// LDS: the zone starts (64 words), the tour of every order (u16, plus the
-// entry of the padding records' order), then one tile of FF_TILE S-shape
-// rows.  Tours never outnumber orders; at most FF_MAX_ORDERS orders keep every
-// tour's free room in 16 registers per lane and the group maxima in one.
-constexpr int FF_TILE = 64;
+// LDS: the zone starts (64 words), then one tile of FF_TILE S-shape rows; the
+// tour of every order goes to a global table with one slice per workgroup of
+// the launch.  Tours never outnumber orders; at most FF_MAX_ORDERS orders
+// keep every tour's free room in 16 registers per lane and an upper bound of
+// each group's largest room in one.
+constexpr int FF_TILE = 128;
 constexpr int FF_MAX_ORDERS = 4096;
-__host__ __device__ inline uint32_t ff_tour_off() { return 256u; }
-__host__ __device__ inline uint32_t ff_rows_off(int32_t n_orders) { return 256u + align16(2u * ((uint32_t)n_orders + 1u)); }
+__host__ __device__ inline uint32_t ff_rows_off() { return 256u; }
 
 // bytes of the cnt table (order sizes, then zeros for the dummy and sink entries)
 __host__ __device__ inline uint32_t cnt_bytes(int32_t n_orders) { return align16((uint32_t)n_orders + 2u); }
-__host__ __device__ inline uint32_t ff_lds_bytes(int32_t n_orders, int32_t words)
+__host__ __device__ inline uint32_t ff_lds_bytes(int32_t words)
 {
-    return ff_rows_off(n_orders) + (uint32_t)FF_TILE * row_bytes(words);
+    return ff_rows_off() + (uint32_t)FF_TILE * row_bytes(words);
 }
 
 __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_units, uint32_t rb,
