@@ -392,7 +392,7 @@ def main(argv=None):
     ap.add_argument("--route", default="sshape", choices=list(ROUTES),
                     help="route of every tour (the default S-shape is the headline)")
     ap.add_argument("--batching", default="next-fit", choices=list(BATCHINGS),
-                    help="order batching rule (first fit takes the S-shape route only)")
+                    help="order batching rule")
     ap.add_argument("--search", action="store_true",
                     help="run the plain vs surrogate-screened search comparison instead")
     ap.add_argument("--population", type=int, default=16384)

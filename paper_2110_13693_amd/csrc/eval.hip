@@ -963,8 +963,8 @@ static __device__ __forceinline__ int32_t wave_max_i32(int32_t v)
 
 // Plans under first-fit order batching (the other greedy batching rule of the
 // order-picking literature beside next fit; section 5, Subproblem 2 leaves
-// the batching of orders into tours open) and the S-shape route.  One
-// wavefront evaluates one plan:
+// the batching of orders into tours open), for each route.  One wavefront
+// evaluates one plan:
 //   1. zone starts: each category's start is the total size of the
 //      categories in lower zones (one pass over the categories per lane);
 //   2. first fit, order by order in sequence: lane l keeps the free room of
@@ -974,13 +974,17 @@ static __device__ __forceinline__ int32_t wave_max_i32(int32_t v)
 //      of the group and a ballot find its first tour with room; a group
 //      without one gets its exact largest room as its new bound.  Every order
 //      has an item, so an empty room never fits;
-//   3. tiles of FF_TILE tours: every line of an order in the tile sets its
-//      aisle bit in the tour's LDS row, and the order raises the tour's
-//      farthest location; then one lane per tour takes the S-shape closed
-//      form;
+//   3. tiles of tours: for the S-shape route, every line of an order in the
+//      tile sets its aisle bit in the tour's LDS row and the order raises the
+//      tour's farthest location, then one lane per tour takes the closed
+//      form; for the other routes every line record appends its location to
+//      its tour's pick row, then one lane per tour sorts the picks and walks
+//      them as the next-fit kernel does;
 //   4. the wave's sum, saturated to int32, and the rate over the window.
+template <int ROUTE>
 __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
 {
+    constexpr int TILE = ff_tile(ROUTE);
     extern __shared__ __align__(16) unsigned char smem[];
     const int lane = threadIdx.x;
     for (int64_t p = blockIdx.x; p < A.n_plans; p += gridDim.x) {
@@ -995,7 +999,7 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
         uint32_t *zs = (uint32_t *)smem;
         uint16_t *tour_of = A.ff_tour + (int64_t)blockIdx.x * A.ff_stride;   // this workgroup's slice
         uint32_t *rows = (uint32_t *)(smem + ff_rows_off());
-        const uint32_t RW = row_bytes(I.words) / 4u;
+        const uint32_t RW = (uint32_t)I.row_b / 4u;
         int bad = 0;
 
         // ---- 1. zone starts ---------------------------------------------
@@ -1085,47 +1089,77 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
             if (i < n && o_l < (uint32_t)n) tour_of[o_l] = (uint16_t)t_l;
         }
 
-        // ---- 3. tiles of tours: aisle sets, farthest locations, S-shape ---
-        // One order per lane, from the groups of 64 orders of like size: an
-        // order outside the tile loads none of its lines.
+        // ---- 3. tiles of tours -----------------------------------------------
         int64_t acc = 0;
-        const uint32_t *grec = A.grec + I.grec_off;
-        const uint32_t *gbase = A.gbase + I.gbase_off;
-        const uint16_t *gord = A.gord + I.gord_off;
-        for (int t0 = 0; t0 < T; t0 += FF_TILE) {
-            for (uint32_t k = lane; k < FF_TILE * RW; k += 64) rows[k] = 0u;
+        for (int t0 = 0; t0 < T; t0 += TILE) {
+            for (uint32_t k = lane; k < TILE * RW; k += 64) rows[k] = 0u;
             __syncthreads();
-            for (int g = 0; g < I.n_grp; g++) {
-                const uint32_t o = gord[64 * g + lane];            // 0xFFFF: no order
-                const uint32_t b0 = gbase[g];
-                const uint32_t len = (gbase[g + 1] - b0) >> 6;     // lines of the group's longest order
-                const uint32_t t = (o < (uint32_t)n ? (uint32_t)tour_of[o] : 0xFFFFu) - (uint32_t)t0;
-                if (t >= (uint32_t)FF_TILE) continue;
-                uint32_t far = 0;
-                for (uint32_t k = 0; k < len; k += 4) {
-                    uint32_t x[4];
+            if (ROUTE == WO_ROUTE_SSHAPE) {
+                // aisle sets and farthest locations, one order per lane from
+                // the groups of 64 orders of like size: an order outside the
+                // tile loads none of its lines
+                const uint32_t *grec = A.grec + I.grec_off;
+                const uint32_t *gbase = A.gbase + I.gbase_off;
+                const uint16_t *gord = A.gord + I.gord_off;
+                for (int g = 0; g < I.n_grp; g++) {
+                    const uint32_t o = gord[64 * g + lane];            // 0xFFFF: no order
+                    const uint32_t b0 = gbase[g];
+                    const uint32_t len = (gbase[g + 1] - b0) >> 6;     // lines of the group's longest order
+                    const uint32_t t = (o < (uint32_t)n ? (uint32_t)tour_of[o] : 0xFFFFu) - (uint32_t)t0;
+                    if (t >= (uint32_t)TILE) continue;
+                    uint32_t far = 0;
+                    for (uint32_t k = 0; k < len; k += 4) {
+                        uint32_t x[4];
 #pragma unroll
-                    for (int q = 0; q < 4; q++)                     // shorter orders repeat their first line
-                        x[q] = grec[b0 + 64u * min(k + (uint32_t)q, len - 1u) + (uint32_t)lane];
+                        for (int q = 0; q < 4; q++)                     // shorter orders repeat their first line
+                            x[q] = grec[b0 + 64u * min(k + (uint32_t)q, len - 1u) + (uint32_t)lane];
 #pragma unroll
-                    for (int q = 0; q < 4; q++) {
-                        const uint32_t ls = x[q] + zs[x[q] >> 26];
-                        const uint32_t a = mulhi24(ls, I.magic);
-                        atomicOr(&rows[t * RW + 1u + (a >> 5)], 1u << (a & 31u));
-                        far = max(far, ls);
+                        for (int q = 0; q < 4; q++) {
+                            const uint32_t ls = x[q] + zs[x[q] >> 26];
+                            const uint32_t a = mulhi24(ls, I.magic);
+                            atomicOr(&rows[t * RW + 1u + (a >> 5)], 1u << (a & 31u));
+                            far = max(far, ls);
+                        }
                     }
+                    atomicMax(&rows[t * RW], far);
                 }
-                atomicMax(&rows[t * RW], far);
+            } else {
+                // pick rows: every line exactly once, from the instance's line
+                // records, which name their order by its entry in the
+                // next-fit kernel's tour table (the padding records name
+                // order n)
+                const uint32_t nf_tour = eval_layout(n, I.n_units, (uint32_t)I.row_b, I.t_cap, I.chase_log2,
+                                                     I.chase_lanes).tour;
+                const uint2 *lines = A.lines + I.line_off;
+                for (int r = lane; r < I.n_lines_pad; r += 64) {
+                    const uint2 rec = lines[r];
+                    const uint32_t o = ((rec.y & 0x7FFFFFFFu) - nf_tour) >> 1;
+                    const uint32_t t = (o < (uint32_t)n ? (uint32_t)tour_of[o] : 0xFFFFu) - (uint32_t)t0;
+                    if (t >= (uint32_t)TILE) continue;
+                    const uint32_t ls = rec.x + zs[rec.x >> 26];
+                    const uint32_t e = atomicAdd(&rows[t * RW], 1u);
+                    rows[t * RW + 1u + min(e, (uint32_t)I.pick_slots - 1u)] = ls;
+                }
             }
             __syncthreads();
-            for (int tt = lane; tt < FF_TILE && t0 + tt < T; tt += 64) {
+            for (int tt = lane; tt < TILE && t0 + tt < T; tt += 64) {
                 const uint32_t *rw = rows + (uint32_t)tt * RW;
-                const uint32_t ls = rw[0];
-                int k = 0;
-                for (int w = 0; w < I.words; w++) k += __popc(rw[1 + w]);
-                const uint32_t a = mulhi24(ls, I.magic);
-                const int64_t y = (int64_t)((ls - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
-                acc += 2ll * I.spacing * a + ((k & 1) ? (int64_t)(k - 1) * I.L + 2 * y : (int64_t)k * I.L);
+                if (ROUTE == WO_ROUTE_SSHAPE) {
+                    const uint32_t ls = rw[0];
+                    int k = 0;
+                    for (int w = 0; w < I.words; w++) k += __popc(rw[1 + w]);
+                    const uint32_t a = mulhi24(ls, I.magic);
+                    const int64_t y = (int64_t)((ls - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
+                    acc += 2ll * I.spacing * a + ((k & 1) ? (int64_t)(k - 1) * I.L + 2 * y : (int64_t)k * I.L);
+                } else {
+                    const uint32_t np = min(rw[0], (uint32_t)I.pick_slots);
+                    if (np == 0) continue;                  // only a malformed row leaves a tour empty
+                    uint32_t v[MAX_PICK_SLOTS];
+#pragma unroll
+                    for (int i = 0; i < MAX_PICK_SLOTS; i++) v[i] = (uint32_t)i < np ? rw[1 + i] : 0xFFFFFFFFu;
+                    sort32(v);
+                    acc += pick_route_cost<ROUTE>(v, np, I, I.magic);
+                }
             }
             __syncthreads();
         }
@@ -1185,30 +1219,53 @@ static int max_blocks_r(int block, uint32_t lds_bytes)
     return 1;
 }
 
-hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
+template <int ROUTE>
+static hipError_t launch_eval_ff_r(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
 {
     static uint32_t attr_bytes = 0;
     if (lds_bytes > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)eval_ff_kernel, hipFuncAttributeMaxDynamicSharedMemorySize,
-                                           (int)lds_bytes);
+        hipError_t e = hipFuncSetAttribute((const void *)eval_ff_kernel<ROUTE>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
             return e;
         }
         attr_bytes = lds_bytes;
     }
-    hipLaunchKernelGGL(eval_ff_kernel, dim3(grid), dim3(64), lds_bytes, s, a);
+    hipLaunchKernelGGL(eval_ff_kernel<ROUTE>, dim3(grid), dim3(64), lds_bytes, s, a);
     return hipGetLastError();
 }
 
-int eval_ff_max_blocks_per_cu(uint32_t lds_bytes)
+hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, int route, hipStream_t s)
+{
+    switch (route) {
+    case WO_ROUTE_SSHAPE: return launch_eval_ff_r<WO_ROUTE_SSHAPE>(a, lds_bytes, grid, s);
+    case WO_ROUTE_RETURN: return launch_eval_ff_r<WO_ROUTE_RETURN>(a, lds_bytes, grid, s);
+    case WO_ROUTE_LARGEST_GAP: return launch_eval_ff_r<WO_ROUTE_LARGEST_GAP>(a, lds_bytes, grid, s);
+    case WO_ROUTE_OPTIMAL: return launch_eval_ff_r<WO_ROUTE_OPTIMAL>(a, lds_bytes, grid, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+template <int ROUTE>
+static int ff_max_blocks_r(uint32_t lds_bytes)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, eval_ff_kernel, 64, lds_bytes) != hipSuccess) {
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, eval_ff_kernel<ROUTE>, 64, lds_bytes) != hipSuccess) {
         (void)hipGetLastError();
         return 1;
     }
     return n > 0 ? n : 1;
+}
+
+int eval_ff_max_blocks_per_cu(int route, uint32_t lds_bytes)
+{
+    switch (route) {
+    case WO_ROUTE_RETURN: return ff_max_blocks_r<WO_ROUTE_RETURN>(lds_bytes);
+    case WO_ROUTE_LARGEST_GAP: return ff_max_blocks_r<WO_ROUTE_LARGEST_GAP>(lds_bytes);
+    case WO_ROUTE_OPTIMAL: return ff_max_blocks_r<WO_ROUTE_OPTIMAL>(lds_bytes);
+    }
+    return ff_max_blocks_r<WO_ROUTE_SSHAPE>(lds_bytes);
 }
 
 int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes)

@@ -176,8 +176,6 @@ static wo_status check_desc(const wo_instance_desc &d, int idx)
         return fail(WO_E_INVAL, "instance %d: unknown routing %d", idx, d.routing);
     if (d.batching < WO_BATCH_NEXT_FIT || d.batching > WO_BATCH_FIRST_FIT)
         return fail(WO_E_INVAL, "instance %d: unknown batching %d", idx, d.batching);
-    if (d.batching == WO_BATCH_FIRST_FIT && d.routing != WO_ROUTE_SSHAPE)
-        return fail(WO_E_UNSUPPORTED, "instance %d: first-fit batching is built for the S-shape route only", idx);
     if (d.batching == WO_BATCH_FIRST_FIT && d.n_orders > FF_MAX_ORDERS)
         return fail(WO_E_UNSUPPORTED, "instance %d: first-fit batching takes at most %d orders (got %d)", idx,
                     FF_MAX_ORDERS, d.n_orders);
@@ -460,7 +458,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         }
         I.n_lines_pad = (int32_t)(lines.size() - (size_t)I.line_off);
         wh->lds[i] = ly.total;
-        wh->ff_lds[i] = ff_lds_bytes(I.words);
+        wh->ff_lds[i] = ff_lds_bytes(d.routing, I.row_b);
     }
 
     size_t b_lines = lines.size() * sizeof(uint2), b_cnt = cnt.size();
@@ -494,7 +492,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         int32_t n_max = 0;
         for (int32_t i = 0; i < n_instances; i++) n_max = std::max(n_max, descs[i].n_orders);
         wh->ff_stride = ((int64_t)n_max + 1 + 63) & ~(int64_t)63;
-        wh->ff_slots = wh->cu_count * eval_ff_max_blocks_per_cu(*std::min_element(wh->ff_lds.begin(), wh->ff_lds.end()));
+        wh->ff_slots = wh->cu_count *
+                       eval_ff_max_blocks_per_cu(wh->route, *std::min_element(wh->ff_lds.begin(), wh->ff_lds.end()));
         if ((st = dev_alloc((void **)&wh->d_ff_tour, sizeof(uint16_t) * (size_t)wh->ff_stride * wh->ff_slots)))
             return st;
     }
@@ -541,7 +540,7 @@ static int launch_grid(const wo_wh *wh, int block, int per_cu_cfg, uint32_t lds,
 
 static int ff_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
 {
-    const int64_t fit = (int64_t)wh->cu_count * eval_ff_max_blocks_per_cu(lds);
+    const int64_t fit = (int64_t)wh->cu_count * eval_ff_max_blocks_per_cu(wh->route, lds);
     return (int)std::min<int64_t>(n_plans, std::min<int64_t>(fit, wh->ff_slots));   // one tour table slice each
 }
 
@@ -683,7 +682,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     if (wh->batching == WO_BATCH_FIRST_FIT) {
         // first fit has a kernel of its own, one wavefront per plan; the
         // launch configuration above applies to next fit only
-        HIP_TRY(launch_eval_ff(a, wh->ff_lds_max, ff_grid(wh, wh->ff_lds_max, n_plans), s));
+        HIP_TRY(launch_eval_ff(a, wh->ff_lds_max, ff_grid(wh, wh->ff_lds_max, n_plans), wh->route, s));
     } else if (!any_small && !wh->queue) {
         // one launch, grid stride over the plan rows
         HIP_TRY(launch_eval(a, wh->lds_max, launch_grid(wh, wh->lds_max, n_plans), wh->block, wh->route, s));
@@ -748,7 +747,7 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.ff_stride = wh->ff_stride;
     if (wh->batching == WO_BATCH_FIRST_FIT) {
         const uint32_t lds = wh->ff_lds[inst];
-        HIP_TRY(launch_eval_ff(a, lds, ff_grid(wh, lds, n_plans), s));
+        HIP_TRY(launch_eval_ff(a, lds, ff_grid(wh, lds, n_plans), wh->route, s));
         return WO_OK;
     }
     const uint32_t lds = wh->lds[inst];

@@ -130,20 +130,21 @@ __host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * ((uin
 __host__ __device__ inline uint32_t pick_row_bytes(int32_t slots) { return 4u * ((uint32_t)(slots + 1) | 1u); }
 
 // First-fit batching runs in a kernel of its own, one wavefront per plan.
-// LDS: the zone starts (64 words), then one tile of FF_TILE S-shape rows; the
-// tour of every order goes to a global table with one slice per workgroup of
-// the launch.  Tours never outnumber orders; at most FF_MAX_ORDERS orders
-// keep every tour's free room in 16 registers per lane and an upper bound of
-// each group's largest room in one.
-constexpr int FF_TILE = 128;
+// LDS: the zone starts (64 words), then one tile of tour rows (128 S-shape
+// rows, or 64 pick rows for the other routes); the tour of every order goes
+// to a global table with one slice per workgroup of the launch.  Tours never
+// outnumber orders; at most FF_MAX_ORDERS orders keep every tour's free room
+// in 16 registers per lane and an upper bound of each group's largest room
+// in one.
 constexpr int FF_MAX_ORDERS = 4096;
+__host__ __device__ constexpr int ff_tile(int route) { return route == WO_ROUTE_SSHAPE ? 128 : 64; }
 __host__ __device__ inline uint32_t ff_rows_off() { return 256u; }
 
 // bytes of the cnt table (order sizes, then zeros for the dummy and sink entries)
 __host__ __device__ inline uint32_t cnt_bytes(int32_t n_orders) { return align16((uint32_t)n_orders + 2u); }
-__host__ __device__ inline uint32_t ff_lds_bytes(int32_t words)
+__host__ __device__ inline uint32_t ff_lds_bytes(int route, int32_t row_b)
 {
-    return ff_rows_off() + (uint32_t)FF_TILE * row_bytes(words);
+    return ff_rows_off() + (uint32_t)ff_tile(route) * (uint32_t)row_b;
 }
 
 __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_units, uint32_t rb,
@@ -176,9 +177,9 @@ __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_un
 hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, int route, hipStream_t s);
 // workgroups of the evaluation kernel that fit one CU (registers and LDS)
 int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes);
-// First-fit batching with the S-shape route: one 64-thread workgroup per plan.
-hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s);
-int eval_ff_max_blocks_per_cu(uint32_t lds_bytes);
+// First-fit batching: one 64-thread workgroup per plan.
+hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, int route, hipStream_t s);
+int eval_ff_max_blocks_per_cu(int route, uint32_t lds_bytes);
 
 // library-internal helpers over a loaded handle
 wo_status eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint8_t *d_zone_of,

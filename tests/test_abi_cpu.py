@@ -167,14 +167,6 @@ def test_load_rejects_optimal_route_beyond_32_bits(wo, tiny):
     assert out.value is None
 
 
-@pytest.mark.parametrize("routing", [1, 2, 3])
-def test_load_rejects_first_fit_with_other_routes(wo, tiny, routing):
-    st, out = _load_status(wo, _mod(tiny, batching=1, routing=routing))
-    assert st == wo.WO_E_UNSUPPORTED, wo.wo_last_error()
-    assert "first-fit" in wo.wo_last_error()
-    assert out.value is None
-
-
 def test_load_rejects_first_fit_beyond_4096_orders(wo):
     inst = synth.make_instance(n_aisles=40, slots_per_side=50, pitch_dm=10, spacing_dm=30, capacity=20,
                                n_categories=8, n_skus=3000, category_mode="dirichlet", n_orders=4097,

@@ -1,5 +1,5 @@
-"""GPU parity of first-fit order batching against the CPU oracle (through the
-C ABI).  Distances must match bit-exactly; the throughput to 1e-6 relative,
+"""GPU parity of first-fit order batching, under every route, against the CPU
+oracle (through the C ABI).  Distances must match bit-exactly; the throughput to 1e-6 relative,
 as for next fit."""
 import dataclasses
 
@@ -14,8 +14,12 @@ from tests.test_gpu_eval import THR_RTOL, _random_instance, _structured_sequence
 pytestmark = pytest.mark.gpu
 
 
-def _ff(inst):
-    return dataclasses.replace(inst, batching=1)
+ROUTES = [0, 1, 2, 3]    # S-shape, return, largest gap, optimal
+
+
+def _ff(inst, routing=None):
+    inst = dataclasses.replace(inst, batching=1)
+    return inst if routing is None else dataclasses.replace(inst, routing=routing)
 
 
 def _compare(inst, Z, S):
@@ -30,18 +34,20 @@ def _compare(inst, Z, S):
     return d_gpu
 
 
-def test_tiny_all_plans():
+@pytest.mark.parametrize("routing", ROUTES)
+def test_tiny_all_plans(routing):
     inst, Z, S = synth.workload("tiny")
-    print("tiny first fit", flush=True)
-    d_ff = _compare(_ff(inst), Z, S)
-    d_nf, _ = oracle.eval_plans(inst, Z, S)
+    print("tiny first fit", routing, flush=True)
+    d_ff = _compare(_ff(inst, routing), Z, S)
+    d_nf, _ = oracle.eval_plans(dataclasses.replace(inst, routing=routing), Z, S)
     assert (d_ff != d_nf).any()          # the rule changes the tours
 
 
-def test_paper_scale_sample():
+@pytest.mark.parametrize("routing", ROUTES)
+def test_paper_scale_sample(routing):
     inst, Z, S = synth.workload("paper", n_plans=64)
-    print("paper first fit", flush=True)
-    _compare(_ff(inst), Z, S)
+    print("paper first fit", routing, flush=True)
+    _compare(_ff(inst, routing), Z, S)
 
 
 def test_worked_plan_on_gpu():
@@ -81,6 +87,25 @@ def test_edge_cases(case):
     _compare(inst, Z, S)
 
 
+ROUTED_CASES = [
+    (1, 5, 7, 3, 3, 2.0),          # one aisle
+    (3, 4, 50, 2, 5, 3.0),         # oversize orders ride alone
+    (33, 7, 300, 32, 64, 1.5),     # rows of 32 picks
+    (400, 250, 4096, 1, 64, 0.0),  # 4,096 tours, 64 tiles of 64
+    (60, 2, 500, 12, 16, 1.5),     # short aisles: loops over empty aisles pay (optimal)
+]
+
+
+@pytest.mark.parametrize("routing", [1, 2, 3])
+@pytest.mark.parametrize("case", ROUTED_CASES, ids=lambda c: "N%d_S%d_n%d_Q%d_C%d" % c[:5])
+def test_routed_edge_cases(case, routing):
+    rng = np.random.default_rng(abs(hash(case)) % (1 << 31))
+    inst = _ff(_random_instance(rng, *case), routing)
+    Z, S = synth.make_plans(inst, 17, seed=int(rng.integers(1 << 30)))
+    print("case", case, routing, flush=True)
+    _compare(inst, Z, S)
+
+
 def test_structured_sequences():
     # sequences sorted by order size, both ways, and blocked: first fit packs
     # the small orders of a run into the room the large ones left
@@ -91,11 +116,13 @@ def test_structured_sequences():
     _compare(inst, Z, S)
 
 
-def test_batched_instances_match_single():
+@pytest.mark.parametrize("routing", [0, 3])
+def test_batched_instances_match_single(routing):
     import torch
     wo = _wo()
     rng = np.random.default_rng(43)
-    insts = [_ff(_random_instance(rng, a, 250, o, 30, 64)) for a, o in [(8, 50), (400, 4000), (37, 700), (120, 61)]]
+    insts = [_ff(_random_instance(rng, a, 250, o, 30, 64), routing)
+             for a, o in [(8, 50), (400, 4000), (37, 700), (120, 61)]]
     per = [5, 3, 8, 2]
     Zs, Ss, offs = [], [], [0]
     for inst, k in zip(insts, per):
