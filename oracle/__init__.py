@@ -8,7 +8,8 @@ its binding) never does, and this package never imports the product path.
 S-shape, return, largest-gap or optimal route distance, time-window throughput);
 ``surrogate.py`` is the float64
 reference of the surrogate network; ``search.py`` re-implements one step of the
-genetic search on the CPU.  Each cites the passage of arXiv 2110.13693 it
+genetic search on the CPU; ``kmeans.py`` is the exact K-means class-based
+storage.  Each cites the passage of arXiv 2110.13693 it
 follows.
 """
 from __future__ import annotations
