@@ -142,6 +142,30 @@ enum { WO_BATCH_NEXT_FIT = 0, WO_BATCH_FIRST_FIT = 1 };
 
 typedef struct wo_wh wo_wh;
 
+/* Class-based storage (section 5, Subproblem 3: products are placed by how
+ * often they are picked, with an unsupervised clustering such as K-means).
+ * Clusters the n_skus SKUs into at most k (1 .. 64) categories by Lloyd's
+ * K-means on pick frequency, the number of entries of d_order_skus naming
+ * each SKU:
+ *   - start: centroid c is the distinct frequency of rank
+ *     floor((2c + 1) D / (2k)) among the D distinct frequencies;
+ *   - a step assigns every SKU to its nearest centroid (exact rational
+ *     arithmetic; a tie goes to the lower index) and moves each non-empty
+ *     cluster's centroid to its members' mean; the iteration ends at the first
+ *     assignment equal to the previous one or after max_iter (>= 1);
+ *   - the non-empty clusters become categories 0 .. k_used - 1 by descending
+ *     mean frequency (equal means: lower cluster first), so category 0 holds
+ *     the fastest movers.
+ * d_order_skus: device int32 [n_lines] (1 .. WO_MAX_LINES), each in
+ * [0, n_skus); d_category: device int32 [n_skus], written.  *k_used and
+ * *n_iter (assignments performed) are written when not NULL.  The result
+ * can serve as a wo_instance_desc's sku_category.  Synchronous on `stream`;
+ * it allocates and frees its own scratch, so it is not for graph capture.
+ * WO_E_INVAL / WO_E_RANGE for bad arguments or an out-of-range SKU id. */
+wo_status wo_kmeans_categories(const int32_t *d_order_skus, int64_t n_lines, int32_t n_skus, int32_t k,
+                               int32_t max_iter, int32_t *d_category, int32_t *k_used, int32_t *n_iter,
+                               void *stream);
+
 /* Load n_instances (>= 1) instances onto the current HIP device.
  * Validates every descriptor (WO_E_INVAL / WO_E_RANGE), packs per-line
  * records and order tables, copies them to device memory on `stream` and

@@ -14,7 +14,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwo.so")
 BUILD_DIR = os.path.join(HERE, "_build")
-SOURCES = ["wo_api.cpp", "eval.hip", "surrogate.hip", "surrogate_api.cpp", "search.hip", "search_api.cpp"]
+SOURCES = ["wo_api.cpp", "eval.hip", "surrogate.hip", "surrogate_api.cpp", "search.hip", "search_api.cpp",
+           "kmeans.hip"]
 ARCH = "gfx950"
 
 

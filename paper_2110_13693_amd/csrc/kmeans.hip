@@ -1,0 +1,256 @@
+// Class-based storage by K-means on pick frequency (section 5, Subproblem 3:
+// products are placed by how often they are picked, with an unsupervised
+// clustering such as K-means, MacQueen 1967).  The feature of a SKU is the
+// number of order lines naming it; Lloyd's iteration clusters the SKUs into
+// k classes, numbered by descending mean frequency, which become the
+// categories the zones hold.
+//
+// SKUs of equal frequency always share a cluster, so after the frequencies
+// and their histogram the iteration runs over the histogram's bins (one
+// thread per frequency value).  The arithmetic is exact: a centroid is the
+// rational S / N, and f is nearer to S_j / N_j than to S_k / N_k iff
+// |f N_j - S_j| N_k < |f N_k - S_k| N_j, compared in 128 bits (ties to the
+// lower index).  Start: centroid c is the distinct frequency of rank
+// floor((2c + 1) D / (2k)) among the D distinct ones.  A step assigns every
+// bin and moves each non-empty cluster's centroid to its members' mean; the
+// iteration ends at the first assignment equal to the previous one or after
+// max_iter assignments.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+
+#include "wo_common.h"
+
+namespace {
+
+constexpr int KM_MAX = 64;
+
+struct KmState {
+    long long S[KM_MAX], N[KM_MAX];       // centroids S / N
+    unsigned long long S2[KM_MAX], N2[KM_MAX];   // sums of the assignment in progress
+    long long cnt[KM_MAX];                // members after the last assignment
+    int changed, done, n_iter, pad;
+    int rank[KM_MAX];
+    int k_used;
+};
+
+// a * b < c * d for a, c < 2^47 and b, d < 2^23 (products up to 2^70: 128 bits)
+__device__ __forceinline__ bool less_prod(unsigned long long a, unsigned long long b, unsigned long long c,
+                                          unsigned long long d)
+{
+    const unsigned long long h1 = __umul64hi(a, b), h2 = __umul64hi(c, d);
+    return h1 < h2 || (h1 == h2 && a * b < c * d);
+}
+
+__device__ __forceinline__ unsigned long long absdiff(long long x, long long y) { return x > y ? x - y : y - x; }
+
+__global__ void km_freq_kernel(const int32_t *skus, int64_t n_lines, int32_t n_skus, int32_t *freq, int32_t *err)
+{
+    for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < n_lines; l += (int64_t)gridDim.x * blockDim.x) {
+        const int32_t s = skus[l];
+        if (s < 0 || s >= n_skus) atomicOr(err, 1);
+        else atomicAdd(&freq[s], 1);
+    }
+}
+
+__global__ void km_hist_kernel(const int32_t *freq, int32_t n_skus, int32_t *hist)
+{
+    for (int32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_skus; s += gridDim.x * blockDim.x)
+        atomicAdd(&hist[freq[s]], 1);
+}
+
+// One block of 1024 threads: count the distinct frequencies, then give
+// every centroid its starting value.
+__global__ __launch_bounds__(1024) void km_init_kernel(const int32_t *hist, int32_t n_bins, int32_t k, KmState *st)
+{
+    __shared__ int part[1024 / 64];
+    __shared__ int D_s;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int d = 0;
+    for (int v = tid; v < n_bins; v += 1024) d += hist[v] > 0;
+    for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
+    if (lane == 0) part[w] = d;
+    __syncthreads();
+    if (tid == 0) {
+        int t = 0;
+        for (int i = 0; i < 1024 / 64; i++) t += part[i];
+        D_s = t;
+    }
+    __syncthreads();
+    const long long D = D_s;
+    // rank of each non-empty bin among the non-empty ones, chunk by chunk
+    int base = 0;
+    for (int v0 = 0; v0 < n_bins; v0 += 1024) {
+        const int v = v0 + tid;
+        const int ne = v < n_bins && hist[v] > 0;
+        const unsigned long long b = __ballot(ne);
+        const int below = __popcll(b & ((1ull << lane) - 1ull));
+        __syncthreads();                       // part[] of the previous chunk has been read
+        if (lane == 0) part[w] = __popcll(b);
+        __syncthreads();
+        int off = base;
+        for (int i = 0; i < w; i++) off += part[i];
+        if (ne) {
+            const long long r = off + below;
+            for (int c = 0; c < k; c++)
+                if ((2ll * c + 1) * D / (2ll * k) == r) {
+                    st->S[c] = v;
+                    st->N[c] = 1;
+                }
+        }
+        for (int i = 0; i < 1024 / 64; i++) base += part[i];
+    }
+}
+
+__global__ void km_assign_kernel(const int32_t *hist, int32_t n_bins, int32_t k, int32_t *label, KmState *st)
+{
+    if (st->done) return;
+    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n_bins; v += gridDim.x * blockDim.x) {
+        const int32_t m = hist[v];
+        if (m == 0) continue;
+        int best = 0;
+        unsigned long long bd = absdiff((long long)v * st->N[0], st->S[0]), bn = (unsigned long long)st->N[0];
+        for (int c = 1; c < k; c++) {
+            const unsigned long long dc = absdiff((long long)v * st->N[c], st->S[c]);
+            const unsigned long long nc = (unsigned long long)st->N[c];
+            if (less_prod(dc, bn, bd, nc)) {   // dc / nc < bd / bn
+                best = c;
+                bd = dc;
+                bn = nc;
+            }
+        }
+        if (label[v] != best) {
+            st->changed = 1;                   // benign race: every writer stores 1
+            label[v] = best;
+        }
+        atomicAdd(&st->S2[best], (unsigned long long)v * (unsigned long long)m);
+        atomicAdd(&st->N2[best], (unsigned long long)m);
+    }
+}
+
+__global__ void km_update_kernel(int32_t k, KmState *st)
+{
+    const int c = threadIdx.x;
+    const int done = st->done, changed = st->changed;
+    __syncthreads();
+    if (done) return;
+    if (c == 0) {
+        st->n_iter += 1;
+        if (!changed) st->done = 1;
+        st->changed = 0;
+    }
+    if (c < k) {
+        if (changed) {
+            st->cnt[c] = (long long)st->N2[c];
+            if (st->N2[c] > 0) {
+                st->S[c] = (long long)st->S2[c];
+                st->N[c] = (long long)st->N2[c];
+            }
+        }
+        st->S2[c] = 0;
+        st->N2[c] = 0;
+    }
+}
+
+// Non-empty clusters by descending mean (exact: S_d N_c > S_c N_d), equal
+// means by lower index.
+__global__ void km_rank_kernel(int32_t k, KmState *st)
+{
+    const int c = threadIdx.x;
+    if (c >= k) return;
+    int r = 0;
+    const bool used = st->cnt[c] > 0;
+    for (int d = 0; d < k; d++) {
+        if (st->cnt[d] <= 0) continue;
+        const long long a = st->S[d] * st->N[c], b = st->S[c] * st->N[d];
+        r += a > b || (a == b && d < c);
+    }
+    st->rank[c] = used ? r : -1;
+    const unsigned long long u = __ballot(used);
+    if (c == 0) st->k_used = __popcll(u);
+}
+
+__global__ void km_label_kernel(const int32_t *freq, int32_t n_skus, const int32_t *label, const KmState *st,
+                                int32_t *category)
+{
+    for (int32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_skus; s += gridDim.x * blockDim.x)
+        category[s] = st->rank[label[freq[s]]];
+}
+
+int grid_for(int64_t n, int block) { return (int)std::min<int64_t>(std::max<int64_t>((n + block - 1) / block, 1), 4096); }
+
+}  // namespace
+
+extern "C" wo_status wo_kmeans_categories(const int32_t *d_order_skus, int64_t n_lines, int32_t n_skus, int32_t k,
+                                          int32_t max_iter, int32_t *d_category, int32_t *k_used, int32_t *n_iter,
+                                          void *stream)
+{
+    if (!d_order_skus || !d_category) return wo_fail(WO_E_INVAL, "NULL device buffer");
+    if (n_lines < 1 || n_lines > WO_MAX_LINES)
+        return wo_fail(WO_E_RANGE, "n_lines must be in 1 .. %d", WO_MAX_LINES);
+    if (n_skus < 1 || n_skus > WO_MAX_LOCATIONS)
+        return wo_fail(WO_E_RANGE, "n_skus must be in 1 .. %d", WO_MAX_LOCATIONS);
+    if (k < 1 || k > KM_MAX) return wo_fail(WO_E_RANGE, "k must be in 1 .. %d", KM_MAX);
+    if (max_iter < 1) return wo_fail(WO_E_INVAL, "max_iter must be >= 1");
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t n_bins = (int32_t)n_lines + 1;      // a frequency is at most n_lines
+    // scratch: frequencies, histogram, bin labels, state, error flag
+    char *buf = nullptr;
+    const size_t o_hist = ((size_t)n_skus * 4 + 255) & ~(size_t)255;
+    const size_t o_label = o_hist + (((size_t)n_bins * 4 + 255) & ~(size_t)255);
+    const size_t o_state = o_label + (((size_t)n_bins * 4 + 255) & ~(size_t)255);
+    const size_t o_err = o_state + ((sizeof(KmState) + 255) & ~(size_t)255);
+    const size_t bytes = o_err + 256;
+    if (wo_fault_injected()) return wo_fail(WO_E_NOMEM, "injected allocation failure");
+    if (hipMalloc((void **)&buf, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return wo_fail(WO_E_NOMEM, "hipMalloc(%zu) failed", bytes);
+    }
+    int32_t *freq = (int32_t *)buf, *hist = (int32_t *)(buf + o_hist), *label = (int32_t *)(buf + o_label);
+    KmState *st = (KmState *)(buf + o_state);
+    int32_t *err = (int32_t *)(buf + o_err);
+    wo_status ret = WO_OK;
+    int32_t h_done = 0, h_err = 0;
+    KmState h{};
+    auto run = [&]() -> wo_status {
+        WO_HIP(hipMemsetAsync(buf, 0, o_label, s));                       // frequencies, histogram
+        WO_HIP(hipMemsetAsync(label, 0xFF, o_state - o_label, s));        // no cluster yet
+        WO_HIP(hipMemsetAsync(st, 0, bytes - o_state, s));                // state, error flag
+        hipLaunchKernelGGL(km_freq_kernel, dim3(grid_for(n_lines, 256)), dim3(256), 0, s, d_order_skus, n_lines,
+                           n_skus, freq, err);
+        hipLaunchKernelGGL(km_hist_kernel, dim3(grid_for(n_skus, 256)), dim3(256), 0, s, freq, n_skus, hist);
+        hipLaunchKernelGGL(km_init_kernel, dim3(1), dim3(1024), 0, s, hist, n_bins, k, st);
+        WO_HIP(hipGetLastError());
+        // assignments in rounds of 8; an assignment after convergence returns at once
+        for (int it = 0; it < max_iter;) {
+            const int r = std::min(8, max_iter - it);
+            for (int i = 0; i < r; i++) {
+                hipLaunchKernelGGL(km_assign_kernel, dim3(grid_for(n_bins, 256)), dim3(256), 0, s, hist, n_bins, k,
+                                   label, st);
+                hipLaunchKernelGGL(km_update_kernel, dim3(1), dim3(KM_MAX), 0, s, k, st);
+            }
+            it += r;
+            WO_HIP(hipGetLastError());
+            WO_HIP(hipMemcpyAsync(&h_done, &st->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+            WO_HIP(hipStreamSynchronize(s));
+            if (h_done) break;
+        }
+        hipLaunchKernelGGL(km_rank_kernel, dim3(1), dim3(KM_MAX), 0, s, k, st);
+        hipLaunchKernelGGL(km_label_kernel, dim3(grid_for(n_skus, 256)), dim3(256), 0, s, freq, n_skus, label, st,
+                           d_category);
+        WO_HIP(hipGetLastError());
+        WO_HIP(hipMemcpyAsync(&h, st, sizeof(KmState), hipMemcpyDeviceToHost, s));
+        WO_HIP(hipMemcpyAsync(&h_err, err, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+        WO_HIP(hipStreamSynchronize(s));
+        if (h_err) return wo_fail(WO_E_INVAL, "an order line names a SKU outside 0 .. %d", n_skus - 1);
+        return WO_OK;
+    };
+    ret = run();
+    (void)hipStreamSynchronize(s);
+    (void)hipFree(buf);
+    if (ret == WO_OK) {
+        if (k_used) *k_used = h.k_used;
+        if (n_iter) *n_iter = h.n_iter;
+    }
+    return ret;
+}

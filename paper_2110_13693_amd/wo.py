@@ -31,6 +31,7 @@ EXPORTS = sorted([
     "wo_screen_plans",
     "wo_search_create", "wo_search_free", "wo_search_step", "wo_search_best", "wo_search_population",
     "wo_set_eval_config", "wo_get_eval_config", "wo_autotune_eval",
+    "wo_kmeans_categories",
 ])
 WO_SUR_PARAMS = 4457985
 WO_SCREEN_MAX_KEEP = 4096
@@ -109,6 +110,7 @@ def lib():
         L.wo_search_step.argtypes = [V, V, V, I32, V]
         L.wo_search_best.argtypes = [V, V, V, P(I32), P(I32), V]
         L.wo_search_population.argtypes = [V, V, V, V, V, V]
+        L.wo_kmeans_categories.argtypes = [V, I64, I32, I32, I32, V, P(I32), P(I32), V]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype if name in (
                 "wo_status_str", "wo_last_error") else ctypes.c_int
@@ -347,6 +349,22 @@ def wo_screen_plans(wh: Warehouse, inst: int, s: Surrogate, zone_of, keep: int, 
                                  _ptr(pred, 4, "pred"), int(keep), _ptr(keep_idx, 4, "keep_idx"),
                                  ctypes.c_void_p(_stream_handle(stream))))
     return keep_idx
+
+
+# ---------------------------------------------------------------------------
+# class-based storage
+# ---------------------------------------------------------------------------
+
+def wo_kmeans_categories(order_skus, n_skus: int, k: int, category, max_iter: int = 100, stream=None):
+    """K-means categories of the SKUs by pick frequency into ``category``
+    (int32 GPU tensor of n_skus); returns (categories used, assignments)."""
+    if category.numel() != n_skus:
+        raise ValueError("category must hold one entry per SKU")
+    used, iters = ctypes.c_int32(0), ctypes.c_int32(0)
+    _check(lib().wo_kmeans_categories(_ptr(order_skus, 4, "order_skus"), int(order_skus.numel()), int(n_skus),
+                                      int(k), int(max_iter), _ptr(category, 4, "category"), ctypes.byref(used),
+                                      ctypes.byref(iters), ctypes.c_void_p(_stream_handle(stream))))
+    return used.value, iters.value
 
 
 # ---------------------------------------------------------------------------
