@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz, one 32-bit integer op per lane per clock
 INT_VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# route of every tour: S-shape (the headline), return, largest gap
+# route of every tour: S-shape (the headline), return, largest gap, optimal
 ROUTES = {"sshape": 0, "return": 1, "largest-gap": 2, "optimal": 3}
 BATCHINGS = {"next-fit": 0, "first-fit": 1}
 HBM_PEAK_BYTES = 8.0e12
@@ -323,6 +323,52 @@ SUR_TRAIN_FLOP = 18.35e6
 BF16_PEAK_FLOPS = 2.5e15
 
 
+def kmeans_bench(args):
+    """K-means class-based storage on the paper-scale order history (10,006
+    lines over 150,000 SKUs, 16 classes), one synchronous call per step."""
+    import torch
+
+    import synth
+    from paper_2110_13693_amd import wo
+
+    torch.cuda.set_device(0)
+    inst, _, _ = synth.workload("paper", n_plans=1)
+    k = 16
+    skus = torch.from_numpy(np.ascontiguousarray(inst.order_skus, dtype=np.int32)).cuda()
+    cat = torch.empty(inst.n_skus, dtype=torch.int32, device="cuda")
+    for _ in range(args.warmup):
+        wo.wo_kmeans_categories(skus, inst.n_skus, k, cat)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        used, iters = wo.wo_kmeans_categories(skus, inst.n_skus, k, cat)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / args.steps
+    # algorithmic bytes of a call: the order lines once, the frequency of
+    # every SKU written, read for the histogram and read for the label, and
+    # the category written
+    bytes_call = 4 * inst.n_items + 16 * inst.n_skus
+    out = {"metric": "K-means class-based storage calls/s", "value": 1e3 / ms, "unit": "calls/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "i32/i64", "data": "synthetic",
+           "config": {"workload": "pick frequencies of the paper-scale order history (10,006 lines over "
+                                  "150,000 SKUs) clustered into %d classes" % k,
+                      "classes_used": used, "assignments": iters, "parallelism": "1 GPU"},
+           "roofline": {"bound": "hbm", "achieved": bytes_call / (ms / 1e3) / 1e9, "peak": HBM_PEAK_BYTES / 1e9,
+                        "unit": "GB/s", "frac": bytes_call / (ms / 1e3) / HBM_PEAK_BYTES, "traffic": None}}
+    if not args.no_cpu_baseline:
+        from oracle import kmeans
+        reps, t1 = 0, time.perf_counter()
+        while time.perf_counter() - t1 < 1.5:
+            kmeans.kmeans_categories(kmeans.pick_frequency(inst.n_skus, inst.order_skus), k)
+            reps += 1
+        dt = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": reps / dt, "unit": "calls/s", "cores": 1, "kind": "oracle",
+                               "sample": "%d calls on the same history (%.1f s)" % (reps, dt)}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def surrogate_bench(args):
     """Surrogate throughput on the BF16 matrix cores: screening predictions
     (65,536 candidates per call) and training (batch 4,096), on random
@@ -403,6 +449,8 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=2e-3, help="surrogate learning rate (search comparison)")
     ap.add_argument("--batched", action="store_true",
                     help="time the 512-instance uneven batch (autotuned, eager and graph replay) instead")
+    ap.add_argument("--kmeans", action="store_true",
+                    help="time K-means class-based storage on the paper-scale order history instead")
     ap.add_argument("--surrogate", action="store_true",
                     help="time surrogate screening and training on the matrix cores instead")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -419,6 +467,8 @@ def main(argv=None):
         return batched_bench(args)
     if args.surrogate:
         return surrogate_bench(args)
+    if args.kmeans:
+        return kmeans_bench(args)
     if args.copy_probe:
         import torch
         a = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")

@@ -53,10 +53,25 @@ __global__ void km_freq_kernel(const int32_t *skus, int64_t n_lines, int32_t n_s
     }
 }
 
+// Most SKUs share a few low frequencies (most are never picked), so the
+// lanes holding the first active lane's frequency add their count with one
+// atomic; the others add one each.
 __global__ void km_hist_kernel(const int32_t *freq, int32_t n_skus, int32_t *hist)
 {
-    for (int32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_skus; s += gridDim.x * blockDim.x)
-        atomicAdd(&hist[freq[s]], 1);
+    for (int32_t s0 = blockIdx.x * blockDim.x; s0 < n_skus; s0 += gridDim.x * blockDim.x) {
+        const int32_t s = s0 + threadIdx.x;
+        const bool act = s < n_skus;
+        const int32_t f = act ? freq[s] : -1;
+        const uint64_t live = __ballot(act);
+        if (!live) continue;
+        const int32_t f0 = __shfl(f, __builtin_ctzll(live), 64);
+        const uint64_t same = __ballot(act && f == f0);
+        if (act && f == f0) {
+            if ((threadIdx.x & 63) == __builtin_ctzll(same)) atomicAdd(&hist[f0], __popcll(same));
+        } else if (act) {
+            atomicAdd(&hist[f], 1);
+        }
+    }
 }
 
 // One block of 1024 threads: count the distinct frequencies, then give
