@@ -35,19 +35,16 @@
 //   6. per tour: k = popcount of the aisle set, S-shape closed form; the
 //      block sums the tours in int64.
 // Tours beyond one tile of rows are handled in further passes over the lines.
-// The return and largest-gap routes (ROUTE = 1, 2) share steps 1-4; their rows
-// hold each tour's picks instead (step 5 appends the line's scaled location),
-// and step 6 sorts a tour's picks by (aisle, depth) and walks them once.
-#include "wo_internal.h"
+// The return, largest-gap and optimal routes (ROUTE = 1, 2, 3) share steps
+// 1-4; their rows hold each tour's picks instead (step 5 appends the line's
+// scaled location), and step 6 sorts a tour's picks by (aisle, depth) and
+// walks them once (eval_device.h).  First-fit batching has a kernel of its
+// own (firstfit.hip).
+#include "eval_device.h"
 
 namespace wo {
 
 typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
-
-static __device__ __forceinline__ uint32_t mulhi24(uint32_t x, uint32_t m)
-{
-    return (uint32_t)(((uint64_t)(x & 0xFFFFFFu) * (uint64_t)(m & 0xFFFFFFu)) >> 32);
-}
 
 static __device__ __forceinline__ uint32_t ffbh(uint32_t x)   // leading zeros, 32 for 0
 {
@@ -120,14 +117,6 @@ static __device__ __forceinline__ int64_t block_sum64(int64_t v, int64_t *slot)
     return t;
 }
 
-static __device__ __forceinline__ float window_throughput(int64_t D, const InstDev &I)
-{
-    // T = D / walk + t_item * items; orders * window / T, IEEE double, no contraction
-    double T = __dadd_rn(__ddiv_rn((double)D, I.walk), __dmul_rn(I.t_item, (double)I.n_lines));
-    double r = __ddiv_rn(__dmul_rn((double)I.n_orders, I.window), T);
-    return __double2float_rn(r);
-}
-
 // LDS by absolute address.  The kernel declares no static LDS, so its dynamic
 // LDS starts at address 0 and a layout offset is the address itself; the line
 // pass uses these so that a table offset held in a register needs no base add.
@@ -173,20 +162,6 @@ static __device__ __forceinline__ uint32_t next_open1(uint32_t B, uint32_t y, ui
     return y + 32u - ffbh_raw(win);
 }
 
-// Instance of plan row p: from the per-plan table when there is one, else the
-// last instance whose first row is <= p.
-static __device__ __forceinline__ int instance_of(const EvalArgs &A, int64_t p)
-{
-    if (A.n_inst <= 1) return 0;
-    if (A.plan_inst) return A.plan_inst[p];
-    int lo = 0, hi = A.n_inst - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (A.plan_begin[mid] <= p) lo = mid; else hi = mid - 1;
-    }
-    return lo;
-}
-
 // The order ids of sequence positions [0, nv) of `s`, two per 32-bit word.
 // A full, 16-byte aligned chunk is loaded as it is and the function returns
 // true: the caller clamps it to n - 1 (with min_u16x2) when it uses it, so
@@ -211,151 +186,6 @@ static __device__ __forceinline__ bool load_chunk(const uint16_t *s, int nv, uin
 #pragma unroll
     for (int j = 0; j < CH / 8; j++) out[j] = make_uint4(w[4 * j], w[4 * j + 1], w[4 * j + 2], w[4 * j + 3]);
     return false;
-}
-
-// Ascending bitonic sort of 32 words held in registers (straight-line min/max).
-static __device__ __forceinline__ void sort32(uint32_t (&v)[MAX_PICK_SLOTS])
-{
-#pragma unroll
-    for (int k = 2; k <= MAX_PICK_SLOTS; k <<= 1)
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1)
-#pragma unroll
-            for (int i = 0; i < MAX_PICK_SLOTS; i++) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const uint32_t a = v[i], b = v[l];
-                    const bool up = (i & k) == 0;
-                    v[i] = up ? min(a, b) : max(a, b);
-                    v[l] = up ? max(a, b) : min(a, b);
-                }
-            }
-}
-
-// Optimal route of one tour (the minimum route distance of section 5,
-// Subproblem 2) in the manner of Ratliff and Rosenthal: a programme over the
-// aisles holding picks, left to right.  A partial walk is in one of five
-// classes at the two ends (front f, back b) of the last aisle decided:
-//   O1: f and b of odd degree, one component;
-//   F : only f in the walk (even degree);
-//   B : only b in the walk (even degree);
-//   E1: f and b of even degree, one component;
-//   E2: f and b of even degree, two components.
-// A tour's distances are bounded at load so that every class cost, including
-// the unreachable value OPT_INF plus any sum of additions, stays below 2^31.
-#define OPT_INF 0x40000000
-struct OptClasses { int32_t o1, f, b, e1, e2; };
-
-// Carry the classes over r >= 1 steps along the cross aisles to the next
-// aisle with picks (r - 1 aisles without picks in between).  One step costs
-// 2w in O1, F and B (one edge each way, or both on one side) and 4w in E1 and
-// E2.  In the aisles passed, a class may change by a crossing (cost L) or a
-// double crossing (2 L); the cheapest such change is taken as early as it
-// lowers the step cost and as late as it raises it, which gives these forms.
-static __device__ __forceinline__ void opt_run(OptClasses &s, int32_t r, int32_t w, int32_t L)
-{
-    const int32_t a = 2 * w;
-    const int32_t ar = a * r, ar1 = ar + a, ar2 = ar1 + a;
-    const int32_t m_fbe = min(min(s.f, s.b), s.e1);
-    OptClasses n;
-    n.o1 = s.o1 + ar;
-    n.f = min(s.f, s.e1) + ar;            // E1 drops its back end
-    n.b = min(s.b, s.e1) + ar;
-    n.e1 = s.e1 + 2 * ar;
-    n.e2 = s.e2 + 2 * ar;
-    if (r >= 2) {                         // an aisle without picks lies in between
-        n.o1 = min(n.o1, min(m_fbe + ar, s.e2 + ar1) + L);
-        n.f = min(n.f, min(min(s.o1 + ar + L, s.b + ar + 2 * L), s.e2 + ar1 + 2 * L));
-        n.b = min(n.b, min(min(s.o1 + ar + L, s.f + ar + 2 * L), s.e2 + ar1 + 2 * L));
-        n.e1 = min(n.e1, min(min(s.o1 + ar1 + L, m_fbe + ar1 + 2 * L), s.e2 + ar2 + 2 * L));
-    }
-    s = n;
-}
-
-// The aisle's own edges: a crossing (L), a double crossing (2 L), in from the
-// front to the last pick (cF), in from the back to the first pick (cB), or in
-// from both sides leaving out the largest gap between two picks (cG; 2 L when
-// the aisle has a single pick, which never beats cF or cB then).
-static __device__ __forceinline__ void opt_aisle(OptClasses &s, int32_t L, int32_t cF, int32_t cB, int32_t cG)
-{
-    const int32_t cmin = min(min(cF, cB), cG);
-    const int32_t m_even = min(min(s.f, s.b), min(s.e1, s.e2));
-    OptClasses n;
-    n.o1 = min(s.o1 + cmin, m_even + L);
-    n.f = s.f + cF;
-    n.b = s.b + cB;
-    n.e1 = min(min(s.o1 + L, s.e1 + cmin), m_even + 2 * L);
-    n.e2 = min(min(s.f + min(cB, cG), s.b + min(cF, cG)), s.e2 + cmin);
-    s = n;
-}
-
-// Return, largest-gap or optimal route of one tour from its np >= 1 picks,
-// sorted by scaled location, i.e. by aisle and then depth (section 5,
-// Subproblem 2).
-template <int ROUTE>
-static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MAX_PICK_SLOTS], uint32_t np,
-                                                          const InstDev &I, uint32_t magic)
-{
-    const int32_t L = I.L;
-    uint32_t ca = mulhi24(v[0], magic);               // current aisle
-    const uint32_t a_lo = ca;
-    if (ROUTE == WO_ROUTE_OPTIMAL) {
-        // start: the depot at the front of aisle 0; if aisle 0 holds no pick
-        // it may still be crossed once or twice
-        OptClasses s = {a_lo ? L : OPT_INF, 0, OPT_INF, a_lo ? 2 * L : OPT_INF, OPT_INF};
-        uint32_t done = 0;                            // the last aisle decided
-        int32_t ylo = 0, yhi = 0, gap = -1;           // first and last depth, largest gap (-1: one pick)
-#pragma unroll
-        for (int i = 0; i < MAX_PICK_SLOTS; i++) {
-            if ((uint32_t)i < np) {
-                const uint32_t a = mulhi24(v[i], magic);
-                const int32_t y = (int32_t)((v[i] - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
-                if (i == 0) {
-                    ylo = y;
-                } else if (a != ca) {                 // aisle ca is complete
-                    if (ca != done) opt_run(s, (int32_t)(ca - done), I.spacing, L);
-                    opt_aisle(s, L, 2 * yhi, 2 * (L - ylo), gap >= 0 ? 2 * (L - gap) : 2 * L);
-                    done = ca;
-                    ca = a;
-                    ylo = y;
-                    gap = -1;
-                } else {
-                    gap = max(gap, y - yhi);
-                }
-                yhi = y;
-            }
-        }
-        if (ca != done) opt_run(s, (int32_t)(ca - done), I.spacing, L);
-        opt_aisle(s, L, 2 * yhi, 2 * (L - ylo), gap >= 0 ? 2 * (L - gap) : 2 * L);
-        return (int64_t)min(min(s.f, s.b), s.e1);     // even ends, one component
-    }
-    int32_t py = 0;                                   // previous depth in the aisle (front: 0)
-    int32_t g = 0;                                    // largest gap so far in the aisle
-    int64_t sum = 0;                                  // return: farthest depths; gap: inner L - gap
-#pragma unroll
-    for (int i = 0; i < MAX_PICK_SLOTS; i++) {
-        if ((uint32_t)i < np) {
-            const uint32_t a = mulhi24(v[i], magic);
-            const int32_t y = (int32_t)((v[i] - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
-            if (a != ca) {                            // close aisle ca
-                if (ROUTE == WO_ROUTE_RETURN) {
-                    sum += py;
-                } else {
-                    g = max(g, L - py);
-                    if (ca != a_lo) sum += L - g;
-                }
-                ca = a;
-                py = 0;
-                g = 0;
-            }
-            g = max(g, y - py);
-            py = y;
-        }
-    }
-    const int64_t horiz = 2ll * I.spacing * ca;       // ca is the farthest aisle now
-    if (ROUTE == WO_ROUTE_RETURN) return horiz + 2 * (sum + py);
-    if (ca == a_lo) return horiz + 2ll * py;           // one aisle: the return route
-    return horiz + 2ll * L + 2 * sum;
 }
 
 template <int BLOCK, int ROUTE>
@@ -948,234 +778,6 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
 // Reset of the work-queue ticket (a kernel, so that it can sit in a graph).
 __global__ void reset_ticket_kernel(uint32_t *ctr) { *ctr = 0u; }
 
-// Largest value over the wavefront (DPP row shifts and broadcasts, as in
-// wave_incl_scan; lanes without a source keep their own value).
-static __device__ __forceinline__ int32_t wave_max_i32(int32_t v)
-{
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false));   // row_shr:1
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xF, 0xF, false));   // row_shr:2
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false));   // row_shr:4
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false));   // row_shr:8
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));   // row_bcast:15
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));   // row_bcast:31
-    return __builtin_amdgcn_readlane(v, 63);
-}
-
-// Plans under first-fit order batching (the other greedy batching rule of the
-// order-picking literature beside next fit; section 5, Subproblem 2 leaves
-// the batching of orders into tours open), for each route.  One wavefront
-// evaluates one plan:
-//   1. zone starts: each category's start is the total size of the
-//      categories in lower zones (one pass over the categories per lane);
-//   2. first fit, order by order in sequence: lane l keeps the free room of
-//      tours l, 64 + l, 128 + l, ... in registers (a byte each), and lane c
-//      an upper bound of the largest room among tours 64c .. 64c + 63.  The
-//      groups whose bound admits the order are tried in turn: one register
-//      of the group and a ballot find its first tour with room; a group
-//      without one gets its exact largest room as its new bound.  Every order
-//      has an item, so an empty room never fits;
-//   3. tiles of tours: for the S-shape route, every line of an order in the
-//      tile sets its aisle bit in the tour's LDS row and the order raises the
-//      tour's farthest location, then one lane per tour takes the closed
-//      form; for the other routes every line record appends its location to
-//      its tour's pick row, then one lane per tour sorts the picks and walks
-//      them as the next-fit kernel does;
-//   4. the wave's sum, saturated to int32, and the rate over the window.
-template <int ROUTE>
-__global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
-{
-    constexpr int TILE = ff_tile(ROUTE);
-    extern __shared__ __align__(16) unsigned char smem[];
-    const int lane = threadIdx.x;
-    for (int64_t p = blockIdx.x; p < A.n_plans; p += gridDim.x) {
-        const int ii = instance_of(A, p);
-        const InstDev &I = A.inst[ii];
-        const int n = I.n_orders;
-        const int C = I.n_cat;
-        const int32_t Q = I.capacity;
-        const int64_t row = p - (A.n_inst > 1 ? A.plan_begin[ii] : 0);
-        const uint16_t *seq = A.seq + A.seq_base[ii] + row * (int64_t)n;
-        const uint8_t *cnt = A.cnt + I.cnt_off;
-        uint32_t *zs = (uint32_t *)smem;
-        uint16_t *tour_of = A.ff_tour + (int64_t)blockIdx.x * A.ff_stride;   // this workgroup's slice
-        uint32_t *rows = (uint32_t *)(smem + ff_rows_off());
-        const uint32_t RW = (uint32_t)I.row_b / 4u;
-        int bad = 0;
-
-        // ---- 1. zone starts ---------------------------------------------
-        {
-            const uint32_t zc = lane < C ? (uint32_t)A.zone_of[p * 64 + lane] : 0xFFu;
-            const uint32_t sz = lane < C ? (uint32_t)I.cat_size[lane] : 0u;
-            uint32_t start = 0;
-            for (int c = 0; c < C; c++) {
-                const uint32_t zo = (uint32_t)__shfl((int)zc, c, 64);
-                start += zo < zc ? (uint32_t)I.cat_size[c] : 0u;
-            }
-            // a malformed row cannot move a category off the warehouse
-            start = min(start, (uint32_t)I.n_skus - sz);
-            zs[lane] = (start << I.shift) - ((uint32_t)(4 * lane) << 24);
-            if (A.validate) {
-                uint64_t m = (lane < C && zc < 64u) ? (1ull << zc) : 0ull;
-#pragma unroll
-                for (int d = 32; d >= 1; d >>= 1) m |= __shfl_xor(m, d, 64);
-                const uint64_t want = (C == 64) ? ~0ull : ((1ull << C) - 1ull);
-                if (m != want) bad = 1;
-            }
-        }
-        for (int o = lane; o <= n; o += 64) tour_of[o] = 0xFFFFu;   // no tour yet; entry n: padding
-        if (A.validate) {
-            // every order exactly once: mark them in the tour table, which
-            // is then reset
-            __syncthreads();
-            for (int i = lane; i < n; i += 64) {
-                const uint32_t o = seq[i];
-                if (o < (uint32_t)n) tour_of[o] = 0; else bad = 1;
-            }
-            __syncthreads();
-            for (int o = lane; o < n; o += 64) {
-                bad |= tour_of[o] != 0;
-                tour_of[o] = 0xFFFFu;
-            }
-        }
-        __syncthreads();
-
-        // ---- 2. first fit -------------------------------------------------
-        int T = 0;                         // tours opened (uniform)
-        int32_t gmax = 0;                  // lane c: >= the largest room in tours 64c..64c+63
-        uint32_t R[FF_MAX_ORDERS / 256];   // byte b of R[q]: room of tour 64 (4q + b) + lane
-#pragma unroll
-        for (int q = 0; q < FF_MAX_ORDERS / 256; q++) R[q] = 0u;
-        for (int i0 = 0; i0 < n; i0 += 64) {
-            const int i = i0 + lane;
-            const uint32_t o_l = i < n ? min((uint32_t)seq[i], (uint32_t)n) : (uint32_t)n;
-            // min(size, Q + 1); 0 for an id out of range, which then joins
-            // some tour without taking room and is left out below
-            const uint32_t s_l = cnt[o_l];
-            const int m = min(64, n - i0);
-            int t_l = 0;                               // lane j: tour of position i0 + j
-            for (int j = 0; j < m; j++) {
-                const int32_t sz = __builtin_amdgcn_readlane((int)s_l, j);
-                int c = -1, k = 0;                     // group and lane of the tour found
-                uint64_t g = __ballot(gmax >= sz);     // none for an order larger than Q
-                while (g) {                            // uniform
-                    const int cg = __builtin_ctzll(g);
-                    const int32_t r = (int32_t)((R[cg >> 2] >> (8u * (uint32_t)(cg & 3))) & 0xFFu);
-                    const uint64_t f = __ballot(r >= sz);
-                    if (f) {
-                        c = cg;
-                        k = __builtin_ctzll(f);
-                        break;
-                    }
-                    const int32_t mx = wave_max_i32(r);        // the bound was stale
-                    if (lane == cg) gmax = mx;
-                    g &= g - 1;
-                }
-                int t;
-                if (c >= 0) {                          // the order joins tour 64c + k
-                    t = 64 * c + k;
-                    // every lane takes part (no divergent update of the register array)
-                    R[c >> 2] -= lane == k ? (uint32_t)sz << (8u * (uint32_t)(c & 3)) : 0u;
-                } else {                               // no open tour has room
-                    t = T;
-                    const int32_t r0 = sz <= Q ? Q - sz : 0;   // a larger order rides alone
-                    const int cn = T >> 6;
-                    R[cn >> 2] |= lane == (T & 63) ? (uint32_t)r0 << (8u * (uint32_t)(cn & 3)) : 0u;
-                    if (lane == cn) gmax = max(gmax, r0);
-                    T++;
-                }
-                t_l = lane == j ? t : t_l;
-            }
-            // read after the tile loop's barrier
-            if (i < n && o_l < (uint32_t)n) tour_of[o_l] = (uint16_t)t_l;
-        }
-
-        // ---- 3. tiles of tours -----------------------------------------------
-        int64_t acc = 0;
-        for (int t0 = 0; t0 < T; t0 += TILE) {
-            for (uint32_t k = lane; k < TILE * RW; k += 64) rows[k] = 0u;
-            __syncthreads();
-            if (ROUTE == WO_ROUTE_SSHAPE) {
-                // aisle sets and farthest locations, one order per lane from
-                // the groups of 64 orders of like size: an order outside the
-                // tile loads none of its lines
-                const uint32_t *grec = A.grec + I.grec_off;
-                const uint32_t *gbase = A.gbase + I.gbase_off;
-                const uint16_t *gord = A.gord + I.gord_off;
-                for (int g = 0; g < I.n_grp; g++) {
-                    const uint32_t o = gord[64 * g + lane];            // 0xFFFF: no order
-                    const uint32_t b0 = gbase[g];
-                    const uint32_t len = (gbase[g + 1] - b0) >> 6;     // lines of the group's longest order
-                    const uint32_t t = (o < (uint32_t)n ? (uint32_t)tour_of[o] : 0xFFFFu) - (uint32_t)t0;
-                    if (t >= (uint32_t)TILE) continue;
-                    uint32_t far = 0;
-                    for (uint32_t k = 0; k < len; k += 4) {
-                        uint32_t x[4];
-#pragma unroll
-                        for (int q = 0; q < 4; q++)                     // shorter orders repeat their first line
-                            x[q] = grec[b0 + 64u * min(k + (uint32_t)q, len - 1u) + (uint32_t)lane];
-#pragma unroll
-                        for (int q = 0; q < 4; q++) {
-                            const uint32_t ls = x[q] + zs[x[q] >> 26];
-                            const uint32_t a = mulhi24(ls, I.magic);
-                            atomicOr(&rows[t * RW + 1u + (a >> 5)], 1u << (a & 31u));
-                            far = max(far, ls);
-                        }
-                    }
-                    atomicMax(&rows[t * RW], far);
-                }
-            } else {
-                // pick rows: every line exactly once, from the instance's line
-                // records, which name their order by its entry in the
-                // next-fit kernel's tour table (the padding records name
-                // order n)
-                const uint32_t nf_tour = eval_layout(n, I.n_units, (uint32_t)I.row_b, I.t_cap, I.chase_log2,
-                                                     I.chase_lanes).tour;
-                const uint2 *lines = A.lines + I.line_off;
-                for (int r = lane; r < I.n_lines_pad; r += 64) {
-                    const uint2 rec = lines[r];
-                    const uint32_t o = ((rec.y & 0x7FFFFFFFu) - nf_tour) >> 1;
-                    const uint32_t t = (o < (uint32_t)n ? (uint32_t)tour_of[o] : 0xFFFFu) - (uint32_t)t0;
-                    if (t >= (uint32_t)TILE) continue;
-                    const uint32_t ls = rec.x + zs[rec.x >> 26];
-                    const uint32_t e = atomicAdd(&rows[t * RW], 1u);
-                    rows[t * RW + 1u + min(e, (uint32_t)I.pick_slots - 1u)] = ls;
-                }
-            }
-            __syncthreads();
-            for (int tt = lane; tt < TILE && t0 + tt < T; tt += 64) {
-                const uint32_t *rw = rows + (uint32_t)tt * RW;
-                if (ROUTE == WO_ROUTE_SSHAPE) {
-                    const uint32_t ls = rw[0];
-                    int k = 0;
-                    for (int w = 0; w < I.words; w++) k += __popc(rw[1 + w]);
-                    const uint32_t a = mulhi24(ls, I.magic);
-                    const int64_t y = (int64_t)((ls - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
-                    acc += 2ll * I.spacing * a + ((k & 1) ? (int64_t)(k - 1) * I.L + 2 * y : (int64_t)k * I.L);
-                } else {
-                    const uint32_t np = min(rw[0], (uint32_t)I.pick_slots);
-                    if (np == 0) continue;                  // only a malformed row leaves a tour empty
-                    uint32_t v[MAX_PICK_SLOTS];
-#pragma unroll
-                    for (int i = 0; i < MAX_PICK_SLOTS; i++) v[i] = (uint32_t)i < np ? rw[1 + i] : 0xFFFFFFFFu;
-                    sort32(v);
-                    acc += pick_route_cost<ROUTE>(v, np, I, I.magic);
-                }
-            }
-            __syncthreads();
-        }
-
-        // ---- 4. sum and rate -----------------------------------------------
-#pragma unroll
-        for (int d = 32; d >= 1; d >>= 1) acc += __shfl_xor(acc, d, 64);
-        if (A.validate && bad) atomicOr(A.err, 1);
-        if (lane == 0) {
-            A.dist[p] = acc > 2147483647ll ? 2147483647 : (int32_t)acc;
-            if (A.thr) A.thr[p] = window_throughput(acc, I);
-        }
-        __syncthreads();
-    }
-}
-
 template <int BLOCK, int ROUTE>
 static hipError_t launch_eval_t(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
 {
@@ -1217,55 +819,6 @@ static int max_blocks_r(int block, uint32_t lds_bytes)
     case 512: return max_blocks_t<512, ROUTE>(lds_bytes);
     }
     return 1;
-}
-
-template <int ROUTE>
-static hipError_t launch_eval_ff_r(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
-{
-    static uint32_t attr_bytes = 0;
-    if (lds_bytes > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)eval_ff_kernel<ROUTE>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
-        if (e != hipSuccess) {
-            (void)hipGetLastError();
-            return e;
-        }
-        attr_bytes = lds_bytes;
-    }
-    hipLaunchKernelGGL(eval_ff_kernel<ROUTE>, dim3(grid), dim3(64), lds_bytes, s, a);
-    return hipGetLastError();
-}
-
-hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, int route, hipStream_t s)
-{
-    switch (route) {
-    case WO_ROUTE_SSHAPE: return launch_eval_ff_r<WO_ROUTE_SSHAPE>(a, lds_bytes, grid, s);
-    case WO_ROUTE_RETURN: return launch_eval_ff_r<WO_ROUTE_RETURN>(a, lds_bytes, grid, s);
-    case WO_ROUTE_LARGEST_GAP: return launch_eval_ff_r<WO_ROUTE_LARGEST_GAP>(a, lds_bytes, grid, s);
-    case WO_ROUTE_OPTIMAL: return launch_eval_ff_r<WO_ROUTE_OPTIMAL>(a, lds_bytes, grid, s);
-    }
-    return hipErrorInvalidValue;
-}
-
-template <int ROUTE>
-static int ff_max_blocks_r(uint32_t lds_bytes)
-{
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, eval_ff_kernel<ROUTE>, 64, lds_bytes) != hipSuccess) {
-        (void)hipGetLastError();
-        return 1;
-    }
-    return n > 0 ? n : 1;
-}
-
-int eval_ff_max_blocks_per_cu(int route, uint32_t lds_bytes)
-{
-    switch (route) {
-    case WO_ROUTE_RETURN: return ff_max_blocks_r<WO_ROUTE_RETURN>(lds_bytes);
-    case WO_ROUTE_LARGEST_GAP: return ff_max_blocks_r<WO_ROUTE_LARGEST_GAP>(lds_bytes);
-    case WO_ROUTE_OPTIMAL: return ff_max_blocks_r<WO_ROUTE_OPTIMAL>(lds_bytes);
-    }
-    return ff_max_blocks_r<WO_ROUTE_SSHAPE>(lds_bytes);
 }
 
 int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes)
