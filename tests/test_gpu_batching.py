@@ -171,3 +171,45 @@ def test_repeat_calls_deterministic():
     d2, t2 = gpu_eval(wh, Z, S)
     wh.free()
     assert np.array_equal(d1, d2) and np.array_equal(t1, t2)
+
+
+def test_graph_capture_replays():
+    # first fit allocates nothing per call: a captured evaluation replays exactly
+    import torch
+    wo = _wo()
+    rng = np.random.default_rng(47)
+    insts = [_ff(_random_instance(rng, a, 250, o, 30, 64)) for a, o in [(8, 50), (400, 4000), (37, 700)]]
+    per = 6
+    Zs, Ss = [], []
+    for inst in insts:
+        Z, S = synth.make_plans(inst, per, seed=int(rng.integers(1 << 30)))
+        Zs.append(Z)
+        Ss.append(S.reshape(-1))
+    offs = np.arange(len(insts) + 1, dtype=np.int64) * per
+    wh = wo.wo_load_warehouse(insts)
+    z = torch.from_numpy(np.concatenate(Zs)).cuda()
+    s = torch.from_numpy(np.concatenate(Ss).view(np.int16)).cuda()
+    n = z.shape[0]
+    d_eager, t_eager = gpu_eval(wh, np.concatenate(Zs), np.concatenate(Ss), plan_offsets=offs)
+    d = torch.zeros(n, dtype=torch.int32, device="cuda")
+    t = torch.zeros(n, dtype=torch.float32, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):
+        wo.wo_eval_plans(wh, z, s, d, t, plan_offsets=offs)   # warm-up on the capture stream
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        wo.wo_eval_plans(wh, z, s, d, t, plan_offsets=offs)
+    for rep in range(4):
+        d.zero_()
+        t.zero_()
+        d2, _ = gpu_eval(wh, np.concatenate(Zs), np.concatenate(Ss), plan_offsets=offs)   # eager work between
+        assert np.array_equal(d2, d_eager)
+        g.replay()
+        torch.cuda.synchronize()
+        assert np.array_equal(d.cpu().numpy(), d_eager), rep
+        assert np.array_equal(t.cpu().numpy(), t_eager), rep
+    del g
+    wh.free()

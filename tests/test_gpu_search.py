@@ -37,11 +37,15 @@ def _population(wo, s, P, n, keep=0):
     return out + ((k.cpu().numpy(),) if keep else ())
 
 
-@pytest.mark.parametrize("workload,P", [("tiny", 64), ("paper", 16)])
-def test_plain_generations_match_cpu(workload, P):
+@pytest.mark.parametrize("workload,P,variant", [("tiny", 64, {}), ("paper", 16, {}),
+                                                ("tiny", 64, {"batching": 1}), ("tiny", 64, {"routing": 3}),
+                                                ("paper", 16, {"batching": 1, "routing": 2})])
+def test_plain_generations_match_cpu(workload, P, variant):
+    import dataclasses
     import torch
     wo = _wo()
     inst, _, _ = synth.workload(workload, n_plans=1)
+    inst = dataclasses.replace(inst, **variant)     # the search evaluates under the load's rules
     Z, S = _init(inst, P, 3)
     wh = wo.wo_load_warehouse([inst])
     seed = 1234
