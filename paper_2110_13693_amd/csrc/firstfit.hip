@@ -106,24 +106,30 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
             // min(size, Q + 1); 0 for an id out of range, which then joins
             // some tour without taking room and is left out below
             const uint32_t s_l = cnt[o_l];
-            const int m = min(64, n - i0);
+            const int m = __builtin_amdgcn_readfirstlane(min(64, n - i0));   // uniform: a scalar loop bound
             int t_l = 0;                               // lane j: tour of position i0 + j
             for (int j = 0; j < m; j++) {
                 const int32_t sz = __builtin_amdgcn_readlane((int)s_l, j);
                 int c = -1, k = 0;                     // group and lane of the tour found
                 uint64_t g = __ballot(gmax >= sz);     // none for an order larger than Q
-                while (g) {                            // uniform
-                    const int cg = __builtin_ctzll(g);
-                    const int32_t r = (int32_t)((R[cg >> 2] >> (8u * (uint32_t)(cg & 3))) & 0xFFu);
-                    const uint64_t f = __ballot(r >= sz);
+                if (g) {
+                    // the first group whose bound admits the order: usually it has room
+                    int cg = __builtin_ctzll(g);
+                    int32_t r = (int32_t)((R[cg >> 2] >> (8u * (uint32_t)(cg & 3))) & 0xFFu);
+                    uint64_t f = __ballot(r >= sz);
+                    while (!f) {                       // the bound was stale (uniform)
+                        const int32_t mx = wave_max_i32(r);
+                        if (lane == cg) gmax = mx;
+                        g &= g - 1;
+                        if (!g) break;
+                        cg = __builtin_ctzll(g);
+                        r = (int32_t)((R[cg >> 2] >> (8u * (uint32_t)(cg & 3))) & 0xFFu);
+                        f = __ballot(r >= sz);
+                    }
                     if (f) {
                         c = cg;
                         k = __builtin_ctzll(f);
-                        break;
                     }
-                    const int32_t mx = wave_max_i32(r);        // the bound was stale
-                    if (lane == cg) gmax = mx;
-                    g &= g - 1;
                 }
                 int t;
                 if (c >= 0) {                          // the order joins tour 64c + k
