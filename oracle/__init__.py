@@ -5,7 +5,7 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 its binding) never does, and this package never imports the product path.
 
 ``wo_oracle.c`` is the plain sequential evaluator (slot map, next-fit tours,
-S-shape, return, largest-gap or optimal route distance, time-window throughput);
+S-shape, return, largest-gap, combined or optimal route distance, time-window throughput);
 ``surrogate.py`` is the float64
 reference of the surrogate network; ``search.py`` re-implements one step of the
 genetic search on the CPU; ``kmeans.py`` is the exact K-means class-based
@@ -41,7 +41,7 @@ class _Inst(ctypes.Structure):
         ("window_s", ctypes.c_double), ("routing", ctypes.c_int32), ("batching", ctypes.c_int32),
     ]
 
-ROUTE_SSHAPE, ROUTE_RETURN, ROUTE_LARGEST_GAP, ROUTE_OPTIMAL = 0, 1, 2, 3
+ROUTE_SSHAPE, ROUTE_RETURN, ROUTE_LARGEST_GAP, ROUTE_OPTIMAL, ROUTE_COMBINED = 0, 1, 2, 3, 4
 BATCH_NEXT_FIT, BATCH_FIRST_FIT = 0, 1
 
 
@@ -69,7 +69,8 @@ def _load():
         lib.orc_tours_first_fit.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_sshape_cost.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_int32]
         lib.orc_sshape_cost.restype = ctypes.c_int64
-        for f in (lib.orc_return_cost, lib.orc_largest_gap_cost, lib.orc_optimal_cost, lib.orc_tour_cost):
+        for f in (lib.orc_return_cost, lib.orc_largest_gap_cost, lib.orc_optimal_cost, lib.orc_combined_cost,
+                  lib.orc_tour_cost):
             f.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_int32]
             f.restype = ctypes.c_int64
         lib.orc_eval_plan.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p,
@@ -166,6 +167,13 @@ def optimal_cost(inst, locs) -> int:
     b = _Bound(inst)
     l = _c(locs, np.int32)
     return int(_load().orc_optimal_cost(b.ref(), l.ctypes.data, l.size))
+
+
+def combined_cost(inst, locs) -> int:
+    """Combined-route length (dm) of one tour given its pick locations."""
+    b = _Bound(inst)
+    l = _c(locs, np.int32)
+    return int(_load().orc_combined_cost(b.ref(), l.ctypes.data, l.size))
 
 
 def tour_cost(inst, locs) -> int:

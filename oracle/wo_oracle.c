@@ -43,6 +43,10 @@
  *        front to first pick, between adjacent picks, last pick to back;
  *        cost = 2 * spacing * a_max + 2 * L + sum over the inner aisles of
  *        2 * (L - gap); with a single aisle it is the return route;
+ *      - combined: every aisle holding a pick is visited once, in ascending
+ *        order, and either crossed to the other cross aisle or entered and
+ *        left from the cross aisle the picker is on, whichever choice makes
+ *        the whole walk shortest (orc_combined_cost below);
  *      - optimal: the shortest closed walk from the depot through every pick
  *        (the paper's minimum route distance), by a dynamic programme over the
  *        aisles (orc_optimal_cost below states it);
@@ -75,7 +79,8 @@ typedef struct {
     int32_t batching;              /* ORC_BATCH_* */
 } orc_instance;
 
-enum { ORC_ROUTE_SSHAPE = 0, ORC_ROUTE_RETURN = 1, ORC_ROUTE_LARGEST_GAP = 2, ORC_ROUTE_OPTIMAL = 3 };
+enum { ORC_ROUTE_SSHAPE = 0, ORC_ROUTE_RETURN = 1, ORC_ROUTE_LARGEST_GAP = 2, ORC_ROUTE_OPTIMAL = 3,
+       ORC_ROUTE_COMBINED = 4 };
 enum { ORC_BATCH_NEXT_FIT = 0, ORC_BATCH_FIRST_FIT = 1 };
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_NOMEM = 3 };
@@ -437,12 +442,61 @@ int64_t orc_optimal_cost(const orc_instance *w, const int32_t *locs, int32_t n)
     return best;
 }
 
+/* Combined route (the combined heuristic of the routing literature the paper
+ * builds on, which mixes S-shape crossings and return visits).  Reading: the
+ * picker starts at the depot on the front cross aisle and visits the aisles
+ * holding picks once each, in ascending order, moving along the cross aisle it
+ * is on; in each it either crosses the aisle (L, ending on the other cross
+ * aisle) or goes in from its own cross aisle to the farthest pick and back
+ * (2 y_max from the front, 2 (L - y_min) from the back).  After the last aisle
+ * it returns to the depot along the front, first crossing the last aisle if
+ * it is on the back.  The choices are made by a programme over the aisles
+ * with one state per cross aisle; S-shape and return are two of the choices,
+ * so the route is never longer than either. */
+int64_t orc_combined_cost(const orc_instance *w, const int32_t *locs, int32_t n)
+{
+    const int64_t L = (int64_t)w->slots_per_side * w->pitch_dm;
+    const int64_t sp = w->spacing_dm;
+    int64_t front = 0, back = -1;          /* best length so far ending on each cross aisle (-1: none) */
+    int32_t i, first, prev = 0;
+    orc_pick *pk;
+    if (n <= 0) return 0;
+    pk = orc_sorted_picks(w, locs, n);
+    if (!pk) return -1;
+    for (first = 0; first < n; first = i) {
+        int32_t a = pk[first].a;
+        int64_t ylo = pk[first].y, yhi, f2, b2, step;
+        for (i = first; i < n && pk[i].a == a; i++) {}
+        yhi = pk[i - 1].y;
+        step = sp * (a - prev);
+        prev = a;
+        /* arrive along the same cross aisle, then return or cross */
+        f2 = front + step + 2 * yhi;                            /* front, return */
+        b2 = front + step + L;                                  /* front, crossed */
+        if (back >= 0) {
+            int64_t bb = back + step + 2 * (L - ylo);           /* back, return */
+            int64_t bf = back + step + L;                       /* back, crossed */
+            if (bb < b2) b2 = bb;
+            if (bf < f2) f2 = bf;
+        }
+        front = f2;
+        back = b2;
+    }
+    free(pk);
+    /* home along the front; from the back, cross the last aisle first */
+    {
+        int64_t home_f = front + sp * prev, home_b = back + L + sp * prev;
+        return home_f < home_b ? home_f : home_b;
+    }
+}
+
 int64_t orc_tour_cost(const orc_instance *w, const int32_t *locs, int32_t n)
 {
     switch (w->routing) {
     case ORC_ROUTE_RETURN: return orc_return_cost(w, locs, n);
     case ORC_ROUTE_LARGEST_GAP: return orc_largest_gap_cost(w, locs, n);
     case ORC_ROUTE_OPTIMAL: return orc_optimal_cost(w, locs, n);
+    case ORC_ROUTE_COMBINED: return orc_combined_cost(w, locs, n);
     default: return orc_sshape_cost(w, locs, n);
     }
 }
@@ -515,7 +569,7 @@ static int orc_check_instance(const orc_instance *w)
     int32_t o, l;
     if (w->n_aisles < 1 || w->slots_per_side < 1 || w->pitch_dm < 2 || (w->pitch_dm & 1) ||
         w->spacing_dm < 0 || w->capacity < 1 || w->n_orders < 1 || w->n_orders > 65535 ||
-        w->routing < ORC_ROUTE_SSHAPE || w->routing > ORC_ROUTE_OPTIMAL ||
+        w->routing < ORC_ROUTE_SSHAPE || w->routing > ORC_ROUTE_COMBINED ||
         w->batching < ORC_BATCH_NEXT_FIT || w->batching > ORC_BATCH_FIRST_FIT)
         return ORC_E_INVAL;
     if (w->order_offsets[0] != 0) return ORC_E_INVAL;

@@ -15,8 +15,8 @@ import numpy as np
 import pytest
 
 import oracle
-from tests.whelpers import (aisle_graph_dijkstra, largest_gap_walk, optimal_tour_length, point,
-                            return_walk, sshape_walk, tiny_geometry)
+from tests.whelpers import (aisle_graph_dijkstra, combined_walks, largest_gap_walk, optimal_tour_length,
+                            point, return_walk, sshape_walk, tiny_geometry)
 
 
 def closed_form_distance(inst, p, q):
@@ -169,7 +169,7 @@ def test_routing_field_selects_the_tour_cost():
     base = tiny_geometry([[0]], n_aisles=10)
     locs = [0, 130, 599]
     for routing, f in ((0, oracle.sshape_cost), (1, oracle.return_cost), (2, oracle.largest_gap_cost),
-                       (3, oracle.optimal_cost)):
+                       (3, oracle.optimal_cost), (4, oracle.combined_cost)):
         inst = dataclasses.replace(base, routing=routing)
         assert oracle.tour_cost(inst, locs) == f(base, locs)
 
@@ -243,3 +243,36 @@ def test_optimal_invariant_under_pick_order_and_duplicates(seed):
     # a pick on the other side of the same aisle position is the same point
     twin = [l ^ 1 for l in locs]
     assert oracle.optimal_cost(inst, twin) == base
+
+
+# ----------------------------------------------------------- combined route
+@pytest.mark.parametrize("geom", range(len(OPT_GEOMETRIES)))
+@pytest.mark.parametrize("seed", range(10))
+def test_combined_equals_best_enumerated_walk(geom, seed):
+    # the two-state programme against every crossing choice walked out
+    inst = tiny_geometry([[0]], **OPT_GEOMETRIES[geom])
+    rng = np.random.default_rng(11000 + 100 * geom + seed)
+    for _ in range(5):
+        locs = _random_tour(rng, inst, int(rng.integers(1, 12)))
+        pts = [point(inst, l) for l in locs]
+        walks = combined_walks(inst, pts)
+        assert all(ok for _, ok in walks)
+        assert oracle.combined_cost(inst, locs) == min(length for length, _ in walks), locs
+
+
+@pytest.mark.parametrize("seed", range(30))
+def test_combined_between_optimum_and_sshape_return(seed):
+    rng = np.random.default_rng(12000 + seed)
+    inst = tiny_geometry([[0]], n_aisles=400, slots=250, n_cat=1, cat_size=1)
+    locs = _random_tour(rng, inst, int(rng.integers(1, 31)))
+    c = oracle.combined_cost(inst, locs)
+    assert c <= min(oracle.sshape_cost(inst, locs), oracle.return_cost(inst, locs))
+    assert c >= oracle.optimal_cost(inst, locs)
+
+
+def test_combined_hand_example():
+    inst = tiny_geometry([[0]], n_aisles=10)       # L = 300 dm, aisles 30 dm apart
+    # (0,5),(2,55),(9,295): return everywhere is 2*30*9 + 2*(5 + 55 + 295) = 1250; crossing
+    # aisles 0 and 9 and returning in aisle 2 from the back costs 2*30*9 + 2*300 + 2*(300 - 55)
+    # = 1630; crossing 2 and 9 and returning in 0: 540 + 10 + 600 = 1150 -- the best
+    assert oracle.combined_cost(inst, [0, 130, 599]) == 1150

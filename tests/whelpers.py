@@ -208,3 +208,42 @@ def largest_gap_walk(inst, points):
         length += 2 * lo
         cover(a, 0, lo)
     return length + x * w, covered
+
+
+def combined_walks(inst, points):
+    """Every walk of the combined policy, by brute force over the crossing
+    choices: aisles holding picks are visited in ascending order along the
+    cross aisle the picker is on; each is crossed, or entered from that cross
+    aisle to its farthest pick (from the front: the deepest; from the back:
+    the shallowest) and left the same way; from the back the picker ends by
+    crossing the last aisle, then walks home along the front.  Returns the
+    list of (length, every pick passed) over all 2^k choices."""
+    import itertools as it
+    L = inst.slots_per_side * inst.pitch_dm
+    w = inst.spacing_dm
+    aisles = sorted({a for a, _ in points})
+    out = []
+    for choice in it.product((0, 1), repeat=len(aisles)):   # 1: cross
+        x, back, length = 0, False, 0
+        covered = [False] * len(points)
+        for a, cross in zip(aisles, choice):
+            length += abs(a * w - x)
+            x = a * w
+            ys = [py for pa, py in points if pa == a]
+            if cross:
+                length += L
+                back = not back
+                lo, hi = 0, L
+            elif not back:
+                length += 2 * max(ys)
+                lo, hi = 0, max(ys)
+            else:
+                length += 2 * (L - min(ys))
+                lo, hi = min(ys), L
+            for i, (pa, py) in enumerate(points):
+                if pa == a and lo <= py <= hi:
+                    covered[i] = True
+        if back:
+            length += L
+        out.append((length + x, all(covered)))
+    return out
