@@ -32,8 +32,8 @@ if ROOT not in sys.path:
 
 # MI355X: 256 CUs x 64 lanes x 2.4 GHz, one 32-bit integer op per lane per clock
 INT_VALU_PEAK_OPS = 256 * 64 * 2.4e9
-# route of every tour: S-shape (the headline), return, largest gap, optimal
-ROUTES = {"sshape": 0, "return": 1, "largest-gap": 2, "optimal": 3}
+# route of every tour: S-shape (the headline), return, largest gap, optimal, combined
+ROUTES = {"sshape": 0, "return": 1, "largest-gap": 2, "optimal": 3, "combined": 4}
 BATCHINGS = {"next-fit": 0, "first-fit": 1}
 HBM_PEAK_BYTES = 8.0e12
 

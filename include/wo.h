@@ -116,15 +116,21 @@ typedef struct {
  *                        each time up to its largest gap (front to first pick,
  *                        between picks, last pick to back) and back; a single
  *                        aisle is a return route;
+ *   WO_ROUTE_COMBINED    every aisle with a pick is visited once, in ascending
+ *                        order, and either crossed or entered and left from
+ *                        the cross aisle the picker is on, the choices that
+ *                        make the walk shortest; the walk ends on the front
+ *                        (crossing the last aisle if it is on the back);
  *   WO_ROUTE_OPTIMAL     the shortest closed walk from the depot through every
  *                        pick (the minimum route distance of the same passage),
  *                        exact for the single-block layout.
- * Return, largest gap and optimal keep every pick of a tour in LDS: a tour may
+ * The routes other than S-shape keep every pick of a tour in LDS: a tour may
  * hold at most WO_MAX_PICK_SLOTS lines (capacity, and any single order), else
  * wo_load_warehouse fails with WO_E_UNSUPPORTED.  The optimal route computes
  * in 32-bit integers: 4 * spacing * (n_aisles + 2) + 4 * L * (n_aisles + 1)
  * must stay below 2^30 dm, else the load fails with WO_E_RANGE. */
-enum { WO_ROUTE_SSHAPE = 0, WO_ROUTE_RETURN = 1, WO_ROUTE_LARGEST_GAP = 2, WO_ROUTE_OPTIMAL = 3 };
+enum { WO_ROUTE_SSHAPE = 0, WO_ROUTE_RETURN = 1, WO_ROUTE_LARGEST_GAP = 2, WO_ROUTE_OPTIMAL = 3,
+       WO_ROUTE_COMBINED = 4 };
 
 /* Batching of orders into tours (the paper cuts the order sequence greedily
  * into capacity-bounded tours, section 5, Subproblem 2 and section 6; these

@@ -35,8 +35,8 @@
 //   6. per tour: k = popcount of the aisle set, S-shape closed form; the
 //      block sums the tours in int64.
 // Tours beyond one tile of rows are handled in further passes over the lines.
-// The return, largest-gap and optimal routes (ROUTE = 1, 2, 3) share steps
-// 1-4; their rows hold each tour's picks instead (step 5 appends the line's
+// The return, largest-gap, optimal and combined routes (ROUTE = 1 .. 4)
+// share steps 1-4; their rows hold each tour's picks instead (step 5 appends the line's
 // scaled location), and step 6 sorts a tour's picks by (aisle, depth) and
 // walks them once (eval_device.h).  First-fit batching has a kernel of its
 // own (firstfit.hip).
@@ -827,6 +827,7 @@ int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes)
     case WO_ROUTE_RETURN: return max_blocks_r<WO_ROUTE_RETURN>(block, lds_bytes);
     case WO_ROUTE_LARGEST_GAP: return max_blocks_r<WO_ROUTE_LARGEST_GAP>(block, lds_bytes);
     case WO_ROUTE_OPTIMAL: return max_blocks_r<WO_ROUTE_OPTIMAL>(block, lds_bytes);
+    case WO_ROUTE_COMBINED: return max_blocks_r<WO_ROUTE_COMBINED>(block, lds_bytes);
     }
     return max_blocks_r<WO_ROUTE_SSHAPE>(block, lds_bytes);
 }
@@ -850,6 +851,7 @@ hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int bloc
     case WO_ROUTE_RETURN: return launch_eval_r<WO_ROUTE_RETURN>(a, lds_bytes, grid, block, s);
     case WO_ROUTE_LARGEST_GAP: return launch_eval_r<WO_ROUTE_LARGEST_GAP>(a, lds_bytes, grid, block, s);
     case WO_ROUTE_OPTIMAL: return launch_eval_r<WO_ROUTE_OPTIMAL>(a, lds_bytes, grid, block, s);
+    case WO_ROUTE_COMBINED: return launch_eval_r<WO_ROUTE_COMBINED>(a, lds_bytes, grid, block, s);
     }
     return hipErrorInvalidValue;
 }

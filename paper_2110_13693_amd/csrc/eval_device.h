@@ -111,7 +111,7 @@ static __device__ __forceinline__ void opt_aisle(OptClasses &s, int32_t L, int32
     s = n;
 }
 
-// Return, largest-gap or optimal route of one tour from its np >= 1 picks,
+// Return, largest-gap, combined or optimal route of one tour from its np >= 1 picks,
 // sorted by scaled location, i.e. by aisle and then depth (section 5,
 // Subproblem 2).
 template <int ROUTE>
@@ -150,6 +150,37 @@ static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MA
         if (ca != done) opt_run(s, (int32_t)(ca - done), I.spacing, L);
         opt_aisle(s, L, 2 * yhi, 2 * (L - ylo), gap >= 0 ? 2 * (L - gap) : 2 * L);
         return (int64_t)min(min(s.f, s.b), s.e1);     // even ends, one component
+    }
+    if (ROUTE == WO_ROUTE_COMBINED) {
+        // each aisle with picks crossed or entered and left from the cross
+        // aisle the picker is on, best choice by one length per cross aisle;
+        // the walk ends on the front (crossing the last aisle from the back)
+        const int64_t W = I.spacing, L2 = 2ll * L;
+        int64_t front = 0, back = (int64_t)1 << 60;   // the back is not reachable yet
+        uint32_t done = 0;
+        int32_t ylo = 0, yhi = 0;
+#pragma unroll
+        for (int i = 0; i < MAX_PICK_SLOTS; i++) {
+            if ((uint32_t)i < np) {
+                const uint32_t a = mulhi24(v[i], magic);
+                const int32_t y = (int32_t)((v[i] - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
+                if (i == 0) {
+                    ylo = y;
+                } else if (a != ca) {                 // aisle ca is complete
+                    const int64_t step = W * (int64_t)(ca - done);
+                    const int64_t f2 = min(front + 2ll * yhi, back + L), b2 = min(front + L, back + L2 - 2ll * ylo);
+                    front = f2 + step;
+                    back = b2 + step;
+                    done = ca;
+                    ca = a;
+                    ylo = y;
+                }
+                yhi = y;
+            }
+        }
+        const int64_t step = W * (int64_t)(ca - done);
+        const int64_t f2 = min(front + 2ll * yhi, back + L), b2 = min(front + L, back + L2 - 2ll * ylo);
+        return min(f2, b2 + L) + step + W * (int64_t)ca;
     }
     int32_t py = 0;                                   // previous depth in the aisle (front: 0)
     int32_t g = 0;                                    // largest gap so far in the aisle

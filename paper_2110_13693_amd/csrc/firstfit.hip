@@ -261,6 +261,7 @@ hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, int r
     case WO_ROUTE_RETURN: return launch_eval_ff_r<WO_ROUTE_RETURN>(a, lds_bytes, grid, s);
     case WO_ROUTE_LARGEST_GAP: return launch_eval_ff_r<WO_ROUTE_LARGEST_GAP>(a, lds_bytes, grid, s);
     case WO_ROUTE_OPTIMAL: return launch_eval_ff_r<WO_ROUTE_OPTIMAL>(a, lds_bytes, grid, s);
+    case WO_ROUTE_COMBINED: return launch_eval_ff_r<WO_ROUTE_COMBINED>(a, lds_bytes, grid, s);
     }
     return hipErrorInvalidValue;
 }
@@ -282,6 +283,7 @@ int eval_ff_max_blocks_per_cu(int route, uint32_t lds_bytes)
     case WO_ROUTE_RETURN: return ff_max_blocks_r<WO_ROUTE_RETURN>(lds_bytes);
     case WO_ROUTE_LARGEST_GAP: return ff_max_blocks_r<WO_ROUTE_LARGEST_GAP>(lds_bytes);
     case WO_ROUTE_OPTIMAL: return ff_max_blocks_r<WO_ROUTE_OPTIMAL>(lds_bytes);
+    case WO_ROUTE_COMBINED: return ff_max_blocks_r<WO_ROUTE_COMBINED>(lds_bytes);
     }
     return ff_max_blocks_r<WO_ROUTE_SSHAPE>(lds_bytes);
 }

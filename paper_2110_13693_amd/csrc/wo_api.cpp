@@ -172,7 +172,7 @@ static wo_status check_desc(const wo_instance_desc &d, int idx)
         return fail(WO_E_INVAL, "instance %d: slot pitch must be even and >= 2 (got %d)", idx, d.pitch_dm);
     if (d.spacing_dm < 0) return fail(WO_E_INVAL, "instance %d: negative aisle spacing", idx);
     if (d.capacity < 1) return fail(WO_E_INVAL, "instance %d: capacity must be >= 1", idx);
-    if (d.routing < WO_ROUTE_SSHAPE || d.routing > WO_ROUTE_OPTIMAL)
+    if (d.routing < WO_ROUTE_SSHAPE || d.routing > WO_ROUTE_COMBINED)
         return fail(WO_E_INVAL, "instance %d: unknown routing %d", idx, d.routing);
     if (d.batching < WO_BATCH_NEXT_FIT || d.batching > WO_BATCH_FIRST_FIT)
         return fail(WO_E_INVAL, "instance %d: unknown batching %d", idx, d.batching);

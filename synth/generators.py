@@ -64,7 +64,7 @@ class Instance:
     walk_dm_per_s: float = 12.0
     seconds_per_item: float = 10.0
     window_s: float = 28800.0
-    routing: int = 0          # 0 S-shape, 1 return, 2 largest gap, 3 optimal
+    routing: int = 0          # 0 S-shape, 1 return, 2 largest gap, 3 optimal, 4 combined
     batching: int = 0         # 0 next fit, 1 first fit
 
     @property

@@ -77,7 +77,7 @@ def _mod(inst, **kw):
     ("capacity", 33, 2),            # above the supported capacity
     ("n_categories", 65, 2),        # more than 64 categories
     ("n_aisles", 1, 2),             # 600 SKUs no longer fit 60 locations
-    ("routing", 4, 1),              # unknown route
+    ("routing", 5, 1),              # unknown route
     ("routing", -1, 1),
     ("batching", 2, 1),             # unknown batching rule
     ("batching", -1, 1),

@@ -14,7 +14,7 @@ from tests.test_gpu_eval import THR_RTOL, _random_instance, _structured_sequence
 pytestmark = pytest.mark.gpu
 
 
-ROUTES = [0, 1, 2, 3]    # S-shape, return, largest gap, optimal
+ROUTES = [0, 1, 2, 3, 4]    # S-shape, return, largest gap, optimal, combined
 
 
 def _ff(inst, routing=None):
@@ -96,7 +96,7 @@ ROUTED_CASES = [
 ]
 
 
-@pytest.mark.parametrize("routing", [1, 2, 3])
+@pytest.mark.parametrize("routing", [1, 2, 3, 4])
 @pytest.mark.parametrize("case", ROUTED_CASES, ids=lambda c: "N%d_S%d_n%d_Q%d_C%d" % c[:5])
 def test_routed_edge_cases(case, routing):
     rng = np.random.default_rng(abs(hash(case)) % (1 << 31))

@@ -1,4 +1,4 @@
-"""GPU parity of the return, largest-gap and optimal routes against the CPU
+"""GPU parity of the return, largest-gap, optimal and combined routes against the CPU
 oracle (through the C ABI).  Distances must match bit-exactly; the throughput to
 1e-6 relative, as for the S-shape route."""
 import dataclasses
@@ -12,7 +12,7 @@ from tests.test_gpu_eval import _compare, _random_instance, _structured_sequence
 
 pytestmark = pytest.mark.gpu
 
-ROUTES = [1, 2, 3]       # return, largest gap, optimal
+ROUTES = [1, 2, 3, 4]    # return, largest gap, optimal, combined
 
 
 def _routed(inst, routing):
@@ -64,7 +64,7 @@ def test_structured_sequences_routed(routing):
     _compare(inst, Z, S)
 
 
-@pytest.mark.parametrize("routing", [2, 3])
+@pytest.mark.parametrize("routing", [2, 3, 4])
 def test_batched_routed_instances_match_single(routing):
     import torch
     wo = _wo()
