@@ -48,6 +48,17 @@ def test_random_histories(seed):
     _compare(skus, n_skus, int(rng.integers(1, 65)))
 
 
+def test_largest_history():
+    # 2^24 lines (the most a call takes) over 2^22 SKUs: 16,777,217 histogram
+    # bins, centroid sums near 2^24 and counts near 2^22, so the distance
+    # products reach 2^68 and need the 128-bit comparison
+    rng = np.random.default_rng(9)
+    n_skus = 1 << 22
+    skus = (rng.zipf(1.3, size=1 << 24) - 1) % n_skus
+    print("largest history", flush=True)
+    _compare(skus, n_skus, 64, max_iter=40)
+
+
 def test_max_iter_stops_early():
     rng = np.random.default_rng(7)
     skus = rng.integers(0, 3000, size=100000) ** 2 // 3000

@@ -33,6 +33,19 @@ def test_paper_scale_sample(routing):
     _compare(_routed(inst, routing), Z, S)
 
 
+def test_optimal_route_near_its_32_bit_bound():
+    # slots 2,000 dm apart: L = 500,000 dm and 4 L (N + 1) + 4 w (N + 2) = 8.0e8 dm,
+    # close to the 2^30 the load allows; the programme's sums stay exact
+    import synth as sy
+    inst = sy.make_instance(n_aisles=400, slots_per_side=250, pitch_dm=2000, spacing_dm=30, capacity=30,
+                            n_categories=64, n_skus=150000, category_mode="dirichlet", n_orders=4000,
+                            lines_lambda=1.5, zipf_s=1.1, seed=17)
+    Z, S = sy.make_plans(inst, 24, seed=18)
+    for routing in (3, 4):
+        print("large geometry", routing, flush=True)
+        _compare(_routed(inst, routing), Z, S)
+
+
 ROUTE_CASES = [
     # (aisles, slots, orders, capacity, categories, lambda)
     (1, 5, 7, 3, 3, 2.0),          # one aisle: every tour is a return route
