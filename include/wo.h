@@ -248,7 +248,8 @@ wo_status wo_get_eval_config(const wo_wh *wh, wo_eval_config *cfg);
  * configuration (best of `reps` runs each, after a warm-up), keeps the
  * fastest in the handle and returns it in best_out.  h_all (nullable)
  * receives up to *n_all timed configurations; *n_all is set to how many
- * were timed.  Synchronous; overwrites d_dist. */
+ * were timed.  Synchronous; overwrites d_dist.  A first-fit handle has one
+ * launch shape: its current configuration is timed once and kept. */
 wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans, const uint8_t *d_zone_of,
                            const uint16_t *d_order_seq, int32_t *d_dist, int32_t reps, void *stream,
                            wo_eval_config *best_out, wo_eval_config *h_all, int32_t *n_all);

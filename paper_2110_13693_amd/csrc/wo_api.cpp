@@ -840,7 +840,10 @@ extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, in
     };
     const int blocks[4] = {64, 128, 256, 512};
     const int per_cus[8] = {1, 2, 3, 4, 6, 8, 12, 16};
-    for (int bi = 0; bi < 4 && !st; bi++) {
+    // first fit has one launch shape: time it once and keep the configuration
+    const int n_blocks = wh->batching == WO_BATCH_FIRST_FIT ? 0 : 4;
+    if (n_blocks == 0) st = time_cfg(saved);
+    for (int bi = 0; bi < n_blocks && !st; bi++) {
         for (int pi = 0; pi < 8 && !st; pi++) {
             const int blk = blocks[bi], pc = per_cus[pi];
             if (pc > eval_max_blocks_per_cu(blk, wh->route, wh->lds_max)) continue;      // registers and LDS
@@ -852,7 +855,7 @@ extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, in
     }
     // the small-instance launch on and off, with the best configuration
     bool any_small = false;
-    for (int32_t i = 0; i < wh->n_inst; i++) any_small |= wh->inst[i].n_orders <= 1024;
+    for (int32_t i = 0; i < wh->n_inst && n_blocks; i++) any_small |= wh->inst[i].n_orders <= 1024;
     if (!st && any_small) {
         wo_eval_config c = best;
         c.small_orders = saved.small_orders > 0 ? 0 : 1024;

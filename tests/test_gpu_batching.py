@@ -213,3 +213,18 @@ def test_graph_capture_replays():
         assert np.array_equal(t.cpu().numpy(), t_eager), rep
     del g
     wh.free()
+
+
+def test_autotune_times_first_fit_once():
+    import torch
+    wo = _wo()
+    inst, Z, S = synth.workload("paper", n_plans=256)
+    wh = wo.wo_load_warehouse([_ff(inst)])
+    z = torch.from_numpy(Z).cuda()
+    s = torch.from_numpy(S.view(np.int16)).cuda().reshape(-1)
+    d = torch.empty(256, dtype=torch.int32, device="cuda")
+    best, all_cfgs = wo.wo_autotune_eval(wh, z, s, d, reps=2)
+    assert len(all_cfgs) == 1 and best["ms"] > 0
+    d_gpu, _ = gpu_eval(wh, Z, S)
+    wh.free()
+    assert np.array_equal(d_gpu, oracle.eval_plans(_ff(inst), Z, S)[0])
