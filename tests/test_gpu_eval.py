@@ -90,6 +90,8 @@ EDGE_CASES = [
     (400, 250, 12000, 3, 64, 1.5),    # oversize orders (serial chain), several tiles, sequence in memory
     (100, 250, 40000, 30, 8, 0.0),    # 40,000 single-line orders: near the LDS limit, tiles halved
     (100, 250, 6000, 2, 8, 0.0),      # single-line orders at capacity 2: 64 chase segments
+    (2000, 100, 2000, 30, 64, 1.5),   # 2,000 aisles: 63-word aisle sets
+    (4096, 512, 3000, 20, 64, 1.5),   # the most locations a warehouse may have (2^22)
 ]
 
 

@@ -55,6 +55,7 @@ ROUTE_CASES = [
     (400, 250, 6000, 30, 64, 1.5), # sequence in memory
     (60, 2, 500, 12, 16, 1.5),     # aisles 20 dm long, 30 dm apart: loops over empty aisles pay
     (300, 1, 400, 8, 8, 1.0),      # aisles 10 dm long, long runs without picks
+    (2000, 100, 2000, 30, 64, 1.5),   # 2,000 aisles: long runs between aisles with picks
 ]
 
 
