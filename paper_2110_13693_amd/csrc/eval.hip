@@ -275,6 +275,12 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
         }
         if (tid < 16) misc[tid] = 0;
 
+        // The phases up to the tour numbering are chains of dependent steps
+        // and barriers; the aisle pass is throughput work.  Waves in the
+        // former issue first, so that a CU's workgroups in their aisle pass
+        // fill the gaps of those in the serial phases rather than delay them.
+        __builtin_amdgcn_s_setprio(2);
+
         // ---- 1. zone starts (wave 0) -------------------------------------
         if (tid < 64) {
             const uint32_t zc = have_pf ? zc_pf : ((lane < C) ? (uint32_t)A.zone_of[p * 64 + lane] : 0xFFu);
@@ -602,6 +608,8 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
                 }
             }
 
+            __builtin_amdgcn_s_setprio(0);
+
             // ---- 5./6. aisle sets and S-shape per tour tile ------------------
             const uint32_t magic = I.magic;
             for (uint32_t t0 = 0; t0 < n_tours; t0 += (uint32_t)T) {
@@ -764,6 +772,7 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
         }
 #undef SV
 #undef CS
+        __builtin_amdgcn_s_setprio(0);                 // also for a plan that was not evaluated
         const int64_t D = block_sum64<BLOCK>(acc, sum_slot);
         if (A.validate && bad) atomicOr(A.err, 1);
         if (tid == 0) {
