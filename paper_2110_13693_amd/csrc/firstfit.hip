@@ -95,6 +95,8 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
         __syncthreads();
 
         // ---- 2. first fit -------------------------------------------------
+        // a chain of dependent steps: it issues ahead of other plans' tiles
+        __builtin_amdgcn_s_setprio(2);
         int T = 0;                         // tours opened (uniform)
         int32_t gmax = 0;                  // lane c: >= the largest room in tours 64c..64c+63
         uint32_t R[FF_MAX_ORDERS / 256];   // byte b of R[q]: room of tour 64 (4q + b) + lane
@@ -149,6 +151,8 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
             // read after the tile loop's barrier
             if (i < n && o_l < (uint32_t)n) tour_of[o_l] = (uint16_t)t_l;
         }
+
+        __builtin_amdgcn_s_setprio(0);
 
         // ---- 3. tiles of tours -----------------------------------------------
         int64_t acc = 0;
