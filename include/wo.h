@@ -389,6 +389,18 @@ wo_status wo_search_free(wo_search *s);
  * otherwise (the search must have been created with candidates > 0). */
 wo_status wo_search_step(wo_wh *wh, wo_search *s, wo_sur *sur, int32_t n_generations, void *stream);
 
+/* Checkpoint of a search to a file: the population, its distances, the
+ * parameters and the generation counter.  Random numbers are a function of
+ * (seed, generation, child, position), so a search resumed with
+ * wo_search_load continues bit-exactly.  Synchronous. */
+wo_status wo_search_save(wo_search *s, const char *path, void *stream);
+
+/* Resume a search saved by wo_search_save on instance `inst` of wh, which
+ * must have the same order and category counts; the population is evaluated
+ * again and its distances must equal the saved ones (else WO_E_INVAL, as for
+ * a file that is not a search checkpoint).  Synchronous. */
+wo_status wo_search_load(wo_wh *wh, int32_t inst, const char *path, void *stream, wo_search **out);
+
 /* Best individual so far (each argument nullable): zone row (64 bytes),
  * sequence (n entries), distance, generations run.  Synchronous. */
 wo_status wo_search_best(wo_search *s, uint8_t *h_zone_of, uint16_t *h_seq, int32_t *h_dist,

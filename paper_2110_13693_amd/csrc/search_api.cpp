@@ -3,7 +3,9 @@
 
 #include <algorithm>
 #include <atomic>
+#include <cstdio>
 #include <cstring>
+#include <vector>
 #include <memory>
 #include <new>
 #include <utility>
@@ -244,5 +246,112 @@ extern "C" wo_status wo_search_population(wo_search *s, uint8_t *d_zone_of, uint
         if (!s->kept) return wo_fail(WO_E_STATE, "search has no screening state");
         WO_HIP(hipMemcpyAsync(d_last_kept, s->kept, (size_t)s->prm.keep * 4, hipMemcpyDeviceToDevice, st));
     }
+    return WO_OK;
+}
+
+// Checkpoint: a header (magic, order and category counts, the parameters, the
+// generation counter), then the population's zone rows, sequences and
+// distances.  The random numbers are a function of (seed, generation, child,
+// position), so a search resumed from the file continues bit-exactly.
+namespace {
+struct SearchFileHeader {
+    char magic[8];
+    int32_t n_orders, n_cat, population, reserved;
+    wo_search_params prm;
+    uint32_t gen, reserved2;
+};
+const char kSearchMagic[8] = {'W', 'O', 'S', 'R', 'C', 'H', '0', '1'};
+}  // namespace
+
+extern "C" wo_status wo_search_save(wo_search *s, const char *path, void *stream)
+{
+    if (!s || !path) return wo_fail(WO_E_INVAL, "NULL argument");
+    SearchBusy busy(&s->busy);
+    if (!busy.ok) return wo_fail(WO_E_STATE, "search is in use by another thread");
+    const size_t P = (size_t)s->P, n = (size_t)s->n;
+    std::vector<uint8_t> z(P * 64);
+    std::vector<uint16_t> q(P * n);
+    std::vector<int32_t> d(P);
+    hipStream_t st = (hipStream_t)stream;
+    WO_HIP(hipMemcpyAsync(z.data(), s->pz, P * 64, hipMemcpyDeviceToHost, st));
+    WO_HIP(hipMemcpyAsync(q.data(), s->ps, P * n * 2, hipMemcpyDeviceToHost, st));
+    WO_HIP(hipMemcpyAsync(d.data(), s->pd, P * 4, hipMemcpyDeviceToHost, st));
+    WO_HIP(hipStreamSynchronize(st));
+    SearchFileHeader h;
+    memset(&h, 0, sizeof h);
+    memcpy(h.magic, kSearchMagic, 8);
+    h.n_orders = s->n;
+    h.n_cat = s->C;
+    h.population = s->P;
+    h.prm = s->prm;
+    h.gen = s->gen;
+    FILE *f = fopen(path, "wb");
+    if (!f) return wo_fail(WO_E_INVAL, "cannot open %s for writing", path);
+    bool ok = fwrite(&h, sizeof h, 1, f) == 1 && fwrite(z.data(), 1, z.size(), f) == z.size() &&
+              fwrite(q.data(), 2, q.size(), f) == q.size() && fwrite(d.data(), 4, d.size(), f) == d.size();
+    ok = (fclose(f) == 0) && ok;
+    return ok ? WO_OK : wo_fail(WO_E_INVAL, "write to %s failed", path);
+}
+
+extern "C" wo_status wo_search_load(wo_wh *wh, int32_t inst, const char *path, void *stream, wo_search **out)
+{
+    if (!path || !out) return wo_fail(WO_E_INVAL, "NULL argument");
+    *out = nullptr;
+    FILE *f = fopen(path, "rb");
+    if (!f) return wo_fail(WO_E_INVAL, "cannot open %s", path);
+    SearchFileHeader h;
+    bool ok = fread(&h, sizeof h, 1, f) == 1 && memcmp(h.magic, kSearchMagic, 8) == 0 && h.n_orders >= 1 &&
+              h.n_orders <= WO_MAX_ORDERS && h.population >= 2 && h.population <= (1 << 24) && h.n_cat >= 1 &&
+              h.n_cat <= WO_MAX_CATEGORIES && h.prm.population == h.population;
+    std::vector<uint8_t> z;
+    std::vector<uint16_t> q;
+    std::vector<int32_t> d;
+    if (ok) {
+        const size_t P = (size_t)h.population, n = (size_t)h.n_orders;
+        z.resize(P * 64);
+        q.resize(P * n);
+        d.resize(P);
+        ok = fread(z.data(), 1, z.size(), f) == z.size() && fread(q.data(), 2, q.size(), f) == q.size() &&
+             fread(d.data(), 4, d.size(), f) == d.size();
+    }
+    fclose(f);
+    if (!ok) return wo_fail(WO_E_INVAL, "%s is not a search checkpoint", path);
+    if (!wh) return wo_fail(WO_E_INVAL, "NULL warehouse handle");
+    if (inst < 0 || inst >= instance_count(wh)) return wo_fail(WO_E_RANGE, "instance %d out of range", inst);
+    if (instance_orders(wh, inst) != h.n_orders || instance_categories(wh, inst) != h.n_cat)
+        return wo_fail(WO_E_INVAL, "the checkpoint has %d orders and %d categories, the instance %d and %d",
+                       h.n_orders, h.n_cat, instance_orders(wh, inst), instance_categories(wh, inst));
+    // the population is re-evaluated on creation; the distances must come
+    // out as saved, which also checks that the instance is the same
+    uint8_t *dz = nullptr;
+    uint16_t *dq = nullptr;
+    wo_status r;
+    if ((r = alloc(&dz, z.size())) || (r = alloc(&dq, q.size()))) {
+        if (dz) (void)hipFree(dz);
+        return r;
+    }
+    hipStream_t st = (hipStream_t)stream;
+    wo_search *s = nullptr;
+    if (hipMemcpyAsync(dz, z.data(), z.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
+        hipMemcpyAsync(dq, q.data(), q.size() * 2, hipMemcpyHostToDevice, st) != hipSuccess) {
+        r = wo_fail(WO_E_DEVICE, "upload of the checkpoint failed");
+    } else {
+        r = wo_search_create(wh, inst, &h.prm, dz, dq, stream, &s);
+    }
+    (void)hipStreamSynchronize(st);
+    (void)hipFree(dz);
+    (void)hipFree(dq);
+    if (r) return r;
+    std::vector<int32_t> d2(d.size());
+    if (hipMemcpy(d2.data(), s->pd, d2.size() * 4, hipMemcpyDeviceToHost) != hipSuccess) {
+        wo_search_free(s);
+        return wo_fail(WO_E_DEVICE, "read-back of the distances failed");
+    }
+    if (d2 != d) {
+        wo_search_free(s);
+        return wo_fail(WO_E_INVAL, "the checkpoint's distances differ on this instance");
+    }
+    s->gen = h.gen;
+    *out = s;
     return WO_OK;
 }

@@ -30,6 +30,7 @@ EXPORTS = sorted([
     "wo_sur_gradients", "wo_sur_train", "wo_sur_predict", "wo_sur_save", "wo_sur_load",
     "wo_screen_plans",
     "wo_search_create", "wo_search_free", "wo_search_step", "wo_search_best", "wo_search_population",
+    "wo_search_save", "wo_search_load",
     "wo_set_eval_config", "wo_get_eval_config", "wo_autotune_eval",
     "wo_kmeans_categories",
 ])
@@ -110,6 +111,8 @@ def lib():
         L.wo_search_step.argtypes = [V, V, V, I32, V]
         L.wo_search_best.argtypes = [V, V, V, P(I32), P(I32), V]
         L.wo_search_population.argtypes = [V, V, V, V, V, V]
+        L.wo_search_save.argtypes = [V, ctypes.c_char_p, V]
+        L.wo_search_load.argtypes = [V, I32, ctypes.c_char_p, V, P(V)]
         L.wo_kmeans_categories.argtypes = [V, I64, I32, I32, I32, V, P(I32), P(I32), V]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype if name in (
@@ -408,6 +411,24 @@ def wo_search_create(wh: Warehouse, inst: int, init_zone_of, init_seq, populatio
                                   _ptr(init_seq, 2, "seq"), ctypes.c_void_p(_stream_handle(stream)),
                                   ctypes.byref(out)))
     return Search(out.value, n, population, keep)
+
+
+def wo_search_save(s: Search, path: str, stream=None):
+    """Checkpoint the search to ``path`` (synchronous)."""
+    _check(lib().wo_search_save(s.handle, os.fsencode(path), ctypes.c_void_p(_stream_handle(stream))))
+
+
+def wo_search_load(wh: Warehouse, inst: int, path: str, stream=None) -> Search:
+    """Resume a checkpointed search on instance ``inst`` of ``wh``."""
+    import struct
+    out = ctypes.c_void_p(0)
+    _check(lib().wo_search_load(wh.handle, int(inst), os.fsencode(path), ctypes.c_void_p(_stream_handle(stream)),
+                                ctypes.byref(out)))
+    with open(path, "rb") as f:                 # population and keep, for the Python-side shapes
+        head = f.read(8 + 16 + ctypes.sizeof(wo_search_params))
+    population = struct.unpack_from("<i", head, 16)[0]
+    prm = wo_search_params.from_buffer_copy(head[24:24 + ctypes.sizeof(wo_search_params)])
+    return Search(out.value, wh.n_orders[inst], population, prm.keep)
 
 
 def wo_search_free(s: Search):

@@ -196,3 +196,19 @@ def test_load_rejects_mixed_routing(wo, tiny):
     assert wo.lib().wo_load_warehouse(arr, 2, None, ctypes.byref(out)) == wo.WO_E_UNSUPPORTED
     assert "routing" in wo.wo_last_error()
     assert out.value is None
+
+
+def test_search_load_rejects_bad_files(wo, tmp_path):
+    # the file is checked before any device work
+    out = ctypes.c_void_p(0)
+    missing = str(tmp_path / "none.bin").encode()
+    assert wo.lib().wo_search_load(None, 0, missing, None, ctypes.byref(out)) == wo.WO_E_INVAL
+    assert "cannot open" in wo.wo_last_error()
+    bad = tmp_path / "bad.bin"
+    bad.write_bytes(b"NOTACKPT" + bytes(200))
+    assert wo.lib().wo_search_load(None, 0, str(bad).encode(), None, ctypes.byref(out)) == wo.WO_E_INVAL
+    assert "not a search checkpoint" in wo.wo_last_error()
+    short = tmp_path / "short.bin"
+    short.write_bytes(b"WOSRCH01" + bytes(10))
+    assert wo.lib().wo_search_load(None, 0, str(short).encode(), None, ctypes.byref(out)) == wo.WO_E_INVAL
+    assert out.value is None

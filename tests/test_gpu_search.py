@@ -112,3 +112,36 @@ def test_search_keeps_best_and_improves():
     assert d == db
     s.free()
     wh.free()
+
+
+def test_checkpoint_resumes_bit_exactly(tmp_path):
+    import torch
+    wo = _wo()
+    inst, _, _ = synth.workload("tiny", n_plans=1)
+    P = 64
+    Z, S = _init(inst, P, 5)
+    wh = wo.wo_load_warehouse([inst])
+    s = wo.wo_search_create(wh, 0, torch.from_numpy(Z).cuda(),
+                            torch.from_numpy(S.view(np.int16)).cuda().reshape(-1), P, seed=77)
+    wo.wo_search_step(wh, s, None, 3)
+    path = str(tmp_path / "search.bin")
+    wo.wo_search_save(s, path)
+    r = wo.wo_search_load(wh, 0, path)
+    assert wo.wo_search_best(r)[3] == 3                       # the generation counter travels
+    wo.wo_search_step(wh, s, None, 4)
+    wo.wo_search_step(wh, r, None, 4)
+    a = _population(wo, s, P, inst.n_orders)
+    b = _population(wo, r, P, inst.n_orders)
+    for x, y in zip(a, b):
+        assert np.array_equal(x, y)
+    assert wo.wo_search_best(s)[2:] == wo.wo_search_best(r)[2:]
+    # a different instance with the same sizes gives other distances: refused
+    other = synth.workload("tiny", seed=9, n_plans=1)[0]
+    assert other.n_orders == inst.n_orders and other.n_categories == inst.n_categories
+    wh2 = wo.wo_load_warehouse([other])
+    with pytest.raises(wo.WoError):
+        wo.wo_search_load(wh2, 0, path)
+    wh2.free()
+    r.free()
+    s.free()
+    wh.free()
