@@ -172,6 +172,32 @@ wo_status wo_kmeans_categories(const int32_t *d_order_skus, int64_t n_lines, int
                                int32_t max_iter, int32_t *d_category, int32_t *k_used, int32_t *n_iter,
                                void *stream);
 
+/* K-means categories without allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc).  The clustering and its arguments are those of
+ * wo_kmeans_categories, with three differences:
+ *   - asynchronous on `stream`: it enqueues kernels only (no allocation,
+ *     memset or host synchronisation), so it may be captured into a graph;
+ *     every one of the max_iter (1 .. WO_KMEANS_NOALLOC_MAX_ITER) assignment
+ *     steps is enqueued, and those after convergence return at once;
+ *   - d_k_used and d_n_iter are device int32 pointers (each nullable) that
+ *     receive the categories used and the assignments performed; an order
+ *     line naming a SKU outside 0 .. n_skus - 1 sets *d_k_used to -1 (and
+ *     d_category is then unspecified);
+ *   - the scratch (4 n_skus + 8 (n_lines + 1) bytes plus the iteration state,
+ *     each part rounded up to 256 bytes) lives in a static device array of
+ *     WO_KMEANS_NOALLOC_SCRATCH bytes that every GPU the library runs on
+ *     holds until the process ends; a larger need returns WO_E_RANGE before
+ *     anything is enqueued.
+ * All calls on one GPU share its array, and each call clears it first:
+ * calls that overlap on one GPU (on different streams, or from several
+ * threads) race, so the caller orders them. */
+#define WO_KMEANS_NOALLOC_SCRATCH (8 << 20)
+#define WO_KMEANS_NOALLOC_MAX_ITER 256
+wo_status wo_kmeans_categories_noalloc(const int32_t *d_order_skus, int64_t n_lines, int32_t n_skus, int32_t k,
+                                       int32_t max_iter, int32_t *d_category, int32_t *d_k_used,
+                                       int32_t *d_n_iter, void *stream);
+
 /* Load n_instances (>= 1) instances onto the current HIP device.
  * Validates every descriptor (WO_E_INVAL / WO_E_RANGE), packs per-line
  * records and order tables, copies them to device memory on `stream` and

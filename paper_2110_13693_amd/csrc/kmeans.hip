@@ -18,6 +18,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <mutex>
 
 #include "wo_common.h"
 
@@ -194,6 +195,73 @@ __global__ void km_label_kernel(const int32_t *freq, int32_t n_skus, const int32
 
 int grid_for(int64_t n, int block) { return (int)std::min<int64_t>(std::max<int64_t>((n + block - 1) / block, 1), 4096); }
 
+// Scratch layout of one call: frequencies [n_skus], histogram [n_bins], bin
+// labels [n_bins], the state, the error flag; each part starts on 256 bytes.
+struct KmLayout {
+    size_t o_hist, o_label, o_state, o_err, bytes;
+};
+
+KmLayout km_layout(int32_t n_skus, int32_t n_bins)
+{
+    KmLayout L;
+    L.o_hist = ((size_t)n_skus * 4 + 255) & ~(size_t)255;
+    L.o_label = L.o_hist + (((size_t)n_bins * 4 + 255) & ~(size_t)255);
+    L.o_state = L.o_label + (((size_t)n_bins * 4 + 255) & ~(size_t)255);
+    L.o_err = L.o_state + ((sizeof(KmState) + 255) & ~(size_t)255);
+    L.bytes = L.o_err + 256;
+    return L;
+}
+
+// Fills words [0, n) with v: clears the scratch of the allocation-free
+// variant inside the stream (a kernel rather than a memset, so that the
+// call can sit in a captured graph).
+__global__ void km_fill_kernel(int32_t *p, int64_t n, int32_t v)
+{
+    for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = v;
+}
+
+// Results of the allocation-free variant, written on the device.
+__global__ void km_finish_kernel(const KmState *st, const int32_t *err, int32_t *k_used, int32_t *n_iter)
+{
+    if (threadIdx.x != 0) return;
+    if (k_used) *k_used = *err ? -1 : st->k_used;
+    if (n_iter) *n_iter = st->n_iter;
+}
+
+}  // namespace
+
+// The allocation-free variant keeps its scratch in this array: one copy per
+// device, held until the process ends.  In host code the name is only a
+// stand-in: the device address comes from hipGetSymbolAddress, taken once
+// per device with that device current, and is what the launches receive.
+static __device__ __align__(256) unsigned char km_scratch[WO_KMEANS_NOALLOC_SCRATCH];
+
+namespace {
+
+constexpr int KM_MAX_DEVICES = 64;
+std::mutex km_scratch_mu;
+void *km_scratch_dev[KM_MAX_DEVICES];
+
+wo_status km_scratch_address(void **out)
+{
+    int dev = 0;
+    WO_HIP(hipGetDevice(&dev));
+    if (dev < 0 || dev >= KM_MAX_DEVICES) return wo_fail(WO_E_UNSUPPORTED, "device %d beyond %d", dev, KM_MAX_DEVICES);
+    std::lock_guard<std::mutex> g(km_scratch_mu);
+    if (!km_scratch_dev[dev]) {
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(km_scratch));
+        if (e != hipSuccess || !p) {
+            (void)hipGetLastError();
+            return wo_fail(WO_E_DEVICE, "hipGetSymbolAddress of the K-means scratch failed: %s", hipGetErrorString(e));
+        }
+        km_scratch_dev[dev] = p;
+    }
+    *out = km_scratch_dev[dev];
+    return WO_OK;
+}
+
 }  // namespace
 
 extern "C" wo_status wo_kmeans_categories(const int32_t *d_order_skus, int64_t n_lines, int32_t n_skus, int32_t k,
@@ -211,11 +279,9 @@ extern "C" wo_status wo_kmeans_categories(const int32_t *d_order_skus, int64_t n
     const int32_t n_bins = (int32_t)n_lines + 1;      // a frequency is at most n_lines
     // scratch: frequencies, histogram, bin labels, state, error flag
     char *buf = nullptr;
-    const size_t o_hist = ((size_t)n_skus * 4 + 255) & ~(size_t)255;
-    const size_t o_label = o_hist + (((size_t)n_bins * 4 + 255) & ~(size_t)255);
-    const size_t o_state = o_label + (((size_t)n_bins * 4 + 255) & ~(size_t)255);
-    const size_t o_err = o_state + ((sizeof(KmState) + 255) & ~(size_t)255);
-    const size_t bytes = o_err + 256;
+    const KmLayout Ly = km_layout(n_skus, n_bins);
+    const size_t o_hist = Ly.o_hist, o_label = Ly.o_label, o_state = Ly.o_state, o_err = Ly.o_err;
+    const size_t bytes = Ly.bytes;
     if (wo_fault_injected()) return wo_fail(WO_E_NOMEM, "injected allocation failure");
     if (hipMalloc((void **)&buf, bytes) != hipSuccess) {
         (void)hipGetLastError();
@@ -268,4 +334,53 @@ extern "C" wo_status wo_kmeans_categories(const int32_t *d_order_skus, int64_t n
         if (n_iter) *n_iter = h.n_iter;
     }
     return ret;
+}
+
+extern "C" wo_status wo_kmeans_categories_noalloc(const int32_t *d_order_skus, int64_t n_lines, int32_t n_skus,
+                                                  int32_t k, int32_t max_iter, int32_t *d_category,
+                                                  int32_t *d_k_used, int32_t *d_n_iter, void *stream)
+{
+    if (!d_order_skus || !d_category) return wo_fail(WO_E_INVAL, "NULL device buffer");
+    if (n_lines < 1 || n_lines > WO_MAX_LINES)
+        return wo_fail(WO_E_RANGE, "n_lines must be in 1 .. %d", WO_MAX_LINES);
+    if (n_skus < 1 || n_skus > WO_MAX_LOCATIONS)
+        return wo_fail(WO_E_RANGE, "n_skus must be in 1 .. %d", WO_MAX_LOCATIONS);
+    if (k < 1 || k > KM_MAX) return wo_fail(WO_E_RANGE, "k must be in 1 .. %d", KM_MAX);
+    if (max_iter < 1 || max_iter > WO_KMEANS_NOALLOC_MAX_ITER)
+        return wo_fail(WO_E_RANGE, "max_iter must be in 1 .. %d", WO_KMEANS_NOALLOC_MAX_ITER);
+    const int32_t n_bins = (int32_t)n_lines + 1;
+    const KmLayout Ly = km_layout(n_skus, n_bins);
+    if (Ly.bytes > (size_t)WO_KMEANS_NOALLOC_SCRATCH)
+        return wo_fail(WO_E_RANGE, "%d SKUs and %lld lines need %zu bytes of scratch, more than the %d it has",
+                       n_skus, (long long)n_lines, Ly.bytes, WO_KMEANS_NOALLOC_SCRATCH);
+    void *base = nullptr;
+    wo_status st0 = km_scratch_address(&base);
+    if (st0) return st0;
+    hipStream_t s = (hipStream_t)stream;
+    char *buf = (char *)base;
+    int32_t *freq = (int32_t *)buf, *hist = (int32_t *)(buf + Ly.o_hist), *label = (int32_t *)(buf + Ly.o_label);
+    KmState *st = (KmState *)(buf + Ly.o_state);
+    int32_t *err = (int32_t *)(buf + Ly.o_err);
+    // the previous call's contents stay in the array: clear what starts at
+    // zero (frequencies, histogram, state, flag) and mark no cluster yet
+    const int64_t w_lab = (int64_t)(Ly.o_state - Ly.o_label) / 4, w_state = (int64_t)(Ly.bytes - Ly.o_state) / 4;
+    hipLaunchKernelGGL(km_fill_kernel, dim3(grid_for((int64_t)Ly.o_label / 4, 256)), dim3(256), 0, s, freq,
+                       (int64_t)Ly.o_label / 4, 0);
+    hipLaunchKernelGGL(km_fill_kernel, dim3(grid_for(w_lab, 256)), dim3(256), 0, s, label, w_lab, -1);
+    hipLaunchKernelGGL(km_fill_kernel, dim3(1), dim3(256), 0, s, (int32_t *)st, w_state, 0);
+    hipLaunchKernelGGL(km_freq_kernel, dim3(grid_for(n_lines, 256)), dim3(256), 0, s, d_order_skus, n_lines, n_skus,
+                       freq, err);
+    hipLaunchKernelGGL(km_hist_kernel, dim3(grid_for(n_skus, 256)), dim3(256), 0, s, freq, n_skus, hist);
+    hipLaunchKernelGGL(km_init_kernel, dim3(1), dim3(1024), 0, s, hist, n_bins, k, st);
+    // every assignment step is enqueued; those after convergence return at once
+    for (int it = 0; it < max_iter; it++) {
+        hipLaunchKernelGGL(km_assign_kernel, dim3(grid_for(n_bins, 256)), dim3(256), 0, s, hist, n_bins, k, label, st);
+        hipLaunchKernelGGL(km_update_kernel, dim3(1), dim3(KM_MAX), 0, s, k, st);
+    }
+    hipLaunchKernelGGL(km_rank_kernel, dim3(1), dim3(KM_MAX), 0, s, k, st);
+    hipLaunchKernelGGL(km_label_kernel, dim3(grid_for(n_skus, 256)), dim3(256), 0, s, freq, n_skus, label, st,
+                       d_category);
+    hipLaunchKernelGGL(km_finish_kernel, dim3(1), dim3(64), 0, s, st, err, d_k_used, d_n_iter);
+    WO_HIP(hipGetLastError());
+    return WO_OK;
 }

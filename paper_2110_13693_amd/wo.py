@@ -32,7 +32,7 @@ EXPORTS = sorted([
     "wo_search_create", "wo_search_free", "wo_search_step", "wo_search_best", "wo_search_population",
     "wo_search_save", "wo_search_load",
     "wo_set_eval_config", "wo_get_eval_config", "wo_autotune_eval",
-    "wo_kmeans_categories",
+    "wo_kmeans_categories", "wo_kmeans_categories_noalloc",
 ])
 WO_SUR_PARAMS = 4457985
 WO_SCREEN_MAX_KEEP = 4096
@@ -114,6 +114,7 @@ def lib():
         L.wo_search_save.argtypes = [V, ctypes.c_char_p, V]
         L.wo_search_load.argtypes = [V, I32, ctypes.c_char_p, V, P(V)]
         L.wo_kmeans_categories.argtypes = [V, I64, I32, I32, I32, V, P(I32), P(I32), V]
+        L.wo_kmeans_categories_noalloc.argtypes = [V, I64, I32, I32, I32, V, V, V, V]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype if name in (
                 "wo_status_str", "wo_last_error") else ctypes.c_int
@@ -368,6 +369,20 @@ def wo_kmeans_categories(order_skus, n_skus: int, k: int, category, max_iter: in
                                       int(k), int(max_iter), _ptr(category, 4, "category"), ctypes.byref(used),
                                       ctypes.byref(iters), ctypes.c_void_p(_stream_handle(stream))))
     return used.value, iters.value
+
+
+def wo_kmeans_categories_noalloc(order_skus, n_skus: int, k: int, category, k_used=None, n_iter=None,
+                                 max_iter: int = 100, stream=None):
+    """The allocation-free K-means (asynchronous): categories into
+    ``category`` (int32 GPU tensor of n_skus), categories used and
+    assignments into the one-element int32 GPU tensors ``k_used`` and
+    ``n_iter`` (each may be None)."""
+    if category.numel() != n_skus:
+        raise ValueError("category must hold one entry per SKU")
+    _check(lib().wo_kmeans_categories_noalloc(
+        _ptr(order_skus, 4, "order_skus"), int(order_skus.numel()), int(n_skus), int(k), int(max_iter),
+        _ptr(category, 4, "category"), _ptr(k_used, 4, "k_used") if k_used is not None else None,
+        _ptr(n_iter, 4, "n_iter") if n_iter is not None else None, ctypes.c_void_p(_stream_handle(stream))))
 
 
 # ---------------------------------------------------------------------------

@@ -212,3 +212,17 @@ def test_search_load_rejects_bad_files(wo, tmp_path):
     short.write_bytes(b"WOSRCH01" + bytes(10))
     assert wo.lib().wo_search_load(None, 0, str(short).encode(), None, ctypes.byref(out)) == wo.WO_E_INVAL
     assert out.value is None
+
+
+def test_kmeans_noalloc_rejects_sizes_beyond_its_scratch(wo):
+    # checked on the host before any device work: the placeholders below are
+    # never dereferenced
+    L = wo.lib()
+    dev = ctypes.c_void_p(256)
+    # 2^21 SKUs and 2^20 lines need 16 MiB of scratch, more than the array holds
+    st = L.wo_kmeans_categories_noalloc(dev, 1 << 20, 1 << 21, 8, 10, dev, None, None, None)
+    assert st == wo.WO_E_RANGE and "scratch" in wo.wo_last_error()
+    st = L.wo_kmeans_categories_noalloc(dev, 1000, 100, 8, 257, dev, None, None, None)
+    assert st == wo.WO_E_RANGE
+    st = L.wo_kmeans_categories_noalloc(None, 1000, 100, 8, 10, dev, None, None, None)
+    assert st == wo.WO_E_INVAL
