@@ -82,26 +82,74 @@ def profiled_traffic():
         return None
 
 
-def cpu_baseline(inst, Z, S, min_wall_s: float = 1.5):
-    import oracle
+def cpu_model() -> str:
     try:
-        cores = len(os.sched_getaffinity(0))
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def host_threads():
+    """Threads the CPU baseline may use: the cores this process may run on,
+    limited to the CPU share its environment declares (OMP_NUM_THREADS; a
+    GPU machine grants one GPU's process 16)."""
+    try:
+        avail = len(os.sched_getaffinity(0))
     except AttributeError:
-        cores = os.cpu_count() or 1
-    cores = max(1, min(cores, 16))
+        avail = os.cpu_count() or 1
+    share = os.environ.get("OMP_NUM_THREADS")
+    used = min(avail, int(share)) if share and share.isdigit() and int(share) > 0 else avail
+    return max(1, used), avail
+
+
+def cpu_baseline(inst, Z, S, ops_per_plan: float, d_gpu, t_gpu, min_wall_s: float = 1.5):
+    """The CPU oracle on the host's cores: all-threads and one-thread rates,
+    the CPU roofline fraction, and the oracle's check of the GPU's results for
+    the same plans (every plan of the timed call)."""
+    import oracle
+    cores, avail = host_threads()
     n = Z.shape[0]
     done, reps = 0, 0
     t0 = time.perf_counter()
+    d_ref = t_ref = None
     while True:
-        oracle.eval_plans(inst, Z, S, n_threads=cores)
+        d, t = oracle.eval_plans(inst, Z, S, n_threads=cores)
+        if d_ref is None:
+            d_ref, t_ref = d, t
         done += n
         reps += 1
         el = time.perf_counter() - t0
         if el >= min_wall_s:
             break
-    return {"value": done / el, "unit": "plans/s", "cores": cores, "kind": "oracle",
-            "sample": "%d passes over the same %d plans (%.1f s wall, ~%.0f core-s)"
-                      % (reps, n, el, el * cores)}
+    rate = done / el
+    # one thread, on a bounded sample of the same plans
+    m = min(n, 256)
+    done1, t1 = 0, time.perf_counter()
+    while True:
+        oracle.eval_plans(inst, Z[:m], S[:m], n_threads=1)
+        done1 += m
+        el1 = time.perf_counter() - t1
+        if el1 >= min_wall_s / 2:
+            break
+    rate1 = done1 / el1
+    per_core = oracle.int_ops_per_second()
+    achieved = ops_per_plan * rate
+    mism_d = int(np.count_nonzero(d_ref != d_gpu))
+    rel = np.abs(t_gpu.astype(np.float64) - t_ref) / np.maximum(np.abs(t_ref.astype(np.float64)), 1e-30)
+    mism_t = int(np.count_nonzero(rel > 1e-6))
+    return ({"value": rate, "unit": "plans/s", "cores": cores, "kind": "oracle",
+             "sample": "%d passes over the same %d plans (%.1f s wall, ~%.0f core-s)" % (reps, n, el, el * cores),
+             "cores_available": avail, "cpu_model": cpu_model(),
+             "value_1core": rate1, "sample_1core": "%d plans, one thread (%.1f s)" % (done1, el1),
+             "roofline": {"bound": "alu", "achieved": achieved / 1e9, "unit": "Gops/s",
+                          "peak": cores * per_core / 1e9, "frac": achieved / (cores * per_core),
+                          "peak_per_core": per_core / 1e9,
+                          "note": "algorithmic ops (8/pick + 4/order + 12/tour) over cores x a measured "
+                                  "scalar integer rate (8 independent add/xor chains)"}},
+            {"oracle_plans_checked": n, "oracle_dist_mismatches": mism_d, "oracle_thr_mismatches": mism_t})
 
 
 def search_comparison(args):
@@ -112,6 +160,12 @@ def search_comparison(args):
     re-scores the best 3,277 exactly.  The surrogate is trained first on plans
     the exact evaluator scores (random slottings at the identity sequence);
     its data generation and training time are reported and counted both ways.
+    Each of ``--seeds`` runs draws its own initial population, GA stream,
+    training slottings and surrogate initialisation; the JSON line gives the
+    median and range over the seeds of the screened/plain best-cost ratio at
+    equal total wall time (training counted) and at equal search time, and of
+    the time the screened arm takes to come within 0.5 % of the plain arm's
+    final best, with and without its training.
     """
     import torch
 
@@ -123,13 +177,10 @@ def search_comparison(args):
     n = inst.n_orders
     P, K, keep = args.population, 65536, 3277
     wh = wo.wo_load_warehouse([inst])
-    rng = np.random.default_rng([0, synth.generators.STREAM_SEARCH_INIT])
-    Z0 = torch.from_numpy(synth.generators.random_zone_perms(rng, P, inst.n_categories)).cuda()
-    S0 = torch.from_numpy(synth.generators.random_order_perms(rng, P, n).view(np.int16)).cuda().reshape(-1)
 
-    def run(sur, budget_s, max_gen, label):
+    def run(sur, budget_s, max_gen, label, Z0, S0, ga_seed):
         s = wo.wo_search_create(wh, 0, Z0, S0, P, candidates=K if sur else 0, keep=keep if sur else 0,
-                                seed=11)
+                                seed=ga_seed)
         torch.cuda.synchronize()
         trace = [(0.0, wo.wo_search_best(s)[2])]
         t0 = time.perf_counter()
@@ -144,94 +195,133 @@ def search_comparison(args):
               file=sys.stderr, flush=True)
         return trace, best
 
-    plain_trace, plain_best = run(None, None, args.generations, "plain")
-    wall = plain_trace[-1][0]
-
-    # surrogate: training pairs from the exact evaluator, then training; the
-    # random slottings are drawn on the device (argsort of seeded uniform keys)
-    def draw_slottings(gen, n):
-        keys = torch.rand(n, inst.n_categories, generator=gen, device="cuda")
-        z = torch.full((n, 64), 0xFF, dtype=torch.uint8, device="cuda")
+    # surrogate training pairs from the exact evaluator: random slottings
+    # drawn on the device (argsort of seeded uniform keys) at the identity
+    # order sequence
+    def draw_slottings(gen, m):
+        keys = torch.rand(m, inst.n_categories, generator=gen, device="cuda")
+        z = torch.full((m, 64), 0xFF, dtype=torch.uint8, device="cuda")
         z[:, :inst.n_categories] = keys.argsort(dim=1).to(torch.uint8)
         return z
 
     draw_slottings(torch.Generator(device="cuda"), 4096)   # first-use set-up of these ops, untimed
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    n_train = args.train_samples
-    gen = torch.Generator(device="cuda")
-    gen.manual_seed(int(synth.generators.STREAM_SURROGATE_TRAIN))
-    ztr = draw_slottings(gen, n_train)
-    dtr = torch.empty(n_train, dtype=torch.int32, device="cuda")
-    ident = torch.arange(n, dtype=torch.int16, device="cuda")
     chunk = 16384
-    seq_chunk = ident.repeat(chunk)
-    for c0 in range(0, n_train, chunk):
-        m = min(chunk, n_train - c0)
-        wo.wo_eval_plans(wh, ztr[c0:c0 + m], seq_chunk[:m * n], dtr[c0:c0 + m])
-    torch.cuda.synchronize()
-    t_data = time.perf_counter() - t0
-    sur = wo.wo_sur_create(inst.n_categories, None, seed=1)
-    t1 = time.perf_counter()
-    loss = wo.wo_sur_train(sur, ztr, dtr, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=2)
-    t_train = time.perf_counter() - t1
-    # held-out error of the surrogate against the exact evaluator
+    seq_chunk = torch.arange(n, dtype=torch.int16, device="cuda").repeat(chunk)
     r_ho = np.random.default_rng([0, synth.generators.STREAM_SURROGATE_HELDOUT])
     zho = torch.from_numpy(synth.generators.random_zone_perms(r_ho, K, inst.n_categories)).cuda()
     dho = torch.empty(K, dtype=torch.int32, device="cuda")
     for c0 in range(0, K, chunk):
         wo.wo_eval_plans(wh, zho[c0:c0 + chunk], seq_chunk, dho[c0:c0 + chunk])
-    pho = torch.empty(K, dtype=torch.float32, device="cuda")
     torch.cuda.synchronize()
-    ts = time.perf_counter()
-    wo.wo_sur_predict(sur, zho, pho)
-    torch.cuda.synchronize()
-    t_pred = time.perf_counter() - ts
-    from scipy.stats import spearmanr   # reporting only: rank correlation, average ranks for ties
     ex = dho.cpu().numpy().astype(np.float64)
-    pr = pho.cpu().numpy().astype(np.float64)
-    rel_mae = float(np.mean(np.abs(pr - ex) / ex))
-    rho = float(spearmanr(pr, ex).correlation)
 
-    scr_trace, scr_best = run(sur, wall, 10 ** 9, "screened")
-    target = plain_best[2] * 1.005
+    def best_at(trace, t):
+        b = trace[0][1]
+        for tt, v in trace:
+            if tt <= t:
+                b = v
+        return b
 
     def time_to(trace, thr):
-        for t, b in trace:
-            if b <= thr:
+        for t, v in trace:
+            if v <= thr:
                 return t
         return None
 
-    t_hit = time_to(scr_trace, target)
-    # throughput of both best plans from the evaluator itself
-    zb = torch.from_numpy(np.stack([plain_best[0], scr_best[0]])).cuda()
-    sb = torch.from_numpy(np.concatenate([plain_best[1], scr_best[1]]).view(np.int16)).cuda()
+    from scipy.stats import spearmanr   # reporting only: rank correlation, average ranks for ties
+    runs = []
+    for i in range(args.seeds):
+        rng = np.random.default_rng([i, synth.generators.STREAM_SEARCH_INIT])
+        Z0 = torch.from_numpy(synth.generators.random_zone_perms(rng, P, inst.n_categories)).cuda()
+        S0 = torch.from_numpy(synth.generators.random_order_perms(rng, P, n).view(np.int16)).cuda().reshape(-1)
+        plain_trace, plain_best = run(None, None, args.generations, "seed %d plain" % i, Z0, S0, 11 + i)
+        wall = plain_trace[-1][0]
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        gen = torch.Generator(device="cuda")
+        gen.manual_seed(int(synth.generators.STREAM_SURROGATE_TRAIN) + 1000 * i)
+        ztr = draw_slottings(gen, args.train_samples)
+        dtr = torch.empty(args.train_samples, dtype=torch.int32, device="cuda")
+        for c0 in range(0, args.train_samples, chunk):
+            m = min(chunk, args.train_samples - c0)
+            wo.wo_eval_plans(wh, ztr[c0:c0 + m], seq_chunk[:m * n], dtr[c0:c0 + m])
+        torch.cuda.synchronize()
+        t_data = time.perf_counter() - t0
+        sur = wo.wo_sur_create(inst.n_categories, None, seed=1 + i)
+        t1 = time.perf_counter()
+        loss = wo.wo_sur_train(sur, ztr, dtr, epochs=args.epochs, batch=args.batch, lr=args.lr, seed=2 + i)
+        t_train = time.perf_counter() - t1
+        del ztr, dtr
+        pho = torch.empty(K, dtype=torch.float32, device="cuda")
+        wo.wo_sur_predict(sur, zho, pho)
+        torch.cuda.synchronize()
+        pr = pho.cpu().numpy().astype(np.float64)
+        # the screened arm searches as long as the plain arm did; the trace
+        # gives its best at equal search time and at equal total time (its
+        # data generation and training counted)
+        scr_trace, scr_best = run(sur, wall, 10 ** 9, "seed %d screened" % i, Z0, S0, 11 + i)
+        sur.free()
+        target = plain_best[2] * 1.005
+        t_hit = time_to(scr_trace, target)
+        t_prep = t_data + t_train
+        runs.append({
+            "seed": i, "plain_best": int(plain_best[2]), "plain_wall_s": wall,
+            "plain_generations": len(plain_trace) - 1, "initial_best": int(plain_trace[0][1]),
+            "screened_best_equal_search_time": int(scr_best[2]),
+            "screened_best_equal_total_time": int(best_at(scr_trace, wall - t_prep)),
+            "screened_generations": len(scr_trace) - 1,
+            "time_to_within_0.5pct_s": t_hit,
+            "time_to_within_0.5pct_incl_training_s": None if t_hit is None else t_hit + t_prep,
+            "reaches_target_in_less_total_time": t_hit is not None and t_hit + t_prep < wall,
+            "data_s": t_data, "train_s": t_train, "last_epoch_loss": loss,
+            "heldout_rel_mae": float(np.mean(np.abs(pr - ex) / ex)),
+            "heldout_spearman": float(spearmanr(pr, ex).correlation),
+            "plain_best_plan": plain_best, "screened_best_plan": scr_best,
+        })
+    # throughput of the first seed's best plans from the evaluator itself
+    r0 = runs[0]
+    zb = torch.from_numpy(np.stack([r0["plain_best_plan"][0], r0["screened_best_plan"][0]])).cuda()
+    sb = torch.from_numpy(np.concatenate([r0["plain_best_plan"][1], r0["screened_best_plan"][1]]).view(np.int16)).cuda()
     db = torch.empty(2, dtype=torch.int32, device="cuda")
     tb = torch.empty(2, dtype=torch.float32, device="cuda")
     wo.wo_eval_plans(wh, zb, sb, db, tb)
     torch.cuda.synchronize()
     thr_plain, thr_scr = [float(x) for x in tb.cpu().numpy()]
+    for r in runs:
+        del r["plain_best_plan"], r["screened_best_plan"]
+
+    def stats(vals):
+        v = np.array([x for x in vals if x is not None], dtype=np.float64)
+        if v.size == 0:
+            return None
+        return {"median": float(np.median(v)), "min": float(v.min()), "max": float(v.max()), "n": int(v.size)}
+
+    ratio_total = [r["screened_best_equal_total_time"] / r["plain_best"] for r in runs]
+    ratio_search = [r["screened_best_equal_search_time"] / r["plain_best"] for r in runs]
     out = {
         "metric": "surrogate vs plain best cost at equal time",
-        "value": float(scr_best[2]) / float(plain_best[2]),
-        "unit": "screened best D / plain best D",
+        "value": float(np.median(ratio_total)),
+        "unit": "screened best D / plain best D at equal total wall time (median over seeds)",
         "higher_is_better": False,
         "n_gpus": 1,
         "config": {"workload": "paper-scale warehouse, population %d, %d generations of plain search; "
-                               "screened: %d candidates, keep %d" % (P, args.generations, K, keep)},
-        "plain": {"best_dist": plain_best[2], "orders_per_window": thr_plain,
-                  "generations": len(plain_trace) - 1, "wall_s": wall},
-        "screened": {"best_dist": scr_best[2], "orders_per_window": thr_scr,
-                     "generations": len(scr_trace) - 1, "wall_s": scr_trace[-1][0],
-                     "time_to_within_0.5pct_s": t_hit,
-                     "time_to_within_0.5pct_incl_training_s": None if t_hit is None else t_hit + t_data + t_train},
-        "surrogate": {"train_samples": n_train, "epochs": args.epochs, "batch": args.batch, "lr": args.lr,
-                      "last_epoch_loss": loss,
-                      "data_s": t_data, "train_s": t_train, "heldout_rel_mae": rel_mae,
-                      "heldout_spearman": rho, "predict_65536_s": t_pred},
-        "initial_best_dist": plain_trace[0][1],
+                               "screened: %d candidates, keep %d; %d seeds" % (P, args.generations, K, keep,
+                                                                                args.seeds),
+                   "surrogate": {"train_samples": args.train_samples, "epochs": args.epochs, "batch": args.batch,
+                                 "lr": args.lr}},
+        "summary": {
+            "ratio_equal_total_time": stats(ratio_total),
+            "ratio_equal_search_time": stats(ratio_search),
+            "time_to_within_0.5pct_s": stats([r["time_to_within_0.5pct_s"] for r in runs]),
+            "time_to_within_0.5pct_incl_training_s": stats([r["time_to_within_0.5pct_incl_training_s"] for r in runs]),
+            "plain_wall_s": stats([r["plain_wall_s"] for r in runs]),
+            "seeds_reaching_target_in_less_total_time": int(sum(r["reaches_target_in_less_total_time"] for r in runs)),
+            "heldout_spearman": stats([r["heldout_spearman"] for r in runs]),
+            "heldout_rel_mae": stats([r["heldout_rel_mae"] for r in runs]),
+        },
+        "orders_per_window_seed0": {"plain": thr_plain, "screened": thr_scr},
+        "runs": runs,
     }
-    sur.free()
     wh.free()
     print(json.dumps(out), flush=True)
     return 0
@@ -447,6 +537,7 @@ def main(argv=None):
     ap.add_argument("--epochs", type=int, default=1, help="surrogate training epochs (search comparison)")
     ap.add_argument("--batch", type=int, default=4096, help="surrogate training batch (search comparison)")
     ap.add_argument("--lr", type=float, default=2e-3, help="surrogate learning rate (search comparison)")
+    ap.add_argument("--seeds", type=int, default=5, help="independent search/surrogate seeds (search comparison)")
     ap.add_argument("--batched", action="store_true",
                     help="time the 512-instance uneven batch (autotuned, eager and graph replay) instead")
     ap.add_argument("--kmeans", action="store_true",
@@ -551,10 +642,17 @@ def main(argv=None):
                    "parallelism": "1 GPU"},
         "roofline": roofline,
     }
+    # the device's own integer peak, beside the one from the unit counts
+    peak_meas = wo.wo_measure_int_peak(5)
+    roofline["peak_measured"] = peak_meas / 1e12
+    roofline["frac_measured"] = achieved_ops / peak_meas
     d_host = dist.cpu().numpy()
+    t_host = thr.cpu().numpy()
     out["check"] = {"dist_min": int(d_host.min()), "dist_max": int(d_host.max())}
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(inst, Z, S)
+        base, chk = cpu_baseline(inst, Z, S, ops / n_plans, d_host, t_host)
+        out["cpu_baseline"] = base
+        out["check"].update(chk)
     wh.free()
     print(json.dumps(out), flush=True)
     return 0

@@ -437,6 +437,19 @@ wo_status wo_search_best(wo_search *s, uint8_t *h_zone_of, uint16_t *h_seq, int3
 wo_status wo_search_population(wo_search *s, uint8_t *d_zone_of, uint16_t *d_seq, int32_t *d_dist,
                                int32_t *d_last_kept, void *stream);
 
+/* ------------------------------------------------------------------ */
+/* Diagnostics                                                          */
+/* ------------------------------------------------------------------ */
+
+/* Measured 32-bit integer VALU throughput of the current device, in
+ * operations per second: the denominator of the evaluator's roofline
+ * measured rather than derived from unit counts and clock.  Every lane of a
+ * grid that fills every CU runs independent chains of 32-bit adds and
+ * exclusive ors (one operation per lane per instruction); the best of `reps`
+ * (1 .. 100) timed launches counts.  Synchronous; allocates a small output
+ * buffer. */
+wo_status wo_measure_int_peak(int32_t reps, double *ops_per_s, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -75,6 +75,8 @@ def _load():
             f.restype = ctypes.c_int64
         lib.orc_eval_plan.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.orc_int_ops.argtypes = [ctypes.c_int64, ctypes.c_uint32, P(ctypes.c_uint32)]
+        lib.orc_int_ops.restype = ctypes.c_int64
         lib.orc_eval_plans.argtypes = [P(_Inst), ctypes.c_int64, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                                        ctypes.c_int]
@@ -209,3 +211,19 @@ def eval_plans(inst, zone_of, seq, n_threads: int = 1):
     _check(_load().orc_eval_plans(b.ref(), n, z.ctypes.data, s.ctypes.data,
                                   dist.ctypes.data, thr.ctypes.data, int(n_threads)))
     return dist, thr
+
+
+def int_ops_per_second(min_s: float = 0.3) -> float:
+    """Measured scalar integer operations per second of one core (eight
+    independent add/xor chains), for the CPU roofline of the baseline timing."""
+    import time
+    lib = _load()
+    sink = ctypes.c_uint32(0)
+    steps = 1 << 20
+    while True:
+        t0 = time.perf_counter()
+        ops = lib.orc_int_ops(steps, 12345, ctypes.byref(sink))
+        dt = time.perf_counter() - t0
+        if dt >= min_s:
+            return ops / dt
+        steps *= 2

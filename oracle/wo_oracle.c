@@ -671,3 +671,27 @@ int orc_eval_plans(const orc_instance *w, int64_t n_plans, const uint8_t *zone_o
     pthread_mutex_destroy(&job.mu);
     return job.rc;
 }
+
+/* Scalar integer throughput of one core, for the CPU side of the roofline
+ * that the benchmark reports beside the oracle's timing (not part of the
+ * method): eight independent chains of one add and one exclusive or per
+ * step.  Returns the operations performed; the chains' combination goes to
+ * *sink so that nothing is folded away. */
+int64_t orc_int_ops(int64_t steps, uint32_t seed, uint32_t *sink)
+{
+    uint32_t a0 = seed, a1 = seed ^ 1u, a2 = seed ^ 2u, a3 = seed ^ 3u;
+    uint32_t a4 = seed ^ 4u, a5 = seed ^ 5u, a6 = seed ^ 6u, a7 = seed ^ 7u;
+    const uint32_t c = seed | 1u, d = seed * 2654435761u;
+    for (int64_t i = 0; i < steps; i++) {
+        a0 = (a0 + c) ^ d;
+        a1 = (a1 + c) ^ d;
+        a2 = (a2 + c) ^ d;
+        a3 = (a3 + c) ^ d;
+        a4 = (a4 + c) ^ d;
+        a5 = (a5 + c) ^ d;
+        a6 = (a6 + c) ^ d;
+        a7 = (a7 + c) ^ d;
+    }
+    *sink = a0 ^ a1 ^ a2 ^ a3 ^ a4 ^ a5 ^ a6 ^ a7;
+    return steps * 16;
+}

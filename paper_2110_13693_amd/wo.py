@@ -32,7 +32,7 @@ EXPORTS = sorted([
     "wo_search_create", "wo_search_free", "wo_search_step", "wo_search_best", "wo_search_population",
     "wo_search_save", "wo_search_load",
     "wo_set_eval_config", "wo_get_eval_config", "wo_autotune_eval",
-    "wo_kmeans_categories", "wo_kmeans_categories_noalloc",
+    "wo_kmeans_categories", "wo_kmeans_categories_noalloc", "wo_measure_int_peak",
 ])
 WO_SUR_PARAMS = 4457985
 WO_SCREEN_MAX_KEEP = 4096
@@ -115,6 +115,7 @@ def lib():
         L.wo_search_load.argtypes = [V, I32, ctypes.c_char_p, V, P(V)]
         L.wo_kmeans_categories.argtypes = [V, I64, I32, I32, I32, V, P(I32), P(I32), V]
         L.wo_kmeans_categories_noalloc.argtypes = [V, I64, I32, I32, I32, V, V, V, V]
+        L.wo_measure_int_peak.argtypes = [I32, P(F64), V]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype if name in (
                 "wo_status_str", "wo_last_error") else ctypes.c_int
@@ -383,6 +384,13 @@ def wo_kmeans_categories_noalloc(order_skus, n_skus: int, k: int, category, k_us
         _ptr(order_skus, 4, "order_skus"), int(order_skus.numel()), int(n_skus), int(k), int(max_iter),
         _ptr(category, 4, "category"), _ptr(k_used, 4, "k_used") if k_used is not None else None,
         _ptr(n_iter, 4, "n_iter") if n_iter is not None else None, ctypes.c_void_p(_stream_handle(stream))))
+
+
+def wo_measure_int_peak(reps: int = 5, stream=None) -> float:
+    """Measured 32-bit integer VALU operations per second of the device."""
+    v = ctypes.c_double(0.0)
+    _check(lib().wo_measure_int_peak(int(reps), ctypes.byref(v), ctypes.c_void_p(_stream_handle(stream))))
+    return v.value
 
 
 # ---------------------------------------------------------------------------
