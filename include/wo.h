@@ -39,6 +39,15 @@
  *     return WO_E_DEVICE.
  *   - Handles are not thread-safe; a handle used from two threads at once
  *     returns WO_E_STATE for the second caller.
+ *   - One stream per handle, or ordered streams: a handle keeps device state
+ *     that its calls share and upload in their own stream (for
+ *     wo_eval_plans: the plan map and the tables built from it, the queue
+ *     tickets, the validation flag, the first-fit tour table).  A call on a
+ *     stream other than the previous call's, while that call may still be
+ *     running, returns WO_E_STATE and enqueues nothing when either call
+ *     rewrites that state; when neither does, the library orders the new
+ *     call after the previous one.  Replays of a captured graph are not seen
+ *     by the handle: the caller orders them with its other calls.
  */
 #ifndef WO_H
 #define WO_H

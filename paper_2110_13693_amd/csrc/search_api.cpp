@@ -303,14 +303,28 @@ extern "C" wo_status wo_search_load(wo_wh *wh, int32_t inst, const char *path, v
     bool ok = fread(&h, sizeof h, 1, f) == 1 && memcmp(h.magic, kSearchMagic, 8) == 0 && h.n_orders >= 1 &&
               h.n_orders <= WO_MAX_ORDERS && h.population >= 2 && h.population <= (1 << 24) && h.n_cat >= 1 &&
               h.n_cat <= WO_MAX_CATEGORIES && h.prm.population == h.population;
+    // the file must be exactly as long as its header says before anything
+    // is sized from the header
+    if (ok) {
+        const uint64_t P = (uint64_t)h.population, n = (uint64_t)h.n_orders;
+        const uint64_t want = sizeof h + P * 64 + P * n * 2 + P * 4;
+        ok = fseek(f, 0, SEEK_END) == 0;
+        const long len = ok ? ftell(f) : -1;
+        ok = ok && len >= 0 && (uint64_t)len == want && fseek(f, (long)sizeof h, SEEK_SET) == 0;
+    }
     std::vector<uint8_t> z;
     std::vector<uint16_t> q;
     std::vector<int32_t> d;
     if (ok) {
         const size_t P = (size_t)h.population, n = (size_t)h.n_orders;
-        z.resize(P * 64);
-        q.resize(P * n);
-        d.resize(P);
+        try {
+            z.resize(P * 64);
+            q.resize(P * n);
+            d.resize(P);
+        } catch (const std::bad_alloc &) {
+            fclose(f);
+            return wo_fail(WO_E_NOMEM, "no host memory for a checkpoint of %zu plans", P);
+        }
         ok = fread(z.data(), 1, z.size(), f) == z.size() && fread(q.data(), 2, q.size(), f) == q.size() &&
              fread(d.data(), 4, d.size(), f) == d.size();
     }

@@ -124,6 +124,14 @@ struct wo_wh {
     int64_t pinst_cap = 0;
     std::vector<int32_t> pinst_host;
     std::vector<int64_t> pinst_map;     // plan map d_pinst was built for
+    // The device state above is shared by every call on the handle.  A call
+    // on a stream other than the previous call's may rewrite it only once
+    // that call has finished: the previous call's completion is recorded in
+    // last_done (outside graph capture).
+    hipEvent_t last_done = nullptr;
+    hipStream_t last_stream = nullptr;
+    bool has_last = false;
+    bool last_wrote = false;            // the previous call rewrote shared state (its uploads run in its stream)
     std::atomic<int> busy{0};
 };
 
@@ -472,6 +480,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     if ((st = dev_alloc((void **)&wh->d_inst, sizeof(InstDev) * n_instances))) return st;
     if ((st = dev_alloc((void **)&wh->d_map, sizeof(int64_t) * (2 * n_instances + 1)))) return st;
     if ((st = dev_alloc((void **)&wh->d_err, 64))) return st;
+    HIP_TRY(hipEventCreateWithFlags(&wh->last_done, hipEventDisableTiming));
     wh->d_lines = (const uint2 *)wh->d_pool;
     wh->d_cnt = (const uint8_t *)wh->d_pool + o_cnt;
     wh->d_grec = (const uint32_t *)((const char *)wh->d_pool + o_grec);
@@ -514,6 +523,7 @@ extern "C" wo_status wo_free_warehouse(wo_wh *wh)
         if (c.d_work) (void)hipFree(c.d_work);
     if (wh->d_pinst) (void)hipFree(wh->d_pinst);
     if (wh->d_ff_tour) (void)hipFree(wh->d_ff_tour);
+    if (wh->last_done) (void)hipEventDestroy(wh->last_done);
     delete wh;
     return WO_OK;
 }
@@ -627,6 +637,41 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     if (n_plans == 0) return WO_OK;
     if (!d_zone_of || !d_order_seq || !d_dist) return fail(WO_E_INVAL, "NULL device buffer");
     hipStream_t s = (hipStream_t)stream;
+    const bool validate = env_flag("WO_VALIDATE", "1");
+    {
+        // shared device state this call writes: the plan map and the tables
+        // built from it, the queue tickets, the validation flag, the
+        // first-fit tour table
+        bool any_small = false;
+        for (int32_t i = 0; i < wh->n_inst; i++) any_small |= class_of(wh, i) != 0 && map[i + 1] > map[i];
+        const bool writes = map != wh->map_cached || (wh->n_inst > 1 && (map != wh->pinst_map || wh->pinst_cap < n_plans)) ||
+                            ((any_small || wh->queue) && (map != wh->wc_map || wh->wc_small != wh->small_orders)) ||
+                            wh->queue || validate || wh->batching == WO_BATCH_FIRST_FIT;
+        // A call on another stream while the previous call may still run:
+        // refused when it would rewrite state the previous call reads, or
+        // read state whose upload the previous call enqueued on its own
+        // stream; when both only read, it is ordered after the previous call
+        // so that one event keeps marking the completion of every earlier
+        // call.
+        // (Under graph capture nothing here runs: an event query would
+        // invalidate the capture, and a captured call runs only when its
+        // graph is replayed, which the caller orders.)
+        hipStreamCaptureStatus cap0 = hipStreamCaptureStatusNone;
+        HIP_TRY(hipStreamIsCapturing(s, &cap0));
+        if (cap0 == hipStreamCaptureStatusNone && wh->has_last && s != wh->last_stream) {
+            const hipError_t q = hipEventQuery(wh->last_done);
+            if (q == hipErrorNotReady) {
+                if (writes || wh->last_wrote)
+                    return fail(WO_E_STATE, "the handle's previous call, on another stream, may still be running "
+                                "and one of the two calls rewrites state the other reads; order the two streams "
+                                "or use one stream");
+                HIP_TRY(hipStreamWaitEvent(s, wh->last_done, 0));
+            } else {
+                (void)hipGetLastError();
+            }
+        }
+        wh->last_wrote = writes;
+    }
     if (map != wh->map_cached) {
         wh->map_cached = map;
         HIP_TRY(hipMemcpyAsync(wh->d_map, wh->map_cached.data(), sizeof(int64_t) * map.size(),
@@ -650,7 +695,6 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
                                hipMemcpyHostToDevice, s));
         wh->pinst_map = map;
     }
-    const bool validate = env_flag("WO_VALIDATE", "1");
     if (validate) HIP_TRY(hipMemsetAsync(wh->d_err, 0, 4, s));
 
     EvalArgs a;
@@ -703,6 +747,15 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
             const int per_cu = c ? 0 : wh->per_cu;
             HIP_TRY(launch_eval(ac, w.lds, launch_grid(wh, block, per_cu, w.lds, w.n), block, wh->route, s));
         }
+    }
+    // the completion of this call, for the next call on another stream (not
+    // under graph capture: a captured call runs only when its graph does)
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    HIP_TRY(hipStreamIsCapturing(s, &cap));
+    if (cap == hipStreamCaptureStatusNone) {
+        HIP_TRY(hipEventRecord(wh->last_done, s));
+        wh->last_stream = s;
+        wh->has_last = true;
     }
     if (validate) {
         int32_t err = 0;

@@ -212,6 +212,18 @@ def test_search_load_rejects_bad_files(wo, tmp_path):
     short.write_bytes(b"WOSRCH01" + bytes(10))
     assert wo.lib().wo_search_load(None, 0, str(short).encode(), None, ctypes.byref(out)) == wo.WO_E_INVAL
     assert out.value is None
+    # a header that claims the largest sizes (2^24 plans of 65,535 orders,
+    # about 2 TB) on a tiny file: refused from the file length, before any
+    # buffer is sized from the header
+    import struct
+    hdr = struct.pack("<8s4i iiIii4xQ II", b"WOSRCH01", 65535, 64, 1 << 24, 0,
+                      1 << 24, 4, 85899345, 0, 0, 1, 0, 0)
+    assert len(hdr) == 64
+    huge = tmp_path / "huge.bin"
+    huge.write_bytes(hdr + bytes(64))
+    assert wo.lib().wo_search_load(None, 0, str(huge).encode(), None, ctypes.byref(out)) == wo.WO_E_INVAL
+    assert "not a search checkpoint" in wo.wo_last_error()
+    assert out.value is None
 
 
 def test_kmeans_noalloc_rejects_sizes_beyond_its_scratch(wo):

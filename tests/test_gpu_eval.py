@@ -227,3 +227,65 @@ def test_repeat_calls_deterministic():
     d2, t2 = gpu_eval(wh, Z, S)
     wh.free()
     assert np.array_equal(d1, d2) and np.array_equal(t1, t2)
+
+
+def test_layout_change_on_another_stream_while_busy_is_refused():
+    # The plan map and the tables built from it are shared by every call on
+    # a handle, and a call uploads them in its own stream.  While the
+    # previous call (first stream) may still run, a call on a second stream
+    # is refused when either call rewrites that state; two calls that only
+    # read it may overlap; once the first stream has drained, the new layout
+    # is accepted too.  Results are checked against the oracle.
+    import torch
+    wo = _wo()
+    rng = np.random.default_rng(5)
+    insts = [_random_instance(rng, 12, 250, 300, 30, 64), _random_instance(rng, 20, 250, 500, 30, 64)]
+
+    def layout(per):
+        Zs, Ss = [], []
+        for inst, k in zip(insts, per):
+            Z, S = synth.make_plans(inst, k, seed=int(rng.integers(1 << 30)))
+            Zs.append(Z)
+            Ss.append(S.reshape(-1))
+        return Zs, Ss, [0, per[0], per[0] + per[1]]
+
+    Z1, S1, off1 = layout((8, 8))
+    Z2, S2, off2 = layout((4, 12))
+    wh = wo.wo_load_warehouse(insts)
+
+    def dev(Zs, Ss):
+        z = torch.from_numpy(np.concatenate(Zs)).cuda()
+        s = torch.from_numpy(np.concatenate(Ss).view(np.int16)).cuda()
+        return z, s, torch.full((z.shape[0],), -1, dtype=torch.int32, device="cuda")
+
+    z1, s1, d0 = dev(Z1, S1)
+    z2, s2, d2 = dev(Z2, S2)
+    _, _, d1 = dev(Z1, S1)
+    _, _, d3 = dev(Z1, S1)
+    # the first layout's tables are uploaded and in place before the streams
+    wo.wo_eval_plans(wh, z1, s1, d0, plan_offsets=off1)
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Stream(), torch.cuda.Stream()
+    x = torch.randn(4096, 4096, device="cuda")
+    w = torch.randn(4096, 4096, device="cuda") / 64.0
+    torch.cuda.synchronize()
+    with torch.cuda.stream(a):
+        for _ in range(40):          # tens of milliseconds of work ahead of the call
+            x = x @ w
+        wo.wo_eval_plans(wh, z1, s1, d1, plan_offsets=off1, stream=a)
+    print("stream a busy; a new layout on stream b", flush=True)
+    with pytest.raises(wo.WoError) as e:
+        wo.wo_eval_plans(wh, z2, s2, d2, plan_offsets=off2, stream=b)
+    assert e.value.status == wo.WO_E_STATE
+    # the same layout only reads the shared tables
+    wo.wo_eval_plans(wh, z1, s1, d3, plan_offsets=off1, stream=b)
+    torch.cuda.synchronize()
+    wo.wo_eval_plans(wh, z2, s2, d2, plan_offsets=off2, stream=b)
+    torch.cuda.synchronize()
+    for (Zs, Ss, off), d in (((Z1, S1, off1), d0), ((Z1, S1, off1), d1), ((Z1, S1, off1), d3),
+                             ((Z2, S2, off2), d2)):
+        got = d.cpu().numpy()
+        for i, inst in enumerate(insts):
+            ref, _ = oracle.eval_plans(inst, Zs[i], Ss[i].reshape(off[i + 1] - off[i], -1))
+            assert np.array_equal(got[off[i]:off[i + 1]], ref)
+    wh.free()
