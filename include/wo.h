@@ -447,6 +447,55 @@ wo_status wo_search_population(wo_search *s, uint8_t *d_zone_of, uint16_t *d_seq
                                int32_t *d_last_kept, void *stream);
 
 /* ------------------------------------------------------------------ */
+/* Aisle width design                                                   */
+/* ------------------------------------------------------------------ */
+/* Section 5, Subproblem 1, Eq. (1): maximise the share of the floor the
+ * racks take, A_ind / A_max, with the width a between racks as the design
+ * variable, subject to k * delta - a <= 0, where delta is the picking
+ * frequency Subproblem 2 returns for the plan (Eq. (2): delta = f(d)).
+ * Reading of the single-block geometry: each aisle is a corridor of width a
+ * with a rack face of depth r on each side (neighbouring aisles' racks stand
+ * back to back), so aisles are a + 2 r apart centre to centre; racks are
+ * L = slots_per_side * pitch long; a cross aisle of width c runs along the
+ * front and the back:
+ *     A_ind / A_max = 2 r L / ((a + 2 r) (L + 2 c)),
+ * falling with a.  delta is the evaluator's orders per window,
+ * n_orders * window / (D / walk + t_item * items), and D grows with the
+ * spacing, so the constraint holds from one width on and the optimum is the
+ * smallest width in [min_width_dm, max_width_dm] that meets it.  k is the
+ * width (dm) the flow of one order per window needs. */
+#define WO_AISLE_MAX_WIDTHS 4096
+typedef struct {
+    int32_t rack_depth_dm;     /* r >= 1 */
+    int32_t cross_aisle_dm;    /* c >= 0 */
+    int32_t min_width_dm;      /* >= 1 */
+    int32_t max_width_dm;      /* >= min; at most WO_AISLE_MAX_WIDTHS widths in the range */
+    double k_dm;               /* >= 0 */
+} wo_aisle_params;
+
+typedef struct {
+    int32_t width_dm;          /* the optimum a (max_width_dm when no width is feasible) */
+    int32_t spacing_dm;        /* a + 2 r: the aisles' centre-to-centre distance */
+    int32_t feasible;          /* 1 when k * delta <= a holds at width_dm */
+    int32_t widths_evaluated;
+    int32_t distance;          /* D of the plan at width_dm (int32, saturating) */
+    double orders_per_window;  /* delta at width_dm, in IEEE double */
+    double utilization;        /* A_ind / A_max at width_dm */
+} wo_aisle_result;
+
+/* Evaluates the plan of instance `inst` (d_zone_of: 64 bytes, d_order_seq:
+ * n_orders uint16 on the device) at every whole-decimetre width of the range
+ * in one launch of the exact evaluator, each copy of the plan with its own
+ * spacing (the load's spacing_dm is not used), and returns the narrowest
+ * width meeting the constraint, deciding each width in IEEE double from the
+ * integer distance.  h_dist (host int32[max - min + 1], nullable) receives
+ * D at every width.  The handle's route and batching apply; the optimal
+ * route needs 4 (max + 2 r)(N + 2) + 4 L (N + 1) < 2^30 dm (else
+ * WO_E_RANGE).  Synchronous; allocates its own buffers. */
+wo_status wo_aisle_width(wo_wh *wh, int32_t inst, const uint8_t *d_zone_of, const uint16_t *d_order_seq,
+                         const wo_aisle_params *params, int32_t *h_dist, void *stream, wo_aisle_result *out);
+
+/* ------------------------------------------------------------------ */
 /* Diagnostics                                                          */
 /* ------------------------------------------------------------------ */
 

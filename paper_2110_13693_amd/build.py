@@ -15,7 +15,7 @@ CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libwo.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 SOURCES = ["wo_api.cpp", "eval.hip", "surrogate.hip", "surrogate_api.cpp", "search.hip", "search_api.cpp",
-           "firstfit.hip", "kmeans.hip", "peaks.hip"]
+           "firstfit.hip", "kmeans.hip", "peaks.hip", "aisle.hip"]
 ARCH = "gfx950"
 
 

@@ -612,6 +612,7 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
 
             // ---- 5./6. aisle sets and S-shape per tour tile ------------------
             const uint32_t magic = I.magic;
+            const int32_t wsp = A.plan_spacing ? A.plan_spacing[p] : I.spacing;   // aisle spacing of this plan
             for (uint32_t t0 = 0; t0 < n_tours; t0 += (uint32_t)T) {
                 if (t0 > 0) {
                     __syncthreads();                     // the previous tile's rows are read
@@ -749,7 +750,7 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
 #pragma unroll
                         for (int i = 0; i < MAX_PICK_SLOTS; i++) v[i] = (uint32_t)i < np ? rw[1 + i] : 0xFFFFFFFFu;
                         sort32(v);
-                        acc += pick_route_cost<ROUTE>(v, np, I, magic);
+                        acc += pick_route_cost<ROUTE>(v, np, wsp, I, magic);
                     }
                     continue;
                 }
@@ -764,7 +765,7 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
                     const uint32_t a = mulhi24(ls, magic);
                     const uint32_t j = (ls - a * I.d_s) >> (I.shift + 1);
                     const int64_t y = (int64_t)j * I.pitch + I.pitch / 2;
-                    int64_t cost = 2ll * I.spacing * a;
+                    int64_t cost = 2ll * wsp * a;
                     cost += (k & 1) ? (int64_t)(k - 1) * I.L + 2 * y : (int64_t)k * I.L;
                     acc += cost;
                 }

@@ -115,7 +115,7 @@ static __device__ __forceinline__ void opt_aisle(OptClasses &s, int32_t L, int32
 // sorted by scaled location, i.e. by aisle and then depth (section 5,
 // Subproblem 2).
 template <int ROUTE>
-static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MAX_PICK_SLOTS], uint32_t np,
+static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MAX_PICK_SLOTS], uint32_t np, int32_t spacing,
                                                           const InstDev &I, uint32_t magic)
 {
     const int32_t L = I.L;
@@ -135,7 +135,7 @@ static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MA
                 if (i == 0) {
                     ylo = y;
                 } else if (a != ca) {                 // aisle ca is complete
-                    if (ca != done) opt_run(s, (int32_t)(ca - done), I.spacing, L);
+                    if (ca != done) opt_run(s, (int32_t)(ca - done), spacing, L);
                     opt_aisle(s, L, 2 * yhi, 2 * (L - ylo), gap >= 0 ? 2 * (L - gap) : 2 * L);
                     done = ca;
                     ca = a;
@@ -147,7 +147,7 @@ static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MA
                 yhi = y;
             }
         }
-        if (ca != done) opt_run(s, (int32_t)(ca - done), I.spacing, L);
+        if (ca != done) opt_run(s, (int32_t)(ca - done), spacing, L);
         opt_aisle(s, L, 2 * yhi, 2 * (L - ylo), gap >= 0 ? 2 * (L - gap) : 2 * L);
         return (int64_t)min(min(s.f, s.b), s.e1);     // even ends, one component
     }
@@ -155,7 +155,7 @@ static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MA
         // each aisle with picks crossed or entered and left from the cross
         // aisle the picker is on, best choice by one length per cross aisle;
         // the walk ends on the front (crossing the last aisle from the back)
-        const int64_t W = I.spacing, L2 = 2ll * L;
+        const int64_t W = spacing, L2 = 2ll * L;
         int64_t front = 0, back = (int64_t)1 << 60;   // the back is not reachable yet
         uint32_t done = 0;
         int32_t ylo = 0, yhi = 0;
@@ -205,7 +205,7 @@ static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MA
             py = y;
         }
     }
-    const int64_t horiz = 2ll * I.spacing * ca;       // ca is the farthest aisle now
+    const int64_t horiz = 2ll * spacing * ca;       // ca is the farthest aisle now
     if (ROUTE == WO_ROUTE_RETURN) return horiz + 2 * (sum + py);
     if (ca == a_lo) return horiz + 2ll * py;           // one aisle: the return route
     return horiz + 2ll * L + 2 * sum;

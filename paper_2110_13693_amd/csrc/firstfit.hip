@@ -48,6 +48,7 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
         const int n = I.n_orders;
         const int C = I.n_cat;
         const int32_t Q = I.capacity;
+        const int32_t wsp = A.plan_spacing ? A.plan_spacing[p] : I.spacing;   // aisle spacing of this plan
         const int64_t row = p - (A.n_inst > 1 ? A.plan_begin[ii] : 0);
         const uint16_t *seq = A.seq + A.seq_base[ii] + row * (int64_t)n;
         const uint8_t *cnt = A.cnt + I.cnt_off;
@@ -215,7 +216,7 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
                     for (int w = 0; w < I.words; w++) k += __popc(rw[1 + w]);
                     const uint32_t a = mulhi24(ls, I.magic);
                     const int64_t y = (int64_t)((ls - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
-                    acc += 2ll * I.spacing * a + ((k & 1) ? (int64_t)(k - 1) * I.L + 2 * y : (int64_t)k * I.L);
+                    acc += 2ll * wsp * a + ((k & 1) ? (int64_t)(k - 1) * I.L + 2 * y : (int64_t)k * I.L);
                 } else {
                     const uint32_t np = min(rw[0], (uint32_t)I.pick_slots);
                     if (np == 0) continue;                  // only a malformed row leaves a tour empty
@@ -223,7 +224,7 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
 #pragma unroll
                     for (int i = 0; i < MAX_PICK_SLOTS; i++) v[i] = (uint32_t)i < np ? rw[1 + i] : 0xFFFFFFFFu;
                     sort32(v);
-                    acc += pick_route_cost<ROUTE>(v, np, I, I.magic);
+                    acc += pick_route_cost<ROUTE>(v, np, wsp, I, I.magic);
                 }
             }
             __syncthreads();

@@ -721,6 +721,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.work = nullptr;
     a.ff_tour = wh->d_ff_tour;
     a.ff_stride = wh->ff_stride;
+    a.plan_spacing = nullptr;
     bool any_small = false;
     for (int32_t i = 0; i < wh->n_inst; i++) any_small |= class_of(wh, i) != 0 && map[i + 1] > map[i];
     if (wh->batching == WO_BATCH_FIRST_FIT) {
@@ -770,7 +771,8 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
 // instance's order count), for callers inside the library.  No argument
 // checks beyond the handle's: the caller owns the buffers.
 wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint8_t *d_zone_of,
-                            const uint16_t *d_order_seq, int32_t *d_dist, float *d_thr, hipStream_t s)
+                            const uint16_t *d_order_seq, int32_t *d_dist, float *d_thr, hipStream_t s,
+                            const int32_t *d_plan_spacing)
 {
     if (n_plans <= 0) return WO_OK;
     EvalArgs a;
@@ -798,6 +800,7 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.work = nullptr;
     a.ff_tour = wh->d_ff_tour;
     a.ff_stride = wh->ff_stride;
+    a.plan_spacing = d_plan_spacing;
     if (wh->batching == WO_BATCH_FIRST_FIT) {
         const uint32_t lds = wh->ff_lds[inst];
         HIP_TRY(launch_eval_ff(a, lds, ff_grid(wh, lds, n_plans), wh->route, s));
@@ -809,6 +812,7 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
 }
 
 int32_t wo::instance_orders(const wo_wh *wh, int32_t inst) { return wh->inst[inst].n_orders; }
+const InstDev &wo::instance_dev(const wo_wh *wh, int32_t inst) { return wh->inst[inst]; }
 int32_t wo::instance_categories(const wo_wh *wh, int32_t inst) { return wh->inst[inst].n_cat; }
 int32_t wo::instance_count(const wo_wh *wh) { return wh->n_inst; }
 

@@ -83,6 +83,7 @@ struct EvalArgs {
     const int32_t *work;    // work item -> plan row (null: identity)
     uint16_t *ff_tour;      // first fit: tour of every order, ff_stride entries per workgroup
     int64_t ff_stride;
+    const int32_t *plan_spacing;   // device [n_plans]: aisle spacing of each plan row (null: the instance's)
 };
 
 // Parallel next-fit: lanes that chase candidate tour chains (at most
@@ -183,7 +184,9 @@ int eval_ff_max_blocks_per_cu(int route, uint32_t lds_bytes);
 
 // library-internal helpers over a loaded handle
 wo_status eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint8_t *d_zone_of,
-                        const uint16_t *d_order_seq, int32_t *d_dist, float *d_thr, hipStream_t s);
+                        const uint16_t *d_order_seq, int32_t *d_dist, float *d_thr, hipStream_t s,
+                        const int32_t *d_plan_spacing = nullptr);
+const InstDev &instance_dev(const wo_wh *wh, int32_t inst);
 int32_t instance_orders(const wo_wh *wh, int32_t inst);
 int32_t instance_categories(const wo_wh *wh, int32_t inst);
 int32_t instance_count(const wo_wh *wh);

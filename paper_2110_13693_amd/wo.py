@@ -32,7 +32,7 @@ EXPORTS = sorted([
     "wo_search_create", "wo_search_free", "wo_search_step", "wo_search_best", "wo_search_population",
     "wo_search_save", "wo_search_load",
     "wo_set_eval_config", "wo_get_eval_config", "wo_autotune_eval",
-    "wo_kmeans_categories", "wo_kmeans_categories_noalloc", "wo_measure_int_peak",
+    "wo_kmeans_categories", "wo_kmeans_categories_noalloc", "wo_measure_int_peak", "wo_aisle_width",
 ])
 WO_SUR_PARAMS = 4457985
 WO_SCREEN_MAX_KEEP = 4096
@@ -54,6 +54,17 @@ class wo_search_params(ctypes.Structure):
     _fields_ = [("population", ctypes.c_int32), ("tournament", ctypes.c_int32),
                 ("mutation_threshold", ctypes.c_uint32), ("candidates", ctypes.c_int32),
                 ("keep", ctypes.c_int32), ("seed", ctypes.c_uint64)]
+
+
+class wo_aisle_params(ctypes.Structure):
+    _fields_ = [("rack_depth_dm", ctypes.c_int32), ("cross_aisle_dm", ctypes.c_int32),
+                ("min_width_dm", ctypes.c_int32), ("max_width_dm", ctypes.c_int32), ("k_dm", ctypes.c_double)]
+
+
+class wo_aisle_result(ctypes.Structure):
+    _fields_ = [("width_dm", ctypes.c_int32), ("spacing_dm", ctypes.c_int32), ("feasible", ctypes.c_int32),
+                ("widths_evaluated", ctypes.c_int32), ("distance", ctypes.c_int32),
+                ("orders_per_window", ctypes.c_double), ("utilization", ctypes.c_double)]
 
 
 class wo_instance_desc(ctypes.Structure):
@@ -116,6 +127,7 @@ def lib():
         L.wo_kmeans_categories.argtypes = [V, I64, I32, I32, I32, V, P(I32), P(I32), V]
         L.wo_kmeans_categories_noalloc.argtypes = [V, I64, I32, I32, I32, V, V, V, V]
         L.wo_measure_int_peak.argtypes = [I32, P(F64), V]
+        L.wo_aisle_width.argtypes = [V, I32, V, V, P(wo_aisle_params), V, V, P(wo_aisle_result)]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype if name in (
                 "wo_status_str", "wo_last_error") else ctypes.c_int
@@ -384,6 +396,23 @@ def wo_kmeans_categories_noalloc(order_skus, n_skus: int, k: int, category, k_us
         _ptr(order_skus, 4, "order_skus"), int(order_skus.numel()), int(n_skus), int(k), int(max_iter),
         _ptr(category, 4, "category"), _ptr(k_used, 4, "k_used") if k_used is not None else None,
         _ptr(n_iter, 4, "n_iter") if n_iter is not None else None, ctypes.c_void_p(_stream_handle(stream))))
+
+
+def wo_aisle_width(wh: Warehouse, zone_of, order_seq, rack_depth_dm: int, cross_aisle_dm: int, k_dm: float,
+                   min_width_dm: int, max_width_dm: int, inst: int = 0, stream=None):
+    """Aisle width design for one plan (zone row of 64 bytes and sequence of
+    n_orders uint16 on the GPU): returns (result dict, distance at every
+    width of the range as a numpy array)."""
+    import numpy as np
+    prm = wo_aisle_params(int(rack_depth_dm), int(cross_aisle_dm), int(min_width_dm), int(max_width_dm), float(k_dm))
+    n_w = max(0, int(max_width_dm) - int(min_width_dm) + 1)
+    dist = np.zeros(max(n_w, 1), dtype=np.int32)
+    out = wo_aisle_result()
+    _check(lib().wo_aisle_width(wh.handle, int(inst), _ptr(zone_of, 1, "zone_of"), _ptr(order_seq, 2, "order_seq"),
+                                ctypes.byref(prm), dist.ctypes.data, ctypes.c_void_p(_stream_handle(stream)),
+                                ctypes.byref(out)))
+    res = {f: getattr(out, f) for f, _ in wo_aisle_result._fields_}
+    return res, dist[:n_w]
 
 
 def wo_measure_int_peak(reps: int = 5, stream=None) -> float:
