@@ -459,6 +459,63 @@ def kmeans_bench(args):
     return 0
 
 
+def svm_bench(args):
+    """Order categories (section 5, subroutine 5) on 1,048,576 synthetic typed
+    orders over the paper-scale warehouse's 64 categories, 8 order types:
+    features of every order, one training step on a window of 65,536 orders,
+    and categories of every order.  The prediction pass reads each order's
+    64 double features once: it is bound by HBM."""
+    import torch
+
+    import synth
+    from paper_2110_13693_amd import wo
+
+    torch.cuda.set_device(0)
+    inst, _, _ = synth.workload("paper", n_plans=1)
+    n, K, F, W = 1 << 20, 8, 64, 1 << 16
+    off, skus, ty = synth.make_typed_orders(n, K, inst.sku_category, inst.n_categories, drift=0.5, seed=0)
+    d_off = torch.from_numpy(off).cuda()
+    d_sku = torch.from_numpy(skus).cuda()
+    d_cat = torch.from_numpy(np.ascontiguousarray(inst.sku_category, np.int32)).cuda()
+    d_ty = torch.from_numpy(ty).cuda()
+    x = torch.empty((n, F), dtype=torch.float64, device="cuda")
+    cls = torch.empty(n, dtype=torch.int32, device="cuda")
+    stream = torch.cuda.current_stream()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+
+    def timed(fn, reps):
+        fn()
+        torch.cuda.synchronize()
+        ev0.record(stream)
+        for _ in range(reps):
+            fn()
+        ev1.record(stream)
+        torch.cuda.synchronize()
+        return ev0.elapsed_time(ev1) / reps
+
+    feat_ms = timed(lambda: wo.wo_order_features(d_off, d_sku, d_cat, F, x), 10)
+    m = wo.wo_svm_create(F, K, W, 1e-3)
+    wo.wo_svm_push(m, x[n - W:], d_ty[n - W:])
+    train_ms = timed(lambda: wo.wo_svm_train(m, 1), 5)
+    wo.wo_svm_train(m, 100)
+    pred_ms = timed(lambda: wo.wo_svm_predict(m, x, cls), 20)
+    acc = float((cls[: n - W] == d_ty[: n - W]).float().mean().item())
+    m.free()
+    bytes_pred = n * (F * 8 + 4)
+    out = {"metric": "order categories per second (SVM prediction)", "value": n / (pred_ms / 1e3),
+           "unit": "orders/s", "n_gpus": 1, "steps": 20, "ms_per_step": pred_ms, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "1,048,576 typed orders (8 types, drifting), 64 categories of the paper-scale "
+                                  "warehouse; window of 65,536 orders, lambda 1e-3",
+                      "features_ms": feat_ms, "train_step_ms": train_ms,
+                      "accuracy_on_older_orders_after_106_steps": acc},
+           "roofline": {"bound": "hbm", "achieved": bytes_pred / (pred_ms / 1e3) / 1e9,
+                        "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
+                        "frac": bytes_pred / (pred_ms / 1e3) / HBM_PEAK_BYTES, "traffic": None}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def surrogate_bench(args):
     """Surrogate throughput on the BF16 matrix cores: screening predictions
     (65,536 candidates per call) and training (batch 4,096), on random
@@ -542,6 +599,8 @@ def main(argv=None):
                     help="time the 512-instance uneven batch (autotuned, eager and graph replay) instead")
     ap.add_argument("--kmeans", action="store_true",
                     help="time K-means class-based storage on the paper-scale order history instead")
+    ap.add_argument("--svm", action="store_true",
+                    help="time order-category features, SVM training and prediction instead")
     ap.add_argument("--surrogate", action="store_true",
                     help="time surrogate screening and training on the matrix cores instead")
     ap.add_argument("--copy-probe", type=int, default=0, metavar="MIB",
@@ -560,6 +619,8 @@ def main(argv=None):
         return surrogate_bench(args)
     if args.kmeans:
         return kmeans_bench(args)
+    if args.svm:
+        return svm_bench(args)
     if args.copy_probe:
         import torch
         a = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")

@@ -496,6 +496,66 @@ wo_status wo_aisle_width(wo_wh *wh, int32_t inst, const uint8_t *d_zone_of, cons
                          const wo_aisle_params *params, int32_t *h_dist, void *stream, wo_aisle_result *out);
 
 /* ------------------------------------------------------------------ */
+/* Order categories (SVM)                                               */
+/* ------------------------------------------------------------------ */
+/* Section 5, subroutine 5: every order belongs to a category of orders; an
+ * SVM (Cortes and Vapnik 1995) configures the categories from the outputs of
+ * the subroutines before it and is refreshed continuously from a window of
+ * the most recent orders, newer data replacing older.  Readings (the paper
+ * gives no features, model or rule):
+ *   - an order's features are the shares of its lines in each product
+ *     category (e.g. the K-means classes of Subproblem 3):
+ *     x[c] = (lines whose SKU is in category c) / (lines of the order);
+ *   - one linear SVM per category of orders against the rest: hinge loss
+ *     plus lambda / 2 times the squared norm of the weights, the bias being
+ *     the weight of a constant feature 1;
+ *   - training: full-batch subgradient steps over the window with the step
+ *     sizes of Pegasos (Shalev-Shwartz et al. 2007), eta_t = 1 / (lambda t),
+ *     t counting every step since creation;
+ *   - an order takes the category of the largest score (ties: the lower).
+ * All arithmetic is IEEE double, one operation at a time, every sum in a
+ * fixed order (features by index, samples from the oldest), so results do
+ * not depend on the launch shape.  Labels outside [0, n_classes) count as
+ * negatives for every class. */
+#define WO_SVM_MAX_FEATURES 64
+#define WO_SVM_MAX_CLASSES 64
+#define WO_SVM_MAX_WINDOW (1 << 22)
+
+typedef struct wo_svm wo_svm;
+
+/* Features of n_orders orders (async): d_order_offsets int32[n_orders + 1],
+ * d_order_skus int32[n_lines], d_sku_category int32[n_skus] (each in
+ * [0, n_features) to count), d_features double[n_orders][n_features] out.
+ * Lines outside [0, n_lines), SKUs outside [0, n_skus) and categories outside
+ * [0, n_features) count in the order's length only. */
+wo_status wo_order_features(const int32_t *d_order_offsets, const int32_t *d_order_skus, int32_t n_orders,
+                            int64_t n_lines, const int32_t *d_sku_category, int32_t n_skus, int32_t n_features,
+                            double *d_features, void *stream);
+
+/* An SVM over n_features (1 .. 64) features and n_classes (2 .. 64)
+ * categories, refreshed from a window of the last `window` samples
+ * (1 .. WO_SVM_MAX_WINDOW); weights start at zero.  Synchronous. */
+wo_status wo_svm_create(int32_t n_features, int32_t n_classes, int32_t window, double lambda, void *stream,
+                        wo_svm **out);
+wo_status wo_svm_free(wo_svm *s);
+
+/* Append n samples to the window (async): d_features double[n][F],
+ * d_labels int32[n]; the window keeps the last `window` samples pushed. */
+wo_status wo_svm_push(wo_svm *s, int64_t n, const double *d_features, const int32_t *d_labels, void *stream);
+
+/* `iterations` subgradient steps on the window's samples from the current
+ * weights (async); WO_E_STATE when the window is empty. */
+wo_status wo_svm_train(wo_svm *s, int32_t iterations, void *stream);
+
+/* Category of each of n samples into d_class int32[n] (async). */
+wo_status wo_svm_predict(wo_svm *s, int64_t n, const double *d_features, int32_t *d_class, void *stream);
+
+/* Weights (host double[n_classes][n_features + 1], bias last; nullable),
+ * steps so far and samples in the window (each nullable).  Synchronous. */
+wo_status wo_svm_get_weights(wo_svm *s, double *h_weights, int64_t *h_steps, int64_t *h_window_count,
+                             void *stream);
+
+/* ------------------------------------------------------------------ */
 /* Diagnostics                                                          */
 /* ------------------------------------------------------------------ */
 

@@ -4,6 +4,8 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the ``cpu_baseline`` leg of
 ``bench.py`` may import this package.  The product path (the HIP library and
 its binding) never does, and this package never imports the product path.
 
+``svm.c`` holds the order categories by linear SVM (features, training,
+prediction; wrapped by ``svm.py``);
 ``wo_oracle.c`` is the plain sequential evaluator (slot map, next-fit tours,
 S-shape, return, largest-gap, combined or optimal route distance, time-window throughput);
 ``surrogate.py`` is the float64
@@ -24,6 +26,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "wo_oracle.c")
+_SRC_SVM = os.path.join(_HERE, "svm.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
 _lock = threading.Lock()
 _lib = None
@@ -52,7 +55,7 @@ def build(force: bool = True) -> str:
             tmp = _LIB + ".tmp%d" % os.getpid()
             subprocess.check_call(["gcc", "-O2", "-std=c99", "-D_POSIX_C_SOURCE=200809L",
                                    "-ffp-contract=off", "-fPIC", "-shared", "-Wall", "-Wextra",
-                                   "-o", tmp, _SRC, "-lpthread"])
+                                   "-o", tmp, _SRC, _SRC_SVM, "-lpthread"])
             os.replace(tmp, _LIB)
     return _LIB
 
@@ -60,7 +63,8 @@ def build(force: bool = True) -> str:
 def _load():
     global _lib
     if _lib is None:
-        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                      os.path.getmtime(_SRC_SVM)):
             build(force=True)
         lib = ctypes.CDLL(_LIB)
         P = ctypes.POINTER
@@ -76,6 +80,13 @@ def _load():
         lib.orc_eval_plan.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p,
                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_int_ops.argtypes = [ctypes.c_int64, ctypes.c_uint32, P(ctypes.c_uint32)]
+        lib.orc_order_features.argtypes = [ctypes.c_int32, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                           ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p]
+        lib.orc_svm_train.argtypes = [ctypes.c_int32, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                      ctypes.c_void_p, ctypes.c_double, ctypes.c_int64, ctypes.c_int32,
+                                      ctypes.c_void_p]
+        lib.orc_svm_predict.argtypes = [ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, ctypes.c_void_p,
+                                        ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_int_ops.restype = ctypes.c_int64
         lib.orc_eval_plans.argtypes = [P(_Inst), ctypes.c_int64, ctypes.c_void_p,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,

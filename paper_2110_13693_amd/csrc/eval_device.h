@@ -15,10 +15,14 @@ static __device__ __forceinline__ uint32_t mulhi24(uint32_t x, uint32_t m)
 
 static __device__ __forceinline__ float window_throughput(int64_t D, const InstDev &I)
 {
-    // T = D / walk + t_item * items; orders * window / T, IEEE double, no contraction
-    double T = __dadd_rn(__ddiv_rn((double)D, I.walk), __dmul_rn(I.t_item, (double)I.n_lines));
-    double r = __ddiv_rn(__dmul_rn((double)I.n_orders, I.window), T);
-    return __double2float_rn(r);
+    // T = D / walk + t_item * items; orders * window / T: IEEE double, one
+    // operation at a time (no multiply-add contraction), rounded once
+#pragma clang fp contract(off)
+    const double q = (double)D / I.walk;
+    const double u = I.t_item * (double)I.n_lines;
+    const double T = q + u;
+    const double r = ((double)I.n_orders * I.window) / T;
+    return (float)r;
 }
 
 // Instance of plan row p: from the per-plan table when there is one, else the

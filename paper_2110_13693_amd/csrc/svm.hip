@@ -1,0 +1,342 @@
+// Order categories by linear support vector machines (arXiv 2110.13693,
+// section 5, subroutine 5): each order belongs to a category of orders; an
+// SVM (Cortes and Vapnik 1995) learns the categories from the outputs of the
+// subroutines before it, and is refreshed continuously from a window of the
+// most recent orders, newer data replacing older.
+//
+// Readings (the paper gives no features, model or training rule):
+//   - an order's features are the shares of its lines in each product
+//     category (the classes of Subproblem 3): x[c] = lines in c / lines;
+//   - one linear SVM per category of orders against the rest: hinge loss
+//     plus lambda / 2 times the squared norm of the weights, the bias being
+//     the weight of a constant feature 1; full-batch subgradient steps over
+//     the window with the step sizes of Pegasos (Shalev-Shwartz et al.
+//     2007), eta_t = 1 / (lambda t), t counting every step since creation;
+//   - an order takes the category of the largest score (ties: the lower).
+// The window is a ring of the last `window` samples on the device.  Every
+// sum runs in a fixed order (features in index order, samples from the
+// oldest) with one IEEE double operation at a time, so the results do not
+// depend on the launch shape.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <atomic>
+#include <new>
+
+#include "wo_common.h"
+
+// one IEEE operation at a time: no multiply-add contraction anywhere below
+// (the file is also built with -ffp-contract=off)
+#pragma clang fp contract(off)
+
+struct wo_svm {
+    int32_t F = 0, K = 0, W = 0;
+    double lambda = 0.0;
+    int64_t steps = 0;       // training steps so far
+    int64_t pushed = 0;      // samples pushed so far; the window holds the last min(pushed, W)
+    double *X = nullptr;     // [W][F], sample g in slot g mod W
+    int32_t *L = nullptr;    // [W]
+    double *Wt = nullptr;    // [K][F + 1], bias last
+    int8_t *coef = nullptr;  // [W][K]: +1 / -1 inside the margin, 0 outside
+    std::atomic<int> busy{0};
+};
+
+namespace {
+
+struct SvmBusy {
+    std::atomic<int> *f;
+    bool ok;
+    explicit SvmBusy(std::atomic<int> *flag) : f(flag)
+    {
+        int z = 0;
+        ok = f->compare_exchange_strong(z, 1);
+    }
+    ~SvmBusy()
+    {
+        if (ok) f->store(0);
+    }
+};
+
+int grid_for(int64_t n, int block) { return (int)std::min<int64_t>(std::max<int64_t>((n + block - 1) / block, 1), 65535); }
+
+// One thread per order: line counts per category, then shares.  Lines are
+// clamped to [0, n_lines); SKUs outside [0, n_skus) and categories outside
+// [0, F) count in the length only.
+__global__ void features_kernel(const int32_t *off, const int32_t *skus, int32_t n_orders, int64_t n_lines,
+                                const int32_t *sku_cat, int32_t n_skus, int32_t F, double *x)
+{
+    for (int32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < n_orders; o += gridDim.x * blockDim.x) {
+        double *row = x + (int64_t)o * F;
+        for (int32_t c = 0; c < F; c++) row[c] = 0.0;
+        const int32_t a = off[o], b = off[o + 1];
+        const int64_t l0 = std::max<int64_t>(a, 0), l1 = std::min<int64_t>(b, n_lines);
+        for (int64_t l = l0; l < l1; l++) {
+            const int32_t s = skus[l];
+            if (s < 0 || s >= n_skus) continue;
+            const int32_t c = sku_cat[s];
+            if (c < 0 || c >= F) continue;
+            row[c] = row[c] + 1.0;
+        }
+        const double len = (double)(b - a);
+        for (int32_t c = 0; c < F; c++) row[c] = row[c] / len;
+    }
+}
+
+__device__ __forceinline__ double score(const double *w, const double *x, int32_t F)
+{
+    double s = 0.0;
+    for (int32_t f = 0; f < F; f++) s = s + w[f] * x[f];
+    return s + w[F];
+}
+
+// One thread per (sample, class): inside the margin at the current weights?
+__global__ void margin_kernel(const double *X, const int32_t *L, int32_t W, int64_t first, int64_t n, int32_t F,
+                              int32_t K, const double *Wt, int8_t *coef)
+{
+    for (int64_t q = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; q < n * K; q += (int64_t)gridDim.x * blockDim.x) {
+        const int64_t i = q / K;
+        const int32_t k = (int32_t)(q - i * K);
+        const int64_t slot = (first + i) % W;
+        const bool pos = L[slot] == k;
+        const double s = score(Wt + (int64_t)k * (F + 1), X + slot * F, F);
+        const double ys = pos ? s : -s;
+        coef[i * K + k] = (int8_t)(ys < 1.0 ? (pos ? 1 : -1) : 0);
+    }
+}
+
+// One thread per (class, weight): the subgradient step; the sum over the
+// samples runs from the oldest, as in the step's definition (its loads are
+// issued ahead in groups, the additions stay in order).
+__global__ void update_kernel(const double *X, const int8_t *coef, int32_t W, int64_t first, int64_t n, int32_t F,
+                              int32_t K, double *Wt, double lambda, double t)
+{
+    const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= K * (F + 1)) return;
+    const int32_t k = q / (F + 1), f = q - k * (F + 1);
+    constexpr int U = 16;
+    double g = 0.0;
+    int64_t i = 0;
+    int64_t slot = first;
+    for (; i + U <= n; i += U) {
+        double v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) {
+            int64_t sl = slot + u;
+            if (sl >= W) sl -= W;
+            const double c = (double)coef[(i + u) * K + k];
+            v[u] = f < F ? c * X[sl * F + f] : c;
+        }
+#pragma unroll
+        for (int u = 0; u < U; u++) g = g + v[u];
+        slot += U;
+        if (slot >= W) slot -= W;
+    }
+    for (; i < n; i++) {
+        const double c = (double)coef[i * K + k];
+        g = g + (f < F ? c * X[slot * F + f] : c);
+        if (++slot == W) slot = 0;
+    }
+    const double eta = 1.0 / (lambda * t);
+    const double w = Wt[q];
+    Wt[q] = w - eta * (lambda * w - g / (double)n);
+}
+
+// Categories of R (64, or 32 where 64 rows and the weights would not fit in
+// 64 KiB) samples per wavefront: the weights and the samples'
+// feature rows pass through LDS (coalesced loads; rows padded to an odd
+// number of doubles so the lanes' reads spread over the banks), then each
+// lane scores its sample class by class, features in index order and the
+// bias last, keeping the class of the largest score (ties: the lower).
+__global__ __launch_bounds__(64) void predict_kernel(const double *X, int64_t n, int32_t F, int32_t K, const double *Wt,
+                                                    int32_t R, int32_t *cls)
+{
+    extern __shared__ double lds[];
+    const int32_t nw = K * (F + 1), ld = F | 1;
+    double *wl = lds, *tile = lds + nw;
+    const int lane = threadIdx.x;
+    for (int32_t e = lane; e < nw; e += 64) wl[e] = Wt[e];
+    for (int64_t i0 = blockIdx.x * (int64_t)R; i0 < n; i0 += (int64_t)gridDim.x * R) {
+        const int32_t rows = (int32_t)std::min<int64_t>(R, n - i0);
+        const double *src = X + i0 * F;
+        __syncthreads();
+        for (int32_t e = lane; e < rows * F; e += 64) {
+            const int32_t r = e / F;
+            tile[r * ld + (e - r * F)] = src[e];
+        }
+        __syncthreads();
+        if (lane < rows) {
+            const double *x = tile + lane * ld;
+            int32_t best = 0;
+            double bs = 0.0;
+            // four classes at a time: independent sums, each in feature order
+            for (int32_t k0 = 0; k0 < K; k0 += 4) {
+                const double *w0 = wl + std::min(k0, K - 1) * (F + 1);
+                const double *w1 = wl + std::min(k0 + 1, K - 1) * (F + 1);
+                const double *w2 = wl + std::min(k0 + 2, K - 1) * (F + 1);
+                const double *w3 = wl + std::min(k0 + 3, K - 1) * (F + 1);
+                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+#pragma unroll 4
+                for (int32_t f = 0; f < F; f++) {
+                    const double xf = x[f];
+                    a0 = a0 + w0[f] * xf;
+                    a1 = a1 + w1[f] * xf;
+                    a2 = a2 + w2[f] * xf;
+                    a3 = a3 + w3[f] * xf;
+                }
+                const double v[4] = {a0 + w0[F], a1 + w1[F], a2 + w2[F], a3 + w3[F]};
+#pragma unroll
+                for (int j = 0; j < 4; j++) {
+                    const int32_t k = k0 + j;
+                    if (k < K && (k == 0 || v[j] > bs)) {
+                        bs = v[j];
+                        best = k;
+                    }
+                }
+            }
+            cls[i0 + lane] = best;
+        }
+    }
+}
+
+}  // namespace
+
+extern "C" wo_status wo_order_features(const int32_t *d_order_offsets, const int32_t *d_order_skus, int32_t n_orders,
+                                       int64_t n_lines, const int32_t *d_sku_category, int32_t n_skus,
+                                       int32_t n_features, double *d_features, void *stream)
+{
+    if (!d_order_offsets || !d_order_skus || !d_sku_category || !d_features) return wo_fail(WO_E_INVAL, "NULL buffer");
+    if (n_orders < 0 || n_lines < 0 || n_skus < 0) return wo_fail(WO_E_INVAL, "negative size");
+    if (n_features < 1 || n_features > WO_SVM_MAX_FEATURES)
+        return wo_fail(WO_E_RANGE, "n_features must be in 1 .. %d", WO_SVM_MAX_FEATURES);
+    if (n_orders == 0) return WO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    hipLaunchKernelGGL(features_kernel, dim3(grid_for(n_orders, 256)), dim3(256), 0, s, d_order_offsets, d_order_skus,
+                       n_orders, n_lines, d_sku_category, n_skus, n_features, d_features);
+    WO_HIP(hipGetLastError());
+    return WO_OK;
+}
+
+extern "C" wo_status wo_svm_create(int32_t n_features, int32_t n_classes, int32_t window, double lambda,
+                                   void *stream, wo_svm **out)
+{
+    if (!out) return wo_fail(WO_E_INVAL, "out is NULL");
+    *out = nullptr;
+    if (n_features < 1 || n_features > WO_SVM_MAX_FEATURES)
+        return wo_fail(WO_E_RANGE, "n_features must be in 1 .. %d", WO_SVM_MAX_FEATURES);
+    if (n_classes < 2 || n_classes > WO_SVM_MAX_CLASSES)
+        return wo_fail(WO_E_RANGE, "n_classes must be in 2 .. %d", WO_SVM_MAX_CLASSES);
+    if (window < 1 || window > WO_SVM_MAX_WINDOW) return wo_fail(WO_E_RANGE, "window must be in 1 .. %d", WO_SVM_MAX_WINDOW);
+    if (!(lambda > 0.0)) return wo_fail(WO_E_INVAL, "lambda must be > 0");
+    if (wo_fault_injected()) return wo_fail(WO_E_NOMEM, "injected allocation failure");
+    wo_svm *m = new (std::nothrow) wo_svm;
+    if (!m) return wo_fail(WO_E_NOMEM, "host allocation failed");
+    m->F = n_features;
+    m->K = n_classes;
+    m->W = window;
+    m->lambda = lambda;
+    hipStream_t s = (hipStream_t)stream;
+    bool ok = hipMalloc((void **)&m->X, sizeof(double) * (size_t)window * n_features) == hipSuccess &&
+              hipMalloc((void **)&m->L, sizeof(int32_t) * (size_t)window) == hipSuccess &&
+              hipMalloc((void **)&m->Wt, sizeof(double) * (size_t)n_classes * (n_features + 1)) == hipSuccess &&
+              hipMalloc((void **)&m->coef, (size_t)window * n_classes) == hipSuccess;
+    if (!ok) {
+        (void)hipGetLastError();
+        wo_svm_free(m);
+        return wo_fail(WO_E_NOMEM, "device allocation failed");
+    }
+    if (hipMemsetAsync(m->Wt, 0, sizeof(double) * (size_t)n_classes * (n_features + 1), s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess) {
+        (void)hipGetLastError();
+        wo_svm_free(m);
+        return wo_fail(WO_E_DEVICE, "clearing the weights failed");
+    }
+    *out = m;
+    return WO_OK;
+}
+
+extern "C" wo_status wo_svm_free(wo_svm *m)
+{
+    if (!m) return WO_OK;
+    if (m->X || m->L || m->Wt || m->coef) (void)hipDeviceSynchronize();
+    if (m->X) (void)hipFree(m->X);
+    if (m->L) (void)hipFree(m->L);
+    if (m->Wt) (void)hipFree(m->Wt);
+    if (m->coef) (void)hipFree(m->coef);
+    delete m;
+    return WO_OK;
+}
+
+extern "C" wo_status wo_svm_push(wo_svm *m, int64_t n, const double *d_features, const int32_t *d_labels, void *stream)
+{
+    if (!m || !d_features || !d_labels) return wo_fail(WO_E_INVAL, "NULL argument");
+    if (n < 0) return wo_fail(WO_E_INVAL, "n < 0");
+    SvmBusy busy(&m->busy);
+    if (!busy.ok) return wo_fail(WO_E_STATE, "SVM in use by another thread");
+    hipStream_t s = (hipStream_t)stream;
+    // only the last min(n, W) samples stay; sample g goes to slot g mod W
+    const int64_t keep = std::min<int64_t>(n, m->W);
+    int64_t g = m->pushed + (n - keep);
+    int64_t r = n - keep;                  // row of the input
+    while (r < n) {
+        const int64_t slot = g % m->W;
+        const int64_t run = std::min<int64_t>(n - r, m->W - slot);
+        WO_HIP(hipMemcpyAsync(m->X + slot * m->F, d_features + r * m->F, sizeof(double) * (size_t)run * m->F,
+                              hipMemcpyDeviceToDevice, s));
+        WO_HIP(hipMemcpyAsync(m->L + slot, d_labels + r, sizeof(int32_t) * (size_t)run, hipMemcpyDeviceToDevice, s));
+        r += run;
+        g += run;
+    }
+    m->pushed += n;
+    return WO_OK;
+}
+
+extern "C" wo_status wo_svm_train(wo_svm *m, int32_t iterations, void *stream)
+{
+    if (!m) return wo_fail(WO_E_INVAL, "NULL SVM");
+    if (iterations < 0) return wo_fail(WO_E_INVAL, "iterations < 0");
+    SvmBusy busy(&m->busy);
+    if (!busy.ok) return wo_fail(WO_E_STATE, "SVM in use by another thread");
+    const int64_t n = std::min<int64_t>(m->pushed, m->W);
+    if (n == 0) return wo_fail(WO_E_STATE, "the window holds no sample");
+    const int64_t first = (m->pushed - n) % m->W;   // slot of the oldest sample
+    hipStream_t s = (hipStream_t)stream;
+    const int32_t nw = m->K * (m->F + 1);
+    for (int32_t it = 0; it < iterations; it++) {
+        const double t = (double)(m->steps + it + 1);
+        hipLaunchKernelGGL(margin_kernel, dim3(grid_for(n * m->K, 256)), dim3(256), 0, s, m->X, m->L, m->W, first, n,
+                           m->F, m->K, m->Wt, m->coef);
+        hipLaunchKernelGGL(update_kernel, dim3((nw + 63) / 64), dim3(64), 0, s, m->X, m->coef, m->W, first, n, m->F,
+                           m->K, m->Wt, m->lambda, t);
+    }
+    WO_HIP(hipGetLastError());
+    m->steps += iterations;
+    return WO_OK;
+}
+
+extern "C" wo_status wo_svm_predict(wo_svm *m, int64_t n, const double *d_features, int32_t *d_class, void *stream)
+{
+    if (!m || !d_features || !d_class) return wo_fail(WO_E_INVAL, "NULL argument");
+    if (n < 0) return wo_fail(WO_E_INVAL, "n < 0");
+    if (n == 0) return WO_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t wbytes = sizeof(double) * (size_t)m->K * (m->F + 1), row = sizeof(double) * (size_t)(m->F | 1);
+    const int32_t R = wbytes + 64 * row <= 65536 ? 64 : 32;
+    hipLaunchKernelGGL(predict_kernel, dim3(grid_for(n, R)), dim3(64), wbytes + R * row, s, d_features, n, m->F, m->K,
+                       m->Wt, R, d_class);
+    WO_HIP(hipGetLastError());
+    return WO_OK;
+}
+
+extern "C" wo_status wo_svm_get_weights(wo_svm *m, double *h_weights, int64_t *h_steps, int64_t *h_window_count,
+                                        void *stream)
+{
+    if (!m) return wo_fail(WO_E_INVAL, "NULL SVM");
+    hipStream_t s = (hipStream_t)stream;
+    if (h_weights) {
+        WO_HIP(hipMemcpyAsync(h_weights, m->Wt, sizeof(double) * (size_t)m->K * (m->F + 1), hipMemcpyDeviceToHost, s));
+        WO_HIP(hipStreamSynchronize(s));
+    }
+    if (h_steps) *h_steps = m->steps;
+    if (h_window_count) *h_window_count = std::min<int64_t>(m->pushed, m->W);
+    return WO_OK;
+}

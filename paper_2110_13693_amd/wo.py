@@ -33,6 +33,8 @@ EXPORTS = sorted([
     "wo_search_save", "wo_search_load",
     "wo_set_eval_config", "wo_get_eval_config", "wo_autotune_eval",
     "wo_kmeans_categories", "wo_kmeans_categories_noalloc", "wo_measure_int_peak", "wo_aisle_width",
+    "wo_order_features", "wo_svm_create", "wo_svm_free", "wo_svm_push", "wo_svm_train", "wo_svm_predict",
+    "wo_svm_get_weights",
 ])
 WO_SUR_PARAMS = 4457985
 WO_SCREEN_MAX_KEEP = 4096
@@ -128,6 +130,13 @@ def lib():
         L.wo_kmeans_categories_noalloc.argtypes = [V, I64, I32, I32, I32, V, V, V, V]
         L.wo_measure_int_peak.argtypes = [I32, P(F64), V]
         L.wo_aisle_width.argtypes = [V, I32, V, V, P(wo_aisle_params), V, V, P(wo_aisle_result)]
+        L.wo_order_features.argtypes = [V, V, I32, I64, V, I32, I32, V, V]
+        L.wo_svm_create.argtypes = [I32, I32, I32, F64, V, P(V)]
+        L.wo_svm_free.argtypes = [V]
+        L.wo_svm_push.argtypes = [V, I64, V, V, V]
+        L.wo_svm_train.argtypes = [V, I32, V]
+        L.wo_svm_predict.argtypes = [V, I64, V, V, V]
+        L.wo_svm_get_weights.argtypes = [V, V, P(I64), P(I64), V]
         for name in EXPORTS:
             getattr(L, name).restype = getattr(L, name).restype if name in (
                 "wo_status_str", "wo_last_error") else ctypes.c_int
@@ -413,6 +422,68 @@ def wo_aisle_width(wh: Warehouse, zone_of, order_seq, rack_depth_dm: int, cross_
                                 ctypes.byref(out)))
     res = {f: getattr(out, f) for f, _ in wo_aisle_result._fields_}
     return res, dist[:n_w]
+
+
+def wo_order_features(order_offsets, order_skus, sku_category, n_features: int, features, stream=None):
+    """Shares of each order's lines per category into ``features`` (float64
+    GPU tensor [n_orders, n_features]); inputs are int32 GPU tensors."""
+    n = int(order_offsets.numel()) - 1
+    if features.shape[0] != n or features.shape[1] != n_features:
+        raise ValueError("features must be [n_orders, n_features]")
+    _check(lib().wo_order_features(_ptr(order_offsets, 4, "order_offsets"), _ptr(order_skus, 4, "order_skus"), n,
+                                   int(order_skus.numel()), _ptr(sku_category, 4, "sku_category"),
+                                   int(sku_category.numel()), int(n_features), _ptr(features, 8, "features"),
+                                   ctypes.c_void_p(_stream_handle(stream))))
+
+
+class Svm:
+    def __init__(self, handle: int, n_features: int, n_classes: int):
+        self.handle = handle
+        self.n_features = n_features
+        self.n_classes = n_classes
+
+    def free(self):
+        if self.handle:
+            lib().wo_svm_free(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
+
+
+def wo_svm_create(n_features: int, n_classes: int, window: int, lam: float, stream=None) -> Svm:
+    out = ctypes.c_void_p(0)
+    _check(lib().wo_svm_create(int(n_features), int(n_classes), int(window), float(lam),
+                               ctypes.c_void_p(_stream_handle(stream)), ctypes.byref(out)))
+    return Svm(out.value, n_features, n_classes)
+
+
+def wo_svm_push(s: Svm, features, labels, stream=None):
+    n = int(labels.numel())
+    _check(lib().wo_svm_push(s.handle, n, _ptr(features, 8, "features"), _ptr(labels, 4, "labels"),
+                             ctypes.c_void_p(_stream_handle(stream))))
+
+
+def wo_svm_train(s: Svm, iterations: int, stream=None):
+    _check(lib().wo_svm_train(s.handle, int(iterations), ctypes.c_void_p(_stream_handle(stream))))
+
+
+def wo_svm_predict(s: Svm, features, out, stream=None):
+    _check(lib().wo_svm_predict(s.handle, int(out.numel()), _ptr(features, 8, "features"), _ptr(out, 4, "class"),
+                                ctypes.c_void_p(_stream_handle(stream))))
+
+
+def wo_svm_get_weights(s: Svm, stream=None):
+    """(weights numpy [n_classes, n_features + 1], steps, samples in the window)."""
+    import numpy as np
+    w = np.zeros((s.n_classes, s.n_features + 1), np.float64)
+    steps, cnt = ctypes.c_int64(0), ctypes.c_int64(0)
+    _check(lib().wo_svm_get_weights(s.handle, w.ctypes.data, ctypes.byref(steps), ctypes.byref(cnt),
+                                    ctypes.c_void_p(_stream_handle(stream))))
+    return w, steps.value, cnt.value
 
 
 def wo_measure_int_peak(reps: int = 5, stream=None) -> float:

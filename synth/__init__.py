@@ -11,5 +11,6 @@ from .generators import (  # noqa: F401
     make_instance,
     make_plans,
     make_batched_instances,
+    make_typed_orders,
     workload,
 )

@@ -41,6 +41,7 @@ STREAM_BATCH_SHAPES = 3
 STREAM_SURROGATE_TRAIN = 4
 STREAM_SURROGATE_HELDOUT = 5
 STREAM_SEARCH_INIT = 6
+STREAM_ORDER_TYPES = 7
 
 
 @dataclasses.dataclass
@@ -281,3 +282,45 @@ def pack_batched_plans(insts: Sequence[Instance], plans_per_instance: int, seed:
         bases.append(base)
         base += s.size
     return np.concatenate(zones), np.concatenate(seqs), np.asarray(bases, dtype=np.int64)
+
+
+def make_typed_orders(n_orders: int, n_types: int, sku_category: np.ndarray, n_categories: int, *,
+                      lines_lambda: float = 1.5, concentration: float = 0.3, drift: float = 0.0,
+                      seed: int = 0, chunk: int = 65536):
+    """Orders that each belong to one of ``n_types`` order types, the labels
+    of the order-category learning (no labelled order history exists).
+
+    Type t prefers categories by a Dirichlet(``concentration``) weight vector
+    that moves linearly, over the order index, from one draw to a second one
+    as far as ``drift`` (0: fixed types, 1: the whole way), so that older
+    orders describe the types less well than recent ones.  An order draws its
+    type uniformly, 1 + Poisson(``lines_lambda``) lines, each line's category
+    from its type's weights and the SKU uniformly within the category.
+    Returns ``(order_offsets int32 [n + 1], order_skus int32, types int32 [n])``.
+    """
+    rng = np.random.default_rng([seed, STREAM_ORDER_TYPES])
+    C = int(n_categories)
+    pref0 = rng.dirichlet(np.full(C, concentration), size=n_types)
+    pref1 = rng.dirichlet(np.full(C, concentration), size=n_types)
+    cat = np.asarray(sku_category, np.int64)
+    order = np.argsort(cat, kind="stable")
+    counts = np.bincount(cat, minlength=C)
+    first = np.concatenate([[0], np.cumsum(counts)[:-1]])
+    types = rng.integers(0, n_types, n_orders).astype(np.int32)
+    lens = (1 + rng.poisson(lines_lambda, n_orders)).astype(np.int64)
+    off = np.zeros(n_orders + 1, np.int64)
+    off[1:] = np.cumsum(lens)
+    skus = np.empty(int(off[-1]), np.int32)
+    for o0 in range(0, n_orders, chunk):
+        o1 = min(n_orders, o0 + chunk)
+        line_order = np.repeat(np.arange(o0, o1), lens[o0:o1])
+        s = drift * line_order / max(1, n_orders - 1)
+        t = types[line_order]
+        p = (1.0 - s)[:, None] * pref0[t] + s[:, None] * pref1[t]
+        cdf = np.cumsum(p, axis=1)
+        u = rng.random(line_order.size) * cdf[:, -1]
+        c = np.minimum((cdf < u[:, None]).sum(axis=1), C - 1)
+        c = np.where(counts[c] > 0, c, np.argmax(counts))   # an empty category gives way to the largest
+        k = (rng.random(line_order.size) * counts[c]).astype(np.int64)
+        skus[off[o0]:off[o1]] = order[first[c] + np.minimum(k, counts[c] - 1)]
+    return off.astype(np.int32), skus, types
