@@ -286,7 +286,12 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
             return fail(WO_E_UNSUPPORTED, "instance %d: no 24-bit reciprocal for %u locations per aisle", i,
                         per_aisle);
         I.n_aisles = d.n_aisles;
-        I.words = (d.n_aisles + 31) / 32;
+        {
+            // zones fill locations [0, n_skus), so only the aisles up to the
+            // one holding location n_skus - 1 can be visited
+            const int32_t used = (int32_t)(((uint32_t)std::max(d.n_skus, 1) - 1u) / per_aisle + 1u);
+            I.words = (std::min(used, d.n_aisles) + 31) / 32;
+        }
         I.route = d.routing;
         {
             // a tour holds at most max(capacity, largest order) lines

@@ -14,7 +14,7 @@ namespace wo {
 // and magic per instance and proves the identity for every location.
 struct InstDev {
     int32_t n_aisles;
-    int32_t words;          // ceil(n_aisles / 32): 32-bit words of a tour's aisle set
+    int32_t words;          // 32-bit words of a tour's aisle set: the aisles that hold SKUs, rounded up
     int32_t capacity;
     int32_t n_cat;
     int32_t n_orders;
