@@ -149,8 +149,7 @@ enum { WO_ROUTE_SSHAPE = 0, WO_ROUTE_RETURN = 1, WO_ROUTE_LARGEST_GAP = 2, WO_RO
  *   WO_BATCH_FIRST_FIT  an order joins the earliest-opened tour with room for
  *                       it, else it opens a new tour.
  * An order larger than the capacity is a tour of its own under both.  First
- * fit takes every route and instances of at most 4,096 orders (larger ones
- * fail at load with WO_E_UNSUPPORTED); the launch configuration
+ * fit takes every route and any number of orders; the launch configuration
  * (wo_set_eval_config, wo_autotune_eval) does not apply to it. */
 enum { WO_BATCH_NEXT_FIT = 0, WO_BATCH_FIRST_FIT = 1 };
 #define WO_MAX_PICK_SLOTS 32

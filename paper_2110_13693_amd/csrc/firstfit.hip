@@ -3,17 +3,10 @@
 
 namespace wo {
 
-// Largest value over the wavefront (DPP row shifts and broadcasts, as in
-// wave_incl_scan; lanes without a source keep their own value).
-static __device__ __forceinline__ int32_t wave_max_i32(int32_t v)
+// x with lane l (uniform) set to v (uniform)
+static __device__ __forceinline__ uint32_t set_lane(uint32_t x, uint32_t v, int l)
 {
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x111, 0xF, 0xF, false));   // row_shr:1
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x112, 0xF, 0xF, false));   // row_shr:2
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x114, 0xF, 0xF, false));   // row_shr:4
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x118, 0xF, 0xF, false));   // row_shr:8
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x142, 0xA, 0xF, false));   // row_bcast:15
-    v = max(v, __builtin_amdgcn_update_dpp(v, v, 0x143, 0xC, 0xF, false));   // row_bcast:31
-    return __builtin_amdgcn_readlane(v, 63);
+    return (int)threadIdx.x % 64 == l ? v : x;
 }
 
 // Plans under first-fit order batching (the other greedy batching rule of the
@@ -22,13 +15,14 @@ static __device__ __forceinline__ int32_t wave_max_i32(int32_t v)
 // evaluates one plan:
 //   1. zone starts: each category's start is the total size of the
 //      categories in lower zones (one pass over the categories per lane);
-//   2. first fit, order by order in sequence: lane l keeps the free room of
-//      tours l, 64 + l, 128 + l, ... in registers (a byte each), and lane c
-//      an upper bound of the largest room among tours 64c .. 64c + 63.  The
-//      groups whose bound admits the order are tried in turn: one register
-//      of the group and a ballot find its first tour with room; a group
-//      without one gets its exact largest room as its new bound.  Every order
-//      has an item, so an empty room never fits;
+//   2. first fit, order by order in sequence, over the open tours only: a
+//      tour whose room falls below the instance's smallest order can never
+//      take another one and is dropped.  Lane j keeps the j-th open tour (in
+//      opening order) and its room, so one ballot finds the earliest tour
+//      with room; a tour that closes moves the later ones down a lane.  The
+//      open tours stay few (first fit keeps filling the earliest ones), but
+//      any beyond 64 wait, in order, in a queue in global memory that is
+//      searched, 64 at a time, when no lane has room, and refills the lanes;
 //   3. tiles of tours: for the S-shape route, every line of an order in the
 //      tile sets its aisle bit in the tour's LDS row and the order raises the
 //      tour's farthest location, then one lane per tour takes the closed
@@ -98,56 +92,89 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
         // ---- 2. first fit -------------------------------------------------
         // a chain of dependent steps: it issues ahead of other plans' tiles
         __builtin_amdgcn_s_setprio(2);
-        int T = 0;                         // tours opened (uniform)
-        int32_t gmax = 0;                  // lane c: >= the largest room in tours 64c..64c+63
-        uint32_t R[FF_MAX_ORDERS / 256];   // byte b of R[q]: room of tour 64 (4q + b) + lane
-#pragma unroll
-        for (int q = 0; q < FF_MAX_ORDERS / 256; q++) R[q] = 0u;
+        const uint32_t mins = (uint32_t)I.min_size;     // a room below it never takes an order
+        int T = 0;                                      // tours opened (uniform)
+        int k = 0;                                      // open tours held in lanes (uniform)
+        uint32_t room = 0, tour = 0;                    // lane j < k: the j-th open tour and its room
+        uint32_t *queue = A.ff_queue + (int64_t)blockIdx.x * A.ff_stride;
+        int qh = 0, qt = 0;                             // queued open tours [qh, qt) (uniform)
+        // the next live queued tour into lane 63 (the lanes are full and the
+        // queue holds the tours opened after theirs, in order)
+        auto refill = [&]() {
+            while (qh < qt) {
+                const uint32_t e = qh + lane < qt ? queue[qh + lane] : 0u;
+                const uint64_t live = __ballot((e >> 16) >= mins);
+                if (live) {
+                    const int f = __builtin_ctzll(live);
+                    const uint32_t ef = (uint32_t)__builtin_amdgcn_readlane((int)e, f);
+                    room = set_lane(room, ef >> 16, 63);
+                    tour = set_lane(tour, ef & 0xFFFFu, 63);
+                    k = 64;
+                    qh += f + 1;
+                    return;
+                }
+                qh = min(qh + 64, qt);
+            }
+        };
         for (int i0 = 0; i0 < n; i0 += 64) {
             const int i = i0 + lane;
             const uint32_t o_l = i < n ? min((uint32_t)seq[i], (uint32_t)n) : (uint32_t)n;
-            // min(size, Q + 1); 0 for an id out of range, which then joins
-            // some tour without taking room and is left out below
-            const uint32_t s_l = cnt[o_l];
+            // min(size, Q + 1); an id out of range (a malformed row, whose
+            // result is unspecified) counts as one item and is left out below
+            const uint32_t s_l = max((uint32_t)cnt[o_l], 1u);
             const int m = __builtin_amdgcn_readfirstlane(min(64, n - i0));   // uniform: a scalar loop bound
-            int t_l = 0;                               // lane j: tour of position i0 + j
+            uint32_t t_l = 0;                               // lane j: tour of position i0 + j
             for (int j = 0; j < m; j++) {
-                const int32_t sz = __builtin_amdgcn_readlane((int)s_l, j);
-                int c = -1, k = 0;                     // group and lane of the tour found
-                uint64_t g = __ballot(gmax >= sz);     // none for an order larger than Q
-                if (g) {
-                    // the first group whose bound admits the order: usually it has room
-                    int cg = __builtin_ctzll(g);
-                    int32_t r = (int32_t)((R[cg >> 2] >> (8u * (uint32_t)(cg & 3))) & 0xFFu);
-                    uint64_t f = __ballot(r >= sz);
-                    while (!f) {                       // the bound was stale (uniform)
-                        const int32_t mx = wave_max_i32(r);
-                        if (lane == cg) gmax = mx;
-                        g &= g - 1;
-                        if (!g) break;
-                        cg = __builtin_ctzll(g);
-                        r = (int32_t)((R[cg >> 2] >> (8u * (uint32_t)(cg & 3))) & 0xFFu);
-                        f = __ballot(r >= sz);
+                const uint32_t sz = (uint32_t)__builtin_amdgcn_readlane((int)s_l, j);
+                // lanes past k hold room 0, which no order (of at least one item) fits
+                const uint64_t hit = __ballot(room >= sz);
+                uint32_t t = 0;
+                if (hit) {                                   // the earliest open tour with room
+                    const int f = __builtin_ctzll(hit);
+                    t = (uint32_t)__builtin_amdgcn_readlane((int)tour, f);
+                    const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)room, f) - sz;
+                    if (r >= mins) {
+                        room = set_lane(room, r, f);
+                    } else {                                 // full: the later open tours move down a lane
+                        const uint32_t rn = (uint32_t)__builtin_amdgcn_ds_bpermute((lane + 1) << 2, (int)room);
+                        const uint32_t tn = (uint32_t)__builtin_amdgcn_ds_bpermute((lane + 1) << 2, (int)tour);
+                        room = lane < f ? room : (lane == 63 ? 0u : rn);
+                        tour = lane < f ? tour : tn;
+                        k--;
+                        if (qh < qt) refill();
                     }
-                    if (f) {
-                        c = cg;
-                        k = __builtin_ctzll(f);
+                } else {
+                    bool found = false;
+                    // the queued tours, in order, 64 at a time
+                    for (int b = qh; b < qt && !found; b += 64) {
+                        const uint32_t e = b + lane < qt ? queue[b + lane] : 0u;
+                        const uint64_t h = __ballot((e >> 16) >= sz);
+                        if (h) {
+                            const int f = __builtin_ctzll(h);
+                            const uint32_t ef = (uint32_t)__builtin_amdgcn_readlane((int)e, f);
+                            t = ef & 0xFFFFu;
+                            const uint32_t r = (ef >> 16) - sz;  // a room below mins stays queued, never taken
+                            if (lane == 0) queue[b + f] = (r << 16) | t;
+                            found = true;
+                        }
                     }
+                    if (!found) {                            // no open tour has room: a new one
+                        t = (uint32_t)T++;
+                        const uint32_t r0 = sz <= (uint32_t)Q ? (uint32_t)Q - sz : 0u;   // a larger order rides alone
+                        if (r0 >= mins) {
+                            if (k < 64) {
+                                room = set_lane(room, r0, k);
+                                tour = set_lane(tour, t, k);
+                                k++;
+                            } else {
+                                if (lane == 0) queue[qt] = (r0 << 16) | t;
+                                qt++;
+                            }
+                        }
+                    }
+                    __threadfence_block();                   // queue stores before later loads of them
                 }
-                int t;
-                if (c >= 0) {                          // the order joins tour 64c + k
-                    t = 64 * c + k;
-                    // every lane takes part (no divergent update of the register array)
-                    R[c >> 2] -= lane == k ? (uint32_t)sz << (8u * (uint32_t)(c & 3)) : 0u;
-                } else {                               // no open tour has room
-                    t = T;
-                    const int32_t r0 = sz <= Q ? Q - sz : 0;   // a larger order rides alone
-                    const int cn = T >> 6;
-                    R[cn >> 2] |= lane == (T & 63) ? (uint32_t)r0 << (8u * (uint32_t)(cn & 3)) : 0u;
-                    if (lane == cn) gmax = max(gmax, r0);
-                    T++;
-                }
-                t_l = lane == j ? t : t_l;
+                t_l = set_lane(t_l, t, j);
             }
             // read after the tile loop's barrier
             if (i < n && o_l < (uint32_t)n) tour_of[o_l] = (uint16_t)t_l;

@@ -104,6 +104,7 @@ struct wo_wh {
     std::vector<uint32_t> ff_lds;       // first fit: LDS of one plan of each instance
     uint32_t ff_lds_max = 0;
     uint16_t *d_ff_tour = nullptr;      // first fit: tour of every order, one slice per workgroup
+    uint32_t *d_ff_queue = nullptr;     // first fit: open tours past the first 64, one slice per workgroup
     int64_t ff_stride = 0;              // entries per slice (largest order count + 1, rounded up)
     int ff_slots = 0;                   // slices: the most workgroups a first-fit launch may have
     int small_orders = 1024;            // instances up to this size get a launch of 64-thread workgroups
@@ -184,9 +185,6 @@ static wo_status check_desc(const wo_instance_desc &d, int idx)
         return fail(WO_E_INVAL, "instance %d: unknown routing %d", idx, d.routing);
     if (d.batching < WO_BATCH_NEXT_FIT || d.batching > WO_BATCH_FIRST_FIT)
         return fail(WO_E_INVAL, "instance %d: unknown batching %d", idx, d.batching);
-    if (d.batching == WO_BATCH_FIRST_FIT && d.n_orders > FF_MAX_ORDERS)
-        return fail(WO_E_UNSUPPORTED, "instance %d: first-fit batching takes at most %d orders (got %d)", idx,
-                    FF_MAX_ORDERS, d.n_orders);
     if (d.capacity > WO_MAX_CAPACITY)
         return fail(WO_E_RANGE, "instance %d: capacity %d > %d", idx, d.capacity, WO_MAX_CAPACITY);
     if (d.n_categories < 1) return fail(WO_E_INVAL, "instance %d: need >= 1 category", idx);
@@ -337,6 +335,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         // zeros for the dummy entry n and the sink entry n + 1, then padding
         while (cnt.size() < (size_t)I.cnt_off + cnt_bytes(d.n_orders)) cnt.push_back(0);
         I.n_units = (int32_t)units;
+        I.min_size = d.capacity + 1;
+        for (int32_t o = 0; o < d.n_orders; o++) I.min_size = std::min<int32_t>(I.min_size, cnt[(size_t)I.cnt_off + o]);
         I.n_skus = d.n_skus;
         // tours of next-fit over the orders in instance order: the orders are
         // exchangeable, so this is the tour count of a typical plan, whatever
@@ -510,6 +510,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
                        eval_ff_max_blocks_per_cu(wh->route, *std::min_element(wh->ff_lds.begin(), wh->ff_lds.end()));
         if ((st = dev_alloc((void **)&wh->d_ff_tour, sizeof(uint16_t) * (size_t)wh->ff_stride * wh->ff_slots)))
             return st;
+        if ((st = dev_alloc((void **)&wh->d_ff_queue, sizeof(uint32_t) * (size_t)wh->ff_stride * wh->ff_slots)))
+            return st;
     }
     guard.release();
     *out = wh;
@@ -519,7 +521,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
 extern "C" wo_status wo_free_warehouse(wo_wh *wh)
 {
     if (!wh) return WO_OK;
-    if (wh->d_pool || wh->d_inst || wh->d_map || wh->d_err || wh->d_ff_tour) (void)hipDeviceSynchronize();
+    if (wh->d_pool || wh->d_inst || wh->d_map || wh->d_err || wh->d_ff_tour || wh->d_ff_queue) (void)hipDeviceSynchronize();
     if (wh->d_pool) (void)hipFree(wh->d_pool);
     if (wh->d_inst) (void)hipFree(wh->d_inst);
     if (wh->d_map) (void)hipFree(wh->d_map);
@@ -528,6 +530,7 @@ extern "C" wo_status wo_free_warehouse(wo_wh *wh)
         if (c.d_work) (void)hipFree(c.d_work);
     if (wh->d_pinst) (void)hipFree(wh->d_pinst);
     if (wh->d_ff_tour) (void)hipFree(wh->d_ff_tour);
+    if (wh->d_ff_queue) (void)hipFree(wh->d_ff_queue);
     if (wh->last_done) (void)hipEventDestroy(wh->last_done);
     delete wh;
     return WO_OK;
@@ -726,6 +729,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.work = nullptr;
     a.ff_tour = wh->d_ff_tour;
     a.ff_stride = wh->ff_stride;
+    a.ff_queue = wh->d_ff_queue;
     a.plan_spacing = nullptr;
     bool any_small = false;
     for (int32_t i = 0; i < wh->n_inst; i++) any_small |= class_of(wh, i) != 0 && map[i + 1] > map[i];
@@ -805,6 +809,7 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.work = nullptr;
     a.ff_tour = wh->d_ff_tour;
     a.ff_stride = wh->ff_stride;
+    a.ff_queue = wh->d_ff_queue;
     a.plan_spacing = d_plan_spacing;
     if (wh->batching == WO_BATCH_FIRST_FIT) {
         const uint32_t lds = wh->ff_lds[inst];

@@ -31,6 +31,7 @@ struct InstDev {
     int32_t n_lines_pad;    // line records stored: n_lines rounded up to whole groups of LINE_PAD
     int32_t chase_log2;     // log2 of the opening records per chase lane
     int32_t chase_lanes;    // chase lanes the LDS layout holds (a multiple of 64, <= CHASE_LANES)
+    int32_t min_size;       // smallest min(size, capacity + 1) over the orders: a room below it never fills
     int32_t route;          // WO_ROUTE_*
     int32_t pick_slots;     // return / largest gap: pick entries per tour row (<= MAX_PICK_SLOTS)
     int32_t row_b;          // bytes of one tour row in LDS
@@ -83,6 +84,7 @@ struct EvalArgs {
     const int32_t *work;    // work item -> plan row (null: identity)
     uint16_t *ff_tour;      // first fit: tour of every order, ff_stride entries per workgroup
     int64_t ff_stride;
+    uint32_t *ff_queue;     // first fit: open tours past the first 64, ff_stride entries per workgroup
     const int32_t *plan_spacing;   // device [n_plans]: aisle spacing of each plan row (null: the instance's)
 };
 
@@ -133,11 +135,9 @@ __host__ __device__ inline uint32_t pick_row_bytes(int32_t slots) { return 4u * 
 // First-fit batching runs in a kernel of its own, one wavefront per plan.
 // LDS: the zone starts (64 words), then one tile of tour rows (128 S-shape
 // rows, or 64 pick rows for the other routes); the tour of every order goes
-// to a global table with one slice per workgroup of the launch.  Tours never
-// outnumber orders; at most FF_MAX_ORDERS orders keep every tour's free room
-// in 16 registers per lane and an upper bound of each group's largest room
-// in one.
-constexpr int FF_MAX_ORDERS = 4096;
+// to a global table with one slice per workgroup of the launch, and open
+// tours beyond the 64 a wavefront keeps in registers to a queue with one
+// slice per workgroup.  Tours never outnumber orders.
 __host__ __device__ constexpr int ff_tile(int route) { return route == WO_ROUTE_SSHAPE ? 128 : 64; }
 __host__ __device__ inline uint32_t ff_rows_off() { return 256u; }
 

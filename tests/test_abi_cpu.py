@@ -167,16 +167,6 @@ def test_load_rejects_optimal_route_beyond_32_bits(wo, tiny):
     assert out.value is None
 
 
-def test_load_rejects_first_fit_beyond_4096_orders(wo):
-    inst = synth.make_instance(n_aisles=40, slots_per_side=50, pitch_dm=10, spacing_dm=30, capacity=20,
-                               n_categories=8, n_skus=3000, category_mode="dirichlet", n_orders=4097,
-                               lines_lambda=1.0, zipf_s=1.0, seed=3)
-    st, out = _load_status(wo, _mod(inst, batching=1))
-    assert st == wo.WO_E_UNSUPPORTED, wo.wo_last_error()
-    assert "4096" in wo.wo_last_error()
-    assert out.value is None
-
-
 def test_load_rejects_mixed_batching(wo, tiny):
     keep = []
     arr = (wo.wo_instance_desc * 2)(wo.make_desc(tiny, keep), wo.make_desc(_mod(tiny, batching=1), keep))

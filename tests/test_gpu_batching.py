@@ -71,7 +71,9 @@ FF_CASES = [
     (33, 7, 300, 32, 64, 1.5),     # capacity 32, two aisle words
     (64, 3, 129, 5, 17, 0.5),      # a multiple of 32 aisles
     (400, 250, 4096, 1, 64, 0.0),  # 4,096 single-item orders at capacity 1: 4,096 tours, 64 tiles
-    (400, 250, 4096, 30, 64, 1.5), # the largest instance first fit takes
+    (400, 250, 4096, 30, 64, 1.5), # 4,096 orders
+    (400, 250, 9000, 30, 64, 1.5), # more orders than tours a wave could keep room for in registers
+    (100, 250, 20000, 2, 8, 0.5),  # 20,000 orders, about 13,000 tours
     (100, 250, 4000, 3, 8, 1.5),   # oversize orders among small ones
     (10, 30, 1, 20, 12, 1.5),      # a single order
     (400, 250, 3000, 7, 64, 4.0),  # large orders, capacity 7
@@ -103,6 +105,52 @@ def test_routed_edge_cases(case, routing):
     inst = _ff(_random_instance(rng, *case), routing)
     Z, S = synth.make_plans(inst, 17, seed=int(rng.integers(1 << 30)))
     print("case", case, routing, flush=True)
+    _compare(inst, Z, S)
+
+
+def _sized_orders(sizes, capacity, seed):
+    """An instance of the tiny geometry whose orders have the given line
+    counts (SKUs drawn uniformly, repeats allowed)."""
+    from tests.whelpers import tiny_geometry
+    rng = np.random.default_rng(seed)
+    return _ff(tiny_geometry([list(rng.integers(0, 600, int(k))) for k in sizes], capacity=capacity))
+
+
+@pytest.mark.parametrize("routing", [0, 1])
+def test_open_tours_beyond_the_lanes(routing):
+    # 150 orders of 16 items each leave a tour with room 14 (capacity 30), so
+    # 150 tours are open at once: 64 in the lanes and 86 queued; the one- to
+    # three-item orders that follow fill them in opening order, the lanes
+    # refilling from the queue, and orders that fit no tour in the lanes find
+    # theirs in the queue.  The plans shuffle this order too.
+    rng = np.random.default_rng(53)
+    sizes = [16] * 150 + list(rng.integers(1, 4, 600)) + [15] * 40 + list(rng.integers(1, 3, 200))
+    inst = dataclasses.replace(_sized_orders(sizes, 30, 5), routing=routing)
+    n = len(sizes)
+    S = np.stack([np.arange(n, dtype=np.uint16)] + [rng.permutation(n).astype(np.uint16) for _ in range(7)])
+    Z = synth.generators.random_zone_perms(rng, S.shape[0], inst.n_categories)
+    # the queue is in use: first fit leaves more than 64 tours open at once
+    lens = np.diff(inst.order_offsets)
+    rooms, most = [], 0
+    for o in S[0]:
+        k = next((i for i, r in enumerate(rooms) if r >= lens[o]), None)
+        if k is None:
+            rooms.append(30 - lens[o])
+        else:
+            rooms[k] -= lens[o]
+        most = max(most, sum(r >= 1 for r in rooms))
+    assert most > 64
+    _compare(inst, Z, S)
+
+
+@pytest.mark.parametrize("routing", [0, 2])
+def test_rooms_no_order_fits_are_dropped(routing):
+    # every order has at least 9 items at capacity 20: a room below 9 is never
+    # used again (no order fits it), so those tours leave the open list
+    rng = np.random.default_rng(59)
+    sizes = list(rng.integers(9, 21, 700))
+    inst = dataclasses.replace(_sized_orders(sizes, 20, 6), routing=routing)
+    Z, S = synth.make_plans(inst, 9, seed=3)
     _compare(inst, Z, S)
 
 
