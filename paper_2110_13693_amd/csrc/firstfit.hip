@@ -3,10 +3,11 @@
 
 namespace wo {
 
-// x with lane l (uniform) set to v (uniform)
+// x with lane l (uniform) set to v (uniform): v_writelane
+extern "C" __device__ int wo_writelane_i32(int src, int lane, int old) __asm("llvm.amdgcn.writelane.i32");
 static __device__ __forceinline__ uint32_t set_lane(uint32_t x, uint32_t v, int l)
 {
-    return (int)threadIdx.x % 64 == l ? v : x;
+    return (uint32_t)wo_writelane_i32((int)v, l, (int)x);
 }
 
 // Plans under first-fit order batching (the other greedy batching rule of the
@@ -15,14 +16,14 @@ static __device__ __forceinline__ uint32_t set_lane(uint32_t x, uint32_t v, int 
 // evaluates one plan:
 //   1. zone starts: each category's start is the total size of the
 //      categories in lower zones (one pass over the categories per lane);
-//   2. first fit, order by order in sequence, over the open tours only: a
+//   2. first fit, order by order in sequence, over the open tours only (a
 //      tour whose room falls below the instance's smallest order can never
-//      take another one and is dropped.  Lane j keeps the j-th open tour (in
-//      opening order) and its room, so one ballot finds the earliest tour
-//      with room; a tour that closes moves the later ones down a lane.  The
-//      open tours stay few (first fit keeps filling the earliest ones), but
-//      any beyond 64 wait, in order, in a queue in global memory that is
-//      searched, 64 at a time, when no lane has room, and refills the lanes;
+//      take another one).  Lane j keeps the j-th tour in opening order and
+//      its room, so one ballot finds the earliest tour with room; full tours
+//      leave the lanes only when the lanes run out.  The open tours stay few
+//      (first fit keeps filling the earliest ones), but any beyond 64 wait,
+//      in order, in a queue in global memory that is searched, 64 at a time,
+//      when no lane has room, and refills the lanes;
 //   3. tiles of tours: for the S-shape route, every line of an order in the
 //      tile sets its aisle bit in the tour's LDS row and the order raises the
 //      tour's farthest location, then one lane per tour takes the closed
@@ -92,28 +93,45 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
         // ---- 2. first fit -------------------------------------------------
         // a chain of dependent steps: it issues ahead of other plans' tiles
         __builtin_amdgcn_s_setprio(2);
-        const uint32_t mins = (uint32_t)I.min_size;     // a room below it never takes an order
+        const uint32_t mins = (uint32_t)__builtin_amdgcn_readfirstlane(I.min_size);   // a room below it never takes an order
         int T = 0;                                      // tours opened (uniform)
-        int k = 0;                                      // open tours held in lanes (uniform)
-        uint32_t room = 0, tour = 0;                    // lane j < k: the j-th open tour and its room
+        // Lanes [0, k) hold tours in opening order with their rooms, lanes
+        // past k room 0.  A tour whose room falls below mins stays in its
+        // lane until the lanes run out (no order fits it, so a ballot never
+        // picks it); open tours opened after the lanes' wait in the queue
+        // [qh, qt), in order, whenever it is not empty.
+        int k = 0;                                      // uniform
+        uint32_t room = 0, tour = 0;
         uint32_t *queue = A.ff_queue + (int64_t)blockIdx.x * A.ff_stride;
-        int qh = 0, qt = 0;                             // queued open tours [qh, qt) (uniform)
-        // the next live queued tour into lane 63 (the lanes are full and the
-        // queue holds the tours opened after theirs, in order)
-        auto refill = [&]() {
-            while (qh < qt) {
+        int qh = 0, qt = 0;                             // uniform
+        // the full tours leave the lanes (the others move down, in order),
+        // then the freed lanes take the queue's open tours, in order
+        auto compact = [&]() {
+            const uint64_t live = __ballot(room >= mins);
+            const uint32_t nlive = (uint32_t)__builtin_popcountll(live);
+            const uint32_t below = __builtin_amdgcn_mbcnt_hi((uint32_t)(live >> 32),
+                                                             __builtin_amdgcn_mbcnt_lo((uint32_t)live, 0u));
+            // a permutation: open tours to lanes [0, nlive), the rest after them
+            const uint32_t dst = ((live >> lane) & 1ull) ? below : nlive + (uint32_t)lane - below;
+            const uint32_t rr = (uint32_t)__builtin_amdgcn_ds_permute((int)(dst << 2), (int)room);
+            const uint32_t tt = (uint32_t)__builtin_amdgcn_ds_permute((int)(dst << 2), (int)tour);
+            room = (uint32_t)lane < nlive ? rr : 0u;
+            tour = tt;
+            k = (int)nlive;
+            while (k < 64 && qh < qt) {
                 const uint32_t e = qh + lane < qt ? queue[qh + lane] : 0u;
-                const uint64_t live = __ballot((e >> 16) >= mins);
-                if (live) {
-                    const int f = __builtin_ctzll(live);
+                uint64_t lv = __ballot((e >> 16) >= mins);
+                int taken = 0;
+                while (lv && k < 64) {
+                    const int f = __builtin_ctzll(lv);
                     const uint32_t ef = (uint32_t)__builtin_amdgcn_readlane((int)e, f);
-                    room = set_lane(room, ef >> 16, 63);
-                    tour = set_lane(tour, ef & 0xFFFFu, 63);
-                    k = 64;
-                    qh += f + 1;
-                    return;
+                    room = set_lane(room, ef >> 16, k);
+                    tour = set_lane(tour, ef & 0xFFFFu, k);
+                    k++;
+                    taken = f + 1;
+                    lv &= lv - 1ull;
                 }
-                qh = min(qh + 64, qt);
+                qh = k < 64 ? min(qh + 64, qt) : qh + taken;
             }
         };
         for (int i0 = 0; i0 < n; i0 += 64) {
@@ -124,25 +142,16 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
             const uint32_t s_l = max((uint32_t)cnt[o_l], 1u);
             const int m = __builtin_amdgcn_readfirstlane(min(64, n - i0));   // uniform: a scalar loop bound
             uint32_t t_l = 0;                               // lane j: tour of position i0 + j
+#pragma unroll 2
             for (int j = 0; j < m; j++) {
                 const uint32_t sz = (uint32_t)__builtin_amdgcn_readlane((int)s_l, j);
-                // lanes past k hold room 0, which no order (of at least one item) fits
+                // no order (of at least one item) fits room 0 or a room below mins
                 const uint64_t hit = __ballot(room >= sz);
                 uint32_t t = 0;
-                if (hit) {                                   // the earliest open tour with room
+                if (hit) {                                   // the earliest tour in the lanes with room
                     const int f = __builtin_ctzll(hit);
                     t = (uint32_t)__builtin_amdgcn_readlane((int)tour, f);
-                    const uint32_t r = (uint32_t)__builtin_amdgcn_readlane((int)room, f) - sz;
-                    if (r >= mins) {
-                        room = set_lane(room, r, f);
-                    } else {                                 // full: the later open tours move down a lane
-                        const uint32_t rn = (uint32_t)__builtin_amdgcn_ds_bpermute((lane + 1) << 2, (int)room);
-                        const uint32_t tn = (uint32_t)__builtin_amdgcn_ds_bpermute((lane + 1) << 2, (int)tour);
-                        room = lane < f ? room : (lane == 63 ? 0u : rn);
-                        tour = lane < f ? tour : tn;
-                        k--;
-                        if (qh < qt) refill();
-                    }
+                    room = set_lane(room, (uint32_t)__builtin_amdgcn_readlane((int)room, f) - sz, f);
                 } else {
                     bool found = false;
                     // the queued tours, in order, 64 at a time
@@ -153,8 +162,7 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
                             const int f = __builtin_ctzll(h);
                             const uint32_t ef = (uint32_t)__builtin_amdgcn_readlane((int)e, f);
                             t = ef & 0xFFFFu;
-                            const uint32_t r = (ef >> 16) - sz;  // a room below mins stays queued, never taken
-                            if (lane == 0) queue[b + f] = (r << 16) | t;
+                            if (lane == 0) queue[b + f] = (((ef >> 16) - sz) << 16) | t;
                             found = true;
                         }
                     }
@@ -162,7 +170,8 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
                         t = (uint32_t)T++;
                         const uint32_t r0 = sz <= (uint32_t)Q ? (uint32_t)Q - sz : 0u;   // a larger order rides alone
                         if (r0 >= mins) {
-                            if (k < 64) {
+                            if (k == 64) compact();
+                            if (k < 64 && qh == qt) {
                                 room = set_lane(room, r0, k);
                                 tour = set_lane(tour, t, k);
                                 k++;

@@ -133,12 +133,12 @@ __host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * ((uin
 __host__ __device__ inline uint32_t pick_row_bytes(int32_t slots) { return 4u * ((uint32_t)(slots + 1) | 1u); }
 
 // First-fit batching runs in a kernel of its own, one wavefront per plan.
-// LDS: the zone starts (64 words), then one tile of tour rows (128 S-shape
+// LDS: the zone starts (64 words), then one tile of tour rows (192 S-shape
 // rows, or 64 pick rows for the other routes); the tour of every order goes
 // to a global table with one slice per workgroup of the launch, and open
 // tours beyond the 64 a wavefront keeps in registers to a queue with one
 // slice per workgroup.  Tours never outnumber orders.
-__host__ __device__ constexpr int ff_tile(int route) { return route == WO_ROUTE_SSHAPE ? 128 : 64; }
+__host__ __device__ constexpr int ff_tile(int route) { return route == WO_ROUTE_SSHAPE ? 192 : 64; }
 __host__ __device__ inline uint32_t ff_rows_off() { return 256u; }
 
 // bytes of the cnt table (order sizes, then zeros for the dummy and sink entries)

@@ -70,7 +70,7 @@ FF_CASES = [
     (3, 4, 50, 2, 5, 3.0),         # many oversize orders
     (33, 7, 300, 32, 64, 1.5),     # capacity 32, two aisle words
     (64, 3, 129, 5, 17, 0.5),      # a multiple of 32 aisles
-    (400, 250, 4096, 1, 64, 0.0),  # 4,096 single-item orders at capacity 1: 4,096 tours, 64 tiles
+    (400, 250, 4096, 1, 64, 0.0),  # 4,096 single-item orders at capacity 1: 4,096 tours, 22 S-shape tiles
     (400, 250, 4096, 30, 64, 1.5), # 4,096 orders
     (400, 250, 9000, 30, 64, 1.5), # more orders than tours a wave could keep room for in registers
     (100, 250, 20000, 2, 8, 0.5),  # 20,000 orders, about 13,000 tours
