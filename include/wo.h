@@ -76,8 +76,9 @@ typedef enum {
 #define WO_MAX_LINES (1 << 24)      /* order lines per instance */
 #define WO_ZONE_PAD 0xFF
 
-/* Short human-readable name of a status code (static string). */
-const char *wo_status_str(wo_status s);
+/* Short human-readable name of a status code (static string); any value
+ * outside the enumeration gives "WO_E_UNKNOWN". */
+const char *wo_status_str(int32_t s);
 
 /* Message of the last failing call on this thread ("" if none). */
 const char *wo_last_error(void);

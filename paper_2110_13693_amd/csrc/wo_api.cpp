@@ -39,9 +39,9 @@ wo_status wo_fail(wo_status s, const char *fmt, ...)
 #define fail wo_fail
 #define HIP_TRY WO_HIP
 
-extern "C" const char *wo_status_str(wo_status s)
+extern "C" const char *wo_status_str(int32_t s)
 {
-    switch (s) {
+    switch (s) {     // any integer: a value outside the enumeration is WO_E_UNKNOWN
     case WO_OK: return "WO_OK";
     case WO_E_INVAL: return "WO_E_INVAL";
     case WO_E_RANGE: return "WO_E_RANGE";

@@ -13,7 +13,8 @@ from typing import Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libwo.so")
+# WO_LIBRARY selects another build of the library (e.g. the host-sanitizer build)
+LIB_PATH = os.environ.get("WO_LIBRARY") or os.path.join(_HERE, "libwo.so")
 
 WO_OK, WO_E_INVAL, WO_E_RANGE, WO_E_NOMEM, WO_E_DEVICE, WO_E_STATE, WO_E_UNSUPPORTED = range(7)
 WO_MAX_CATEGORIES = 64
