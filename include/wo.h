@@ -289,6 +289,32 @@ wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, int64_t n_pla
                            const uint16_t *d_order_seq, int32_t *d_dist, int32_t reps, void *stream,
                            wo_eval_config *best_out, wo_eval_config *h_all, int32_t *n_all);
 
+/* Persistent autotune cache: a JSON file {"entries": [...]} whose entries
+ * hold a key -- the device's architecture name ("arch", e.g. "gfx950"), its
+ * compute units ("cus"), the handle's route and batching, and the buckets
+ * ceil(log2(.)) of its instance count ("instances"), of its largest order
+ * count ("orders") and of the call's plan count ("plans") -- and a launch
+ * configuration ("block_threads", "blocks_per_cu", "queue", "line_pass",
+ * "small_orders", and the measured "ms").
+ *  - wo_autotune_eval stores its winner in the file named by the
+ *    environment variable WO_TUNE_CACHE, if set (the tuned configuration is
+ *    applied either way; a write failure is returned as WO_E_INVAL).
+ *  - Until a configuration is chosen (wo_set_eval_config, wo_autotune_eval,
+ *    wo_tune_cache_lookup), wo_eval_plans consults that file whenever the
+ *    plan-count bucket differs from the previous call's and uses the
+ *    matching entry, else the default configuration (also when the file is
+ *    missing or malformed).
+ *  - wo_tune_cache_store writes cfg (NULL: the handle's configuration) as
+ *    the entry of the handle's key for n_plans plans, replacing one with the
+ *    same key; the file is rewritten through a temporary file beside it.
+ *  - wo_tune_cache_lookup applies the entry of the handle's key for n_plans
+ *    plans if there is one (*found = 1) and chooses it; *found = 0 leaves the
+ *    configuration as it is.  A missing file is an empty cache; a malformed
+ *    one, or an entry with an invalid configuration, gives WO_E_INVAL.
+ * Synchronous host calls; they touch no device memory. */
+wo_status wo_tune_cache_store(wo_wh *wh, const char *path, int64_t n_plans, const wo_eval_config *cfg);
+wo_status wo_tune_cache_lookup(wo_wh *wh, const char *path, int64_t n_plans, int32_t *found);
+
 /* Graph capture: after one call with the same plan_offsets and n_plans (which
  * uploads the plan map and the work lists), wo_eval_plans enqueues kernels
  * only (ticket reset kernels and one or two evaluation launches) and may be

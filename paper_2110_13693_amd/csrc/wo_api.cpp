@@ -108,6 +108,9 @@ struct wo_wh {
     int64_t ff_stride = 0;              // entries per slice (largest order count + 1, rounded up)
     int ff_slots = 0;                   // slices: the most workgroups a first-fit launch may have
     int small_orders = 1024;            // instances up to this size get a launch of 64-thread workgroups
+    std::string arch;                   // the device's architecture name, e.g. "gfx950"
+    bool cfg_chosen = false;            // set by wo_set_eval_config, the autotuner or a cache lookup
+    int cache_bucket = -1;              // plan-count bucket of the last lookup in the WO_TUNE_CACHE file
     // Work lists by launch class (0: the configured workgroups, 1: 64-thread
     // workgroups for instances of at most small_orders orders, 2: 128-thread
     // workgroups for instances of at most twice that): plan rows, most
@@ -261,6 +264,12 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     int lds_max = 0;
     HIP_TRY(hipDeviceGetAttribute(&lds_max, hipDeviceAttributeMaxSharedMemoryPerBlock, wh->device));
     HIP_TRY(hipDeviceGetAttribute(&wh->cu_count, hipDeviceAttributeMultiprocessorCount, wh->device));
+    {
+        hipDeviceProp_t prop;
+        HIP_TRY(hipGetDeviceProperties(&prop, wh->device));
+        wh->arch = prop.gcnArchName;
+        wh->arch = wh->arch.substr(0, wh->arch.find(':'));   // "gfx950:sramecc+:xnack-" -> "gfx950"
+    }
     wh->lds_max = (uint32_t)std::min(lds_max, 160 * 1024) - 256;   // room for the kernels' static LDS
     wh->n_inst = n_instances;
     wh->route = descs[0].routing;
@@ -616,6 +625,13 @@ static wo_status prepare_work(wo_wh *wh, const std::vector<int64_t> &map, int64_
     return WO_OK;
 }
 
+namespace {
+int log2_bucket(int64_t x);
+wo_status tune_cache_lookup(wo_wh *wh, const char *path, int64_t n_plans, bool *found, bool chosen);
+}  // namespace
+static wo_status check_cfg(const wo_eval_config *cfg);
+static void apply_cfg(wo_wh *wh, const wo_eval_config &c, bool chosen);
+
 extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans,
                                    const uint8_t *d_zone_of, const uint16_t *d_order_seq, int32_t *d_dist,
                                    float *d_orders_per_window, void *stream)
@@ -646,6 +662,20 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     if (!d_zone_of || !d_order_seq || !d_dist) return fail(WO_E_INVAL, "NULL device buffer");
     hipStream_t s = (hipStream_t)stream;
     const bool validate = env_flag("WO_VALIDATE", "1");
+    // Unless the caller chose a configuration, a call whose plan count falls
+    // in another bucket than the previous call's takes its configuration from
+    // the WO_TUNE_CACHE file: the matching entry, else the defaults (also for
+    // a file that cannot be read).
+    if (!wh->cfg_chosen) {
+        const char *cache = getenv("WO_TUNE_CACHE");
+        const int b = log2_bucket(n_plans);
+        if (cache && *cache && b != wh->cache_bucket) {
+            wh->cache_bucket = b;
+            bool found = false;
+            if (tune_cache_lookup(wh, cache, n_plans, &found, false) != WO_OK || !found)
+                apply_cfg(wh, wo_eval_config{256, 0, 0, 0, 1024, 0.f}, false);
+        }
+    }
     {
         // shared device state this call writes: the plan map and the tables
         // built from it, the queue tickets, the validation flag, the
@@ -826,9 +856,8 @@ const InstDev &wo::instance_dev(const wo_wh *wh, int32_t inst) { return wh->inst
 int32_t wo::instance_categories(const wo_wh *wh, int32_t inst) { return wh->inst[inst].n_cat; }
 int32_t wo::instance_count(const wo_wh *wh) { return wh->n_inst; }
 
-extern "C" wo_status wo_set_eval_config(wo_wh *wh, const wo_eval_config *cfg)
+static wo_status check_cfg(const wo_eval_config *cfg)
 {
-    if (!wh || !cfg) return fail(WO_E_INVAL, "NULL argument");
     if (cfg->block_threads != 64 && cfg->block_threads != 128 && cfg->block_threads != 256 &&
         cfg->block_threads != 512)
         return fail(WO_E_INVAL, "block_threads must be 64, 128, 256 or 512");
@@ -836,13 +865,28 @@ extern "C" wo_status wo_set_eval_config(wo_wh *wh, const wo_eval_config *cfg)
     if (cfg->queue != 0 && cfg->queue != 1) return fail(WO_E_INVAL, "queue must be 0 or 1");
     if (cfg->line_pass != 0 && cfg->line_pass != 1) return fail(WO_E_INVAL, "line_pass must be 0 or 1");
     if (cfg->small_orders < 0 || cfg->small_orders > 1024) return fail(WO_E_INVAL, "small_orders in [0, 1024]");
+    return WO_OK;
+}
+
+// chosen: set by the caller (wo_set_eval_config, the autotuner, an explicit
+// cache lookup), after which calls no longer consult the WO_TUNE_CACHE file
+static void apply_cfg(wo_wh *wh, const wo_eval_config &c, bool chosen)
+{
+    wh->block = c.block_threads;
+    wh->per_cu = c.blocks_per_cu;
+    wh->queue = c.queue;
+    wh->main_mode = c.line_pass;
+    wh->small_orders = c.small_orders;
+    if (chosen) wh->cfg_chosen = true;
+}
+
+extern "C" wo_status wo_set_eval_config(wo_wh *wh, const wo_eval_config *cfg)
+{
+    if (!wh || !cfg) return fail(WO_E_INVAL, "NULL argument");
+    if (wo_status st = check_cfg(cfg)) return st;
     Busy busy(&wh->busy);
     if (!busy.ok) return fail(WO_E_STATE, "handle is in use by another thread");
-    wh->block = cfg->block_threads;
-    wh->per_cu = cfg->blocks_per_cu;
-    wh->queue = cfg->queue;
-    wh->main_mode = cfg->line_pass;
-    wh->small_orders = cfg->small_orders;
+    apply_cfg(wh, *cfg, true);
     return WO_OK;
 }
 
@@ -858,6 +902,224 @@ extern "C" wo_status wo_get_eval_config(const wo_wh *wh, wo_eval_config *cfg)
     return WO_OK;
 }
 
+// ---- persistent autotune cache ------------------------------------------
+// A JSON file {"entries": [{...}, ...]}; an entry holds its key -- "arch",
+// "cus", "route", "batching", and the buckets "instances", "orders", "plans"
+// (ceil(log2) of the instance count, the largest order count and the plan
+// count) -- and the configuration: "block_threads", "blocks_per_cu",
+// "queue", "line_pass", "small_orders", "ms".
+namespace {
+
+struct TuneEntry {
+    std::string arch;
+    int64_t v[13];   // cus route batching instances orders plans | block per_cu queue line_pass small_orders | ms*1e6 | -
+};
+const char *const kTuneKeys[12] = {"cus", "route", "batching", "instances", "orders", "plans", "block_threads",
+                                   "blocks_per_cu", "queue", "line_pass", "small_orders", "ms"};
+
+int log2_bucket(int64_t x)
+{
+    int b = 0;
+    while (b < 62 && ((int64_t)1 << b) < x) b++;
+    return b;
+}
+
+void tune_key(const wo_wh *wh, int64_t n_plans, TuneEntry *e)
+{
+    int32_t n_max = 0;
+    for (const InstDev &I : wh->inst) n_max = std::max(n_max, I.n_orders);
+    e->arch = wh->arch;
+    e->v[0] = wh->cu_count;
+    e->v[1] = wh->route;
+    e->v[2] = wh->batching;
+    e->v[3] = log2_bucket(wh->n_inst);
+    e->v[4] = log2_bucket(n_max);
+    e->v[5] = log2_bucket(n_plans);
+}
+
+bool same_key(const TuneEntry &a, const TuneEntry &b)
+{
+    if (a.arch != b.arch) return false;
+    for (int k = 0; k < 6; k++)
+        if (a.v[k] != b.v[k]) return false;
+    return true;
+}
+
+// Reads every entry; a missing file is an empty cache.  Returns false (with
+// the message set) on a file that is not such a JSON document.
+bool read_tune_cache(const char *path, std::vector<TuneEntry> *out)
+{
+    out->clear();
+    FILE *f = fopen(path, "rb");
+    if (!f) return true;
+    std::string text;
+    char buf[4096];
+    size_t got;
+    while ((got = fread(buf, 1, sizeof buf, f)) > 0) text.append(buf, got);
+    fclose(f);
+    size_t p = text.find("\"entries\"");
+    if (p == std::string::npos || (p = text.find('[', p)) == std::string::npos) {
+        wo_fail(WO_E_INVAL, "tune cache %s: no \"entries\" array", path);
+        return false;
+    }
+    p++;
+    for (;;) {
+        while (p < text.size() && (isspace((unsigned char)text[p]) || text[p] == ',')) p++;
+        if (p < text.size() && text[p] == ']') return true;
+        if (p >= text.size() || text[p] != '{') break;
+        const size_t end = text.find('}', p);
+        if (end == std::string::npos) break;
+        const std::string obj = text.substr(p + 1, end - p - 1);
+        TuneEntry e;
+        bool have[12] = {false}, have_arch = false;
+        size_t q = 0;
+        for (;;) {
+            const size_t k0 = obj.find('"', q);
+            if (k0 == std::string::npos) break;
+            const size_t k1 = obj.find('"', k0 + 1);
+            const size_t colon = k1 == std::string::npos ? k1 : obj.find(':', k1);
+            if (colon == std::string::npos) {
+                wo_fail(WO_E_INVAL, "tune cache %s: malformed entry", path);
+                return false;
+            }
+            const std::string key = obj.substr(k0 + 1, k1 - k0 - 1);
+            size_t v = colon + 1;
+            while (v < obj.size() && isspace((unsigned char)obj[v])) v++;
+            if (v < obj.size() && obj[v] == '"') {
+                const size_t v1 = obj.find('"', v + 1);
+                if (v1 == std::string::npos) {
+                    wo_fail(WO_E_INVAL, "tune cache %s: unterminated string", path);
+                    return false;
+                }
+                if (key == "arch") {
+                    e.arch = obj.substr(v + 1, v1 - v - 1);
+                    have_arch = true;
+                }
+                q = v1 + 1;
+            } else {
+                char *stop = nullptr;
+                const double x = strtod(obj.c_str() + v, &stop);
+                if (stop == obj.c_str() + v) {
+                    wo_fail(WO_E_INVAL, "tune cache %s: value of \"%s\" is not a number", path, key.c_str());
+                    return false;
+                }
+                for (int k = 0; k < 12; k++)
+                    if (key == kTuneKeys[k]) {
+                        e.v[k] = k == 11 ? (int64_t)llround(x * 1e6) : (int64_t)llround(x);
+                        have[k] = true;
+                    }
+                q = (size_t)(stop - obj.c_str());
+            }
+        }
+        for (int k = 0; k < 12; k++)
+            if (!have[k]) {
+                wo_fail(WO_E_INVAL, "tune cache %s: an entry lacks \"%s\"", path, kTuneKeys[k]);
+                return false;
+            }
+        if (!have_arch) {
+            wo_fail(WO_E_INVAL, "tune cache %s: an entry lacks \"arch\"", path);
+            return false;
+        }
+        out->push_back(e);
+        p = end + 1;
+    }
+    wo_fail(WO_E_INVAL, "tune cache %s: malformed \"entries\" array", path);
+    return false;
+}
+
+// Writes the entries to a temporary file beside `path`, then renames it.
+bool write_tune_cache(const char *path, const std::vector<TuneEntry> &entries)
+{
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE *f = fopen(tmp.c_str(), "wb");
+    if (!f) {
+        wo_fail(WO_E_INVAL, "tune cache %s: cannot write %s", path, tmp.c_str());
+        return false;
+    }
+    fprintf(f, "{\"entries\": [");
+    for (size_t i = 0; i < entries.size(); i++) {
+        const TuneEntry &e = entries[i];
+        fprintf(f, "%s\n  {\"arch\": \"%s\"", i ? "," : "", e.arch.c_str());
+        for (int k = 0; k < 11; k++) fprintf(f, ", \"%s\": %lld", kTuneKeys[k], (long long)e.v[k]);
+        fprintf(f, ", \"ms\": %.6f}", (double)e.v[11] * 1e-6);
+    }
+    fprintf(f, "\n]}\n");
+    const bool ok = fflush(f) == 0;
+    if (fclose(f) != 0 || !ok || rename(tmp.c_str(), path) != 0) {
+        remove(tmp.c_str());
+        wo_fail(WO_E_INVAL, "tune cache %s: write failed", path);
+        return false;
+    }
+    return true;
+}
+
+wo_status tune_cache_store(wo_wh *wh, const char *path, int64_t n_plans, const wo_eval_config &c)
+{
+    std::vector<TuneEntry> entries;
+    if (!read_tune_cache(path, &entries)) return WO_E_INVAL;
+    TuneEntry e;
+    tune_key(wh, n_plans, &e);
+    e.v[6] = c.block_threads;
+    e.v[7] = c.blocks_per_cu;
+    e.v[8] = c.queue;
+    e.v[9] = c.line_pass;
+    e.v[10] = c.small_orders;
+    e.v[11] = (int64_t)llround((double)c.ms * 1e6);
+    bool replaced = false;
+    for (TuneEntry &x : entries)
+        if (same_key(x, e)) {
+            x = e;
+            replaced = true;
+        }
+    if (!replaced) entries.push_back(e);
+    return write_tune_cache(path, entries) ? WO_OK : WO_E_INVAL;
+}
+
+wo_status tune_cache_lookup(wo_wh *wh, const char *path, int64_t n_plans, bool *found, bool chosen)
+{
+    *found = false;
+    std::vector<TuneEntry> entries;
+    if (!read_tune_cache(path, &entries)) return WO_E_INVAL;
+    TuneEntry key;
+    tune_key(wh, n_plans, &key);
+    for (const TuneEntry &e : entries)
+        if (same_key(e, key)) {
+            const wo_eval_config c{(int32_t)e.v[6], (int32_t)e.v[7], (int32_t)e.v[8], (int32_t)e.v[9],
+                                   (int32_t)e.v[10], (float)((double)e.v[11] * 1e-6)};
+            if (wo_status st = check_cfg(&c)) return st;
+            apply_cfg(wh, c, chosen);
+            *found = true;
+        }
+    return WO_OK;
+}
+
+}  // namespace
+
+extern "C" wo_status wo_tune_cache_store(wo_wh *wh, const char *path, int64_t n_plans, const wo_eval_config *cfg)
+{
+    if (!wh || !path) return fail(WO_E_INVAL, "NULL argument");
+    if (n_plans < 1) return fail(WO_E_INVAL, "n_plans must be >= 1");
+    if (cfg)
+        if (wo_status st = check_cfg(cfg)) return st;
+    Busy busy(&wh->busy);
+    if (!busy.ok) return fail(WO_E_STATE, "handle is in use by another thread");
+    const wo_eval_config c = cfg ? *cfg : wo_eval_config{wh->block, wh->per_cu, wh->queue, wh->main_mode,
+                                                         wh->small_orders, 0.f};
+    return tune_cache_store(wh, path, n_plans, c);
+}
+
+extern "C" wo_status wo_tune_cache_lookup(wo_wh *wh, const char *path, int64_t n_plans, int32_t *found)
+{
+    if (!wh || !path || !found) return fail(WO_E_INVAL, "NULL argument");
+    if (n_plans < 1) return fail(WO_E_INVAL, "n_plans must be >= 1");
+    Busy busy(&wh->busy);
+    if (!busy.ok) return fail(WO_E_STATE, "handle is in use by another thread");
+    bool f = false;
+    const wo_status st = tune_cache_lookup(wh, path, n_plans, &f, true);
+    *found = f ? 1 : 0;
+    return st;
+}
+
 extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans,
                                       const uint8_t *d_zone_of, const uint16_t *d_order_seq, int32_t *d_dist,
                                       int32_t reps, void *stream, wo_eval_config *best_out,
@@ -868,6 +1130,8 @@ extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, in
     if (n_plans < 1) return fail(WO_E_INVAL, "need plans to time");
     hipStream_t s = (hipStream_t)stream;
     const wo_eval_config saved{wh->block, wh->per_cu, wh->queue, wh->main_mode, wh->small_orders, 0.f};
+    const bool chosen0 = wh->cfg_chosen;
+    wh->cfg_chosen = true;              // no cache lookup while configurations are timed
     hipEvent_t e0, e1;
     HIP_TRY(hipEventCreate(&e0));
     HIP_TRY(hipEventCreate(&e1));
@@ -932,10 +1196,13 @@ extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, in
     (void)hipEventDestroy(e1);
     if (st) {
         apply(saved);
+        wh->cfg_chosen = chosen0;
         return st;
     }
     apply(best);
     if (best_out) *best_out = best;
     if (n_all) *n_all = count;
+    const char *cache = getenv("WO_TUNE_CACHE");
+    if (cache && *cache) return tune_cache_store(wh, cache, n_plans, best);
     return WO_OK;
 }

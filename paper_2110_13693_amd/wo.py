@@ -32,7 +32,7 @@ EXPORTS = sorted([
     "wo_screen_plans",
     "wo_search_create", "wo_search_free", "wo_search_step", "wo_search_best", "wo_search_population",
     "wo_search_save", "wo_search_load",
-    "wo_set_eval_config", "wo_get_eval_config", "wo_autotune_eval",
+    "wo_set_eval_config", "wo_get_eval_config", "wo_autotune_eval", "wo_tune_cache_store", "wo_tune_cache_lookup",
     "wo_kmeans_categories", "wo_kmeans_categories_noalloc", "wo_measure_int_peak", "wo_aisle_width",
     "wo_order_features", "wo_svm_create", "wo_svm_free", "wo_svm_push", "wo_svm_train", "wo_svm_predict",
     "wo_svm_get_weights",
@@ -120,6 +120,8 @@ def lib():
         L.wo_set_eval_config.argtypes = [V, P(wo_eval_config)]
         L.wo_get_eval_config.argtypes = [V, P(wo_eval_config)]
         L.wo_autotune_eval.argtypes = [V, V, I64, V, V, V, I32, V, P(wo_eval_config), V, P(I32)]
+        L.wo_tune_cache_store.argtypes = [V, ctypes.c_char_p, I64, V]
+        L.wo_tune_cache_lookup.argtypes = [V, ctypes.c_char_p, I64, P(I32)]
         L.wo_search_create.argtypes = [V, I32, P(wo_search_params), V, V, V, P(V)]
         L.wo_search_free.argtypes = [V]
         L.wo_search_step.argtypes = [V, V, V, I32, V]
@@ -597,6 +599,24 @@ def wo_get_eval_config(wh: Warehouse) -> dict:
     _check(lib().wo_get_eval_config(wh.handle, ctypes.byref(cfg)))
     return {"block_threads": cfg.block_threads, "blocks_per_cu": cfg.blocks_per_cu, "queue": cfg.queue,
             "line_pass": cfg.line_pass, "small_orders": cfg.small_orders}
+
+
+def wo_tune_cache_store(wh: Warehouse, path: str, n_plans: int, cfg: Optional[dict] = None):
+    """Store ``cfg`` (None: the handle's configuration) as the cache entry of
+    the handle's key for ``n_plans`` plans."""
+    c = None
+    if cfg is not None:
+        c = wo_eval_config(int(cfg["block_threads"]), int(cfg["blocks_per_cu"]), int(cfg["queue"]),
+                           int(cfg["line_pass"]), int(cfg["small_orders"]), float(cfg.get("ms", 0.0)))
+    _check(lib().wo_tune_cache_store(wh.handle, os.fsencode(path), int(n_plans),
+                                     None if c is None else ctypes.byref(c)))
+
+
+def wo_tune_cache_lookup(wh: Warehouse, path: str, n_plans: int) -> bool:
+    """Apply the cache entry of the handle's key for ``n_plans`` plans; True if found."""
+    found = ctypes.c_int32(0)
+    _check(lib().wo_tune_cache_lookup(wh.handle, os.fsencode(path), int(n_plans), ctypes.byref(found)))
+    return bool(found.value)
 
 
 def wo_autotune_eval(wh: Warehouse, zone_of, order_seq, dist, plan_offsets=None, reps: int = 3, stream=None):

@@ -143,6 +143,14 @@ def test_eval_rejects_null_handle(wo):
     assert L.wo_instance_info(None, 0, ctypes.byref(n), None, None) == wo.WO_E_INVAL
 
 
+def test_tune_cache_rejects_null_arguments(wo):
+    L = wo.lib()
+    found = ctypes.c_int32(7)
+    assert L.wo_tune_cache_store(None, b"/tmp/x.json", 16, None) == wo.WO_E_INVAL
+    assert L.wo_tune_cache_lookup(None, b"/tmp/x.json", 16, ctypes.byref(found)) == wo.WO_E_INVAL
+    assert found.value == 7
+
+
 def test_binding_refuses_host_tensors(wo):
     import torch
 
