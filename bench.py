@@ -155,7 +155,9 @@ def cpu_baseline(inst, Z, S, ops_per_plan: float, d_gpu, t_gpu, min_wall_s: floa
 def search_comparison(args):
     """Plain genetic search vs surrogate-screened search at equal wall time.
 
-    Paper-scale warehouse, population 16,384, tournament 4, mutation 0.02 per
+    The ``--workload`` warehouse (the paper-scale one by default; ``tiny`` is
+    the 12-category, 200-order one, where the one-hot input is zero-padded),
+    population 16,384, tournament 4, mutation 0.02 per
     position; the screened arm proposes 65,536 children per generation and
     re-scores the best 3,277 exactly.  The surrogate is trained first on plans
     the exact evaluator scores (random slottings at the identity sequence);
@@ -173,7 +175,7 @@ def search_comparison(args):
     from paper_2110_13693_amd import wo
 
     torch.cuda.set_device(0)
-    inst = synth.WORKLOADS["paper"]["make"](0)
+    inst = synth.WORKLOADS[args.workload]["make"](0)
     n = inst.n_orders
     P, K, keep = args.population, 65536, 3277
     wh = wo.wo_load_warehouse([inst])
@@ -304,9 +306,10 @@ def search_comparison(args):
         "unit": "screened best D / plain best D at equal total wall time (median over seeds)",
         "higher_is_better": False,
         "n_gpus": 1,
-        "config": {"workload": "paper-scale warehouse, population %d, %d generations of plain search; "
-                               "screened: %d candidates, keep %d; %d seeds" % (P, args.generations, K, keep,
-                                                                                args.seeds),
+        "config": {"workload": "%s warehouse (%d categories, %d orders), population %d, %d generations of "
+                               "plain search; screened: %d candidates, keep %d; %d seeds"
+                               % ("paper-scale" if args.workload == "paper" else "tiny", inst.n_categories, n, P,
+                                  args.generations, K, keep, args.seeds),
                    "surrogate": {"train_samples": args.train_samples, "epochs": args.epochs, "batch": args.batch,
                                  "lr": args.lr}},
         "summary": {
@@ -398,7 +401,7 @@ def batched_bench(args):
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / INT_VALU_PEAK_OPS, "traffic": None},
         "autotune_table": [[c["block_threads"], c["blocks_per_cu"], c["queue"], c["line_pass"],
-                            round(c["ms"], 4)] for c in table],
+                            c["small_orders"], round(c["ms"], 4)] for c in table],
     }
     wh.free()
     print(json.dumps(out), flush=True)
@@ -582,6 +585,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="time every launch configuration first and keep the fastest (table in the JSON line)")
     ap.add_argument("--route", default="sshape", choices=list(ROUTES),
                     help="route of every tour (the default S-shape is the headline)")
     ap.add_argument("--batching", default="next-fit", choices=list(BATCHINGS),
@@ -647,6 +652,12 @@ def main(argv=None):
     thr = torch.empty(n_plans, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
+    tuned = None
+    if args.autotune:
+        # every launch configuration timed on these plans; the fastest is kept
+        best, table = wo.wo_autotune_eval(wh, z, s, dist, reps=5, stream=stream)
+        tuned = {"best": best, "table": [[c["block_threads"], c["blocks_per_cu"], c["queue"], c["line_pass"],
+                                          c["small_orders"], round(c["ms"], 4)] for c in table]}
     for _ in range(args.warmup):
         wo.wo_eval_plans(wh, z, s, dist, thr, stream=stream)
     torch.cuda.synchronize()
@@ -703,6 +714,10 @@ def main(argv=None):
                    "parallelism": "1 GPU"},
         "roofline": roofline,
     }
+    if tuned is not None:
+        out["autotune"] = tuned
+    if os.environ.get("WO_TILE_TOURS"):
+        out["config"]["tile_tours_cap"] = int(os.environ["WO_TILE_TOURS"])
     # the device's own integer peak, beside the one from the unit counts
     peak_meas = wo.wo_measure_int_peak(5)
     roofline["peak_measured"] = peak_meas / 1e12

@@ -211,7 +211,12 @@ wo_status wo_kmeans_categories_noalloc(const int32_t *d_order_skus, int64_t n_li
  * Validates every descriptor (WO_E_INVAL / WO_E_RANGE), packs per-line
  * records and order tables, copies them to device memory on `stream` and
  * synchronises it.  On success *out owns the device memory until
- * wo_free_warehouse.  Synchronous. */
+ * wo_free_warehouse.  Synchronous.
+ * The next-fit evaluator keeps one tile of tour rows in LDS and passes over
+ * the lines once per tile; a tile holds the expected tour count of the
+ * instance with a margin (fewer where LDS runs out).  The environment
+ * variable WO_TILE_TOURS=t (t >= 1) caps every instance's tile at t tours,
+ * for measuring that choice. */
 wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_instances,
                             void *stream, wo_wh **out);
 

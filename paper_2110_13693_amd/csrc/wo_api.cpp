@@ -436,6 +436,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         int64_t t_cap = (int64_t)std::ceil(1.04 * (double)tours_est) + 8;
         t_cap = std::min<int64_t>(t_cap, d.n_orders);
         t_cap = std::min<int64_t>(t_cap, 65535 / I.row_b - 1);
+        if (const char *cap = getenv("WO_TILE_TOURS"))
+            if (atoll(cap) >= 1) t_cap = std::min<int64_t>(t_cap, atoll(cap));
         t_cap = std::max<int64_t>(t_cap, 1);
         EvalLayout ly = eval_layout(d.n_orders, I.n_units, (uint32_t)I.row_b, (int32_t)t_cap, I.chase_log2, I.chase_lanes);
         while (ly.total > wh->lds_max && t_cap > 1) {
@@ -494,7 +496,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     if ((st = dev_alloc((void **)&wh->d_inst, sizeof(InstDev) * n_instances))) return st;
     if ((st = dev_alloc((void **)&wh->d_map, sizeof(int64_t) * (2 * n_instances + 1)))) return st;
     if ((st = dev_alloc((void **)&wh->d_err, 64))) return st;
-    HIP_TRY(hipEventCreateWithFlags(&wh->last_done, hipEventDisableTiming));
+    // ordering between streams of this device only: no timing, no system-scope fence
+    HIP_TRY(hipEventCreateWithFlags(&wh->last_done, hipEventDisableTiming | hipEventDisableSystemFence));
     wh->d_lines = (const uint2 *)wh->d_pool;
     wh->d_cnt = (const uint8_t *)wh->d_pool + o_cnt;
     wh->d_grec = (const uint32_t *)((const char *)wh->d_pool + o_grec);
