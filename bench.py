@@ -519,6 +519,52 @@ def svm_bench(args):
     return 0
 
 
+def aisle_bench(args):
+    """Aisle-width design (section 5, Subproblem 1, Eq. (1)) for one plan of
+    the paper-scale warehouse: racks 12 dm deep, cross aisles 30 dm, widths
+    5 .. 404 dm (400 widths, every one evaluated exactly in one launch).  A
+    call is synchronous (it returns the chosen width), so it is timed on the
+    host; its CPU baseline is the oracle's sweep over a sample of widths."""
+    import torch
+
+    import synth
+    from oracle import aisles as A
+    from paper_2110_13693_amd import wo
+
+    torch.cuda.set_device(0)
+    inst, Z, S = synth.workload("paper", n_plans=1)
+    wh = wo.wo_load_warehouse([inst])
+    z = torch.from_numpy(Z).cuda()
+    s = torch.from_numpy(S.view(np.int16)).cuda().reshape(-1)
+    r, c, k, a0, a1 = 12, 30, 0.5, 5, 404
+    for _ in range(3):
+        res, dist = wo.wo_aisle_width(wh, z, s, r, c, k, a0, a1)
+    torch.cuda.synchronize()
+    reps = max(5, args.steps // 10)
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        res, dist = wo.wo_aisle_width(wh, z, s, r, c, k, a0, a1)
+    dt = (time.perf_counter() - t0) / reps
+    n_w = a1 - a0 + 1
+    wh.free()
+    # oracle check of sampled widths and its own rate
+    sample = list(range(a0, a1 + 1, 40))
+    t1 = time.perf_counter()
+    ref = [A.distance_at(inst, Z[0], S[0], a + 2 * r) for a in sample]
+    t_cpu = (time.perf_counter() - t1) / len(sample)
+    mism = int(sum(int(dist[a - a0]) != d for a, d in zip(sample, ref)))
+    out = {"metric": "aisle widths evaluated per second (Eq. (1) sweep)", "value": n_w / dt,
+           "unit": "widths/s", "n_gpus": 1, "steps": reps, "ms_per_step": dt * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+           "config": {"workload": "one plan of the paper-scale warehouse, racks 12 dm, cross aisles 30 dm, "
+                                  "widths 5..404 dm, k 0.5", "result": res},
+           "check": {"oracle_widths_checked": len(sample), "oracle_mismatches": mism},
+           "cpu_baseline": {"value": 1.0 / t_cpu, "unit": "widths/s", "cores": 1, "kind": "oracle",
+                            "sample": "%d widths of the same plan" % len(sample)}}
+    print(json.dumps(out), flush=True)
+    return 0
+
+
 def surrogate_bench(args):
     """Surrogate throughput on the BF16 matrix cores: screening predictions
     (65,536 candidates per call) and training (batch 4,096), on random
@@ -604,6 +650,8 @@ def main(argv=None):
                     help="time the 512-instance uneven batch (autotuned, eager and graph replay) instead")
     ap.add_argument("--kmeans", action="store_true",
                     help="time K-means class-based storage on the paper-scale order history instead")
+    ap.add_argument("--aisle", action="store_true",
+                    help="time the aisle-width design (400 widths of one paper-scale plan) instead")
     ap.add_argument("--svm", action="store_true",
                     help="time order-category features, SVM training and prediction instead")
     ap.add_argument("--surrogate", action="store_true",
@@ -626,6 +674,8 @@ def main(argv=None):
         return kmeans_bench(args)
     if args.svm:
         return svm_bench(args)
+    if args.aisle:
+        return aisle_bench(args)
     if args.copy_probe:
         import torch
         a = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device="cuda")
