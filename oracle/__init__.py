@@ -45,7 +45,7 @@ class _Inst(ctypes.Structure):
     ]
 
 ROUTE_SSHAPE, ROUTE_RETURN, ROUTE_LARGEST_GAP, ROUTE_OPTIMAL, ROUTE_COMBINED = 0, 1, 2, 3, 4
-BATCH_NEXT_FIT, BATCH_FIRST_FIT = 0, 1
+BATCH_NEXT_FIT, BATCH_FIRST_FIT, BATCH_SEED = 0, 1, 2
 
 
 def build(force: bool = True) -> str:
@@ -71,6 +71,8 @@ def _load():
         lib.orc_locations.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_tours.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
         lib.orc_tours_first_fit.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+        lib.orc_tours_seed.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                       ctypes.c_void_p]
         lib.orc_sshape_cost.argtypes = [P(_Inst), ctypes.c_void_p, ctypes.c_int32]
         lib.orc_sshape_cost.restype = ctypes.c_int64
         for f in (lib.orc_return_cost, lib.orc_largest_gap_cost, lib.orc_optimal_cost, lib.orc_combined_cost,
@@ -150,6 +152,19 @@ def tours_first_fit(inst, seq) -> np.ndarray:
     out = np.empty(b.n_orders, dtype=np.int32)
     n = ctypes.c_int32(0)
     _check(_load().orc_tours_first_fit(b.ref(), s.ctypes.data, out.ctypes.data, ctypes.byref(n)))
+    assert n.value == int(out.max()) + 1
+    return out
+
+
+def tours_seed(inst, zone_of, seq) -> np.ndarray:
+    """Seed-batching tour of every sequence position under slotting
+    ``zone_of``, tours numbered in the order they are built."""
+    b = _Bound(inst)
+    loc = locations(inst, zone_of)
+    s = _c(seq, np.uint16)
+    out = np.empty(b.n_orders, dtype=np.int32)
+    n = ctypes.c_int32(0)
+    _check(_load().orc_tours_seed(b.ref(), loc.ctypes.data, s.ctypes.data, out.ctypes.data, ctypes.byref(n)))
     assert n.value == int(out.max()) + 1
     return out
 

@@ -24,7 +24,7 @@
  *      item count plus the order's stays <= capacity, otherwise it opens a new
  *      tour; an order is never split (an order larger than the capacity is a
  *      tour of its own); or, when the instance asks for it, first fit
- *      (orc_tours_first_fit below);
+ *      (orc_tours_first_fit below) or seed batching (orc_tours_seed below);
  *   4. route per tour, by one of the standard policies of the routing
  *      literature the paper builds on (de Koster et al. 2007), depot at the
  *      front of aisle 0, L = S * pitch:
@@ -81,7 +81,7 @@ typedef struct {
 
 enum { ORC_ROUTE_SSHAPE = 0, ORC_ROUTE_RETURN = 1, ORC_ROUTE_LARGEST_GAP = 2, ORC_ROUTE_OPTIMAL = 3,
        ORC_ROUTE_COMBINED = 4 };
-enum { ORC_BATCH_NEXT_FIT = 0, ORC_BATCH_FIRST_FIT = 1 };
+enum { ORC_BATCH_NEXT_FIT = 0, ORC_BATCH_FIRST_FIT = 1, ORC_BATCH_SEED = 2 };
 
 enum { ORC_OK = 0, ORC_E_INVAL = 1, ORC_E_NOMEM = 3 };
 
@@ -190,6 +190,70 @@ int orc_tours_first_fit(const orc_instance *w, const uint16_t *seq, int32_t *tou
         tour_of[i] = t;
     }
     free(load);
+    *n_tours = T;
+    return ORC_OK;
+}
+
+/* Seed batching, the third greedy rule of the order-batching literature
+ * (seed algorithms; de Koster, Van der Poort and Wolters 1999): tours are
+ * built one at a time.  A tour starts from a seed, the order earliest in the
+ * sequence that is in no tour yet; then, while some such order fits (the
+ * tour's item count plus the order's stays <= capacity), the one that adds
+ * the fewest aisles the tour does not visit yet joins it, ties going to the
+ * order earlier in the sequence.  An order's aisles are those of its lines'
+ * locations under the plan's slotting (loc_of_sku).  An order larger than the
+ * capacity never fits a tour it does not seed, and a tour it seeds takes
+ * nothing else.  tour_of[i] = tour of the order at position i, tours numbered
+ * in the order they are built. */
+int orc_tours_seed(const orc_instance *w, const int32_t *loc_of_sku, const uint16_t *seq, int32_t *tour_of,
+                   int32_t *n_tours)
+{
+    const int32_t n = w->n_orders, per_aisle = 2 * w->slots_per_side;
+    int32_t i, T = 0;
+    int32_t *visits = (int32_t *)malloc(sizeof(int32_t) * (size_t)w->n_aisles);   /* tour that last visited */
+    int32_t *seen = (int32_t *)malloc(sizeof(int32_t) * (size_t)w->n_aisles);     /* order scan that saw it */
+    int32_t stamp = 0;
+    if (!visits || !seen) { free(visits); free(seen); return ORC_E_NOMEM; }
+    for (i = 0; i < w->n_aisles; i++) visits[i] = -1, seen[i] = -1;
+    for (i = 0; i < n; i++) {
+        if (seq[i] >= n) { free(visits); free(seen); return ORC_E_INVAL; }
+        tour_of[i] = -1;
+    }
+    for (;;) {
+        int32_t s = -1, l;
+        int64_t load;
+        for (i = 0; i < n; i++)
+            if (tour_of[i] < 0) { s = i; break; }
+        if (s < 0) break;
+        /* the seed */
+        tour_of[s] = T;
+        load = w->order_offsets[seq[s] + 1] - w->order_offsets[seq[s]];
+        for (l = w->order_offsets[seq[s]]; l < w->order_offsets[seq[s] + 1]; l++)
+            visits[loc_of_sku[w->order_skus[l]] / per_aisle] = T;
+        for (;;) {
+            int32_t best = -1, best_new = 0;
+            for (i = 0; i < n; i++) {
+                int32_t o = seq[i], fresh = 0;
+                if (tour_of[i] >= 0) continue;
+                if (load + (w->order_offsets[o + 1] - w->order_offsets[o]) > w->capacity) continue;
+                /* distinct aisles of the order that the tour does not visit */
+                stamp++;
+                for (l = w->order_offsets[o]; l < w->order_offsets[o + 1]; l++) {
+                    int32_t a = loc_of_sku[w->order_skus[l]] / per_aisle;
+                    if (visits[a] != T && seen[a] != stamp) fresh++;
+                    seen[a] = stamp;
+                }
+                if (best < 0 || fresh < best_new) best = i, best_new = fresh;
+            }
+            if (best < 0) break;
+            tour_of[best] = T;
+            load += w->order_offsets[seq[best] + 1] - w->order_offsets[seq[best]];
+            for (l = w->order_offsets[seq[best]]; l < w->order_offsets[seq[best] + 1]; l++)
+                visits[loc_of_sku[w->order_skus[l]] / per_aisle] = T;
+        }
+        T++;
+    }
+    free(visits); free(seen);
     *n_tours = T;
     return ORC_OK;
 }
@@ -522,10 +586,11 @@ static int orc_eval_plan_ws(const orc_instance *w, const uint8_t *zone_of, const
     int64_t D = 0;
     int rc = orc_locations(w, zone_of, loc_of_sku);
     if (rc) return rc;
-    if (w->batching == ORC_BATCH_FIRST_FIT) {
+    if (w->batching == ORC_BATCH_FIRST_FIT || w->batching == ORC_BATCH_SEED) {
         /* tour_first holds the tour of every position here; a tour's picks
          * are the lines of its orders */
-        rc = orc_tours_first_fit(w, seq, tour_first, &n_tours);
+        rc = w->batching == ORC_BATCH_SEED ? orc_tours_seed(w, loc_of_sku, seq, tour_first, &n_tours)
+                                           : orc_tours_first_fit(w, seq, tour_first, &n_tours);
         if (rc) return rc;
         for (t = 0; t < n_tours; t++) {
             int32_t n = 0;
@@ -570,7 +635,7 @@ static int orc_check_instance(const orc_instance *w)
     if (w->n_aisles < 1 || w->slots_per_side < 1 || w->pitch_dm < 2 || (w->pitch_dm & 1) ||
         w->spacing_dm < 0 || w->capacity < 1 || w->n_orders < 1 || w->n_orders > 65535 ||
         w->routing < ORC_ROUTE_SSHAPE || w->routing > ORC_ROUTE_COMBINED ||
-        w->batching < ORC_BATCH_NEXT_FIT || w->batching > ORC_BATCH_FIRST_FIT)
+        w->batching < ORC_BATCH_NEXT_FIT || w->batching > ORC_BATCH_SEED)
         return ORC_E_INVAL;
     if (w->order_offsets[0] != 0) return ORC_E_INVAL;
     for (o = 0; o < w->n_orders; o++)

@@ -66,7 +66,7 @@ class Instance:
     seconds_per_item: float = 10.0
     window_s: float = 28800.0
     routing: int = 0          # 0 S-shape, 1 return, 2 largest gap, 3 optimal, 4 combined
-    batching: int = 0         # 0 next fit, 1 first fit
+    batching: int = 0         # 0 next fit, 1 first fit, 2 seed
 
     @property
     def n_skus(self) -> int:

@@ -67,7 +67,7 @@ int main(void)
 {
     int routing, batching, rc = 0;
     for (routing = 0; routing <= 4 && !rc; routing++)
-        for (batching = 0; batching <= 1 && !rc; batching++) {
+        for (batching = 0; batching <= ORC_BATCH_SEED && !rc; batching++) {
             rc = check_instance(routing, batching, 10, 30, 5, 40);
             if (!rc) rc = check_instance(routing, batching, 1, 3, 1, 7);       /* one aisle, capacity 1 */
             if (!rc) rc = check_instance(routing, batching, 33, 2, 9, 64);     /* short aisles */
