@@ -34,7 +34,7 @@ if ROOT not in sys.path:
 INT_VALU_PEAK_OPS = 256 * 64 * 2.4e9
 # route of every tour: S-shape (the headline), return, largest gap, optimal, combined
 ROUTES = {"sshape": 0, "return": 1, "largest-gap": 2, "optimal": 3, "combined": 4}
-BATCHINGS = {"next-fit": 0, "first-fit": 1}
+BATCHINGS = {"next-fit": 0, "first-fit": 1, "seed": 2}
 HBM_PEAK_BYTES = 8.0e12
 
 
@@ -732,10 +732,17 @@ def main(argv=None):
     if args.batching == "next-fit":
         ops = algorithmic_ops(inst, S)
     else:
-        # first fit's tours are not counted on the host: the fewest tours
-        # possible, ceil(items / capacity), keeps the figure a lower bound
+        # first fit's and seed batching's tours are not counted on the host:
+        # the fewest tours possible, ceil(items / capacity), keeps the figure
+        # a lower bound
         t_min = -(-inst.n_items // inst.capacity)
         ops = float((8 * inst.n_items + 4 * inst.n_orders + 12 * t_min) * S.shape[0])
+        if args.batching == "seed":
+            # each of the n joins (or seeds) follows a test of every order
+            # not yet in a tour: n (n + 1) / 2 tests of 3 operations (fit,
+            # key, minimum), a lower bound of the rule's work
+            n = inst.n_orders
+            ops += 3.0 * n * (n + 1) / 2 * S.shape[0]
     # one launch per step: the kernel's average duration is the step time
     achieved_ops = ops / (ms_per_step / 1e3)
     roofline = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": INT_VALU_PEAK_OPS / 1e12,

@@ -148,11 +148,21 @@ enum { WO_ROUTE_SSHAPE = 0, WO_ROUTE_RETURN = 1, WO_ROUTE_LARGEST_GAP = 2, WO_RO
  *   WO_BATCH_NEXT_FIT   an order joins the open tour if the items fit, else
  *                       it opens a new tour (tours are runs of the sequence);
  *   WO_BATCH_FIRST_FIT  an order joins the earliest-opened tour with room for
- *                       it, else it opens a new tour.
- * An order larger than the capacity is a tour of its own under both.  First
- * fit takes every route and any number of orders; the launch configuration
- * (wo_set_eval_config, wo_autotune_eval) does not apply to it. */
-enum { WO_BATCH_NEXT_FIT = 0, WO_BATCH_FIRST_FIT = 1 };
+ *                       it, else it opens a new tour;
+ *   WO_BATCH_SEED       seed batching: tours are built one at a time; a tour
+ *                       starts from the order earliest in the sequence that
+ *                       is in no tour yet, then, while any such order fits,
+ *                       takes the one that adds the fewest aisles the tour
+ *                       does not visit yet (ties: earlier in the sequence).
+ *                       The tours depend on the slotting as well.
+ * An order larger than the capacity is a tour of its own under all three.
+ * First fit and seed batching take every route; the launch configuration
+ * (wo_set_eval_config, wo_autotune_eval) does not apply to them.  Seed
+ * batching keeps per-plan tables in LDS -- about 4 bytes per order, 2 per
+ * line and 4 per aisle -- and takes orders that visit at most 1,023 aisles;
+ * an instance beyond either limit fails at load with WO_E_UNSUPPORTED (the
+ * paper-scale instance needs 38 KB). */
+enum { WO_BATCH_NEXT_FIT = 0, WO_BATCH_FIRST_FIT = 1, WO_BATCH_SEED = 2 };
 #define WO_MAX_PICK_SLOTS 32
 
 typedef struct wo_wh wo_wh;

@@ -58,20 +58,6 @@ static __device__ __forceinline__ uint32_t min_u16x2(uint32_t a, uint32_t b)
                               __builtin_elementwise_min(__builtin_bit_cast(u16x2, a), __builtin_bit_cast(u16x2, b)));
 }
 
-// Inclusive prefix sum over the 64 lanes of a wave (all lanes active): shifts
-// by 1, 2, 4, 8 inside each row of 16 lanes, then the row totals carried by
-// the row broadcasts of lanes 15 and 31.
-static __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
-{
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);   // row_shr:1
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);   // row_shr:2
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);   // row_shr:4
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);   // row_shr:8
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);   // row_bcast:15
-    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);   // row_bcast:31
-    return x;
-}
-
 // Exclusive block scan with one barrier.  `slot` holds BLOCK / 64 words and
 // must not be reused before the block has passed another barrier.
 template <int BLOCK>

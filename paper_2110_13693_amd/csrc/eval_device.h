@@ -1,12 +1,39 @@
 // Device helpers shared by the plan-evaluation kernels (eval.hip: next-fit
-// batching; firstfit.hip: first-fit batching): location arithmetic, the
-// time-window rate, the instance of a plan row, and the route of one tour
-// from its picks (section 5, Subproblem 2).
+// batching; firstfit.hip: first-fit and seed batching): wave scans, location
+// arithmetic, the time-window rate, the instance of a plan row, and the route
+// of one tour from its picks (section 5, Subproblem 2).
 #pragma once
 
 #include "wo_internal.h"
 
 namespace wo {
+
+// Inclusive prefix sum over the 64 lanes of a wave (all lanes active): shifts
+// by 1, 2, 4, 8 inside each row of 16 lanes, then the row totals carried by
+// the row broadcasts of lanes 15 and 31.
+static __device__ __forceinline__ uint32_t wave_incl_scan(uint32_t x)
+{
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x111, 0xF, 0xF, false);   // row_shr:1
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x112, 0xF, 0xF, false);   // row_shr:2
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x114, 0xF, 0xF, false);   // row_shr:4
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x118, 0xF, 0xF, false);   // row_shr:8
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x142, 0xA, 0xF, false);   // row_bcast:15
+    x += (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, 0x143, 0xC, 0xF, false);   // row_bcast:31
+    return x;
+}
+
+// Smallest value over the 64 lanes of a wave (all lanes active), the same
+// shifts and broadcasts; every lane gets it.
+static __device__ __forceinline__ uint32_t wave_min_u32(uint32_t v)
+{
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x111, 0xF, 0xF, false));   // row_shr:1
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x112, 0xF, 0xF, false));   // row_shr:2
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x114, 0xF, 0xF, false));   // row_shr:4
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x118, 0xF, 0xF, false));   // row_shr:8
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x142, 0xA, 0xF, false));   // row_bcast:15
+    v = min(v, (uint32_t)__builtin_amdgcn_update_dpp((int)v, (int)v, 0x143, 0xC, 0xF, false));   // row_bcast:31
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, 63);
+}
 
 static __device__ __forceinline__ uint32_t mulhi24(uint32_t x, uint32_t m)
 {

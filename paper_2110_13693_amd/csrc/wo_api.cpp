@@ -90,6 +90,8 @@ struct wo_wh {
     const uint32_t *d_grec = nullptr;
     const uint32_t *d_gbase = nullptr;
     const uint16_t *d_gord = nullptr;
+    const uint32_t *d_ordoff = nullptr;
+    const uint32_t *d_ordrec = nullptr;
     InstDev *d_inst = nullptr;
     int64_t *d_map = nullptr;           // plan_begin [n+1] | seq_base [n]
     int32_t *d_err = nullptr;
@@ -186,7 +188,7 @@ static wo_status check_desc(const wo_instance_desc &d, int idx)
     if (d.capacity < 1) return fail(WO_E_INVAL, "instance %d: capacity must be >= 1", idx);
     if (d.routing < WO_ROUTE_SSHAPE || d.routing > WO_ROUTE_COMBINED)
         return fail(WO_E_INVAL, "instance %d: unknown routing %d", idx, d.routing);
-    if (d.batching < WO_BATCH_NEXT_FIT || d.batching > WO_BATCH_FIRST_FIT)
+    if (d.batching < WO_BATCH_NEXT_FIT || d.batching > WO_BATCH_SEED)
         return fail(WO_E_INVAL, "instance %d: unknown batching %d", idx, d.batching);
     if (d.capacity > WO_MAX_CAPACITY)
         return fail(WO_E_RANGE, "instance %d: capacity %d > %d", idx, d.capacity, WO_MAX_CAPACITY);
@@ -283,6 +285,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     std::vector<uint8_t> cnt;
     std::vector<uint32_t> grec, gbase;
     std::vector<uint16_t> gord;
+    std::vector<uint32_t> ordoff, ordrec;   // seed batching: each order's line records
     for (int32_t i = 0; i < n_instances; i++) {
         const wo_instance_desc &d = descs[i];
         InstDev &I = wh->inst[i];
@@ -483,6 +486,26 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         I.n_lines_pad = (int32_t)(lines.size() - (size_t)I.line_off);
         wh->lds[i] = ly.total;
         wh->ff_lds[i] = ff_lds_bytes(d.routing, I.row_b);
+        if (d.batching == WO_BATCH_SEED) {
+            I.ordoff_off = (int64_t)ordoff.size();
+            I.ordrec_off = (int64_t)ordrec.size();
+            for (int32_t o = 0; o <= d.n_orders; o++) ordoff.push_back((uint32_t)d.order_offsets[o]);
+            for (int32_t l = 0; l < d.order_offsets[d.n_orders]; l++) {
+                const int32_t sk = d.order_skus[l];
+                ordrec.push_back(((uint32_t)rank[sk] << I.shift) | ((4u * (uint32_t)d.sku_category[sk]) << 24));
+            }
+            int32_t max_lines = 0;
+            for (int32_t o = 0; o < d.n_orders; o++)
+                max_lines = std::max(max_lines, d.order_offsets[o + 1] - d.order_offsets[o]);
+            if (std::min(max_lines, d.n_aisles) > SEED_MAX_AISLES)
+                return fail(WO_E_UNSUPPORTED, "instance %d: seed batching takes orders of at most %d aisles (an order "
+                            "has %d lines over %d aisles)", i, SEED_MAX_AISLES, max_lines, d.n_aisles);
+            const uint32_t need = seed_layout(d.n_orders, d.n_aisles, d.order_offsets[d.n_orders]).total;
+            if (need > wh->lds_max)
+                return fail(WO_E_UNSUPPORTED, "instance %d: seed batching needs %u bytes of LDS (about 4 per order, "
+                            "2 per line and 4 per aisle), the device has %u", i, need, wh->lds_max);
+            wh->ff_lds[i] = std::max(wh->ff_lds[i], need);
+        }
     }
 
     size_t b_lines = lines.size() * sizeof(uint2), b_cnt = cnt.size();
@@ -490,7 +513,9 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     size_t o_grec = (o_cnt + b_cnt + 255) & ~size_t(255);
     size_t o_gbase = (o_grec + grec.size() * 4 + 255) & ~size_t(255);
     size_t o_gord = (o_gbase + gbase.size() * 4 + 255) & ~size_t(255);
-    size_t bytes = o_gord + gord.size() * 2;
+    size_t o_ordoff = (o_gord + gord.size() * 2 + 255) & ~size_t(255);
+    size_t o_ordrec = (o_ordoff + ordoff.size() * 4 + 255) & ~size_t(255);
+    size_t bytes = o_ordrec + ordrec.size() * 4;
     wo_status st;
     if ((st = dev_alloc(&wh->d_pool, bytes))) return st;
     if ((st = dev_alloc((void **)&wh->d_inst, sizeof(InstDev) * n_instances))) return st;
@@ -503,23 +528,30 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     wh->d_grec = (const uint32_t *)((const char *)wh->d_pool + o_grec);
     wh->d_gbase = (const uint32_t *)((const char *)wh->d_pool + o_gbase);
     wh->d_gord = (const uint16_t *)((const char *)wh->d_pool + o_gord);
+    wh->d_ordoff = (const uint32_t *)((const char *)wh->d_pool + o_ordoff);
+    wh->d_ordrec = (const uint32_t *)((const char *)wh->d_pool + o_ordrec);
     hipStream_t s = (hipStream_t)stream;
     if (b_lines) HIP_TRY(hipMemcpyAsync(wh->d_pool, lines.data(), b_lines, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_cnt, cnt.data(), b_cnt, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_grec, grec.data(), grec.size() * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_gbase, gbase.data(), gbase.size() * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_gord, gord.data(), gord.size() * 2, hipMemcpyHostToDevice, s));
+    if (!ordoff.empty())
+        HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_ordoff, ordoff.data(), ordoff.size() * 4, hipMemcpyHostToDevice, s));
+    if (!ordrec.empty())
+        HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_ordrec, ordrec.data(), ordrec.size() * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(wh->d_inst, wh->inst.data(), sizeof(InstDev) * n_instances, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(wh->d_err, 0, 64, s));
     HIP_TRY(hipStreamSynchronize(s));
     wh->lds_max = *std::max_element(wh->lds.begin(), wh->lds.end());
     wh->ff_lds_max = *std::max_element(wh->ff_lds.begin(), wh->ff_lds.end());
-    if (wh->batching == WO_BATCH_FIRST_FIT) {
+    if (wh->batching != WO_BATCH_NEXT_FIT) {
         int32_t n_max = 0;
         for (int32_t i = 0; i < n_instances; i++) n_max = std::max(n_max, descs[i].n_orders);
         wh->ff_stride = ((int64_t)n_max + 1 + 63) & ~(int64_t)63;
         wh->ff_slots = wh->cu_count *
-                       eval_ff_max_blocks_per_cu(wh->route, *std::min_element(wh->ff_lds.begin(), wh->ff_lds.end()));
+                       eval_ff_max_blocks_per_cu(wh->route, wh->batching == WO_BATCH_SEED,
+                                                 *std::min_element(wh->ff_lds.begin(), wh->ff_lds.end()));
         if ((st = dev_alloc((void **)&wh->d_ff_tour, sizeof(uint16_t) * (size_t)wh->ff_stride * wh->ff_slots)))
             return st;
         if ((st = dev_alloc((void **)&wh->d_ff_queue, sizeof(uint32_t) * (size_t)wh->ff_stride * wh->ff_slots)))
@@ -570,7 +602,7 @@ static int launch_grid(const wo_wh *wh, int block, int per_cu_cfg, uint32_t lds,
 
 static int ff_grid(const wo_wh *wh, uint32_t lds, int64_t n_plans)
 {
-    const int64_t fit = (int64_t)wh->cu_count * eval_ff_max_blocks_per_cu(wh->route, lds);
+    const int64_t fit = (int64_t)wh->cu_count * eval_ff_max_blocks_per_cu(wh->route, wh->batching == WO_BATCH_SEED, lds);
     return (int)std::min<int64_t>(n_plans, std::min<int64_t>(fit, wh->ff_slots));   // one tour table slice each
 }
 
@@ -687,7 +719,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
         for (int32_t i = 0; i < wh->n_inst; i++) any_small |= class_of(wh, i) != 0 && map[i + 1] > map[i];
         const bool writes = map != wh->map_cached || (wh->n_inst > 1 && (map != wh->pinst_map || wh->pinst_cap < n_plans)) ||
                             ((any_small || wh->queue) && (map != wh->wc_map || wh->wc_small != wh->small_orders)) ||
-                            wh->queue || validate || wh->batching == WO_BATCH_FIRST_FIT;
+                            wh->queue || validate || wh->batching != WO_BATCH_NEXT_FIT;
         // A call on another stream while the previous call may still run:
         // refused when it would rewrite state the previous call reads, or
         // read state whose upload the previous call enqueued on its own
@@ -750,6 +782,8 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.grec = wh->d_grec;
     a.gbase = wh->d_gbase;
     a.gord = wh->d_gord;
+    a.ordoff = wh->d_ordoff;
+    a.ordrec = wh->d_ordrec;
     a.main_mode = wh->route == WO_ROUTE_SSHAPE ? wh->main_mode : 0;   // pick rows: line per lane only
     a.zone_of = d_zone_of;
     a.seq = d_order_seq;
@@ -766,10 +800,11 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.plan_spacing = nullptr;
     bool any_small = false;
     for (int32_t i = 0; i < wh->n_inst; i++) any_small |= class_of(wh, i) != 0 && map[i + 1] > map[i];
-    if (wh->batching == WO_BATCH_FIRST_FIT) {
+    if (wh->batching != WO_BATCH_NEXT_FIT) {
         // first fit has a kernel of its own, one wavefront per plan; the
         // launch configuration above applies to next fit only
-        HIP_TRY(launch_eval_ff(a, wh->ff_lds_max, ff_grid(wh, wh->ff_lds_max, n_plans), wh->route, s));
+        HIP_TRY(launch_eval_ff(a, wh->ff_lds_max, ff_grid(wh, wh->ff_lds_max, n_plans), wh->route,
+                               wh->batching == WO_BATCH_SEED, s));
     } else if (!any_small && !wh->queue) {
         // one launch, grid stride over the plan rows
         HIP_TRY(launch_eval(a, wh->lds_max, launch_grid(wh, wh->lds_max, n_plans), wh->block, wh->route, s));
@@ -830,6 +865,8 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.grec = wh->d_grec;
     a.gbase = wh->d_gbase;
     a.gord = wh->d_gord;
+    a.ordoff = wh->d_ordoff;
+    a.ordrec = wh->d_ordrec;
     a.main_mode = wh->route == WO_ROUTE_SSHAPE ? wh->main_mode : 0;   // pick rows: line per lane only
     a.zone_of = d_zone_of;
     a.seq = d_order_seq;
@@ -844,9 +881,9 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.ff_stride = wh->ff_stride;
     a.ff_queue = wh->d_ff_queue;
     a.plan_spacing = d_plan_spacing;
-    if (wh->batching == WO_BATCH_FIRST_FIT) {
+    if (wh->batching != WO_BATCH_NEXT_FIT) {
         const uint32_t lds = wh->ff_lds[inst];
-        HIP_TRY(launch_eval_ff(a, lds, ff_grid(wh, lds, n_plans), wh->route, s));
+        HIP_TRY(launch_eval_ff(a, lds, ff_grid(wh, lds, n_plans), wh->route, wh->batching == WO_BATCH_SEED, s));
         return WO_OK;
     }
     const uint32_t lds = wh->lds[inst];
@@ -1175,7 +1212,7 @@ extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, in
     const int blocks[4] = {64, 128, 256, 512};
     const int per_cus[8] = {1, 2, 3, 4, 6, 8, 12, 16};
     // first fit has one launch shape: time it once and keep the configuration
-    const int n_blocks = wh->batching == WO_BATCH_FIRST_FIT ? 0 : 4;
+    const int n_blocks = wh->batching != WO_BATCH_NEXT_FIT ? 0 : 4;
     if (n_blocks == 0) st = time_cfg(saved);
     for (int bi = 0; bi < n_blocks && !st; bi++) {
         for (int pi = 0; pi < 8 && !st; pi++) {

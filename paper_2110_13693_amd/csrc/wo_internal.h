@@ -53,6 +53,10 @@ struct InstDev {
     int64_t gbase_off;      // u32 [n_grp + 1], relative to grec_off
     int64_t gord_off;       // u16 [64 * n_grp]
     int32_t n_grp;
+    // seed batching: order o's lines are ordrec[ordoff[o] .. ordoff[o + 1])
+    // (same packing as grec), both relative to the offsets below
+    int64_t ordoff_off;     // u32 [n_orders + 1]
+    int64_t ordrec_off;     // u32 [n_lines]
     int32_t n_skus;         // sum of the category sizes: a zone start never exceeds n_skus - size
     double walk;
     double t_item;
@@ -72,6 +76,8 @@ struct EvalArgs {
     const uint32_t *grec;
     const uint32_t *gbase;
     const uint16_t *gord;
+    const uint32_t *ordoff;
+    const uint32_t *ordrec;
     int32_t main_mode;      // 0: one line per lane, 1: one order per lane (groups)
     const uint8_t *zone_of;
     const uint16_t *seq;
@@ -175,12 +181,35 @@ __host__ __device__ inline EvalLayout eval_layout(int32_t n_orders, int32_t n_un
     return L;
 }
 
+// Seed batching builds its tours in LDS before the tile pass, in the space
+// the tile's rows take afterwards: per sequence position a state word (new
+// aisles of the order for the tour being built, bits 0-9; its aisle count,
+// bits 10-19; its size, bits 20-27; bit 31 once it is in a tour); per aisle
+// the end of its list of positions; the positions grouped by aisle (one entry
+// per order and aisle it visits, at most one per line); the tour's aisle set.
+// An order visits at most SEED_MAX_AISLES aisles.
+constexpr int SEED_MAX_AISLES = 1023;
+struct SeedLayout {
+    uint32_t st, aend, apos, tbits, total;
+};
+__host__ __device__ inline SeedLayout seed_layout(int32_t n_orders, int32_t n_aisles, int32_t n_lines)
+{
+    SeedLayout L;
+    uint32_t b = ff_rows_off();
+    L.st = b;     b = (b + 4u * (uint32_t)n_orders + 15u) & ~15u;
+    L.aend = b;   b += 4u * (uint32_t)n_aisles;
+    L.tbits = b;  b += 4u * (((uint32_t)n_aisles + 31u) / 32u);
+    L.apos = b;   b = (b + 2u * (uint32_t)n_lines + 15u) & ~15u;
+    L.total = b;
+    return L;
+}
+
 hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, int route, hipStream_t s);
 // workgroups of the evaluation kernel that fit one CU (registers and LDS)
 int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes);
 // First-fit batching: one 64-thread workgroup per plan.
-hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, int route, hipStream_t s);
-int eval_ff_max_blocks_per_cu(int route, uint32_t lds_bytes);
+hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, int route, bool seed, hipStream_t s);
+int eval_ff_max_blocks_per_cu(int route, bool seed, uint32_t lds_bytes);
 
 // library-internal helpers over a loaded handle
 wo_status eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint8_t *d_zone_of,

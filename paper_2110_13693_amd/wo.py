@@ -84,7 +84,7 @@ class wo_instance_desc(ctypes.Structure):
 
 
 WO_ROUTE_SSHAPE, WO_ROUTE_RETURN, WO_ROUTE_LARGEST_GAP, WO_ROUTE_OPTIMAL, WO_ROUTE_COMBINED = 0, 1, 2, 3, 4
-WO_BATCH_NEXT_FIT, WO_BATCH_FIRST_FIT = 0, 1
+WO_BATCH_NEXT_FIT, WO_BATCH_FIRST_FIT, WO_BATCH_SEED = 0, 1, 2
 
 _lib = None
 

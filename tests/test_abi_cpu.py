@@ -79,7 +79,7 @@ def _mod(inst, **kw):
     ("n_aisles", 1, 2),             # 600 SKUs no longer fit 60 locations
     ("routing", 5, 1),              # unknown route
     ("routing", -1, 1),
-    ("batching", 2, 1),             # unknown batching rule
+    ("batching", 3, 1),             # unknown batching rule
     ("batching", -1, 1),
 ])
 def test_load_rejects_descriptor(wo, tiny, field, value, status):
