@@ -197,8 +197,7 @@ wo_status wo_kmeans_categories(const int32_t *d_order_skus, int64_t n_lines, int
  * wo_kmeans_categories, with three differences:
  *   - asynchronous on `stream`: it enqueues kernels only (no allocation,
  *     memset or host synchronisation), so it may be captured into a graph;
- *     every one of the max_iter (1 .. WO_KMEANS_NOALLOC_MAX_ITER) assignment
- *     steps is enqueued, and those after convergence return at once;
+ *     max_iter is in 1 .. WO_KMEANS_NOALLOC_MAX_ITER;
  *   - d_k_used and d_n_iter are device int32 pointers (each nullable) that
  *     receive the categories used and the assignments performed; an order
  *     line naming a SKU outside 0 .. n_skus - 1 sets *d_k_used to -1 (and

@@ -6,8 +6,8 @@
 // categories the zones hold.
 //
 // SKUs of equal frequency always share a cluster, so after the frequencies
-// and their histogram the iteration runs over the histogram's bins (one
-// thread per frequency value).  The arithmetic is exact: a centroid is the
+// and their histogram the iteration runs over the histogram's non-empty bins,
+// all of it in one workgroup (km_lloyd_kernel).  The arithmetic is exact: a centroid is the
 // rational S / N, and f is nearer to S_j / N_j than to S_k / N_k iff
 // |f N_j - S_j| N_k < |f N_k - S_k| N_j, compared in 128 bits (ties to the
 // lower index).  Start: centroid c is the distinct frequency of rank
@@ -45,20 +45,37 @@ __device__ __forceinline__ bool less_prod(unsigned long long a, unsigned long lo
 
 __device__ __forceinline__ unsigned long long absdiff(long long x, long long y) { return x > y ? x - y : y - x; }
 
-__global__ void km_freq_kernel(const int32_t *skus, int64_t n_lines, int32_t n_skus, int32_t *freq, int32_t *err)
+// SKU ids are popularity ranks, so the low ids take most lines: their counts
+// gather in the workgroup's LDS first and reach memory once per workgroup.
+constexpr int KM_HOT_SKUS = 2048;
+__global__ __launch_bounds__(1024) void km_freq_kernel(const int32_t *skus, int64_t n_lines, int32_t n_skus,
+                                                       int32_t *freq, int32_t *err)
 {
+    __shared__ int32_t hot[KM_HOT_SKUS];
+    for (int i = threadIdx.x; i < KM_HOT_SKUS; i += blockDim.x) hot[i] = 0;
+    __syncthreads();
     for (int64_t l = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; l < n_lines; l += (int64_t)gridDim.x * blockDim.x) {
         const int32_t s = skus[l];
         if (s < 0 || s >= n_skus) atomicOr(err, 1);
+        else if (s < KM_HOT_SKUS) atomicAdd(&hot[s], 1);
         else atomicAdd(&freq[s], 1);
     }
+    __syncthreads();
+    for (int i = threadIdx.x; i < KM_HOT_SKUS && i < n_skus; i += blockDim.x)
+        if (hot[i]) atomicAdd(&freq[i], hot[i]);
 }
 
 // Most SKUs share a few low frequencies (most are never picked), so the
-// lanes holding the first active lane's frequency add their count with one
-// atomic; the others add one each.
-__global__ void km_hist_kernel(const int32_t *freq, int32_t n_skus, int32_t *hist)
+// counts of frequencies below KM_HOT gather in the workgroup's LDS first (the
+// lanes of a wave holding the first active lane's frequency add theirs with
+// one atomic), and each workgroup adds them to memory once; higher
+// frequencies, few SKUs each, go to memory directly.
+constexpr int KM_HOT = 64;
+__global__ __launch_bounds__(1024) void km_hist_kernel(const int32_t *freq, int32_t n_skus, int32_t *hist)
 {
+    __shared__ int32_t hot[KM_HOT];
+    if (threadIdx.x < KM_HOT) hot[threadIdx.x] = 0;
+    __syncthreads();
     for (int32_t s0 = blockIdx.x * blockDim.x; s0 < n_skus; s0 += gridDim.x * blockDim.x) {
         const int32_t s = s0 + threadIdx.x;
         const bool act = s < n_skus;
@@ -68,122 +85,17 @@ __global__ void km_hist_kernel(const int32_t *freq, int32_t n_skus, int32_t *his
         const int32_t f0 = __shfl(f, __builtin_ctzll(live), 64);
         const uint64_t same = __ballot(act && f == f0);
         if (act && f == f0) {
-            if ((threadIdx.x & 63) == __builtin_ctzll(same)) atomicAdd(&hist[f0], __popcll(same));
+            if ((threadIdx.x & 63) == __builtin_ctzll(same)) {
+                if (f0 < KM_HOT) atomicAdd(&hot[f0], __popcll(same));
+                else atomicAdd(&hist[f0], __popcll(same));
+            }
         } else if (act) {
-            atomicAdd(&hist[f], 1);
+            if (f < KM_HOT) atomicAdd(&hot[f], 1);
+            else atomicAdd(&hist[f], 1);
         }
-    }
-}
-
-// One block of 1024 threads: count the distinct frequencies, then give
-// every centroid its starting value.
-__global__ __launch_bounds__(1024) void km_init_kernel(const int32_t *hist, int32_t n_bins, int32_t k, KmState *st)
-{
-    __shared__ int part[1024 / 64];
-    __shared__ int D_s;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    int d = 0;
-    for (int v = tid; v < n_bins; v += 1024) d += hist[v] > 0;
-    for (int o = 32; o >= 1; o >>= 1) d += __shfl_xor(d, o, 64);
-    if (lane == 0) part[w] = d;
-    __syncthreads();
-    if (tid == 0) {
-        int t = 0;
-        for (int i = 0; i < 1024 / 64; i++) t += part[i];
-        D_s = t;
     }
     __syncthreads();
-    const long long D = D_s;
-    // rank of each non-empty bin among the non-empty ones, chunk by chunk
-    int base = 0;
-    for (int v0 = 0; v0 < n_bins; v0 += 1024) {
-        const int v = v0 + tid;
-        const int ne = v < n_bins && hist[v] > 0;
-        const unsigned long long b = __ballot(ne);
-        const int below = __popcll(b & ((1ull << lane) - 1ull));
-        __syncthreads();                       // part[] of the previous chunk has been read
-        if (lane == 0) part[w] = __popcll(b);
-        __syncthreads();
-        int off = base;
-        for (int i = 0; i < w; i++) off += part[i];
-        if (ne) {
-            const long long r = off + below;
-            for (int c = 0; c < k; c++)
-                if ((2ll * c + 1) * D / (2ll * k) == r) {
-                    st->S[c] = v;
-                    st->N[c] = 1;
-                }
-        }
-        for (int i = 0; i < 1024 / 64; i++) base += part[i];
-    }
-}
-
-__global__ void km_assign_kernel(const int32_t *hist, int32_t n_bins, int32_t k, int32_t *label, KmState *st)
-{
-    if (st->done) return;
-    for (int32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n_bins; v += gridDim.x * blockDim.x) {
-        const int32_t m = hist[v];
-        if (m == 0) continue;
-        int best = 0;
-        unsigned long long bd = absdiff((long long)v * st->N[0], st->S[0]), bn = (unsigned long long)st->N[0];
-        for (int c = 1; c < k; c++) {
-            const unsigned long long dc = absdiff((long long)v * st->N[c], st->S[c]);
-            const unsigned long long nc = (unsigned long long)st->N[c];
-            if (less_prod(dc, bn, bd, nc)) {   // dc / nc < bd / bn
-                best = c;
-                bd = dc;
-                bn = nc;
-            }
-        }
-        if (label[v] != best) {
-            st->changed = 1;                   // benign race: every writer stores 1
-            label[v] = best;
-        }
-        atomicAdd(&st->S2[best], (unsigned long long)v * (unsigned long long)m);
-        atomicAdd(&st->N2[best], (unsigned long long)m);
-    }
-}
-
-__global__ void km_update_kernel(int32_t k, KmState *st)
-{
-    const int c = threadIdx.x;
-    const int done = st->done, changed = st->changed;
-    __syncthreads();
-    if (done) return;
-    if (c == 0) {
-        st->n_iter += 1;
-        if (!changed) st->done = 1;
-        st->changed = 0;
-    }
-    if (c < k) {
-        if (changed) {
-            st->cnt[c] = (long long)st->N2[c];
-            if (st->N2[c] > 0) {
-                st->S[c] = (long long)st->S2[c];
-                st->N[c] = (long long)st->N2[c];
-            }
-        }
-        st->S2[c] = 0;
-        st->N2[c] = 0;
-    }
-}
-
-// Non-empty clusters by descending mean (exact: S_d N_c > S_c N_d), equal
-// means by lower index.
-__global__ void km_rank_kernel(int32_t k, KmState *st)
-{
-    const int c = threadIdx.x;
-    if (c >= k) return;
-    int r = 0;
-    const bool used = st->cnt[c] > 0;
-    for (int d = 0; d < k; d++) {
-        if (st->cnt[d] <= 0) continue;
-        const long long a = st->S[d] * st->N[c], b = st->S[c] * st->N[d];
-        r += a > b || (a == b && d < c);
-    }
-    st->rank[c] = used ? r : -1;
-    const unsigned long long u = __ballot(used);
-    if (c == 0) st->k_used = __popcll(u);
+    if (threadIdx.x < KM_HOT && hot[threadIdx.x]) atomicAdd(&hist[threadIdx.x], hot[threadIdx.x]);
 }
 
 __global__ void km_label_kernel(const int32_t *freq, int32_t n_skus, const int32_t *label, const KmState *st,
@@ -191,6 +103,127 @@ __global__ void km_label_kernel(const int32_t *freq, int32_t n_skus, const int32
 {
     for (int32_t s = blockIdx.x * blockDim.x + threadIdx.x; s < n_skus; s += gridDim.x * blockDim.x)
         category[s] = st->rank[label[freq[s]]];
+}
+
+// The whole iteration in one workgroup: the non-empty bins (the distinct
+// frequencies, at most sqrt(2 n_lines) + 1 <= KM_MAX_BINS of them since the
+// positive ones sum to at most n_lines) are compacted in order into LDS;
+// then the start, every assignment and centroid move, and the ranking run
+// with block barriers between them, and the bins' labels and the state go to
+// memory once.  The same steps as the kernels above, in one launch.
+constexpr int KM_MAX_BINS = 5800;
+constexpr int KM_BLOCK = 1024;
+
+__global__ __launch_bounds__(KM_BLOCK) void km_lloyd_kernel(const int32_t *hist, int32_t n_bins, int32_t k,
+                                                           int32_t max_iter, int32_t *label, KmState *st)
+{
+    __shared__ int32_t bv[KM_MAX_BINS], bm[KM_MAX_BINS];
+    __shared__ uint8_t bl[KM_MAX_BINS];
+    __shared__ unsigned long long S2[KM_MAX], N2[KM_MAX];
+    __shared__ long long S[KM_MAX], N[KM_MAX], cnt[KM_MAX];
+    __shared__ int part[KM_BLOCK / 64];
+    __shared__ int D_s, changed_s;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    // ---- compaction of the non-empty bins, in order of frequency
+    int base = 0;
+    int m_next = tid < n_bins ? hist[tid] : 0;       // each chunk's counts are read one chunk ahead
+    for (int v0 = 0; v0 < n_bins; v0 += KM_BLOCK) {
+        const int v = v0 + tid;
+        const int m = m_next;
+        m_next = v + KM_BLOCK < n_bins ? hist[v + KM_BLOCK] : 0;
+        const unsigned long long b = __ballot(m > 0);
+        const int below = __popcll(b & ((1ull << lane) - 1ull));
+        __syncthreads();                           // part[] of the previous chunk has been read
+        if (lane == 0) part[w] = __popcll(b);
+        __syncthreads();
+        int off = base;
+        for (int i = 0; i < w; i++) off += part[i];
+        if (m > 0 && off + below < KM_MAX_BINS) {
+            bv[off + below] = v;
+            bm[off + below] = m;
+            bl[off + below] = 0xFF;
+        }
+        for (int i = 0; i < KM_BLOCK / 64; i++) base += part[i];
+    }
+    if (tid == 0) D_s = min(base, KM_MAX_BINS);
+    if (tid < KM_MAX) {
+        S2[tid] = 0;
+        N2[tid] = 0;
+        cnt[tid] = 0;
+    }
+    __syncthreads();
+    const int D = D_s;
+    // ---- start: centroid c is the distinct frequency of rank (2c + 1) D / (2k)
+    if (tid < k) {
+        const long long r = (2ll * tid + 1) * D / (2ll * k);
+        S[tid] = bv[r];
+        N[tid] = 1;
+    }
+    int n_iter = 0;
+    for (;;) {
+        if (tid == 0) changed_s = 0;
+        __syncthreads();
+        // ---- assignment: the nearest centroid, exactly; ties to the lower index
+        for (int i = tid; i < D; i += KM_BLOCK) {
+            const long long v = bv[i];
+            int best = 0;
+            unsigned long long bd = absdiff(v * N[0], S[0]), bn = (unsigned long long)N[0];
+            for (int c = 1; c < k; c++) {
+                const unsigned long long dc = absdiff(v * N[c], S[c]);
+                const unsigned long long nc = (unsigned long long)N[c];
+                if (less_prod(dc, bn, bd, nc)) {
+                    best = c;
+                    bd = dc;
+                    bn = nc;
+                }
+            }
+            if (bl[i] != best) {
+                changed_s = 1;                     // benign race: every writer stores 1
+                bl[i] = (uint8_t)best;
+            }
+            atomicAdd(&S2[best], (unsigned long long)v * (unsigned long long)bm[i]);
+            atomicAdd(&N2[best], (unsigned long long)bm[i]);
+        }
+        __syncthreads();
+        n_iter++;
+        const int changed = changed_s;
+        // ---- centroids: each non-empty cluster moves to its members' mean
+        if (tid < k) {
+            if (changed) {
+                cnt[tid] = (long long)N2[tid];
+                if (N2[tid] > 0) {
+                    S[tid] = (long long)S2[tid];
+                    N[tid] = (long long)N2[tid];
+                }
+            }
+            S2[tid] = 0;
+            N2[tid] = 0;
+        }
+        __syncthreads();
+        if (!changed || n_iter >= max_iter) break;
+    }
+    // ---- results: bin labels, state, ranks of the non-empty clusters
+    for (int i = tid; i < D; i += KM_BLOCK) label[bv[i]] = bl[i];
+    if (tid < KM_MAX) {
+        const bool in = tid < k;
+        st->S[tid] = in ? S[tid] : 0;
+        st->N[tid] = in ? N[tid] : 0;
+        st->cnt[tid] = in ? cnt[tid] : 0;
+        int r = 0;
+        const bool used = in && cnt[tid] > 0;
+        for (int d = 0; d < k; d++) {
+            if (cnt[d] <= 0) continue;
+            const long long a = S[d] * N[tid], b = S[tid] * N[d];
+            r += a > b || (a == b && d < tid);
+        }
+        st->rank[tid] = used ? r : -1;
+        const unsigned long long u = __ballot(used);
+        if (tid == 0) {
+            st->k_used = __popcll(u);
+            st->n_iter = n_iter;
+            st->done = 1;
+        }
+    }
 }
 
 int grid_for(int64_t n, int block) { return (int)std::min<int64_t>(std::max<int64_t>((n + block - 1) / block, 1), 4096); }
@@ -291,32 +324,16 @@ extern "C" wo_status wo_kmeans_categories(const int32_t *d_order_skus, int64_t n
     KmState *st = (KmState *)(buf + o_state);
     int32_t *err = (int32_t *)(buf + o_err);
     wo_status ret = WO_OK;
-    int32_t h_done = 0, h_err = 0;
+    int32_t h_err = 0;
     KmState h{};
     auto run = [&]() -> wo_status {
         WO_HIP(hipMemsetAsync(buf, 0, o_label, s));                       // frequencies, histogram
         WO_HIP(hipMemsetAsync(label, 0xFF, o_state - o_label, s));        // no cluster yet
         WO_HIP(hipMemsetAsync(st, 0, bytes - o_state, s));                // state, error flag
-        hipLaunchKernelGGL(km_freq_kernel, dim3(grid_for(n_lines, 256)), dim3(256), 0, s, d_order_skus, n_lines,
+        hipLaunchKernelGGL(km_freq_kernel, dim3(std::min(grid_for(n_lines, 1024), 64)), dim3(1024), 0, s, d_order_skus, n_lines,
                            n_skus, freq, err);
-        hipLaunchKernelGGL(km_hist_kernel, dim3(grid_for(n_skus, 256)), dim3(256), 0, s, freq, n_skus, hist);
-        hipLaunchKernelGGL(km_init_kernel, dim3(1), dim3(1024), 0, s, hist, n_bins, k, st);
-        WO_HIP(hipGetLastError());
-        // assignments in rounds of 8; an assignment after convergence returns at once
-        for (int it = 0; it < max_iter;) {
-            const int r = std::min(8, max_iter - it);
-            for (int i = 0; i < r; i++) {
-                hipLaunchKernelGGL(km_assign_kernel, dim3(grid_for(n_bins, 256)), dim3(256), 0, s, hist, n_bins, k,
-                                   label, st);
-                hipLaunchKernelGGL(km_update_kernel, dim3(1), dim3(KM_MAX), 0, s, k, st);
-            }
-            it += r;
-            WO_HIP(hipGetLastError());
-            WO_HIP(hipMemcpyAsync(&h_done, &st->done, sizeof(int32_t), hipMemcpyDeviceToHost, s));
-            WO_HIP(hipStreamSynchronize(s));
-            if (h_done) break;
-        }
-        hipLaunchKernelGGL(km_rank_kernel, dim3(1), dim3(KM_MAX), 0, s, k, st);
+        hipLaunchKernelGGL(km_hist_kernel, dim3(std::min(grid_for(n_skus, 1024), 128)), dim3(1024), 0, s, freq, n_skus, hist);
+        hipLaunchKernelGGL(km_lloyd_kernel, dim3(1), dim3(KM_BLOCK), 0, s, hist, n_bins, k, max_iter, label, st);
         hipLaunchKernelGGL(km_label_kernel, dim3(grid_for(n_skus, 256)), dim3(256), 0, s, freq, n_skus, label, st,
                            d_category);
         WO_HIP(hipGetLastError());
@@ -368,16 +385,10 @@ extern "C" wo_status wo_kmeans_categories_noalloc(const int32_t *d_order_skus, i
                        (int64_t)Ly.o_label / 4, 0);
     hipLaunchKernelGGL(km_fill_kernel, dim3(grid_for(w_lab, 256)), dim3(256), 0, s, label, w_lab, -1);
     hipLaunchKernelGGL(km_fill_kernel, dim3(1), dim3(256), 0, s, (int32_t *)st, w_state, 0);
-    hipLaunchKernelGGL(km_freq_kernel, dim3(grid_for(n_lines, 256)), dim3(256), 0, s, d_order_skus, n_lines, n_skus,
+    hipLaunchKernelGGL(km_freq_kernel, dim3(std::min(grid_for(n_lines, 1024), 64)), dim3(1024), 0, s, d_order_skus, n_lines, n_skus,
                        freq, err);
-    hipLaunchKernelGGL(km_hist_kernel, dim3(grid_for(n_skus, 256)), dim3(256), 0, s, freq, n_skus, hist);
-    hipLaunchKernelGGL(km_init_kernel, dim3(1), dim3(1024), 0, s, hist, n_bins, k, st);
-    // every assignment step is enqueued; those after convergence return at once
-    for (int it = 0; it < max_iter; it++) {
-        hipLaunchKernelGGL(km_assign_kernel, dim3(grid_for(n_bins, 256)), dim3(256), 0, s, hist, n_bins, k, label, st);
-        hipLaunchKernelGGL(km_update_kernel, dim3(1), dim3(KM_MAX), 0, s, k, st);
-    }
-    hipLaunchKernelGGL(km_rank_kernel, dim3(1), dim3(KM_MAX), 0, s, k, st);
+    hipLaunchKernelGGL(km_hist_kernel, dim3(std::min(grid_for(n_skus, 1024), 128)), dim3(1024), 0, s, freq, n_skus, hist);
+    hipLaunchKernelGGL(km_lloyd_kernel, dim3(1), dim3(KM_BLOCK), 0, s, hist, n_bins, k, max_iter, label, st);
     hipLaunchKernelGGL(km_label_kernel, dim3(grid_for(n_skus, 256)), dim3(256), 0, s, freq, n_skus, label, st,
                        d_category);
     hipLaunchKernelGGL(km_finish_kernel, dim3(1), dim3(64), 0, s, st, err, d_k_used, d_n_iter);
