@@ -617,7 +617,7 @@ def surrogate_bench(args):
                      "unit": "TFLOP/s", "frac": pred_flops / BF16_PEAK_FLOPS, "traffic": None},
         "train": {"samples_per_s": n_train / train_s, "epoch_s": train_s,
                   "achieved_tflops": train_flops / 1e12, "frac": train_flops / BF16_PEAK_FLOPS,
-                  "note": "wall time of one epoch, host shuffle included"},
+                  "note": "wall time of one epoch; shuffle and loss table on the device"},
     }
     sur.free()
     print(json.dumps(out), flush=True)

@@ -386,9 +386,10 @@ wo_status wo_sur_gradients(wo_sur *s, int32_t n, const uint8_t *d_zone_of, const
 
 /* Train on n (plan, exact distance) pairs: d_zone_of uint8[n][64],
  * d_dist int32[n] (e.g. from wo_eval_plans).  Mini-batch Adam (lr, beta
- * 0.9 / 0.999, eps 1e-8) over `epochs` shuffled passes (shuffle drawn from
- * `seed`); batch a multiple of 128 in [128, 4096]; a last partial batch is
- * dropped.  h_last_loss (nullable) receives the mean batch loss of the last
+ * 0.9 / 0.999, eps 1e-8) over `epochs` shuffled passes (each epoch's
+ * shuffle is a keyed pseudorandom permutation of the samples, keyed by `seed`
+ * and the epoch, evaluated on the device); batch a multiple of 128 in
+ * [128, 4096]; a last partial batch is dropped; n <= 2^31 - 1.  h_last_loss (nullable) receives the mean batch loss of the last
  * epoch.  Returns when the work is done (it synchronises the stream). */
 wo_status wo_sur_train(wo_sur *s, int64_t n, const uint8_t *d_zone_of, const int32_t *d_dist,
                        int32_t epochs, int32_t batch, float lr, uint64_t seed, float *h_last_loss,

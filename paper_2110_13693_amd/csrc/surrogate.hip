@@ -368,16 +368,48 @@ __global__ __launch_bounds__(256) void refresh_bf16_kernel(const float *W1t, con
 }
 
 // Gather a batch: zone rows and standardised targets of the given samples.
-__global__ __launch_bounds__(256) void gather_batch_kernel(const uint8_t *zone, const int32_t *dist,
-                                                           const int32_t *idx, int n, double mean, double inv_std,
-                                                           uint8_t *zb, float *tb)
+// A keyed pseudorandom permutation of [0, n): a four-round balanced Feistel
+// network on 2h bits (2^2h >= n) whose round function is the SplitMix64
+// finaliser of (key, round, half), with cycle walking -- values at or above
+// n are encrypted again until they fall inside, which keeps a bijection of
+// [0, n) (Black and Rogaway 2002).  The training shuffle is computed where the
+// batch is gathered, with no table and no host work.
+__device__ __forceinline__ uint64_t mix64(uint64_t z)
+{
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    return z ^ (z >> 31);
+}
+
+__device__ __forceinline__ uint64_t feistel_perm(uint64_t x, uint64_t n, int h, uint64_t key)
+{
+    const uint64_t mask = (1ull << h) - 1ull;
+    do {
+        uint64_t l = x >> h, r = x & mask;
+        for (int round = 0; round < 4; round++) {
+            const uint64_t f = mix64(key + 0x9E3779B97F4A7C15ull * (uint64_t)(round + 1) + r) & mask;
+            const uint64_t t = l ^ f;
+            l = r;
+            r = t;
+        }
+        x = (l << h) | r;
+    } while (x >= n);
+    return x;
+}
+
+__global__ __launch_bounds__(256) void gather_batch_kernel(const uint8_t *zone, const int32_t *dist, int64_t n_all,
+                                                           int h, uint64_t key, int64_t first, int n, double mean,
+                                                           double inv_std, uint8_t *zb, float *tb)
 {
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (b >= n) return;
-    const int64_t s = idx[b];
+    const int64_t s = (int64_t)feistel_perm((uint64_t)(first + b), (uint64_t)n_all, h, key);
     zb[(int64_t)b * 64 + lane] = zone[s * 64 + lane];
     if (lane == 0) tb[b] = (float)(((double)dist[s] - mean) * inv_std);
 }
+
+// One batch's loss into the epoch's loss table (no host round trip per batch).
+__global__ void keep_loss_kernel(const float *loss, float *table, int64_t b) { table[b] = *loss; }
 
 // Mean and standard deviation of int32 distances (two fixed-order passes,
 // one block, double accumulation).
@@ -580,11 +612,17 @@ hipError_t launch_refresh_bf16(const float *W1t, const float *W2t, uint16_t *W1b
     return hipGetLastError();
 }
 
-hipError_t launch_gather_batch(const uint8_t *zone, const int32_t *dist, const int32_t *idx, int n, double mean,
-                               double inv_std, uint8_t *zb, float *tb, hipStream_t s)
+hipError_t launch_gather_batch(const uint8_t *zone, const int32_t *dist, int64_t n_all, int h, uint64_t key,
+                               int64_t first, int n, double mean, double inv_std, uint8_t *zb, float *tb, hipStream_t s)
 {
-    hipLaunchKernelGGL(gather_batch_kernel, dim3((n + 3) / 4), dim3(256), 0, s, zone, dist, idx, n, mean, inv_std,
-                       zb, tb);
+    hipLaunchKernelGGL(gather_batch_kernel, dim3((n + 3) / 4), dim3(256), 0, s, zone, dist, n_all, h, key, first, n,
+                       mean, inv_std, zb, tb);
+    return hipGetLastError();
+}
+
+hipError_t launch_keep_loss(const float *loss, float *table, int64_t b, hipStream_t s)
+{
+    hipLaunchKernelGGL(keep_loss_kernel, dim3(1), dim3(1), 0, s, loss, table, b);
     return hipGetLastError();
 }
 

@@ -44,8 +44,8 @@ struct wo_sur {
     uint16_t *d_H1 = nullptr, *d_H1T = nullptr, *d_DU2 = nullptr, *d_DU2T = nullptr, *d_DU1T = nullptr;
     float *d_pred = nullptr;            // screening scratch [capacity]
     int64_t pred_cap = 0;
-    int32_t *d_idx = nullptr;           // training permutation
-    int64_t idx_cap = 0;
+    float *d_losses = nullptr;          // training: the loss of every batch of an epoch
+    int64_t losses_cap = 0;
     double *d_mom = nullptr;
     float *d_loss = nullptr;
     double mean = 0.0, std = 1.0;
@@ -322,7 +322,7 @@ extern "C" wo_status wo_sur_free(wo_sur *s)
     (void)hipDeviceSynchronize();
     void *bufs[] = {s->d_p,  s->d_g,   s->d_m,  s->d_v,   s->d_W1b, s->d_W2b,  s->d_W2kn, s->d_zb,   s->d_tb,
                     s->d_U1, s->d_U2,  s->d_H2, s->d_dy,  s->d_sq,  s->d_H1,   s->d_H1T,  s->d_DU2,  s->d_DU2T,
-                    s->d_DU1T, s->d_pred, s->d_idx, s->d_mom, s->d_loss};
+                    s->d_DU1T, s->d_pred, s->d_losses, s->d_mom, s->d_loss};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete s;
@@ -410,43 +410,42 @@ extern "C" wo_status wo_sur_train(wo_sur *s, int64_t n, const uint8_t *d_zone_of
         s->std = mom[1];
         s->scaled = true;
     }
-    if (s->idx_cap < n) {
-        if (s->d_idx) (void)hipFree(s->d_idx);
-        s->d_idx = nullptr;
-        s->idx_cap = 0;
-        wo_status r = alloc(&s->d_idx, (size_t)n);
-        if (r) return r;
-        s->idx_cap = n;
-    }
-    std::vector<int32_t> perm(n);
     const int64_t n_batches = n / batch;
+    if (s->losses_cap < n_batches) {
+        if (s->d_losses) (void)hipFree(s->d_losses);
+        s->d_losses = nullptr;
+        s->losses_cap = 0;
+        wo_status r = alloc(&s->d_losses, (size_t)n_batches);
+        if (r) return r;
+        s->losses_cap = n_batches;
+    }
+    // the shuffle of an epoch: a keyed permutation of [0, n) evaluated where
+    // the batch is gathered (key from the counter generator on seed and
+    // epoch), over 2h bits with 2^2h >= n
+    int h = 1;
+    while ((1ll << (2 * h)) < n) h++;
     double loss_sum = 0.0;
     std::vector<float> losses;
     for (int ep = 0; ep < epochs; ep++) {
-        // Fisher-Yates with the counter generator (seed, epoch, position)
-        for (int64_t i = 0; i < n; i++) perm[i] = (int32_t)i;
-        for (int64_t i = n - 1; i > 0; i--) {
-            const uint64_t r = splitmix64(splitmix64(seed + (uint64_t)ep * 0x100000001ull) ^ (uint64_t)i);
-            const int64_t j = (int64_t)(((r >> 32) * (uint64_t)(i + 1)) >> 32);
-            std::swap(perm[i], perm[j]);
-        }
-        WO_HIP(hipMemcpyAsync(s->d_idx, perm.data(), sizeof(int32_t) * n, hipMemcpyHostToDevice, st));
+        const uint64_t key = splitmix64(splitmix64(seed + (uint64_t)ep * 0x100000001ull));
         const bool last = ep == epochs - 1;
-        if (last) losses.assign(n_batches, 0.f);
         for (int64_t b = 0; b < n_batches; b++) {
-            WO_HIP(launch_gather_batch(d_zone_of, d_dist, s->d_idx + b * batch, batch, s->mean, 1.0 / s->std,
+            WO_HIP(launch_gather_batch(d_zone_of, d_dist, n, h, key, b * batch, batch, s->mean, 1.0 / s->std,
                                        s->d_zb, s->d_tb, st));
             wo_status r = gradients(s, batch, st);
             if (r) return r;
             s->step++;
             WO_HIP(launch_adam(s->d_p, s->d_g, s->d_m, s->d_v, P_TOTAL, lr, s->step, s->d_W1b, s->d_W2b, s->d_W2kn,
                                st));
-            if (last && h_last_loss)
-                WO_HIP(hipMemcpyAsync(&losses[b], s->d_loss, sizeof(float), hipMemcpyDeviceToHost, st));
+            if (last && h_last_loss) WO_HIP(launch_keep_loss(s->d_loss, s->d_losses, b, st));
         }
-        // the host permutation buffer is reused next epoch: wait for the copy
-        WO_HIP(hipStreamSynchronize(st));
     }
+    if (h_last_loss) {
+        losses.assign(n_batches, 0.f);
+        if (n_batches)
+            WO_HIP(hipMemcpyAsync(losses.data(), s->d_losses, sizeof(float) * n_batches, hipMemcpyDeviceToHost, st));
+    }
+    WO_HIP(hipStreamSynchronize(st));
     if (h_last_loss) {
         for (float l : losses) loss_sum += l;
         *h_last_loss = (float)(loss_sum / std::max<int64_t>(1, n_batches));

@@ -75,8 +75,9 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, 
                        uint16_t *W1b, uint16_t *W2b, uint16_t *W2kn, hipStream_t s);
 hipError_t launch_refresh_bf16(const float *W1t, const float *W2t, uint16_t *W1b, uint16_t *W2b, uint16_t *W2kn,
                                hipStream_t s);
-hipError_t launch_gather_batch(const uint8_t *zone, const int32_t *dist, const int32_t *idx, int n, double mean,
-                               double inv_std, uint8_t *zb, float *tb, hipStream_t s);
+hipError_t launch_gather_batch(const uint8_t *zone, const int32_t *dist, int64_t n_all, int h, uint64_t key,
+                               int64_t first, int n, double mean, double inv_std, uint8_t *zb, float *tb, hipStream_t s);
+hipError_t launch_keep_loss(const float *loss, float *table, int64_t b, hipStream_t s);
 hipError_t launch_moments(const int32_t *d, int64_t n, double *out, hipStream_t s);
 hipError_t launch_topk(const float *pred, int n, int k, int32_t *out, hipStream_t s);
 hipError_t launch_worst(const int32_t *dist, int n, int k, int32_t *out, hipStream_t s);
