@@ -631,6 +631,8 @@ def main(argv=None):
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--workload", default="paper", choices=["paper", "tiny"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--line-pass", type=int, default=None, choices=[0, 1, 2],
+                    help="mapping of the aisle-set pass (0 instance order, 1 order per lane, 2 sequence order)")
     ap.add_argument("--autotune", action="store_true",
                     help="time every launch configuration first and keep the fastest (table in the JSON line)")
     ap.add_argument("--route", default="sshape", choices=list(ROUTES),
@@ -702,6 +704,10 @@ def main(argv=None):
     thr = torch.empty(n_plans, dtype=torch.float32, device="cuda")
     stream = torch.cuda.current_stream()
 
+    if args.line_pass is not None:
+        cfg = wo.wo_get_eval_config(wh)
+        cfg["line_pass"] = args.line_pass
+        wo.wo_set_eval_config(wh, **cfg)
     tuned = None
     if args.autotune:
         # every launch configuration timed on these plans; the fastest is kept
@@ -748,7 +754,8 @@ def main(argv=None):
     roofline = {"bound": "alu", "achieved": achieved_ops / 1e12, "peak": INT_VALU_PEAK_OPS / 1e12,
                 "unit": "Tops/s", "frac": achieved_ops / INT_VALU_PEAK_OPS,
                 "traffic": profiled_traffic() if (args.workload == "paper" and args.route == "sshape"
-                                                  and args.batching == "next-fit") else None}
+                                                  and args.batching == "next-fit"
+                                                  and not args.line_pass and not args.autotune) else None}
 
     out = {
         "metric": "exact plan evals/s @4k orders",
@@ -771,6 +778,8 @@ def main(argv=None):
                    "parallelism": "1 GPU"},
         "roofline": roofline,
     }
+    if args.line_pass is not None:
+        out["config"]["line_pass"] = args.line_pass
     if tuned is not None:
         out["autotune"] = tuned
     if os.environ.get("WO_TILE_TOURS"):

@@ -273,7 +273,13 @@ wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64_t n_plans,
  *  - queue: the work distribution (0 = grid stride over plan rows, 1 = a
  *    ticket queue over a work list that puts the plans of the most
  *    expensive instances first -- useful for uneven batches);
- *  - line_pass: the mapping of the aisle-set pass;
+ *  - line_pass: the mapping of the aisle-set pass (S-shape; the other routes
+ *    always take 0): 0 = the instance's lines in a fixed order, one per
+ *    lane, each order's tour entry looked up in a table (default); 1 = one
+ *    order per lane; 2 = the lines in sequence order, 64 consecutive ones
+ *    per wave, so that the lines of a tour sit in adjacent lanes and its
+ *    farthest location is one segmented wave maximum (instances with an
+ *    order larger than the capacity take 0);
  *  - small_orders: plans of instances with at most this many orders (0 to
  *    1024) are evaluated in a launch of their own with 64-thread
  *    workgroups, and those with at most twice as many in one with
@@ -285,7 +291,7 @@ typedef struct {
     int32_t block_threads;
     int32_t blocks_per_cu;
     int32_t queue;
-    int32_t line_pass;   /* 0: one order line per lane (default), 1: one order per lane */
+    int32_t line_pass;   /* 0: one line per lane (default), 1: one order per lane, 2: sequence order */
     int32_t small_orders;
     float ms;
 } wo_eval_config;

@@ -174,7 +174,7 @@ static __device__ __forceinline__ bool load_chunk(const uint16_t *s, int nv, uin
     return false;
 }
 
-template <int BLOCK, int ROUTE>
+template <int BLOCK, int ROUTE, bool SEQ_PASS>
 __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_plans_kernel(EvalArgs A)
 {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -389,7 +389,8 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
             for (uint32_t w = w0; w < w1; w++) pc += __popc(B[w]);
 
             // ---- 3. segments and their candidate entries (wave 0) --------
-            int G = (misc[0] || I.n_seg <= 1) ? 1 : I.n_seg;   // uniform
+            const bool any_big = misc[0] != 0;         // uniform: an order larger than Q
+            int G = (any_big || I.n_seg <= 1) ? 1 : I.n_seg;   // uniform
             if (G > 1 && tid < 64) {
                 const int g = lane;
                 const uint32_t s_g = segs[g];
@@ -570,7 +571,26 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
                     }
                 }
             };
-            write_entries(0u, one_piece);
+            // line pass in sequence order: every unit is a line (no order
+            // larger than Q); tours come from the openings counted per word
+            // of P, with no tour table
+            const int mm = (ROUTE == WO_ROUTE_SSHAPE && SEQ_PASS && !any_big) ? 2 : (A.main_mode == 1 ? 1 : 0);
+            if (SEQ_PASS && mm == 2) {
+                uint32_t *pp = (uint32_t *)tour;         // the tour table is not used
+                const uint32_t npw = ((uint32_t)n + 31u) / 32u;
+                const uint32_t ppt = (npw + BLOCK - 1) / BLOCK;
+                const uint32_t q0 = min(npw, (uint32_t)tid * ppt), q1 = min(npw, q0 + ppt);
+                uint32_t c = 0;
+                for (uint32_t w = q0; w < q1; w++) c += __popc(P[w]);
+                uint32_t tot;
+                uint32_t base = block_excl_scan<BLOCK>(c, scan_a, &tot);
+                for (uint32_t w = q0; w < q1; w++) {
+                    pp[w] = base;
+                    base += __popc(P[w]);
+                }
+            } else {
+                write_entries(0u, one_piece);
+            }
             __syncthreads();
 
             // ---- prefetch of the next plan's inputs -----------------------
@@ -602,13 +622,71 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
             for (uint32_t t0 = 0; t0 < n_tours; t0 += (uint32_t)T) {
                 if (t0 > 0) {
                     __syncthreads();                     // the previous tile's rows are read
-                    write_entries(t0, false);
+                    if (!(SEQ_PASS && mm == 2)) write_entries(t0, false);
                     uint4 *rows = (uint4 *)(smem + LDS_REGION);
                     const int nr4 = (int)((RB * (uint32_t)(T + 1) + 15u) / 16u);
                     for (int k = tid; k < nr4; k += BLOCK) rows[k] = make_uint4(0u, 0u, 0u, 0u);
                     __syncthreads();
                 }
-                if (ROUTE != WO_ROUTE_SSHAPE || A.main_mode == 0) {
+                if (ROUTE == WO_ROUTE_SSHAPE && SEQ_PASS && mm == 2) {
+                    // each wave takes 64 consecutive units (lines) of the
+                    // sequence: a line finds its order from the unit bitmap,
+                    // its record in the order's line list, its tour from the
+                    // opening flags; the farthest location of each tour's
+                    // lanes is one segmented max across the wave (tours are
+                    // contiguous), raised once per tour and wave
+                    const uint32_t *ordoff = A.ordoff + I.ordoff_off;
+                    const uint32_t *ordrec = A.ordrec + I.ordrec_off;
+                    const uint32_t *pp = (const uint32_t *)tour;
+                    const int zsv = (int)zs[lane];
+                    for (uint32_t c0 = (uint32_t)(tid >> 6) * 64u; c0 < n_units; c0 += (uint32_t)BLOCK) {
+                        const uint32_t su = c0 + (uint32_t)lane;
+                        const bool act = su < n_units;
+                        uint32_t rec = 0, tr = 0xFFFFFFFFu;
+                        if (act) {
+                            const uint32_t w = su >> 5;
+                            const uint32_t hi = B[w] & (0xFFFFFFFFu >> (31u - (su & 31u)));
+                            uint32_t start, cle;
+                            if (hi) {
+                                start = (w << 5) + 31u - (uint32_t)__builtin_clz(hi);
+                                cle = pref[w] + __popc(hi);
+                            } else {                     // the order began in the word below (size <= Q <= 32)
+                                const uint32_t lo = w ? B[w - 1] : 1u;
+                                start = ((w - 1u) << 5) + 31u - ffbh(lo);
+                                cle = pref[w];
+                            }
+                            const uint32_t pos = min(cle - 1u, (uint32_t)(n - 1));
+                            const uint32_t o = min((uint32_t)seq[pos], (uint32_t)(n - 1));
+                            const uint32_t j = min(su - start, ordoff[o + 1] - ordoff[o] - 1u);
+                            rec = ordrec[ordoff[o] + j];
+                            const uint32_t pw = pos >> 5;
+                            const uint32_t t = pp[pw] + __popc(P[pw] & (0xFFFFFFFFu >> (31u - (pos & 31u)))) - 1u;
+                            const uint32_t rel = t - t0;
+                            tr = rel < (uint32_t)T ? rel * RB : dummy;
+                        }
+                        const uint32_t ls = rec + (uint32_t)__builtin_amdgcn_ds_bpermute((int)(rec >> 24), zsv);
+                        if (act) {
+                            const uint32_t a = mulhi24(ls, magic);
+                            __hip_atomic_fetch_or(lds32(LDS_REGION + 4u + tr + ((a >> 5) << 2)), 1u << (a & 31u),
+                                                  __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                        }
+                        // segments of equal tour rows: heads by ballot, max by
+                        // shifted lane reads within each segment
+                        const uint32_t prev = (uint32_t)__shfl_up((int)tr, 1, 64);
+                        const uint64_t heads = __ballot(lane == 0 || prev != tr);
+                        const int seg0 = 63 - __builtin_clzll(heads & (lane == 63 ? ~0ull : ((2ull << lane) - 1ull)));
+                        uint32_t m = act ? ls : 0u;
+#pragma unroll
+                        for (int d = 1; d < 64; d <<= 1) {
+                            const uint32_t x = (uint32_t)__shfl_up((int)m, d, 64);
+                            if (lane - d >= seg0) m = max(m, x);
+                        }
+                        const bool last = lane == 63 || ((heads >> (lane + 1)) & 1ull);
+                        if (act && last)
+                            __hip_atomic_fetch_max(lds32(LDS_REGION + tr), m, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                    }
+                } else if (ROUTE != WO_ROUTE_SSHAPE || mm == 0) {
                     // each wave takes whole groups of 64 lanes x 8 line slots
                     constexpr int U = LINE_SLOTS;
                     constexpr int NW = BLOCK / 64;
@@ -774,13 +852,13 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
 // Reset of the work-queue ticket (a kernel, so that it can sit in a graph).
 __global__ void reset_ticket_kernel(uint32_t *ctr) { *ctr = 0u; }
 
-template <int BLOCK, int ROUTE>
+template <int BLOCK, int ROUTE, bool SEQ_PASS>
 static hipError_t launch_eval_t(const EvalArgs &a, uint32_t lds_bytes, int grid, hipStream_t s)
 {
     // raise the dynamic LDS limit to what this launch needs
     static uint32_t attr_bytes = 0;
     if (lds_bytes > attr_bytes) {
-        hipError_t e = hipFuncSetAttribute((const void *)eval_plans_kernel<BLOCK, ROUTE>,
+        hipError_t e = hipFuncSetAttribute((const void *)eval_plans_kernel<BLOCK, ROUTE, SEQ_PASS>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds_bytes);
         if (e != hipSuccess) {
             (void)hipGetLastError();
@@ -789,15 +867,15 @@ static hipError_t launch_eval_t(const EvalArgs &a, uint32_t lds_bytes, int grid,
         attr_bytes = lds_bytes;
     }
     if (a.queue) hipLaunchKernelGGL(reset_ticket_kernel, dim3(1), dim3(1), 0, s, a.queue_ctr);
-    hipLaunchKernelGGL((eval_plans_kernel<BLOCK, ROUTE>), dim3(grid), dim3(BLOCK), lds_bytes, s, a);
+    hipLaunchKernelGGL((eval_plans_kernel<BLOCK, ROUTE, SEQ_PASS>), dim3(grid), dim3(BLOCK), lds_bytes, s, a);
     return hipGetLastError();
 }
 
-template <int BLOCK, int ROUTE>
+template <int BLOCK, int ROUTE, bool SEQ_PASS>
 static int max_blocks_t(uint32_t lds_bytes)
 {
     int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, eval_plans_kernel<BLOCK, ROUTE>, BLOCK, lds_bytes) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, eval_plans_kernel<BLOCK, ROUTE, SEQ_PASS>, BLOCK, lds_bytes) !=
         hipSuccess) {
         (void)hipGetLastError();
         return 1;
@@ -805,20 +883,21 @@ static int max_blocks_t(uint32_t lds_bytes)
     return n > 0 ? n : 1;
 }
 
-template <int ROUTE>
+template <int ROUTE, bool SEQ_PASS = false>
 static int max_blocks_r(int block, uint32_t lds_bytes)
 {
     switch (block) {
-    case 64: return max_blocks_t<64, ROUTE>(lds_bytes);
-    case 128: return max_blocks_t<128, ROUTE>(lds_bytes);
-    case 256: return max_blocks_t<256, ROUTE>(lds_bytes);
-    case 512: return max_blocks_t<512, ROUTE>(lds_bytes);
+    case 64: return max_blocks_t<64, ROUTE, SEQ_PASS>(lds_bytes);
+    case 128: return max_blocks_t<128, ROUTE, SEQ_PASS>(lds_bytes);
+    case 256: return max_blocks_t<256, ROUTE, SEQ_PASS>(lds_bytes);
+    case 512: return max_blocks_t<512, ROUTE, SEQ_PASS>(lds_bytes);
     }
     return 1;
 }
 
-int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes)
+int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes, int line_pass)
 {
+    if (route == WO_ROUTE_SSHAPE && line_pass == 2) return max_blocks_r<WO_ROUTE_SSHAPE, true>(block, lds_bytes);
     switch (route) {
     case WO_ROUTE_RETURN: return max_blocks_r<WO_ROUTE_RETURN>(block, lds_bytes);
     case WO_ROUTE_LARGEST_GAP: return max_blocks_r<WO_ROUTE_LARGEST_GAP>(block, lds_bytes);
@@ -828,14 +907,14 @@ int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes)
     return max_blocks_r<WO_ROUTE_SSHAPE>(block, lds_bytes);
 }
 
-template <int ROUTE>
+template <int ROUTE, bool SEQ_PASS = false>
 static hipError_t launch_eval_r(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, hipStream_t s)
 {
     switch (block) {
-    case 64: return launch_eval_t<64, ROUTE>(a, lds_bytes, grid, s);
-    case 128: return launch_eval_t<128, ROUTE>(a, lds_bytes, grid, s);
-    case 256: return launch_eval_t<256, ROUTE>(a, lds_bytes, grid, s);
-    case 512: return launch_eval_t<512, ROUTE>(a, lds_bytes, grid, s);
+    case 64: return launch_eval_t<64, ROUTE, SEQ_PASS>(a, lds_bytes, grid, s);
+    case 128: return launch_eval_t<128, ROUTE, SEQ_PASS>(a, lds_bytes, grid, s);
+    case 256: return launch_eval_t<256, ROUTE, SEQ_PASS>(a, lds_bytes, grid, s);
+    case 512: return launch_eval_t<512, ROUTE, SEQ_PASS>(a, lds_bytes, grid, s);
     }
     return hipErrorInvalidValue;
 }
@@ -843,7 +922,11 @@ static hipError_t launch_eval_r(const EvalArgs &a, uint32_t lds_bytes, int grid,
 hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, int route, hipStream_t s)
 {
     switch (route) {
-    case WO_ROUTE_SSHAPE: return launch_eval_r<WO_ROUTE_SSHAPE>(a, lds_bytes, grid, block, s);
+    case WO_ROUTE_SSHAPE:
+        // the line pass in sequence order is an instantiation of its own, so
+        // that the default one carries none of its code
+        if (a.main_mode == 2) return launch_eval_r<WO_ROUTE_SSHAPE, true>(a, lds_bytes, grid, block, s);
+        return launch_eval_r<WO_ROUTE_SSHAPE>(a, lds_bytes, grid, block, s);
     case WO_ROUTE_RETURN: return launch_eval_r<WO_ROUTE_RETURN>(a, lds_bytes, grid, block, s);
     case WO_ROUTE_LARGEST_GAP: return launch_eval_r<WO_ROUTE_LARGEST_GAP>(a, lds_bytes, grid, block, s);
     case WO_ROUTE_OPTIMAL: return launch_eval_r<WO_ROUTE_OPTIMAL>(a, lds_bytes, grid, block, s);

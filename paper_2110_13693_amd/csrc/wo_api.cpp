@@ -100,7 +100,7 @@ struct wo_wh {
     int block = 256;
     int per_cu = 0;                     // 0: as many as LDS allows
     int queue = 0;                      // 1: ticket queue over the cost-ordered work list
-    int main_mode = 0;                  // 0: one line per lane in the line pass, 1: one order per lane
+    int main_mode = 0;                  // line pass: 0 one line per lane, 1 one order per lane, 2 sequence order
     int route = WO_ROUTE_SSHAPE;        // the route of every instance of the handle
     int batching = WO_BATCH_NEXT_FIT;   // the order batching of every instance of the handle
     std::vector<uint32_t> ff_lds;       // first fit: LDS of one plan of each instance
@@ -486,7 +486,9 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         I.n_lines_pad = (int32_t)(lines.size() - (size_t)I.line_off);
         wh->lds[i] = ly.total;
         wh->ff_lds[i] = ff_lds_bytes(d.routing, I.row_b);
-        if (d.batching == WO_BATCH_SEED) {
+        {
+            // each order's line records (seed batching, and the line pass in
+            // sequence order)
             I.ordoff_off = (int64_t)ordoff.size();
             I.ordrec_off = (int64_t)ordrec.size();
             for (int32_t o = 0; o <= d.n_orders; o++) ordoff.push_back((uint32_t)d.order_offsets[o]);
@@ -494,6 +496,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
                 const int32_t sk = d.order_skus[l];
                 ordrec.push_back(((uint32_t)rank[sk] << I.shift) | ((4u * (uint32_t)d.sku_category[sk]) << 24));
             }
+        }
+        if (d.batching == WO_BATCH_SEED) {
             int32_t max_lines = 0;
             for (int32_t o = 0; o < d.n_orders; o++)
                 max_lines = std::max(max_lines, d.order_offsets[o + 1] - d.order_offsets[o]);
@@ -595,7 +599,7 @@ extern "C" wo_status wo_instance_info(const wo_wh *wh, int32_t i, int32_t *n_ord
 // at most 32 waves per CU), never more than there are plans.
 static int launch_grid(const wo_wh *wh, int block, int per_cu_cfg, uint32_t lds, int64_t n_plans)
 {
-    const int fit = eval_max_blocks_per_cu(block, wh->route, lds);
+    const int fit = eval_max_blocks_per_cu(block, wh->route, lds, wh->main_mode);
     const int per_cu = per_cu_cfg > 0 ? std::min(per_cu_cfg, fit) : fit;
     return (int)std::min<int64_t>(n_plans, (int64_t)wh->cu_count * per_cu);
 }
@@ -903,7 +907,7 @@ static wo_status check_cfg(const wo_eval_config *cfg)
         return fail(WO_E_INVAL, "block_threads must be 64, 128, 256 or 512");
     if (cfg->blocks_per_cu < 0 || cfg->blocks_per_cu > 32) return fail(WO_E_INVAL, "blocks_per_cu in [0, 32]");
     if (cfg->queue != 0 && cfg->queue != 1) return fail(WO_E_INVAL, "queue must be 0 or 1");
-    if (cfg->line_pass != 0 && cfg->line_pass != 1) return fail(WO_E_INVAL, "line_pass must be 0 or 1");
+    if (cfg->line_pass < 0 || cfg->line_pass > 2) return fail(WO_E_INVAL, "line_pass must be 0, 1 or 2");
     if (cfg->small_orders < 0 || cfg->small_orders > 1024) return fail(WO_E_INVAL, "small_orders in [0, 1024]");
     return WO_OK;
 }
@@ -1217,9 +1221,9 @@ extern "C" wo_status wo_autotune_eval(wo_wh *wh, const int64_t *plan_offsets, in
     for (int bi = 0; bi < n_blocks && !st; bi++) {
         for (int pi = 0; pi < 8 && !st; pi++) {
             const int blk = blocks[bi], pc = per_cus[pi];
-            if (pc > eval_max_blocks_per_cu(blk, wh->route, wh->lds_max)) continue;      // registers and LDS
-            for (int qm = 0; qm < 4 && !st; qm++) {
+            for (int qm = 0; qm < 6 && !st; qm++) {
                 if (wh->route != WO_ROUTE_SSHAPE && (qm >> 1)) continue;   // pick rows: line per lane only
+                if (pc > eval_max_blocks_per_cu(blk, wh->route, wh->lds_max, qm >> 1)) continue;   // registers, LDS
                 st = time_cfg(wo_eval_config{blk, pc, qm & 1, qm >> 1, saved.small_orders, 0.f});
             }
         }

@@ -78,7 +78,7 @@ struct EvalArgs {
     const uint16_t *gord;
     const uint32_t *ordoff;
     const uint32_t *ordrec;
-    int32_t main_mode;      // 0: one line per lane, 1: one order per lane (groups)
+    int32_t main_mode;      // 0: one line per lane, 1: one order per lane (groups), 2: sequence order
     const uint8_t *zone_of;
     const uint16_t *seq;
     int32_t *dist;
@@ -206,7 +206,7 @@ __host__ __device__ inline SeedLayout seed_layout(int32_t n_orders, int32_t n_ai
 
 hipError_t launch_eval(const EvalArgs &a, uint32_t lds_bytes, int grid, int block, int route, hipStream_t s);
 // workgroups of the evaluation kernel that fit one CU (registers and LDS)
-int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes);
+int eval_max_blocks_per_cu(int block, int route, uint32_t lds_bytes, int line_pass = 0);
 // First-fit batching: one 64-thread workgroup per plan.
 hipError_t launch_eval_ff(const EvalArgs &a, uint32_t lds_bytes, int grid, int route, bool seed, hipStream_t s);
 int eval_ff_max_blocks_per_cu(int route, bool seed, uint32_t lds_bytes);

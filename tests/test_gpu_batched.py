@@ -114,6 +114,23 @@ def test_small_instance_launch_matches_single_launch(queue):
     wh.free()
 
 
+@pytest.mark.parametrize("line_pass", [1, 2])
+def test_line_passes_agree_on_uneven_batch(line_pass):
+    # the aisle-set pass by order per lane (1) and in sequence order (2), in
+    # every launch class (64-, 128- and 256-thread workgroups), against the
+    # default mapping and the oracle
+    wo = _wo()
+    insts, Z, S, offs = _batch(40, 6, seed=8)
+    wh = wo.wo_load_warehouse(insts)
+    z, s = _dev(Z, S)
+    d_ref, t_ref = _run(wo, wh, z, s, offs)
+    wo.wo_set_eval_config(wh, 256, 0, 1, line_pass, 1024)
+    d, t = _run(wo, wh, z, s, offs)
+    assert np.array_equal(d, d_ref) and np.array_equal(t, t_ref)
+    _check_sample(insts, Z, S, offs, d, t, 6, range(0, len(d), 9))
+    wh.free()
+
+
 def test_64_thread_workgroups_all_instances():
     # every instance in 64-thread workgroups, including those with more orders
     # than one wave keeps in registers

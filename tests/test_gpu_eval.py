@@ -25,13 +25,13 @@ def _wo():
     return wo
 
 
-def _compare(inst, Z, S, wh=None, n_threads=8, line_passes=(1, 0)):
+def _compare(inst, Z, S, wh=None, n_threads=8, line_passes=(1, 2, 0)):
     wo = _wo()
     own = wh is None
     if own:
         wh = wo.wo_load_warehouse([inst])
     d_ref, t_ref = oracle.eval_plans(inst, Z, S, n_threads=n_threads)
-    for lp in line_passes:           # both mappings of the aisle-set pass
+    for lp in line_passes:           # every mapping of the aisle-set pass
         wo.wo_set_eval_config(wh, 256, 0, 0, lp)
         d_gpu, t_gpu = gpu_eval(wh, Z, S)
         bad = np.flatnonzero(d_gpu != d_ref)
