@@ -351,7 +351,10 @@ def batched_bench(args):
     s = torch.from_numpy(S.view(np.int16)).cuda()
     dist = torch.empty(n_plans, dtype=torch.int32, device="cuda")
     thr = torch.empty(n_plans, dtype=torch.float32, device="cuda")
-    best, table = wo.wo_autotune_eval(wh, z, s, dist, plan_offsets=offs, reps=3)
+    if args.no_autotune:
+        best, table = wo.wo_get_eval_config(wh), []
+    else:
+        best, table = wo.wo_autotune_eval(wh, z, s, dist, plan_offsets=offs, reps=3)
     stream = torch.cuda.current_stream()
     for _ in range(args.warmup):
         wo.wo_eval_plans(wh, z, s, dist, thr, plan_offsets=offs, stream=stream)
@@ -397,7 +400,7 @@ def batched_bench(args):
         "data": "synthetic",
         "config": {"workload": "512 warehouses, aisles log-uniform in [8, 400], orders log-uniform in "
                                "[50, 4000], capacity 30, 256 plans each (131,072 plans per call)",
-                   "items": int(sum(i.n_items for i in insts)), "autotuned": best},
+                   "items": int(sum(i.n_items for i in insts)), "autotuned" if not args.no_autotune else "launch_config": best},
         "roofline": {"bound": "alu", "achieved": achieved / 1e12, "peak": INT_VALU_PEAK_OPS / 1e12,
                      "unit": "Tops/s", "frac": achieved / INT_VALU_PEAK_OPS, "traffic": None},
         "autotune_table": [[c["block_threads"], c["blocks_per_cu"], c["queue"], c["line_pass"],
@@ -633,6 +636,8 @@ def main(argv=None):
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--line-pass", type=int, default=None, choices=[0, 1, 2],
                     help="mapping of the aisle-set pass (0 instance order, 1 order per lane, 2 sequence order)")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="--batched: keep the default launch configuration (for profiling the timed calls alone)")
     ap.add_argument("--autotune", action="store_true",
                     help="time every launch configuration first and keep the fastest (table in the JSON line)")
     ap.add_argument("--route", default="sshape", choices=list(ROUTES),

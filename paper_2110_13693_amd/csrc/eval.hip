@@ -185,13 +185,16 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
     int loaded = -1;                        // instance whose tables sit in LDS
 
     // work items: a grid stride, or a queue (atomic ticket) over a work order
-    // that puts the most expensive plans first
+    // that puts the most expensive plans first; either hands out chunks of
+    // A.chunk consecutive items (a work list keeps an instance's plans
+    // together, so a chunk mostly stages its instance once)
     const int64_t seq_base0 = A.seq_base[0];
-    int64_t item = blockIdx.x;
+    const int64_t K = A.chunk;
+    int64_t item = (int64_t)blockIdx.x * K;
     if (A.queue) {
         if (tid == 0) s_next = atomicAdd(A.queue_ctr, 1u);
         __syncthreads();
-        item = s_next;
+        item = (int64_t)s_next * K;
         __syncthreads();
     }
     // the next plan's sequence chunk and zone row, loaded while the current
@@ -201,7 +204,8 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
     uint4 sv_pf[SEQ_CHUNK / 8];             // two 16-bit order ids per 32-bit word
     uint32_t zc_pf = 0xFFu;
     while (item < A.n_plans) {
-        if (A.queue && tid == 0) s_next = atomicAdd(A.queue_ctr, 1u);   // ticket of the next plan
+        const bool chunk_end = (item + 1) % K == 0;    // uniform
+        if (A.queue && chunk_end && tid == 0) s_next = atomicAdd(A.queue_ctr, 1u);   // ticket of the next chunk
         const int64_t p = A.work ? (int64_t)A.work[item] : item;
         const int ii = instance_of(A, p);
         const InstDev &I = A.inst[ii];
@@ -323,7 +327,9 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
 #define SV(k) ((svp[(k) >> 1] >> (16 * ((k) & 1))) & 0xFFFFu)
 #define CS(k) ((csp[(k) >> 2] >> (8 * ((k) & 3))) & 0xFFu)
         __syncthreads();                                 // tables, zeroed bitmaps, zone starts
-        const int64_t next_item = A.queue ? (int64_t)s_next : item + (int64_t)gridDim.x;
+        const int64_t next_item = !chunk_end ? item + 1
+                                  : A.queue ? (int64_t)s_next * K
+                                            : item + 1 + (int64_t)(gridDim.x - 1) * K;
         uint32_t local = 0, cmax = 0;
         if (one_piece) {
 #pragma unroll

@@ -796,6 +796,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.err = wh->d_err;
     a.validate = validate ? 1 : 0;
     a.queue = 0;
+    a.chunk = 1;
     a.queue_ctr = (uint32_t *)((char *)wh->d_err + 48);
     a.work = nullptr;
     a.ff_tour = wh->d_ff_tour;
@@ -824,6 +825,10 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
             ac.n_plans = w.n;
             ac.work = w.d_work;
             ac.queue = wh->queue;
+            // the small instances' plans go out in chunks of consecutive
+            // work items, so that a workgroup mostly keeps its instance's
+            // tables (grid stride: 2 per step; queue: 4 per ticket)
+            ac.chunk = c ? (wh->queue ? 4 : 2) : 1;
             ac.queue_ctr = (uint32_t *)((char *)wh->d_err + 48 + 4 * c);
             const int block = c ? class_block[c] : wh->block;
             const int per_cu = c ? 0 : wh->per_cu;
@@ -879,6 +884,7 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.err = wh->d_err;
     a.validate = 0;
     a.queue = 0;
+    a.chunk = 1;
     a.queue_ctr = nullptr;
     a.work = nullptr;
     a.ff_tour = wh->d_ff_tour;

@@ -86,6 +86,7 @@ struct EvalArgs {
     int32_t *err;           // device flag, validation mode
     int32_t validate;
     int32_t queue;          // 1: take plans from a ticket counter
+    int32_t chunk;          // consecutive work items per grid-stride step or ticket (>= 1)
     uint32_t *queue_ctr;
     const int32_t *work;    // work item -> plan row (null: identity)
     uint16_t *ff_tour;      // first fit: tour of every order, ff_stride entries per workgroup
