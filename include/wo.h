@@ -134,9 +134,12 @@ typedef struct {
  *   WO_ROUTE_OPTIMAL     the shortest closed walk from the depot through every
  *                        pick (the minimum route distance of the same passage),
  *                        exact for the single-block layout.
- * The routes other than S-shape keep every pick of a tour in LDS: a tour may
- * hold at most WO_MAX_PICK_SLOTS lines (capacity, and any single order), else
- * wo_load_warehouse fails with WO_E_UNSUPPORTED.  The optimal route computes
+ * The routes other than S-shape keep every pick of a tour in an LDS row of
+ * WO_MAX_PICK_SLOTS entries, sorted and walked per tour; an order of more
+ * lines is a tour of its own (the capacity is at most WO_MAX_PICK_SLOTS) and
+ * is sorted and walked apart, by the whole workgroup, from the order's own
+ * line list.  Such an order may have up to WO_MAX_ROUTED_ORDER_LINES lines;
+ * a longer one fails wo_load_warehouse with WO_E_UNSUPPORTED.  The optimal route computes
  * in 32-bit integers: 4 * spacing * (n_aisles + 2) + 4 * L * (n_aisles + 1)
  * must stay below 2^30 dm, else the load fails with WO_E_RANGE. */
 enum { WO_ROUTE_SSHAPE = 0, WO_ROUTE_RETURN = 1, WO_ROUTE_LARGEST_GAP = 2, WO_ROUTE_OPTIMAL = 3,
@@ -164,6 +167,7 @@ enum { WO_ROUTE_SSHAPE = 0, WO_ROUTE_RETURN = 1, WO_ROUTE_LARGEST_GAP = 2, WO_RO
  * paper-scale instance needs 38 KB). */
 enum { WO_BATCH_NEXT_FIT = 0, WO_BATCH_FIRST_FIT = 1, WO_BATCH_SEED = 2 };
 #define WO_MAX_PICK_SLOTS 32
+#define WO_MAX_ROUTED_ORDER_LINES 8192
 
 typedef struct wo_wh wo_wh;
 

@@ -815,7 +815,8 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
                 if (ROUTE != WO_ROUTE_SSHAPE) {
                     for (int t = tid; t < nt; t += BLOCK) {
                         const uint32_t *rw = (const uint32_t *)(smem + LDS_REGION + (uint32_t)t * RB);
-                        const uint32_t np = min(rw[0], (uint32_t)I.pick_slots);   // >= 1: a tour has picks
+                        const uint32_t np = rw[0];                 // >= 1: a tour has picks
+                        if (np > (uint32_t)I.pick_slots) continue; // an order routed apart (below)
                         uint32_t v[MAX_PICK_SLOTS];
 #pragma unroll
                         for (int i = 0; i < MAX_PICK_SLOTS; i++) v[i] = (uint32_t)i < np ? rw[1 + i] : 0xFFFFFFFFu;
@@ -840,6 +841,9 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
                     acc += cost;
                 }
             }
+            // orders longer than a pick row, each a tour of its own
+            if (ROUTE != WO_ROUTE_SSHAPE && I.n_big > 0)   // uniform
+                acc += big_orders_cost<ROUTE, BLOCK>(A, I, zs, (uint32_t *)(smem + LDS_REGION), wsp);
         }
 #undef SV
 #undef CS

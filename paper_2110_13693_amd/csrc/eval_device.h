@@ -142,86 +142,94 @@ static __device__ __forceinline__ void opt_aisle(OptClasses &s, int32_t L, int32
     s = n;
 }
 
-// Return, largest-gap, combined or optimal route of one tour from its np >= 1 picks,
-// sorted by scaled location, i.e. by aisle and then depth (section 5,
-// Subproblem 2).
+// Walk of one tour for the return, largest-gap, combined or optimal route,
+// fed the tour's picks one at a time sorted by scaled location, i.e. by
+// aisle and then depth (section 5, Subproblem 2).  The first pick starts the
+// walk, each further one is a step, and cost() closes it.
 template <int ROUTE>
-static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MAX_PICK_SLOTS], uint32_t np, int32_t spacing,
-                                                          const InstDev &I, uint32_t magic)
-{
-    const int32_t L = I.L;
-    uint32_t ca = mulhi24(v[0], magic);               // current aisle
-    const uint32_t a_lo = ca;
-    if (ROUTE == WO_ROUTE_OPTIMAL) {
-        // start: the depot at the front of aisle 0; if aisle 0 holds no pick
-        // it may still be crossed once or twice
-        OptClasses s = {a_lo ? L : OPT_INF, 0, OPT_INF, a_lo ? 2 * L : OPT_INF, OPT_INF};
-        uint32_t done = 0;                            // the last aisle decided
-        int32_t ylo = 0, yhi = 0, gap = -1;           // first and last depth, largest gap (-1: one pick)
-#pragma unroll
-        for (int i = 0; i < MAX_PICK_SLOTS; i++) {
-            if ((uint32_t)i < np) {
-                const uint32_t a = mulhi24(v[i], magic);
-                const int32_t y = (int32_t)((v[i] - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
-                if (i == 0) {
-                    ylo = y;
-                } else if (a != ca) {                 // aisle ca is complete
-                    if (ca != done) opt_run(s, (int32_t)(ca - done), spacing, L);
-                    opt_aisle(s, L, 2 * yhi, 2 * (L - ylo), gap >= 0 ? 2 * (L - gap) : 2 * L);
-                    done = ca;
-                    ca = a;
-                    ylo = y;
-                    gap = -1;
-                } else {
-                    gap = max(gap, y - yhi);
-                }
-                yhi = y;
-            }
-        }
-        if (ca != done) opt_run(s, (int32_t)(ca - done), spacing, L);
-        opt_aisle(s, L, 2 * yhi, 2 * (L - ylo), gap >= 0 ? 2 * (L - gap) : 2 * L);
-        return (int64_t)min(min(s.f, s.b), s.e1);     // even ends, one component
+struct PickWalk {
+    const InstDev &I;
+    uint32_t magic;
+    int32_t spacing;
+    uint32_t ca, a_lo;                // current aisle, first aisle
+    // optimal: the five classes, the last aisle decided, first and last
+    // depth in the current aisle and its largest gap (-1: one pick)
+    OptClasses s;
+    uint32_t done;
+    int32_t ylo, yhi, gap;
+    // combined: the best walks ending on the front and on the back
+    int64_t front, back;
+    // return / largest gap: previous depth in the aisle (front: 0), largest
+    // gap so far in it, and the sum over closed aisles
+    int32_t py, g;
+    int64_t sum;
+
+    __device__ __forceinline__ int32_t depth(uint32_t ls, uint32_t a) const
+    {
+        return (int32_t)((ls - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
     }
-    if (ROUTE == WO_ROUTE_COMBINED) {
-        // each aisle with picks crossed or entered and left from the cross
-        // aisle the picker is on, best choice by one length per cross aisle;
-        // the walk ends on the front (crossing the last aisle from the back)
-        const int64_t W = spacing, L2 = 2ll * L;
-        int64_t front = 0, back = (int64_t)1 << 60;   // the back is not reachable yet
-        uint32_t done = 0;
-        int32_t ylo = 0, yhi = 0;
-#pragma unroll
-        for (int i = 0; i < MAX_PICK_SLOTS; i++) {
-            if ((uint32_t)i < np) {
-                const uint32_t a = mulhi24(v[i], magic);
-                const int32_t y = (int32_t)((v[i] - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
-                if (i == 0) {
-                    ylo = y;
-                } else if (a != ca) {                 // aisle ca is complete
-                    const int64_t step = W * (int64_t)(ca - done);
-                    const int64_t f2 = min(front + 2ll * yhi, back + L), b2 = min(front + L, back + L2 - 2ll * ylo);
-                    front = f2 + step;
-                    back = b2 + step;
-                    done = ca;
-                    ca = a;
-                    ylo = y;
-                }
-                yhi = y;
-            }
+
+    __device__ __forceinline__ PickWalk(const InstDev &inst, int32_t sp, uint32_t m, uint32_t first)
+        : I(inst), magic(m), spacing(sp)
+    {
+        const int32_t L = I.L;
+        ca = mulhi24(first, magic);
+        a_lo = ca;
+        const int32_t y = depth(first, ca);
+        if (ROUTE == WO_ROUTE_OPTIMAL) {
+            // start: the depot at the front of aisle 0; if aisle 0 holds no
+            // pick it may still be crossed once or twice
+            s = {a_lo ? L : OPT_INF, 0, OPT_INF, a_lo ? 2 * L : OPT_INF, OPT_INF};
+            done = 0;
+            ylo = y;
+            yhi = y;
+            gap = -1;
+        } else if (ROUTE == WO_ROUTE_COMBINED) {
+            front = 0;
+            back = (int64_t)1 << 60;      // the back is not reachable yet
+            done = 0;
+            ylo = y;
+            yhi = y;
+        } else {
+            sum = 0;
+            g = y;
+            py = y;
         }
-        const int64_t step = W * (int64_t)(ca - done);
-        const int64_t f2 = min(front + 2ll * yhi, back + L), b2 = min(front + L, back + L2 - 2ll * ylo);
-        return min(f2, b2 + L) + step + W * (int64_t)ca;
     }
-    int32_t py = 0;                                   // previous depth in the aisle (front: 0)
-    int32_t g = 0;                                    // largest gap so far in the aisle
-    int64_t sum = 0;                                  // return: farthest depths; gap: inner L - gap
-#pragma unroll
-    for (int i = 0; i < MAX_PICK_SLOTS; i++) {
-        if ((uint32_t)i < np) {
-            const uint32_t a = mulhi24(v[i], magic);
-            const int32_t y = (int32_t)((v[i] - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
-            if (a != ca) {                            // close aisle ca
+
+    __device__ __forceinline__ void step(uint32_t ls)
+    {
+        const int32_t L = I.L;
+        const uint32_t a = mulhi24(ls, magic);
+        const int32_t y = depth(ls, a);
+        if (ROUTE == WO_ROUTE_OPTIMAL) {
+            if (a != ca) {                // aisle ca is complete
+                if (ca != done) opt_run(s, (int32_t)(ca - done), spacing, L);
+                opt_aisle(s, L, 2 * yhi, 2 * (L - ylo), gap >= 0 ? 2 * (L - gap) : 2 * L);
+                done = ca;
+                ca = a;
+                ylo = y;
+                gap = -1;
+            } else {
+                gap = max(gap, y - yhi);
+            }
+            yhi = y;
+        } else if (ROUTE == WO_ROUTE_COMBINED) {
+            // each aisle with picks crossed or entered and left from the
+            // cross aisle the picker is on, best choice by one length per
+            // cross aisle
+            if (a != ca) {
+                const int64_t st = (int64_t)spacing * (int64_t)(ca - done);
+                const int64_t f2 = min(front + 2ll * yhi, back + L), b2 = min(front + L, back + 2ll * L - 2ll * ylo);
+                front = f2 + st;
+                back = b2 + st;
+                done = ca;
+                ca = a;
+                ylo = y;
+            }
+            yhi = y;
+        } else {
+            if (a != ca) {                // close aisle ca
                 if (ROUTE == WO_ROUTE_RETURN) {
                     sum += py;
                 } else {
@@ -236,10 +244,90 @@ static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MA
             py = y;
         }
     }
-    const int64_t horiz = 2ll * spacing * ca;       // ca is the farthest aisle now
-    if (ROUTE == WO_ROUTE_RETURN) return horiz + 2 * (sum + py);
-    if (ca == a_lo) return horiz + 2ll * py;           // one aisle: the return route
-    return horiz + 2ll * L + 2 * sum;
+
+    __device__ __forceinline__ int64_t cost()
+    {
+        const int32_t L = I.L;
+        if (ROUTE == WO_ROUTE_OPTIMAL) {
+            if (ca != done) opt_run(s, (int32_t)(ca - done), spacing, L);
+            opt_aisle(s, L, 2 * yhi, 2 * (L - ylo), gap >= 0 ? 2 * (L - gap) : 2 * L);
+            return (int64_t)min(min(s.f, s.b), s.e1);   // even ends, one component
+        }
+        if (ROUTE == WO_ROUTE_COMBINED) {
+            // the walk ends on the front (crossing the last aisle from the back)
+            const int64_t st = (int64_t)spacing * (int64_t)(ca - done);
+            const int64_t f2 = min(front + 2ll * yhi, back + L), b2 = min(front + L, back + 2ll * L - 2ll * ylo);
+            return min(f2, b2 + L) + st + (int64_t)spacing * (int64_t)ca;
+        }
+        const int64_t horiz = 2ll * spacing * ca;    // ca is the farthest aisle now
+        if (ROUTE == WO_ROUTE_RETURN) return horiz + 2 * (sum + py);
+        if (ca == a_lo) return horiz + 2ll * py;     // one aisle: the return route
+        return horiz + 2ll * L + 2 * sum;
+    }
+};
+
+// Route cost of one tour from its np (1 .. MAX_PICK_SLOTS) sorted picks in
+// registers.
+template <int ROUTE>
+static __device__ __forceinline__ int64_t pick_route_cost(const uint32_t (&v)[MAX_PICK_SLOTS], uint32_t np, int32_t spacing,
+                                                          const InstDev &I, uint32_t magic)
+{
+    PickWalk<ROUTE> w(I, spacing, magic, v[0]);
+#pragma unroll
+    for (int i = 1; i < MAX_PICK_SLOTS; i++)
+        if ((uint32_t)i < np) w.step(v[i]);
+    return w.cost();
+}
+
+// Route costs of the instance's orders with more lines than a pick row keeps
+// (each a tour of its own, since the capacity is at most MAX_PICK_SLOTS), for
+// one plan: the workgroup's NT threads stage an order's scaled locations in
+// LDS (`scr`, at least 4 * I.big_np2 bytes, free for the call; zs the zone
+// starts), sort them (bitonic, padded with all ones), and thread 0 walks
+// them.  Returns the sum on thread 0 and 0 elsewhere; every thread must call.
+template <int ROUTE, int NT>
+static __device__ int64_t big_orders_cost(const EvalArgs &A, const InstDev &I, const uint32_t *zs, uint32_t *scr,
+                                          int32_t spacing)
+{
+    const int tid = threadIdx.x;
+    const uint32_t *big = A.big + I.big_off;
+    const uint32_t *ordoff = A.ordoff + I.ordoff_off;
+    const uint32_t *ordrec = A.ordrec + I.ordrec_off;
+    int64_t acc = 0;
+    for (int b = 0; b < I.n_big; b++) {
+        const uint32_t o = big[b];
+        const uint32_t r0 = ordoff[o];
+        const uint32_t m2 = min(1u << (32 - __builtin_clz(max(ordoff[o + 1] - r0, 2u) - 1u)), (uint32_t)I.big_np2);
+        const uint32_t m = min(ordoff[o + 1] - r0, m2);
+        __syncthreads();                 // scr is free (earlier use, previous order)
+        for (uint32_t i = tid; i < m2; i += NT) {
+            const uint32_t r = i < m ? ordrec[r0 + i] : 0u;
+            scr[i] = i < m ? r + zs[r >> 26] : 0xFFFFFFFFu;
+        }
+        for (uint32_t k = 2; k <= m2; k <<= 1)
+            for (uint32_t j = k >> 1; j > 0; j >>= 1) {
+                __syncthreads();
+                for (uint32_t i = tid; i < m2; i += NT) {
+                    const uint32_t l = i ^ j;
+                    if (l > i) {
+                        const uint32_t x = scr[i], y = scr[l];
+                        const bool up = (i & k) == 0;
+                        if ((x > y) == up) {
+                            scr[i] = y;
+                            scr[l] = x;
+                        }
+                    }
+                }
+            }
+        __syncthreads();
+        if (tid == 0) {
+            PickWalk<ROUTE> w(I, spacing, I.magic, scr[0]);
+            for (uint32_t i = 1; i < m; i++) w.step(scr[i]);
+            acc += w.cost();
+        }
+    }
+    __syncthreads();                     // scr is free again
+    return acc;
 }
 
 }  // namespace wo

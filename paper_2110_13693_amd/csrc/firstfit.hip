@@ -412,8 +412,9 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
                     const int64_t y = (int64_t)((ls - a * I.d_s) >> (I.shift + 1)) * I.pitch + I.pitch / 2;
                     acc += 2ll * wsp * a + ((k & 1) ? (int64_t)(k - 1) * I.L + 2 * y : (int64_t)k * I.L);
                 } else {
-                    const uint32_t np = min(rw[0], (uint32_t)I.pick_slots);
+                    const uint32_t np = rw[0];
                     if (np == 0) continue;                  // only a malformed row leaves a tour empty
+                    if (np > (uint32_t)I.pick_slots) continue;   // an order routed apart (below)
                     uint32_t v[MAX_PICK_SLOTS];
 #pragma unroll
                     for (int i = 0; i < MAX_PICK_SLOTS; i++) v[i] = (uint32_t)i < np ? rw[1 + i] : 0xFFFFFFFFu;
@@ -423,6 +424,8 @@ __global__ __launch_bounds__(64) void eval_ff_kernel(EvalArgs A)
             }
             __syncthreads();
         }
+        // orders longer than a pick row, each a tour of its own
+        if (ROUTE != WO_ROUTE_SSHAPE && I.n_big > 0) acc += big_orders_cost<ROUTE, 64>(A, I, zs, rows, wsp);
 
         // ---- 4. sum and rate -----------------------------------------------
 #pragma unroll

@@ -92,6 +92,7 @@ struct wo_wh {
     const uint16_t *d_gord = nullptr;
     const uint32_t *d_ordoff = nullptr;
     const uint32_t *d_ordrec = nullptr;
+    const uint32_t *d_big = nullptr;
     InstDev *d_inst = nullptr;
     int64_t *d_map = nullptr;           // plan_begin [n+1] | seq_base [n]
     int32_t *d_err = nullptr;
@@ -285,7 +286,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     std::vector<uint8_t> cnt;
     std::vector<uint32_t> grec, gbase;
     std::vector<uint16_t> gord;
-    std::vector<uint32_t> ordoff, ordrec;   // seed batching: each order's line records
+    std::vector<uint32_t> ordoff, ordrec;   // each order's line records
+    std::vector<uint32_t> big;              // pick rows: the orders routed apart
     for (int32_t i = 0; i < n_instances; i++) {
         const wo_instance_desc &d = descs[i];
         InstDev &I = wh->inst[i];
@@ -304,14 +306,32 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         }
         I.route = d.routing;
         {
-            // a tour holds at most max(capacity, largest order) lines
-            int32_t max_lines = 0;
-            for (int32_t o = 0; o < d.n_orders; o++)
-                max_lines = std::max(max_lines, d.order_offsets[o + 1] - d.order_offsets[o]);
+            // a tour holds at most max(capacity, largest order) lines; with
+            // pick rows, the orders of more than MAX_PICK_SLOTS lines (each a
+            // tour of its own, as the capacity is at most MAX_PICK_SLOTS) are
+            // listed and routed apart, and the rows keep the others
+            int32_t max_lines = 0, max_big = 0;
+            I.big_off = (int64_t)big.size();
+            I.n_big = 0;
+            for (int32_t o = 0; o < d.n_orders; o++) {
+                const int32_t len = d.order_offsets[o + 1] - d.order_offsets[o];
+                if (d.routing != WO_ROUTE_SSHAPE && len > MAX_PICK_SLOTS) {
+                    if (len > MAX_BIG_ORDER_LINES)
+                        return fail(WO_E_UNSUPPORTED, "instance %d: order %d has %d lines; the routes other than "
+                                    "S-shape take orders of at most %d", i, o, len, MAX_BIG_ORDER_LINES);
+                    big.push_back((uint32_t)o);
+                    I.n_big++;
+                    max_big = std::max(max_big, len);
+                } else {
+                    max_lines = std::max(max_lines, len);
+                }
+            }
+            I.big_np2 = 0;
+            if (max_big) {
+                I.big_np2 = 1;
+                while (I.big_np2 < max_big) I.big_np2 <<= 1;
+            }
             I.pick_slots = std::max(d.capacity, max_lines);
-            if (d.routing != WO_ROUTE_SSHAPE && I.pick_slots > MAX_PICK_SLOTS)
-                return fail(WO_E_UNSUPPORTED, "instance %d: a tour may hold %d lines, more than the %d a "
-                            "route's pick row keeps", i, I.pick_slots, MAX_PICK_SLOTS);
             I.row_b = (int32_t)(d.routing == WO_ROUTE_SSHAPE ? row_bytes(I.words) : pick_row_bytes(I.pick_slots));
         }
         I.capacity = d.capacity;
@@ -442,14 +462,18 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         if (const char *cap = getenv("WO_TILE_TOURS"))
             if (atoll(cap) >= 1) t_cap = std::min<int64_t>(t_cap, atoll(cap));
         t_cap = std::max<int64_t>(t_cap, 1);
+        // the region of the rows also holds the sort of the largest listed order
+        const int64_t t_big = ((int64_t)4 * I.big_np2 + I.row_b - 1) / I.row_b;
+        t_cap = std::max(t_cap, t_big);
         EvalLayout ly = eval_layout(d.n_orders, I.n_units, (uint32_t)I.row_b, (int32_t)t_cap, I.chase_log2, I.chase_lanes);
         while (ly.total > wh->lds_max && t_cap > 1) {
             t_cap = t_cap / 2;
             ly = eval_layout(d.n_orders, I.n_units, (uint32_t)I.row_b, (int32_t)t_cap, I.chase_log2, I.chase_lanes);
         }
         I.t_cap = (int32_t)t_cap;
-        if (ly.total > wh->lds_max)
-            return fail(WO_E_RANGE, "instance %d: needs %u bytes of LDS, device has %u", i, ly.total, wh->lds_max);
+        if (ly.total > wh->lds_max || t_cap < t_big)
+            return fail(WO_E_RANGE, "instance %d: needs %u bytes of LDS, device has %u", i,
+                        std::max(ly.total, (uint32_t)(LDS_REGION + 4 * I.big_np2)), wh->lds_max);
 
         // line records; y is the LDS byte offset of the order's tour entry in
         // this instance's layout.  Padding records sit on the dummy entry
@@ -485,7 +509,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         }
         I.n_lines_pad = (int32_t)(lines.size() - (size_t)I.line_off);
         wh->lds[i] = ly.total;
-        wh->ff_lds[i] = ff_lds_bytes(d.routing, I.row_b);
+        wh->ff_lds[i] = std::max(ff_lds_bytes(d.routing, I.row_b), ff_rows_off() + 4u * (uint32_t)I.big_np2);
         {
             // each order's line records (seed batching, and the line pass in
             // sequence order)
@@ -519,7 +543,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     size_t o_gord = (o_gbase + gbase.size() * 4 + 255) & ~size_t(255);
     size_t o_ordoff = (o_gord + gord.size() * 2 + 255) & ~size_t(255);
     size_t o_ordrec = (o_ordoff + ordoff.size() * 4 + 255) & ~size_t(255);
-    size_t bytes = o_ordrec + ordrec.size() * 4;
+    size_t o_big = (o_ordrec + ordrec.size() * 4 + 255) & ~size_t(255);
+    size_t bytes = o_big + big.size() * 4;
     wo_status st;
     if ((st = dev_alloc(&wh->d_pool, bytes))) return st;
     if ((st = dev_alloc((void **)&wh->d_inst, sizeof(InstDev) * n_instances))) return st;
@@ -534,6 +559,7 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
     wh->d_gord = (const uint16_t *)((const char *)wh->d_pool + o_gord);
     wh->d_ordoff = (const uint32_t *)((const char *)wh->d_pool + o_ordoff);
     wh->d_ordrec = (const uint32_t *)((const char *)wh->d_pool + o_ordrec);
+    wh->d_big = (const uint32_t *)((const char *)wh->d_pool + o_big);
     hipStream_t s = (hipStream_t)stream;
     if (b_lines) HIP_TRY(hipMemcpyAsync(wh->d_pool, lines.data(), b_lines, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_cnt, cnt.data(), b_cnt, hipMemcpyHostToDevice, s));
@@ -544,6 +570,8 @@ extern "C" wo_status wo_load_warehouse(const wo_instance_desc *descs, int32_t n_
         HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_ordoff, ordoff.data(), ordoff.size() * 4, hipMemcpyHostToDevice, s));
     if (!ordrec.empty())
         HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_ordrec, ordrec.data(), ordrec.size() * 4, hipMemcpyHostToDevice, s));
+    if (!big.empty())
+        HIP_TRY(hipMemcpyAsync((char *)wh->d_pool + o_big, big.data(), big.size() * 4, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemcpyAsync(wh->d_inst, wh->inst.data(), sizeof(InstDev) * n_instances, hipMemcpyHostToDevice, s));
     HIP_TRY(hipMemsetAsync(wh->d_err, 0, 64, s));
     HIP_TRY(hipStreamSynchronize(s));
@@ -788,6 +816,7 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
     a.gord = wh->d_gord;
     a.ordoff = wh->d_ordoff;
     a.ordrec = wh->d_ordrec;
+    a.big = wh->d_big;
     a.main_mode = wh->route == WO_ROUTE_SSHAPE ? wh->main_mode : 0;   // pick rows: line per lane only
     a.zone_of = d_zone_of;
     a.seq = d_order_seq;
@@ -876,6 +905,7 @@ wo_status wo::eval_instance(wo_wh *wh, int32_t inst, int64_t n_plans, const uint
     a.gord = wh->d_gord;
     a.ordoff = wh->d_ordoff;
     a.ordrec = wh->d_ordrec;
+    a.big = wh->d_big;
     a.main_mode = wh->route == WO_ROUTE_SSHAPE ? wh->main_mode : 0;   // pick rows: line per lane only
     a.zone_of = d_zone_of;
     a.seq = d_order_seq;

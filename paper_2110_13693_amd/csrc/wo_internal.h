@@ -33,7 +33,7 @@ struct InstDev {
     int32_t chase_lanes;    // chase lanes the LDS layout holds (a multiple of 64, <= CHASE_LANES)
     int32_t min_size;       // smallest min(size, capacity + 1) over the orders: a room below it never fills
     int32_t route;          // WO_ROUTE_*
-    int32_t pick_slots;     // return / largest gap: pick entries per tour row (<= MAX_PICK_SLOTS)
+    int32_t pick_slots;     // routes other than S-shape: pick entries per tour row (<= MAX_PICK_SLOTS)
     int32_t row_b;          // bytes of one tour row in LDS
     // uint2 line records [n_lines_pad]: x = (rank << shift) | (4*cat) << 24,
     // y = LDS byte offset of the order's tour entry (2 * order + the tour
@@ -53,10 +53,15 @@ struct InstDev {
     int64_t gbase_off;      // u32 [n_grp + 1], relative to grec_off
     int64_t gord_off;       // u16 [64 * n_grp]
     int32_t n_grp;
-    // seed batching: order o's lines are ordrec[ordoff[o] .. ordoff[o + 1])
-    // (same packing as grec), both relative to the offsets below
+    // order o's lines are ordrec[ordoff[o] .. ordoff[o + 1]) (same packing as
+    // grec), both relative to the offsets below
     int64_t ordoff_off;     // u32 [n_orders + 1]
     int64_t ordrec_off;     // u32 [n_lines]
+    // routes with pick rows: the orders with more than MAX_PICK_SLOTS lines
+    // (each a tour of its own), evaluated apart from the pick rows
+    int64_t big_off;        // u32 order ids [n_big] in the pooled list
+    int32_t n_big;
+    int32_t big_np2;        // the largest such order's line count rounded up to a power of two (0: none)
     int32_t n_skus;         // sum of the category sizes: a zone start never exceeds n_skus - size
     double walk;
     double t_item;
@@ -78,6 +83,7 @@ struct EvalArgs {
     const uint16_t *gord;
     const uint32_t *ordoff;
     const uint32_t *ordrec;
+    const uint32_t *big;    // orders beyond a pick row, per instance (InstDev::big_off)
     int32_t main_mode;      // 0: one line per lane, 1: one order per lane (groups), 2: sequence order
     const uint8_t *zone_of;
     const uint16_t *seq;
@@ -136,6 +142,11 @@ __host__ __device__ inline uint32_t bitmap_words(int32_t n_units) { return ((uin
 // Rows are padded to an odd word count so that rows of random tours spread
 // over all 32 LDS banks.
 constexpr int MAX_PICK_SLOTS = 32;
+// a tour of several orders holds at most the capacity: an order longer than a
+// pick row is always a tour of its own
+static_assert(WO_MAX_CAPACITY <= MAX_PICK_SLOTS, "capacity beyond a pick row");
+// routes other than S-shape: the most lines an order may have (its sort in LDS)
+constexpr int MAX_BIG_ORDER_LINES = WO_MAX_ROUTED_ORDER_LINES;
 __host__ __device__ inline uint32_t row_bytes(int32_t words) { return 4u * ((uint32_t)(words + 1) | 1u); }
 __host__ __device__ inline uint32_t pick_row_bytes(int32_t slots) { return 4u * ((uint32_t)(slots + 1) | 1u); }
 

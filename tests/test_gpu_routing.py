@@ -104,19 +104,72 @@ def test_batched_routed_instances_match_single(routing):
     wh.free()
 
 
-def test_too_many_picks_per_tour_is_rejected():
-    # an order of 40 lines cannot sit in a 32-pick row
-    wo = _wo()
-    rng = np.random.default_rng(37)
-    base = _random_instance(rng, 20, 30, 50, 20, 8, lam=1.0)
+def _with_long_orders(rng, base, long_sizes):
+    """`base` with some orders replaced by longer ones (the routes keep 32
+    picks per tour row; longer orders are tours of their own, routed apart)."""
     sizes = np.diff(base.order_offsets).copy()
-    sizes[7] = 40
+    idx = rng.choice(len(sizes), size=len(long_sizes), replace=False)
+    sizes[idx] = long_sizes
     offs = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int32)
     skus = rng.integers(0, base.n_skus, size=int(offs[-1]), dtype=np.int32)
-    inst = dataclasses.replace(base, order_offsets=offs, order_skus=skus, routing=1)
+    return dataclasses.replace(base, order_offsets=offs, order_skus=skus)
+
+
+@pytest.mark.parametrize("batching", [0, 1, 2])
+@pytest.mark.parametrize("routing", ROUTES)
+def test_orders_longer_than_a_pick_row(routing, batching):
+    # orders of 33 .. 700 lines among ordinary ones (capacity 20): each is a
+    # tour of its own, sorted and walked apart from the pick rows, under
+    # next fit, first fit and seed batching
+    rng = np.random.default_rng(41 + routing)
+    base = _random_instance(rng, 120, 40, 400, 20, 16, lam=1.5)
+    inst = _with_long_orders(rng, base, [33, 40, 64, 65, 200, 700])
+    inst = dataclasses.replace(inst, routing=routing, batching=batching)
+    Z, S = synth.make_plans(inst, 19, seed=int(rng.integers(1 << 30)))
+    print("long orders", routing, batching, flush=True)
+    _compare(inst, Z, S, line_passes=(0,))
+
+
+def test_longest_routed_order_and_beyond():
+    # an order of WO_MAX_ROUTED_ORDER_LINES lines is evaluated (its sort
+    # fills 32 KB of LDS); one line more is refused at load
+    wo = _wo()
+    rng = np.random.default_rng(37)
+    base = _random_instance(rng, 400, 250, 60, 30, 64, lam=1.0)
+    inst = dataclasses.replace(_with_long_orders(rng, base, [8192, 100]), routing=3)
+    Z, S = synth.make_plans(inst, 6, seed=5)
+    print("order of 8,192 lines", flush=True)
+    _compare(inst, Z, S, line_passes=(0,))
+    inst = dataclasses.replace(_with_long_orders(rng, base, [8193]), routing=1)
     with pytest.raises(wo.WoError) as e:
         wo.wo_load_warehouse([inst])
     assert "lines" in str(e.value)
     # the S-shape route has no such limit
     wh = wo.wo_load_warehouse([dataclasses.replace(inst, routing=0)])
+    wh.free()
+
+
+@pytest.mark.parametrize("routing", [1, 3])
+def test_batched_instances_with_long_orders(routing):
+    # long orders in every launch class (64-, 128- and 256-thread workgroups)
+    import torch
+    wo = _wo()
+    rng = np.random.default_rng(43)
+    insts = []
+    for n_a, n_o in ((20, 300), (60, 1500), (100, 3000)):
+        base = _random_instance(rng, n_a, 40, n_o, 20, 16)
+        insts.append(dataclasses.replace(_with_long_orders(rng, base, [35, 150]), routing=routing))
+    plans = [synth.make_plans(i, 12, seed=k) for k, i in enumerate(insts)]
+    wh = wo.wo_load_warehouse(insts)
+    Z = np.concatenate([p[0] for p in plans])
+    S = np.concatenate([p[1].reshape(-1) for p in plans])
+    n = 12 * len(insts)
+    offs = np.arange(0, n + 1, 12, dtype=np.int64)
+    d = torch.empty(n, dtype=torch.int32, device="cuda")
+    wo.wo_eval_plans(wh, torch.from_numpy(Z).cuda(), torch.from_numpy(S.view(np.int16)).cuda(), d,
+                     plan_offsets=offs)
+    torch.cuda.synchronize()
+    for k, (inst, (Zi, Si)) in enumerate(zip(insts, plans)):
+        d_ref, _ = oracle.eval_plans(inst, Zi, Si)
+        assert np.array_equal(d.cpu().numpy()[12 * k:12 * (k + 1)], d_ref), k
     wh.free()
