@@ -84,6 +84,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int wm = w >> 1, wn = w & 1;
     const int m0 = blockIdx.y * TM, n0 = blockIdx.x * TM;
+    // split K: this workgroup's part [kbeg, kend)
+    const int kc = g.K / max(g.ksplit, 1);
+    const int kbeg = (int)blockIdx.z * kc, kend = kbeg + kc;
     const int fr = lane & 15, fk = (lane >> 4) * 8;
 
     floatx4 acc[FT][FT];
@@ -150,11 +153,11 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 
     // one operand set per K step: the next one loads into registers while the
     // current one is multiplied from LDS, then goes to the other buffer
-    WO_LOAD_TILE(0);
+    WO_LOAD_TILE(kbeg);
     WO_STORE_TILE(0);
     __syncthreads();
-    for (int k0 = 0, cur = 0; k0 < g.K; k0 += GBK, cur ^= 1) {
-        const bool more = k0 + GBK < g.K;
+    for (int k0 = kbeg, cur = 0; k0 < kend; k0 += GBK, cur ^= 1) {
+        const bool more = k0 + GBK < kend;
         WO_LOAD_TILE(more ? k0 + GBK : k0);          // unconditional, so the operands stay in registers
         // a K step of 64 is one category: the zone of each of the wave's rows
         uint32_t zrow[FT];
@@ -215,8 +218,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             const int col = n0 + wn * WT + tj * 16 + fr;
             const int rb = m0 + wm * WT + ti * 16 + (lane >> 4) * 4;
             if (EPI == EPI_STORE) {
+                float *C = g.C + (int64_t)blockIdx.z * g.c_split;
 #pragma unroll
-                for (int r = 0; r < 4; r++) g.C[(uint32_t)((rb + r) * g.ldc + col)] = acc[ti][tj][r];
+                for (int r = 0; r < 4; r++) C[(uint32_t)((rb + r) * g.ldc + col)] = acc[ti][tj][r];
             } else if (EPI == EPI_BIAS_GELU) {
                 const float bias = g.bias[col];
                 uint16_t hv[4];
@@ -291,35 +295,85 @@ __global__ __launch_bounds__(256) void layer3_kernel(L3Args a)
 
 // Gradients that are sums over the batch, in a fixed order (deterministic):
 // gW3[j] = sum_b h2[b][j] dy[b], gb3 = sum_b dy[b], gb2[j] = sum_b du2[b][j],
-// gb1[i] = sum_b du1[b][i] (du from the transposed bf16 copies), loss.
+// gb1[i] = sum_b du1[b][i] (du from the transposed bf16 copies), the loss,
+// and gW2 as the sum of its split-K parts.  Workgroups by task:
+//   [0, W3_SLICES): gW3 over a slice of the batch, one thread per output
+//     (rows of h2 read whole); the last of them to finish adds the slices;
+//   then one wave per output of gb3, gb2, gb1 and the loss;
+//   then 1,024 outputs of gW2 per workgroup (if split).
 __global__ __launch_bounds__(256) void batch_sums_kernel(SumArgs a)
 {
-    const int lane = threadIdx.x & 63;
-    const int row = blockIdx.x * 4 + (threadIdx.x >> 6);   // one wave per output
-    const int n_out = N_H2 + 1 + N_H2 + N_H1 + 1;
-    if (row >= n_out) return;
-    float s = 0.f;
-    if (row < N_H2) {
-        for (int b = lane; b < a.n; b += 64) s += a.H2[(int64_t)b * N_H2 + row] * a.dy[b];
-    } else if (row == N_H2) {
-        for (int b = lane; b < a.n; b += 64) s += a.dy[b];
-    } else if (row < 2 * N_H2 + 1) {
-        const int j = row - N_H2 - 1;
-        for (int b = lane; b < a.n; b += 64) s += bf2f(a.DU2T[(int64_t)j * a.ld_t + b]);
-    } else if (row < 2 * N_H2 + 1 + N_H1) {
-        const int i = row - 2 * N_H2 - 1;
-        for (int b = lane; b < a.n; b += 64) s += bf2f(a.DU1T[(int64_t)i * a.ld_t + b]);
-    } else {
-        for (int b = lane; b < a.n; b += 64) s += a.sq[b];
+    const int tid = threadIdx.x, lane = tid & 63;
+    int blk = blockIdx.x;
+    if (blk < W3_SLICES) {
+        __shared__ int last;
+        const int per = (a.n + W3_SLICES - 1) / W3_SLICES;
+        const int b0 = min(a.n, blk * per), b1 = min(a.n, b0 + per);
+        float s = 0.f;
+#pragma unroll 16
+        for (int b = b0; b < b1; b++) s += a.H2[(int64_t)b * N_H2 + tid] * a.dy[b];
+        a.w3part[blk * N_H2 + tid] = s;
+        __threadfence();
+        __syncthreads();
+        if (tid == 0) last = atomicAdd(a.w3ctr, 1u) == (uint32_t)(W3_SLICES - 1);
+        __syncthreads();
+        if (last) {
+            __threadfence();
+            float t = 0.f;
+#pragma unroll 16
+            for (int k = 0; k < W3_SLICES; k++)
+                t += __hip_atomic_load(&a.w3part[k * N_H2 + tid], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            a.gW3[tid] = t;
+            if (tid == 0) atomicExch(a.w3ctr, 0u);   // zero for the next call
+        }
+        return;
     }
+    blk -= W3_SLICES;
+    const int n_rows = 1 + N_H2 + N_H1 + 1;
+    const int row_blocks = (n_rows + 3) / 4;
+    if (blk < row_blocks) {
+        const int row = blk * 4 + (tid >> 6);   // one wave per output
+        if (row >= n_rows) return;
+        // n is a multiple of 128: 16-byte loads, 8 bf16 or 4 floats a lane
+        float s = 0.f;
+        if (row == 0 || row == n_rows - 1) {
+            const float *x = row == 0 ? a.dy : a.sq;
+            for (int b = lane * 4; b < a.n; b += 256) {
+                const float4 v = *(const float4 *)(x + b);
+                s += (v.x + v.y) + (v.z + v.w);
+            }
+        } else {
+            const uint16_t *x = row < 1 + N_H2 ? a.DU2T + (int64_t)(row - 1) * a.ld_t
+                                               : a.DU1T + (int64_t)(row - 1 - N_H2) * a.ld_t;
+            for (int b = lane * 8; b < a.n; b += 512) {
+                const uint4 v = *(const uint4 *)(x + b);
+                const uint32_t w4[4] = {v.x, v.y, v.z, v.w};
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-    if (lane != 0) return;
-    if (row < N_H2) a.gW3[row] = s;
-    else if (row == N_H2) a.gb3[0] = s;
-    else if (row < 2 * N_H2 + 1) a.gb2[row - N_H2 - 1] = s;
-    else if (row < 2 * N_H2 + 1 + N_H1) a.gb1[row - 2 * N_H2 - 1] = s;
-    else a.loss[0] = s / (float)a.n;
+                for (int e = 0; e < 4; e++) s += bf2f((uint16_t)(w4[e] & 0xFFFFu)) + bf2f((uint16_t)(w4[e] >> 16));
+            }
+        }
+#pragma unroll
+        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+        if (lane != 0) return;
+        if (row == 0) a.gb3[0] = s;
+        else if (row < 1 + N_H2) a.gb2[row - 1] = s;
+        else if (row < 1 + N_H2 + N_H1) a.gb1[row - 1 - N_H2] = s;
+        else a.loss[0] = s / (float)a.n;
+        return;
+    }
+    blk -= row_blocks;
+    const int64_t i = ((int64_t)blk * 256 + tid) * 4;
+    if (a.w2part && i < (int64_t)N_H2 * N_H1) {
+        float4 t = *(const float4 *)(a.w2part + i);
+        for (int k = 1; k < a.w2_splits; k++) {
+            const float4 u = *(const float4 *)(a.w2part + k * a.w2_stride + i);
+            t.x += u.x;
+            t.y += u.y;
+            t.z += u.z;
+            t.w += u.w;
+        }
+        *(float4 *)(a.gW2 + i) = t;
+    }
 }
 
 // Adam over the flat fp32 parameter vector (Kingma & Ba 2015, bias-corrected).
@@ -407,9 +461,6 @@ __global__ __launch_bounds__(256) void gather_batch_kernel(const uint8_t *zone, 
     zb[(int64_t)b * 64 + lane] = zone[s * 64 + lane];
     if (lane == 0) tb[b] = (float)(((double)dist[s] - mean) * inv_std);
 }
-
-// One batch's loss into the epoch's loss table (no host round trip per batch).
-__global__ void keep_loss_kernel(const float *loss, float *table, int64_t b) { table[b] = *loss; }
 
 // Mean and standard deviation of int32 distances (two fixed-order passes,
 // one block, double accumulation).
@@ -562,10 +613,11 @@ __global__ __launch_bounds__(TOPK_THREADS) void topk_kernel(const void *src, int
 template <int AM, int BM, int EP>
 static hipError_t launch_gemm_t(const GemmArgs &g, hipStream_t s)
 {
-    if ((int64_t)(g.N / 128) * (g.M / 128) >= 256) {
-        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 128>), dim3(g.N / 128, g.M / 128), dim3(256), 0, s, g);
+    const int ks = g.ksplit > 1 ? g.ksplit : 1;
+    if ((int64_t)(g.N / 128) * (g.M / 128) * ks >= 256) {
+        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 128>), dim3(g.N / 128, g.M / 128, ks), dim3(256), 0, s, g);
     } else {
-        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 64>), dim3(g.N / 64, g.M / 64), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 64>), dim3(g.N / 64, g.M / 64, ks), dim3(256), 0, s, g);
     }
     return hipGetLastError();
 }
@@ -573,6 +625,7 @@ static hipError_t launch_gemm_t(const GemmArgs &g, hipStream_t s)
 hipError_t launch_gemm(int amode, int bmode, int epi, const GemmArgs &g, hipStream_t s)
 {
     if (g.M % 128 || g.N % 128 || g.K % GBK) return hipErrorInvalidValue;
+    if (g.ksplit > 1 && (epi != EPI_STORE || g.K % (g.ksplit * GBK))) return hipErrorInvalidValue;
     if ((int64_t)g.M * g.ldc >= (int64_t)1 << 31) return hipErrorInvalidValue;   // 32-bit output offsets
     if (amode == A_ONEHOT && bmode == B_BF16 && epi == EPI_BIAS_GELU) return launch_gemm_t<A_ONEHOT, B_BF16, EPI_BIAS_GELU>(g, s);
     if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_BIAS_GELU) return launch_gemm_t<A_BF16, B_BF16, EPI_BIAS_GELU>(g, s);
@@ -590,8 +643,9 @@ hipError_t launch_layer3(const L3Args &a, hipStream_t s)
 
 hipError_t launch_batch_sums(const SumArgs &a, hipStream_t s)
 {
-    const int n_out = N_H2 + 1 + N_H2 + N_H1 + 1;
-    hipLaunchKernelGGL(batch_sums_kernel, dim3((n_out + 3) / 4), dim3(256), 0, s, a);
+    const int n_rows = 1 + N_H2 + N_H1 + 1;
+    const int blocks = W3_SLICES + (n_rows + 3) / 4 + (a.w2part ? N_H2 * N_H1 / 1024 : 0);
+    hipLaunchKernelGGL(batch_sums_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
@@ -617,12 +671,6 @@ hipError_t launch_gather_batch(const uint8_t *zone, const int32_t *dist, int64_t
 {
     hipLaunchKernelGGL(gather_batch_kernel, dim3((n + 3) / 4), dim3(256), 0, s, zone, dist, n_all, h, key, first, n,
                        mean, inv_std, zb, tb);
-    return hipGetLastError();
-}
-
-hipError_t launch_keep_loss(const float *loss, float *table, int64_t b, hipStream_t s)
-{
-    hipLaunchKernelGGL(keep_loss_kernel, dim3(1), dim3(1), 0, s, loss, table, b);
     return hipGetLastError();
 }
 

@@ -48,6 +48,7 @@ struct wo_sur {
     int64_t losses_cap = 0;
     double *d_mom = nullptr;
     float *d_loss = nullptr;
+    float *d_red = nullptr;             // gW3 slice sums, then the slices' counter (zero between calls)
     double mean = 0.0, std = 1.0;
     bool scaled = false;
     int step = 0;                       // Adam steps taken
@@ -106,8 +107,9 @@ wo_status forward(wo_sur *s, const uint8_t *zone, int rows_real, int rows, bool 
 }
 
 // forward + backward of one batch of `rows` (multiple of 128) whose zone rows
-// are d_zb and standardised targets d_tb; gradients into d_g, loss into d_loss.
-wo_status gradients(wo_sur *s, int rows, hipStream_t st)
+// are d_zb and standardised targets d_tb; gradients into d_g, loss into
+// loss_out (null: d_loss).
+wo_status gradients(wo_sur *s, int rows, hipStream_t st, float *loss_out = nullptr)
 {
     wo_status r = forward(s, s->d_zb, rows, rows, true, st);
     if (r) return r;
@@ -125,18 +127,6 @@ wo_status gradients(wo_sur *s, int rows, hipStream_t st)
     l.DU2T = s->d_DU2T;
     l.ld_t = rows;
     WO_HIP(launch_layer3(l, st));
-    // gW2^T [256][1024] = du2^T [256][b] . (h1^T [1024][b])^T
-    GemmArgs g2{};
-    g2.M = N_H2;
-    g2.N = N_H1;
-    g2.K = rows;
-    g2.A = s->d_DU2T;
-    g2.lda = rows;
-    g2.B = s->d_H1T;
-    g2.ldb = rows;
-    g2.C = s->d_g + P_W2;
-    g2.ldc = N_H1;
-    WO_HIP(launch_gemm(A_BF16, B_BF16, EPI_STORE, g2, st));
     // du1^T [1024][b] = (du2 [b][256] . W2 [1024][256]^T) * GELU'(u1), transposed
     GemmArgs g1{};
     g1.M = rows;
@@ -151,6 +141,24 @@ wo_status gradients(wo_sur *s, int rows, hipStream_t st)
     g1.HT = s->d_DU1T;
     g1.ldt = rows;
     WO_HIP(launch_gemm(A_BF16, B_BF16, EPI_GELU_GRAD_T, g1, st));
+    // gW2^T [256][1024] = du2^T [256][b] . (h1^T [1024][b])^T: a long K over
+    // few outputs, so K is split in parts (into u1's buffer, free now) that
+    // the batch sums add in order
+    int ks = 8;
+    while (ks > 1 && rows % (ks * 64)) ks >>= 1;
+    GemmArgs g2{};
+    g2.M = N_H2;
+    g2.N = N_H1;
+    g2.K = rows;
+    g2.A = s->d_DU2T;
+    g2.lda = rows;
+    g2.B = s->d_H1T;
+    g2.ldb = rows;
+    g2.C = ks > 1 ? s->d_U1 : s->d_g + P_W2;
+    g2.ldc = N_H1;
+    g2.ksplit = ks;
+    g2.c_split = (int64_t)N_H2 * N_H1;
+    WO_HIP(launch_gemm(A_BF16, B_BF16, EPI_STORE, g2, st));
     // gW1^T [1024][4096] = du1^T [1024][b] . (x^T [4096][b])^T, x one-hot
     GemmArgs g0{};
     g0.M = N_H1;
@@ -176,7 +184,13 @@ wo_status gradients(wo_sur *s, int rows, hipStream_t st)
     sm.gb3 = s->d_g + P_B3;
     sm.gb2 = s->d_g + P_B2;
     sm.gb1 = s->d_g + P_B1;
-    sm.loss = s->d_loss;
+    sm.loss = loss_out ? loss_out : s->d_loss;
+    sm.w3part = s->d_red;
+    sm.w3ctr = (uint32_t *)(s->d_red + W3_SLICES * N_H2);
+    sm.w2part = ks > 1 ? s->d_U1 : nullptr;
+    sm.w2_splits = ks;
+    sm.w2_stride = (int64_t)N_H2 * N_H1;
+    sm.gW2 = s->d_g + P_W2;
     WO_HIP(launch_batch_sums(sm, st));
     return WO_OK;
 }
@@ -294,7 +308,7 @@ extern "C" wo_status wo_sur_create(int32_t n_categories, const float *h_init, ui
         (r = alloc(&s->d_sq, WORK_ROWS)) || (r = alloc(&s->d_H1, (size_t)WORK_ROWS * N_H1)) ||
         (r = alloc(&s->d_H1T, (size_t)WORK_ROWS * N_H1)) || (r = alloc(&s->d_DU2, (size_t)WORK_ROWS * N_H2)) ||
         (r = alloc(&s->d_DU2T, (size_t)WORK_ROWS * N_H2)) || (r = alloc(&s->d_DU1T, (size_t)WORK_ROWS * N_H1)) ||
-        (r = alloc(&s->d_mom, 2)) || (r = alloc(&s->d_loss, 1)))
+        (r = alloc(&s->d_mom, 2)) || (r = alloc(&s->d_loss, 1)) || (r = alloc(&s->d_red, W3_SLICES * N_H2 + 16)))
         return r;
     std::vector<float> host, dev;
     if (h_init) {
@@ -309,6 +323,7 @@ extern "C" wo_status wo_sur_create(int32_t n_categories, const float *h_init, ui
     WO_HIP(hipMemcpyAsync(s->d_p, dev.data(), sizeof(float) * P_TOTAL, hipMemcpyHostToDevice, st));
     WO_HIP(hipMemsetAsync(s->d_m, 0, sizeof(float) * P_TOTAL, st));
     WO_HIP(hipMemsetAsync(s->d_v, 0, sizeof(float) * P_TOTAL, st));
+    WO_HIP(hipMemsetAsync(s->d_red, 0, sizeof(float) * (W3_SLICES * N_H2 + 16), st));
     WO_HIP(launch_refresh_bf16(s->d_p + P_W1, s->d_p + P_W2, s->d_W1b, s->d_W2b, s->d_W2kn, st));
     WO_HIP(hipStreamSynchronize(st));
     guard.release();
@@ -322,7 +337,7 @@ extern "C" wo_status wo_sur_free(wo_sur *s)
     (void)hipDeviceSynchronize();
     void *bufs[] = {s->d_p,  s->d_g,   s->d_m,  s->d_v,   s->d_W1b, s->d_W2b,  s->d_W2kn, s->d_zb,   s->d_tb,
                     s->d_U1, s->d_U2,  s->d_H2, s->d_dy,  s->d_sq,  s->d_H1,   s->d_H1T,  s->d_DU2,  s->d_DU2T,
-                    s->d_DU1T, s->d_pred, s->d_losses, s->d_mom, s->d_loss};
+                    s->d_DU1T, s->d_pred, s->d_losses, s->d_mom, s->d_loss, s->d_red};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete s;
@@ -432,12 +447,11 @@ extern "C" wo_status wo_sur_train(wo_sur *s, int64_t n, const uint8_t *d_zone_of
         for (int64_t b = 0; b < n_batches; b++) {
             WO_HIP(launch_gather_batch(d_zone_of, d_dist, n, h, key, b * batch, batch, s->mean, 1.0 / s->std,
                                        s->d_zb, s->d_tb, st));
-            wo_status r = gradients(s, batch, st);
+            wo_status r = gradients(s, batch, st, last && h_last_loss ? s->d_losses + b : nullptr);
             if (r) return r;
             s->step++;
             WO_HIP(launch_adam(s->d_p, s->d_g, s->d_m, s->d_v, P_TOTAL, lr, s->step, s->d_W1b, s->d_W2b, s->d_W2kn,
                                st));
-            if (last && h_last_loss) WO_HIP(launch_keep_loss(s->d_loss, s->d_losses, b, st));
         }
     }
     if (h_last_loss) {

@@ -42,6 +42,8 @@ struct GemmArgs {
     uint16_t *HT;             // EPI_BIAS_GELU / EPI_GELU_GRAD_T: bf16 transposed [N][ldt]
     int ldt;
     const float *Uin;         // EPI_GELU_GRAD_T: pre-activation [M][ldc]
+    int ksplit;               // EPI_STORE: K cut into ksplit equal parts (0 or 1: none), part z
+    int64_t c_split;          // into C + z * c_split (partial products, summed by the caller)
 };
 
 struct L3Args {
@@ -58,12 +60,22 @@ struct L3Args {
     int ld_t;
 };
 
+// gW3 is summed over W3_SLICES slices of the batch, then over the slices by
+// the last of their workgroups (w3part, w3ctr: W3_SLICES * N_H2 floats and a
+// counter that is zero between calls)
+constexpr int W3_SLICES = 64;
 struct SumArgs {
     int n;
     const float *H2, *dy, *sq;
     const uint16_t *DU2T, *DU1T;
     int ld_t;
     float *gW3, *gb3, *gb2, *gb1, *loss;
+    float *w3part;
+    uint32_t *w3ctr;
+    const float *w2part;      // split-K parts of gW2 (w2_splits of them, w2_stride apart), or null
+    int w2_splits;
+    int64_t w2_stride;
+    float *gW2;
 };
 
 hipError_t launch_gemm(int amode, int bmode, int epi, const GemmArgs &g, hipStream_t s);
@@ -77,7 +89,6 @@ hipError_t launch_refresh_bf16(const float *W1t, const float *W2t, uint16_t *W1b
                                hipStream_t s);
 hipError_t launch_gather_batch(const uint8_t *zone, const int32_t *dist, int64_t n_all, int h, uint64_t key,
                                int64_t first, int n, double mean, double inv_std, uint8_t *zb, float *tb, hipStream_t s);
-hipError_t launch_keep_loss(const float *loss, float *table, int64_t b, hipStream_t s);
 hipError_t launch_moments(const int32_t *d, int64_t n, double *out, hipStream_t s);
 hipError_t launch_topk(const float *pred, int n, int k, int32_t *out, hipStream_t s);
 hipError_t launch_worst(const int32_t *dist, int n, int k, int32_t *out, hipStream_t s);
