@@ -518,6 +518,9 @@ def svm_bench(args):
            "roofline": {"bound": "hbm", "achieved": bytes_pred / (pred_ms / 1e3) / 1e9,
                         "peak": HBM_PEAK_BYTES / 1e9, "unit": "GB/s",
                         "frac": bytes_pred / (pred_ms / 1e3) / HBM_PEAK_BYTES, "traffic": None}}
+    hbm_meas = wo.wo_measure_peaks(3)["hbm_read_bytes_per_s"]
+    out["roofline"]["peak_measured"] = hbm_meas / 1e9
+    out["roofline"]["frac_measured"] = bytes_pred / (pred_ms / 1e3) / hbm_meas
     print(json.dumps(out), flush=True)
     return 0
 
@@ -623,6 +626,10 @@ def surrogate_bench(args):
                   "note": "wall time of one epoch; shuffle and loss table on the device"},
     }
     sur.free()
+    bf16_meas = wo.wo_measure_peaks(3)["bf16_flops_per_s"]
+    out["roofline"]["peak_measured"] = bf16_meas / 1e12
+    out["roofline"]["frac_measured"] = pred_flops / bf16_meas
+    out["train"]["frac_measured"] = train_flops / bf16_meas
     print(json.dumps(out), flush=True)
     return 0
 
@@ -790,9 +797,14 @@ def main(argv=None):
     if os.environ.get("WO_TILE_TOURS"):
         out["config"]["tile_tours_cap"] = int(os.environ["WO_TILE_TOURS"])
     # the device's own integer peak, beside the one from the unit counts
-    peak_meas = wo.wo_measure_int_peak(5)
+    peaks = wo.wo_measure_peaks(3)
+    peak_meas = peaks["int_ops_per_s"]
     roofline["peak_measured"] = peak_meas / 1e12
     roofline["frac_measured"] = achieved_ops / peak_meas
+    out["peaks_measured"] = {"int_valu_Tops": peaks["int_ops_per_s"] / 1e12,
+                             "lds_read_TBps": peaks["lds_bytes_per_s"] / 1e12,
+                             "hbm_read_TBps": peaks["hbm_read_bytes_per_s"] / 1e12,
+                             "bf16_mfma_TFLOPs": peaks["bf16_flops_per_s"] / 1e12}
     d_host = dist.cpu().numpy()
     t_host = thr.cpu().numpy()
     out["check"] = {"dist_min": int(d_host.min()), "dist_max": int(d_host.max())}

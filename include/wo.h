@@ -619,6 +619,22 @@ wo_status wo_svm_get_weights(wo_svm *s, double *h_weights, int64_t *h_steps, int
  * buffer. */
 wo_status wo_measure_int_peak(int32_t reps, double *ops_per_s, void *stream);
 
+/* Measured peaks of the current device, the denominators of the rooflines
+ * measured rather than taken from published figures: the integer VALU rate
+ * as wo_measure_int_peak gives it; the LDS read bandwidth (every wave reads
+ * 1 KB per instruction, without bank conflicts); the HBM read bandwidth (a
+ * 1 GiB buffer read once with 16-byte loads); the dense BF16 MFMA rate
+ * (four independent 32 x 32 x 16 products per wave).  Each is the best of
+ * `reps` (1 .. 100) timed launches.  Synchronous; allocates 1 GiB and small
+ * output buffers for the call. */
+typedef struct {
+    double int_ops_per_s;
+    double lds_bytes_per_s;
+    double hbm_read_bytes_per_s;
+    double bf16_flops_per_s;
+} wo_peaks;
+wo_status wo_measure_peaks(int32_t reps, wo_peaks *out, void *stream);
+
 #ifdef __cplusplus
 }
 #endif

@@ -8,11 +8,13 @@
 //   h2  = GELU(h1 W2 + b2)     256
 //   y   = h2 W3 + b3           (standardised distance)
 //
-// GEMMs run on MFMA (v_mfma_f32_16x16x32_bf16: bf16 operands, fp32
+// GEMMs run on MFMA (v_mfma_f32_32x32x16_bf16: bf16 operands, fp32
 // accumulation).  Weights are kept as fp32 masters in [out][in] layout with
 // bf16 working copies; the one-hot operand is generated in registers from the
 // zone bytes and never stored.  Every GEMM here is C[M][N] = A[M][K] . B[N][K]^T
 // with both operands K-contiguous.
+#include <type_traits>
+
 #include "wo_internal.h"
 #include "wo_surrogate.h"
 
@@ -20,6 +22,7 @@ namespace wo {
 
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
+typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
 
 // fp32 -> bf16, nearest with ties to even (the hardware conversion)
@@ -65,11 +68,13 @@ constexpr int GBK = 64, GPAD = 8, GLDK = GBK + GPAD;
 // read one category's bytes from 16 different LDS banks
 constexpr int ZLD = 68;
 
-template <int AMODE, int BMODE, int EPI, int TM>
+template <int AMODE, int BMODE, int EPI, int TM, int MS>
 __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 {
     constexpr int WT = TM / 2;                 // wave tile
-    constexpr int FT = WT / 16;                // MFMA tiles per wave and dimension
+    constexpr int FT = WT / MS;                // MS x MS MFMA tiles per wave and dimension
+    constexpr int KM = MS == 32 ? 16 : 32;     // K depth of one MFMA
+    using AccT = typename std::conditional<MS == 32, floatx16, floatx4>::type;
     constexpr int NLD = TM * GBK / 8 / 256;    // 16-byte loads per thread per operand tile
     // operand tiles in two buffers: step k reads buffer k & 1 while the next
     // step's operands are written to the other one
@@ -87,13 +92,18 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     // split K: this workgroup's part [kbeg, kend)
     const int kc = g.K / max(g.ksplit, 1);
     const int kbeg = (int)blockIdx.z * kc, kend = kbeg + kc;
-    const int fr = lane & 15, fk = (lane >> 4) * 8;
+    // v_mfma_f32_32x32x16_bf16 (MS = 32) or v_mfma_f32_16x16x32_bf16 (MS =
+    // 16): lane l holds row (or column) l % MS and the 8 K elements from
+    // 8 (l / MS) of a KM-deep step
+    const int fr = lane & (MS - 1), fk = (lane / MS) * 8;
 
-    floatx4 acc[FT][FT];
+    AccT acc[FT][FT];
 #pragma unroll
     for (int i = 0; i < FT; i++)
 #pragma unroll
-        for (int j = 0; j < FT; j++) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
+        for (int j = 0; j < FT; j++)
+#pragma unroll
+            for (int e = 0; e < (MS == 32 ? 16 : 4); e++) acc[i][j][e] = 0.f;
 
     if (AMODE == A_ONEHOT) {
         if (tid < 36) {
@@ -165,14 +175,14 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             const int cat = k0 >> 6;
 #pragma unroll
             for (int ti = 0; ti < FT; ti++)
-                zrow[ti] = cat < g.n_cat ? (uint32_t)ZsA[(wm * WT + ti * 16 + fr) * ZLD + cat] : 0xFFu;
+                zrow[ti] = cat < g.n_cat ? (uint32_t)ZsA[(wm * WT + ti * MS + fr) * ZLD + cat] : 0xFFu;
         }
 #pragma unroll
-        for (int ks = 0; ks < GBK; ks += 32) {
+        for (int ks = 0; ks < GBK; ks += KM) {
             bf16x8 af[FT], bfr[FT];
 #pragma unroll
             for (int ti = 0; ti < FT; ti++) {
-                const int row = wm * WT + ti * 16 + fr;
+                const int row = wm * WT + ti * MS + fr;
                 if (AMODE == A_BF16) {
                     af[ti] = *(const bf16x8 *)(&As[cur][row * GLDK + ks + fk]);
                 } else {
@@ -181,7 +191,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             }
 #pragma unroll
             for (int tj = 0; tj < FT; tj++) {
-                const int col = wn * WT + tj * 16 + fr;
+                const int col = wn * WT + tj * MS + fr;
                 if (BMODE == B_BF16) {
                     bfr[tj] = *(const bf16x8 *)(&Bs[cur][col * GLDK + ks + fk]);
                 } else {
@@ -202,7 +212,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
             for (int ti = 0; ti < FT; ti++)
 #pragma unroll
                 for (int tj = 0; tj < FT; tj++)
-                    acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ti], bfr[tj], acc[ti][tj], 0, 0, 0);
+                    if constexpr (MS == 32)
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(af[ti], bfr[tj], acc[ti][tj], 0, 0, 0);
+                    else
+                        acc[ti][tj] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(af[ti], bfr[tj], acc[ti][tj], 0, 0, 0);
         }
         if (more) WO_STORE_TILE(cur ^ 1);
         __syncthreads();
@@ -210,42 +223,48 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 #undef WO_LOAD_TILE
 #undef WO_STORE_TILE
 
-    // epilogue: lane holds rows 4*(lane/16) + r, column lane % 16 of each tile
+    // epilogue: of each MS x MS tile, lane l holds column l % MS and, for
+    // q = 0 .. QN - 1, rows 8 q + 4 (l / MS) + r (r = 0 .. 3) in elements
+    // 4 q + r (MS = 32: QN = 4; MS = 16: QN = 1)
+    constexpr int QN = MS == 32 ? 4 : 1;
 #pragma unroll
     for (int ti = 0; ti < FT; ti++) {
 #pragma unroll
         for (int tj = 0; tj < FT; tj++) {
-            const int col = n0 + wn * WT + tj * 16 + fr;
-            const int rb = m0 + wm * WT + ti * 16 + (lane >> 4) * 4;
-            if (EPI == EPI_STORE) {
-                float *C = g.C + (int64_t)blockIdx.z * g.c_split;
+            const int col = n0 + wn * WT + tj * MS + fr;
 #pragma unroll
-                for (int r = 0; r < 4; r++) C[(uint32_t)((rb + r) * g.ldc + col)] = acc[ti][tj][r];
-            } else if (EPI == EPI_BIAS_GELU) {
-                const float bias = g.bias[col];
-                uint16_t hv[4];
+            for (int q = 0; q < QN; q++) {
+                const int rb = m0 + wm * WT + ti * MS + 8 * q + (lane / MS) * 4;
+                if (EPI == EPI_STORE) {
+                    float *C = g.C + (int64_t)blockIdx.z * g.c_split;
 #pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const float u = acc[ti][tj][r] + bias;
-                    if (g.U) g.U[(uint32_t)((rb + r) * g.ldc + col)] = u;
-                    if (g.H || g.HT) hv[r] = f2bf(gelu_f(u));
-                    if (g.H) g.H[(uint32_t)((rb + r) * g.ldc + col)] = hv[r];
-                }
-                if (g.HT) {
+                    for (int r = 0; r < 4; r++) C[(uint32_t)((rb + r) * g.ldc + col)] = acc[ti][tj][4 * q + r];
+                } else if (EPI == EPI_BIAS_GELU) {
+                    const float bias = g.bias[col];
+                    uint16_t hv[4];
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const float u = acc[ti][tj][4 * q + r] + bias;
+                        if (g.U) g.U[(uint32_t)((rb + r) * g.ldc + col)] = u;
+                        if (g.H || g.HT) hv[r] = f2bf(gelu_f(u));
+                        if (g.H) g.H[(uint32_t)((rb + r) * g.ldc + col)] = hv[r];
+                    }
+                    if (g.HT) {
+                        uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
+                                              (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
+                        *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pk;
+                    }
+                } else {   // EPI_GELU_GRAD_T: v = acc * gelu'(U), stored transposed in bf16
+                    uint16_t hv[4];
+#pragma unroll
+                    for (int r = 0; r < 4; r++) {
+                        const float u = g.Uin[(uint32_t)((rb + r) * g.ldc + col)];
+                        hv[r] = f2bf(acc[ti][tj][4 * q + r] * gelu_grad_f(u));
+                    }
                     uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
                                           (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
                     *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pk;
                 }
-            } else {   // EPI_GELU_GRAD_T: v = acc * gelu'(U), stored transposed in bf16
-                uint16_t hv[4];
-#pragma unroll
-                for (int r = 0; r < 4; r++) {
-                    const float u = g.Uin[(uint32_t)((rb + r) * g.ldc + col)];
-                    hv[r] = f2bf(acc[ti][tj][r] * gelu_grad_f(u));
-                }
-                uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
-                                      (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
-                *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pk;
             }
         }
     }
@@ -609,15 +628,21 @@ __global__ __launch_bounds__(TOPK_THREADS) void topk_kernel(const void *src, int
 // ---------------------------------------------------------------------------
 // launchers
 // ---------------------------------------------------------------------------
-// 128 x 128 tiles when they give at least one workgroup per CU, else 64 x 64
+// 128 x 128 tiles when they give at least one workgroup per CU, else 64 x 64.
+// MFMA shape: 32 x 32 x 16 where there is about one workgroup per CU (the
+// training products: 5 % faster); 16 x 16 x 32 for the large screening
+// passes (at least 1,024 workgroups: 3 % faster)
 template <int AM, int BM, int EP>
 static hipError_t launch_gemm_t(const GemmArgs &g, hipStream_t s)
 {
     const int ks = g.ksplit > 1 ? g.ksplit : 1;
-    if ((int64_t)(g.N / 128) * (g.M / 128) * ks >= 256) {
-        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 128>), dim3(g.N / 128, g.M / 128, ks), dim3(256), 0, s, g);
+    const int64_t t128 = (int64_t)(g.N / 128) * (g.M / 128) * ks;
+    if (t128 >= 1024) {
+        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 128, 16>), dim3(g.N / 128, g.M / 128, ks), dim3(256), 0, s, g);
+    } else if (t128 >= 256) {
+        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 128, 32>), dim3(g.N / 128, g.M / 128, ks), dim3(256), 0, s, g);
     } else {
-        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 64>), dim3(g.N / 64, g.M / 64, ks), dim3(256), 0, s, g);
+        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 64, 32>), dim3(g.N / 64, g.M / 64, ks), dim3(256), 0, s, g);
     }
     return hipGetLastError();
 }

@@ -33,7 +33,8 @@ EXPORTS = sorted([
     "wo_search_create", "wo_search_free", "wo_search_step", "wo_search_best", "wo_search_population",
     "wo_search_save", "wo_search_load",
     "wo_set_eval_config", "wo_get_eval_config", "wo_autotune_eval", "wo_tune_cache_store", "wo_tune_cache_lookup",
-    "wo_kmeans_categories", "wo_kmeans_categories_noalloc", "wo_measure_int_peak", "wo_aisle_width",
+    "wo_kmeans_categories", "wo_kmeans_categories_noalloc", "wo_measure_int_peak", "wo_measure_peaks",
+    "wo_aisle_width",
     "wo_order_features", "wo_svm_create", "wo_svm_free", "wo_svm_push", "wo_svm_train", "wo_svm_predict",
     "wo_svm_get_weights",
 ])
@@ -62,6 +63,11 @@ class wo_search_params(ctypes.Structure):
 class wo_aisle_params(ctypes.Structure):
     _fields_ = [("rack_depth_dm", ctypes.c_int32), ("cross_aisle_dm", ctypes.c_int32),
                 ("min_width_dm", ctypes.c_int32), ("max_width_dm", ctypes.c_int32), ("k_dm", ctypes.c_double)]
+
+
+class wo_peaks(ctypes.Structure):
+    _fields_ = [("int_ops_per_s", ctypes.c_double), ("lds_bytes_per_s", ctypes.c_double),
+                ("hbm_read_bytes_per_s", ctypes.c_double), ("bf16_flops_per_s", ctypes.c_double)]
 
 
 class wo_aisle_result(ctypes.Structure):
@@ -132,6 +138,7 @@ def lib():
         L.wo_kmeans_categories.argtypes = [V, I64, I32, I32, I32, V, P(I32), P(I32), V]
         L.wo_kmeans_categories_noalloc.argtypes = [V, I64, I32, I32, I32, V, V, V, V]
         L.wo_measure_int_peak.argtypes = [I32, P(F64), V]
+        L.wo_measure_peaks.argtypes = [I32, P(wo_peaks), V]
         L.wo_aisle_width.argtypes = [V, I32, V, V, P(wo_aisle_params), V, V, P(wo_aisle_result)]
         L.wo_order_features.argtypes = [V, V, I32, I64, V, I32, I32, V, V]
         L.wo_svm_create.argtypes = [I32, I32, I32, F64, V, P(V)]
@@ -487,6 +494,15 @@ def wo_svm_get_weights(s: Svm, stream=None):
     _check(lib().wo_svm_get_weights(s.handle, w.ctypes.data, ctypes.byref(steps), ctypes.byref(cnt),
                                     ctypes.c_void_p(_stream_handle(stream))))
     return w, steps.value, cnt.value
+
+
+def wo_measure_peaks(reps: int = 3, stream=None) -> dict:
+    """Measured peaks of the device: integer VALU ops/s, LDS read bytes/s,
+    HBM read bytes/s and dense BF16 MFMA FLOP/s."""
+    p = wo_peaks()
+    _check(lib().wo_measure_peaks(int(reps), ctypes.byref(p), ctypes.c_void_p(_stream_handle(stream))))
+    return {"int_ops_per_s": p.int_ops_per_s, "lds_bytes_per_s": p.lds_bytes_per_s,
+            "hbm_read_bytes_per_s": p.hbm_read_bytes_per_s, "bf16_flops_per_s": p.bf16_flops_per_s}
 
 
 def wo_measure_int_peak(reps: int = 5, stream=None) -> float:

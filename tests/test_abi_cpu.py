@@ -236,3 +236,11 @@ def test_kmeans_noalloc_rejects_sizes_beyond_its_scratch(wo):
     assert st == wo.WO_E_RANGE
     st = L.wo_kmeans_categories_noalloc(None, 1000, 100, 8, 10, dev, None, None, None)
     assert st == wo.WO_E_INVAL
+
+
+def test_measure_peaks_rejects_bad_arguments(wo):
+    # checked on the host before any device call
+    assert wo.lib().wo_measure_peaks(3, None, None) == 1          # WO_E_INVAL
+    p = wo.wo_peaks()
+    assert wo.lib().wo_measure_peaks(0, ctypes.byref(p), None) == 2    # WO_E_RANGE
+    assert wo.lib().wo_measure_peaks(101, ctypes.byref(p), None) == 2
