@@ -141,60 +141,84 @@ __global__ void update_kernel(const double *X, const int8_t *coef, int32_t W, in
     Wt[q] = w - eta * (lambda * w - g / (double)n);
 }
 
-// Categories of R (64, or 32 where 64 rows and the weights would not fit in
-// 64 KiB) samples per wavefront: the weights and the samples'
-// feature rows pass through LDS (coalesced loads; rows padded to an odd
-// number of doubles so the lanes' reads spread over the banks), then each
-// lane scores its sample class by class, features in index order and the
-// bias last, keeping the class of the largest score (ties: the lower).
-__global__ __launch_bounds__(64) void predict_kernel(const double *X, int64_t n, int32_t F, int32_t K, const double *Wt,
-                                                    int32_t R, int32_t *cls)
+// Prediction, one lane per order: the class of the largest score (ties: the
+// lower class), a score being weights . features in feature order, then the
+// bias, as in training: every wave takes 64 orders and streams their
+// features through LDS in chunks of 8, read coalesced (8 lanes per 64-byte
+// piece of a row; the next chunk in flight while the current one is
+// multiplied), for up to 8 classes at a time; the weights sit in LDS for the
+// whole grid stride.
+constexpr int PK_CHUNK = 8, PK_LD = PK_CHUNK + 1, PK_KG = 8;
+
+// A wave's LDS accesses take effect in program order, so a lane may read what
+// another lane of its wave wrote before: only the compiler must keep the order.
+__device__ __forceinline__ void wave_lds_order() { asm volatile("" ::: "memory"); }
+
+__global__ __launch_bounds__(256) void predict_kernel(const double *X, int64_t n, int32_t F, int32_t K,
+                                                     const double *Wt, int32_t *cls)
 {
     extern __shared__ double lds[];
-    const int32_t nw = K * (F + 1), ld = F | 1;
-    double *wl = lds, *tile = lds + nw;
-    const int lane = threadIdx.x;
-    for (int32_t e = lane; e < nw; e += 64) wl[e] = Wt[e];
-    for (int64_t i0 = blockIdx.x * (int64_t)R; i0 < n; i0 += (int64_t)gridDim.x * R) {
-        const int32_t rows = (int32_t)std::min<int64_t>(R, n - i0);
+    const int32_t nw = K * (F + 1);
+    double *wl = lds;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double *tile = lds + nw + w * 64 * PK_LD;
+    for (int32_t e = tid; e < nw; e += 256) wl[e] = Wt[e];
+    __syncthreads();
+    for (int64_t i0 = ((int64_t)blockIdx.x * 4 + w) * 64; i0 < n; i0 += (int64_t)gridDim.x * 256) {
+        const int32_t rows = (int32_t)std::min<int64_t>(64, n - i0);   // uniform in the wave
         const double *src = X + i0 * F;
-        __syncthreads();
-        for (int32_t e = lane; e < rows * F; e += 64) {
-            const int32_t r = e / F;
-            tile[r * ld + (e - r * F)] = src[e];
-        }
-        __syncthreads();
-        if (lane < rows) {
-            const double *x = tile + lane * ld;
-            int32_t best = 0;
-            double bs = 0.0;
-            // four classes at a time: independent sums, each in feature order
-            for (int32_t k0 = 0; k0 < K; k0 += 4) {
-                const double *w0 = wl + std::min(k0, K - 1) * (F + 1);
-                const double *w1 = wl + std::min(k0 + 1, K - 1) * (F + 1);
-                const double *w2 = wl + std::min(k0 + 2, K - 1) * (F + 1);
-                const double *w3 = wl + std::min(k0 + 3, K - 1) * (F + 1);
-                double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-#pragma unroll 4
-                for (int32_t f = 0; f < F; f++) {
-                    const double xf = x[f];
-                    a0 = a0 + w0[f] * xf;
-                    a1 = a1 + w1[f] * xf;
-                    a2 = a2 + w2[f] * xf;
-                    a3 = a3 + w3[f] * xf;
-                }
-                const double v[4] = {a0 + w0[F], a1 + w1[F], a2 + w2[F], a3 + w3[F]};
+        int32_t best = 0;
+        double bs = 0.0;
+        for (int32_t k0 = 0; k0 < K; k0 += PK_KG) {
+            double acc[PK_KG];
 #pragma unroll
-                for (int j = 0; j < 4; j++) {
-                    const int32_t k = k0 + j;
-                    if (k < K && (k == 0 || v[j] > bs)) {
-                        bs = v[j];
+            for (int j = 0; j < PK_KG; j++) acc[j] = 0.0;
+            // a lane's 8 loads of a chunk: row idx / 8, feature idx % 8 of
+            // the chunk (idx = t * 64 + lane)
+            double nx[PK_CHUNK];
+#pragma unroll
+            for (int t = 0; t < PK_CHUNK; t++) {
+                const int idx = t * 64 + lane, r = idx / PK_CHUNK, f = idx % PK_CHUNK;
+                nx[t] = (r < rows && f < F) ? src[(int64_t)r * F + f] : 0.0;
+            }
+            for (int32_t c = 0; c < F; c += PK_CHUNK) {
+                wave_lds_order();                // the previous chunk is read
+#pragma unroll
+                for (int t = 0; t < PK_CHUNK; t++) {
+                    const int idx = t * 64 + lane, r = idx / PK_CHUNK, f = idx % PK_CHUNK;
+                    tile[r * PK_LD + f] = nx[t];
+                }
+                wave_lds_order();
+                if (c + PK_CHUNK < F) {
+#pragma unroll
+                    for (int t = 0; t < PK_CHUNK; t++) {
+                        const int idx = t * 64 + lane, r = idx / PK_CHUNK, f = c + PK_CHUNK + idx % PK_CHUNK;
+                        nx[t] = (r < rows && f < F) ? src[(int64_t)r * F + f] : 0.0;
+                    }
+                }
+#pragma unroll
+                for (int f = 0; f < PK_CHUNK; f++) {
+                    if (c + f < F) {
+                        const double xf = tile[lane * PK_LD + f];
+#pragma unroll
+                        for (int j = 0; j < PK_KG; j++)
+                            if (k0 + j < K) acc[j] = acc[j] + wl[(k0 + j) * (F + 1) + c + f] * xf;
+                    }
+                }
+            }
+#pragma unroll
+            for (int j = 0; j < PK_KG; j++) {
+                const int32_t k = k0 + j;
+                if (k < K) {
+                    const double v = acc[j] + wl[k * (F + 1) + F];
+                    if (k == 0 || v > bs) {
+                        bs = v;
                         best = k;
                     }
                 }
             }
-            cls[i0 + lane] = best;
         }
+        if (lane < rows) cls[i0 + lane] = best;
     }
 }
 
@@ -319,10 +343,9 @@ extern "C" wo_status wo_svm_predict(wo_svm *m, int64_t n, const double *d_featur
     if (n < 0) return wo_fail(WO_E_INVAL, "n < 0");
     if (n == 0) return WO_OK;
     hipStream_t s = (hipStream_t)stream;
-    const size_t wbytes = sizeof(double) * (size_t)m->K * (m->F + 1), row = sizeof(double) * (size_t)(m->F | 1);
-    const int32_t R = wbytes + 64 * row <= 65536 ? 64 : 32;
-    hipLaunchKernelGGL(predict_kernel, dim3(grid_for(n, R)), dim3(64), wbytes + R * row, s, d_features, n, m->F, m->K,
-                       m->Wt, R, d_class);
+    const size_t lds = sizeof(double) * ((size_t)m->K * (m->F + 1) + 4 * 64 * PK_LD);
+    hipLaunchKernelGGL(predict_kernel, dim3(grid_for(n, 256)), dim3(256), lds, s, d_features, n, m->F, m->K, m->Wt,
+                       d_class);
     WO_HIP(hipGetLastError());
     return WO_OK;
 }

@@ -114,8 +114,8 @@ def test_small_and_degenerate():
 
 @pytest.mark.parametrize("F,K,n", [(64, 64, 200), (63, 64, 131), (64, 8, 1000), (1, 2, 65), (17, 5, 64)])
 def test_prediction_shapes(F, K, n):
-    # the largest model (the rows of 32 samples per tile), odd feature counts,
-    # a ragged last tile and a tile of exactly 64 samples
+    # the largest model (64 classes over 64 features), odd feature counts,
+    # a ragged last wave of orders and a wave of exactly 64
     import torch
     wo = _wo()
     rng = np.random.default_rng(F * 1000 + K)
