@@ -59,26 +59,41 @@ struct SvmBusy {
 
 int grid_for(int64_t n, int block) { return (int)std::min<int64_t>(std::max<int64_t>((n + block - 1) / block, 1), 65535); }
 
-// One thread per order: line counts per category, then shares.  Lines are
-// clamped to [0, n_lines); SKUs outside [0, n_skus) and categories outside
-// [0, F) count in the length only.
-__global__ void features_kernel(const int32_t *off, const int32_t *skus, int32_t n_orders, int64_t n_lines,
-                                const int32_t *sku_cat, int32_t n_skus, int32_t F, double *x)
+// Line counts per category, then shares, 64 orders per wave: each lane
+// counts its order's lines in its own LDS row (lines clamped to
+// [0, n_lines); SKUs outside [0, n_skus) and categories outside [0, F) count
+// in the length only), then the wave writes the 64 rows of shares, one
+// coalesced row per store (lane = feature).
+constexpr int FT_LD = WO_SVM_MAX_FEATURES + 1;
+
+__global__ __launch_bounds__(64) void features_kernel(const int32_t *off, const int32_t *skus, int32_t n_orders,
+                                                     int64_t n_lines, const int32_t *sku_cat, int32_t n_skus,
+                                                     int32_t F, double *x)
 {
-    for (int32_t o = blockIdx.x * blockDim.x + threadIdx.x; o < n_orders; o += gridDim.x * blockDim.x) {
-        double *row = x + (int64_t)o * F;
-        for (int32_t c = 0; c < F; c++) row[c] = 0.0;
-        const int32_t a = off[o], b = off[o + 1];
-        const int64_t l0 = std::max<int64_t>(a, 0), l1 = std::min<int64_t>(b, n_lines);
-        for (int64_t l = l0; l < l1; l++) {
-            const int32_t s = skus[l];
-            if (s < 0 || s >= n_skus) continue;
-            const int32_t c = sku_cat[s];
-            if (c < 0 || c >= F) continue;
-            row[c] = row[c] + 1.0;
+    __shared__ uint32_t cnt[64 * FT_LD];
+    __shared__ double len[64];
+    const int lane = threadIdx.x;
+    for (int64_t o0 = (int64_t)blockIdx.x * 64; o0 < n_orders; o0 += (int64_t)gridDim.x * 64) {
+        uint32_t *mine = cnt + lane * FT_LD;
+        for (int32_t c = 0; c < F; c++) mine[c] = 0u;
+        const int64_t o = o0 + lane;
+        if (o < n_orders) {
+            const int32_t a = off[o], b = off[o + 1];
+            const int64_t l0 = std::max<int64_t>(a, 0), l1 = std::min<int64_t>(b, n_lines);
+            for (int64_t l = l0; l < l1; l++) {
+                const int32_t sk = skus[l];
+                if (sk < 0 || sk >= n_skus) continue;
+                const int32_t c = sku_cat[sk];
+                if (c < 0 || c >= F) continue;
+                mine[c] += 1u;
+            }
+            len[lane] = (double)(b - a);
         }
-        const double len = (double)(b - a);
-        for (int32_t c = 0; c < F; c++) row[c] = row[c] / len;
+        asm volatile("" ::: "memory");   // a wave's LDS accesses take effect in program order
+        const int32_t rows = (int32_t)std::min<int64_t>(64, n_orders - o0);
+        for (int32_t r = 0; r < rows; r++)
+            for (int32_t c = lane; c < F; c += 64) x[(o0 + r) * F + c] = (double)cnt[r * FT_LD + c] / len[r];
+        asm volatile("" ::: "memory");
     }
 }
 
@@ -234,7 +249,7 @@ extern "C" wo_status wo_order_features(const int32_t *d_order_offsets, const int
         return wo_fail(WO_E_RANGE, "n_features must be in 1 .. %d", WO_SVM_MAX_FEATURES);
     if (n_orders == 0) return WO_OK;
     hipStream_t s = (hipStream_t)stream;
-    hipLaunchKernelGGL(features_kernel, dim3(grid_for(n_orders, 256)), dim3(256), 0, s, d_order_offsets, d_order_skus,
+    hipLaunchKernelGGL(features_kernel, dim3(grid_for(n_orders, 64)), dim3(64), 0, s, d_order_offsets, d_order_skus,
                        n_orders, n_lines, d_sku_category, n_skus, n_features, d_features);
     WO_HIP(hipGetLastError());
     return WO_OK;
