@@ -120,31 +120,61 @@ __global__ void margin_kernel(const double *X, const int32_t *L, int32_t W, int6
 }
 
 // One thread per (class, weight): the subgradient step; the sum over the
-// samples runs from the oldest, as in the step's definition (its loads are
-// issued ahead in groups, the additions stay in order).
-__global__ void update_kernel(const double *X, const int8_t *coef, int32_t W, int64_t first, int64_t n, int32_t F,
-                              int32_t K, double *Wt, double lambda, double t)
+// samples runs from the oldest, as in the step's definition.  The additions
+// stay in order; the loads run a group of 32 samples ahead of them (two
+// register buffers), since a weight's sum is one chain over the whole window
+// and the loads' latency would otherwise set its pace.
+constexpr int UP_U = 32;
+
+__device__ __forceinline__ void update_load(const double *X, const int8_t *coef, int32_t W, int64_t i, int64_t slot,
+                                            int32_t F, int32_t K, int32_t k, int32_t f, double (&v)[UP_U])
+{
+#pragma unroll
+    for (int u = 0; u < UP_U; u++) {
+        int64_t sl = slot + u;
+        if (sl >= W) sl -= W;
+        // every lane loads (the bias lane a feature it does not use), so
+        // that no branch splits the loads of the group
+        const double c = (double)coef[(i + u) * K + k];
+        const double x = X[sl * F + (f < F ? f : F - 1)];
+        v[u] = f < F ? c * x : c;
+    }
+}
+
+__global__ __launch_bounds__(64) void update_kernel(const double *X, const int8_t *coef, int32_t W, int64_t first,
+                                                   int64_t n, int32_t F, int32_t K, double *Wt, double lambda, double t)
 {
     const int32_t q = blockIdx.x * blockDim.x + threadIdx.x;
     if (q >= K * (F + 1)) return;
     const int32_t k = q / (F + 1), f = q - k * (F + 1);
-    constexpr int U = 16;
     double g = 0.0;
     int64_t i = 0;
     int64_t slot = first;
-    for (; i + U <= n; i += U) {
-        double v[U];
-#pragma unroll
-        for (int u = 0; u < U; u++) {
-            int64_t sl = slot + u;
-            if (sl >= W) sl -= W;
-            const double c = (double)coef[(i + u) * K + k];
-            v[u] = f < F ? c * X[sl * F + f] : c;
-        }
-#pragma unroll
-        for (int u = 0; u < U; u++) g = g + v[u];
-        slot += U;
+    auto advance = [&](int64_t by) {
+        slot += by;
         if (slot >= W) slot -= W;
+    };
+    const int64_t groups = n / UP_U;
+    double a[UP_U], b[UP_U];
+    if (groups > 0) update_load(X, coef, W, 0, slot, F, K, k, f, a);
+    for (int64_t gi = 0; gi < groups; gi += 2) {
+        // a holds group gi; load gi + 1 into b, then add a
+        int64_t s1 = slot + UP_U;
+        if (s1 >= W) s1 -= W;
+        if (gi + 1 < groups) update_load(X, coef, W, i + UP_U, s1, F, K, k, f, b);
+#pragma unroll
+        for (int u = 0; u < UP_U; u++) g = g + a[u];
+        i += UP_U;
+        advance(UP_U);
+        if (gi + 1 >= groups) break;
+        // b holds group gi + 1; load gi + 2 into a, then add b
+        s1 = slot + UP_U;
+        if (s1 >= W) s1 -= W;
+        if (gi + 2 < groups) update_load(X, coef, W, i + UP_U, s1, F, K, k, f, a);
+#pragma unroll
+        for (int u = 0; u < UP_U; u++) g = g + b[u];
+        i += UP_U;
+        advance(UP_U);
     }
     for (; i < n; i++) {
         const double c = (double)coef[i * K + k];
