@@ -242,7 +242,7 @@ def test_padding_bytes_are_ignored():
     s.free()
 
 
-@pytest.mark.parametrize("n", [128, 384])
+@pytest.mark.parametrize("n", [128, 384, 4096])   # 4,096: the training batch (its own tile and MFMA shapes)
 def test_gradients_match_reference(n):
     import torch
     wo = _wo()
