@@ -319,7 +319,7 @@ __global__ __launch_bounds__(256) void layer3_kernel(L3Args a)
 //   [0, W3_SLICES): gW3 over a slice of the batch, one thread per output
 //     (rows of h2 read whole); the last of them to finish adds the slices;
 //   then one wave per output of gb3, gb2, gb1 and the loss;
-//   then 1,024 outputs of gW2 per workgroup (if split).
+//   then 1,024 outputs of gW2 per workgroup (if split), then of gW1 (if split).
 __global__ __launch_bounds__(256) void batch_sums_kernel(SumArgs a)
 {
     const int tid = threadIdx.x, lane = tid & 63;
@@ -381,17 +381,29 @@ __global__ __launch_bounds__(256) void batch_sums_kernel(SumArgs a)
         return;
     }
     blk -= row_blocks;
+    const float *part = a.w2part;
+    int splits = a.w2_splits;
+    int64_t stride = a.w2_stride;
+    float *out = a.gW2;
+    const int w2_blocks = a.w2part ? N_H2 * N_H1 / 1024 : 0;
+    if (blk >= w2_blocks) {
+        blk -= w2_blocks;
+        part = a.w1part;
+        splits = a.w1_splits;
+        stride = a.w1_stride;
+        out = a.gW1;
+    }
     const int64_t i = ((int64_t)blk * 256 + tid) * 4;
-    if (a.w2part && i < (int64_t)N_H2 * N_H1) {
-        float4 t = *(const float4 *)(a.w2part + i);
-        for (int k = 1; k < a.w2_splits; k++) {
-            const float4 u = *(const float4 *)(a.w2part + k * a.w2_stride + i);
+    if (part) {
+        float4 t = *(const float4 *)(part + i);
+        for (int k = 1; k < splits; k++) {
+            const float4 u = *(const float4 *)(part + k * stride + i);
             t.x += u.x;
             t.y += u.y;
             t.z += u.z;
             t.w += u.w;
         }
-        *(float4 *)(a.gW2 + i) = t;
+        *(float4 *)(out + i) = t;
     }
 }
 
@@ -669,7 +681,8 @@ hipError_t launch_layer3(const L3Args &a, hipStream_t s)
 hipError_t launch_batch_sums(const SumArgs &a, hipStream_t s)
 {
     const int n_rows = 1 + N_H2 + N_H1 + 1;
-    const int blocks = W3_SLICES + (n_rows + 3) / 4 + (a.w2part ? N_H2 * N_H1 / 1024 : 0);
+    const int blocks = W3_SLICES + (n_rows + 3) / 4 + (a.w2part ? N_H2 * N_H1 / 1024 : 0) +
+                       (a.w1part ? N_H1 * N_IN / 1024 : 0);
     hipLaunchKernelGGL(batch_sums_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }

@@ -159,7 +159,13 @@ wo_status gradients(wo_sur *s, int rows, hipStream_t st, float *loss_out = nullp
     g2.ksplit = ks;
     g2.c_split = (int64_t)N_H2 * N_H1;
     WO_HIP(launch_gemm(A_BF16, B_BF16, EPI_STORE, g2, st));
-    // gW1^T [1024][4096] = du1^T [1024][b] . (x^T [4096][b])^T, x one-hot
+    // gW1^T [1024][4096] = du1^T [1024][b] . (x^T [4096][b])^T, x one-hot:
+    // one workgroup per CU unsplit, so K is split in parts as well (after
+    // gW2's parts in u1's buffer), each part's loads then overlapping
+    // another's products
+    int ks1 = 2;
+    while (ks1 > 1 && rows % (ks1 * 64)) ks1 >>= 1;
+    float *w1part = s->d_U1 + (int64_t)8 * N_H2 * N_H1;
     GemmArgs g0{};
     g0.M = N_H1;
     g0.N = N_IN;
@@ -169,8 +175,10 @@ wo_status gradients(wo_sur *s, int rows, hipStream_t st, float *loss_out = nullp
     g0.A = s->d_DU1T;
     g0.lda = rows;
     g0.zoneB = s->d_zb;
-    g0.C = s->d_g + P_W1;
+    g0.C = ks1 > 1 ? w1part : s->d_g + P_W1;
     g0.ldc = N_IN;
+    g0.ksplit = ks1;
+    g0.c_split = (int64_t)N_H1 * N_IN;
     WO_HIP(launch_gemm(A_BF16, B_ONEHOT_T, EPI_STORE, g0, st));
     SumArgs sm{};
     sm.n = rows;
@@ -191,6 +199,10 @@ wo_status gradients(wo_sur *s, int rows, hipStream_t st, float *loss_out = nullp
     sm.w2_splits = ks;
     sm.w2_stride = (int64_t)N_H2 * N_H1;
     sm.gW2 = s->d_g + P_W2;
+    sm.w1part = ks1 > 1 ? w1part : nullptr;
+    sm.w1_splits = ks1;
+    sm.w1_stride = (int64_t)N_H1 * N_IN;
+    sm.gW1 = s->d_g + P_W1;
     WO_HIP(launch_batch_sums(sm, st));
     return WO_OK;
 }

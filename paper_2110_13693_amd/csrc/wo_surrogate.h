@@ -76,6 +76,10 @@ struct SumArgs {
     int w2_splits;
     int64_t w2_stride;
     float *gW2;
+    const float *w1part;      // the same for gW1
+    int w1_splits;
+    int64_t w1_stride;
+    float *gW1;
 };
 
 hipError_t launch_gemm(int amode, int bmode, int epi, const GemmArgs &g, hipStream_t s);
