@@ -704,23 +704,20 @@ __global__ __launch_bounds__(BLOCK, ROUTE == WO_ROUTE_SSHAPE ? 4 : 2) void eval_
                         uint32_t tb[U], zv[U];
 #pragma unroll
                         for (int u = 0; u < U; u++) v[u] = lines[gi * LINE_PAD + u * 64];
-                        // all table reads of the group before its atomics; a
-                        // lane's slots hold consecutive lines, so an order's
-                        // tour entry is read once (bit 31 of y marks the first
-                        // slot of its run) and its farthest location is raised
-                        // once per run
+                        // all table reads of the group before its atomics.
+                        // Every slot reads its order's tour entry (reading it
+                        // only at the first slot of a run takes a branch per
+                        // slot, which costs more); a lane's slots hold
+                        // consecutive lines, so an order's farthest location
+                        // is raised once per run (bit 31 of y marks the first
+                        // slot of a run)
                         bool first[U];
 #pragma unroll
                         for (int u = 0; u < U; u++) {
                             first[u] = u == 0 || (int32_t)v[u].y < 0;
-                            uint32_t t = 0;
-                            if (first[u]) t = *lds16(v[u].y & 0x7FFFFFFFu);
-                            tb[u] = t;
+                            tb[u] = *lds16(v[u].y & 0x7FFFFFFFu);
                             zv[u] = (uint32_t)__builtin_amdgcn_ds_bpermute((int)(v[u].x >> 24), zsv);
                         }
-#pragma unroll
-                        for (int u = 1; u < U; u++)
-                            if (!first[u]) tb[u] = tb[u - 1];
                         if (ROUTE != WO_ROUTE_SSHAPE) {
                             // pick rows: take the next entry of the tour's row
                             // (the dummy row's count runs past its entries,
