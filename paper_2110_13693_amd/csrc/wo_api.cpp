@@ -854,14 +854,17 @@ extern "C" wo_status wo_eval_plans(wo_wh *wh, const int64_t *plan_offsets, int64
             ac.n_plans = w.n;
             ac.work = w.d_work;
             ac.queue = wh->queue;
-            // the small instances' plans go out in chunks of consecutive
-            // work items, so that a workgroup mostly keeps its instance's
-            // tables (grid stride: 2 per step; queue: 4 per ticket)
-            ac.chunk = c ? (wh->queue ? 4 : 2) : 1;
             ac.queue_ctr = (uint32_t *)((char *)wh->d_err + 48 + 4 * c);
             const int block = c ? class_block[c] : wh->block;
             const int per_cu = c ? 0 : wh->per_cu;
-            HIP_TRY(launch_eval(ac, w.lds, launch_grid(wh, block, per_cu, w.lds, w.n), block, wh->route, s));
+            const int grid = launch_grid(wh, block, per_cu, w.lds, w.n);
+            // the small instances' plans go out in chunks of consecutive
+            // work items, so that a workgroup mostly keeps its instance's
+            // tables (grid stride: 2 per step; queue: 4 per ticket), where
+            // every workgroup has many plans (with few, chunks would leave
+            // workgroups idle)
+            ac.chunk = (c && w.n >= (int64_t)grid * 8) ? (wh->queue ? 4 : 2) : 1;
+            HIP_TRY(launch_eval(ac, w.lds, grid, block, wh->route, s));
         }
     }
     // the completion of this call, for the next call on another stream (not
