@@ -94,8 +94,7 @@ def cpu_model() -> str:
 
 def host_threads():
     """Threads the CPU baseline may use: the cores this process may run on,
-    limited to the CPU share its environment declares (OMP_NUM_THREADS; a
-    GPU machine grants one GPU's process 16)."""
+    limited to the CPU share its environment declares (OMP_NUM_THREADS)."""
     try:
         avail = len(os.sched_getaffinity(0))
     except AttributeError:
