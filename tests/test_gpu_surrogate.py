@@ -379,3 +379,26 @@ def test_training_steps_match_reference_adam():
     y, cache = S.forward(q, S.one_hot(Z, 64))
     assert_within(pred.cpu().numpy(), y, device_error_model(q, cache, y)["s_y"], "prediction after training")
     s.free()
+
+
+def test_training_is_deterministic_and_follows_its_seed():
+    # 434 samples at batch 128: three batches per epoch and a dropped
+    # remainder, the epoch's shuffle a keyed permutation of 434 (walked back
+    # into range); every reduction of the step (split-K parts, sliced batch
+    # sums) runs in a fixed order, so the same seed gives the same parameters
+    # bit for bit and another seed other ones
+    import torch
+    wo = _wo()
+    n = 434
+    Z = _zones(n, 21)
+    d = np.random.default_rng(22).integers(20_000_000, 24_000_000, n).astype(np.int32)
+    z, dd = torch.from_numpy(Z).cuda(), torch.from_numpy(d).cuda()
+    out = []
+    for seed in (5, 5, 6):
+        s = wo.wo_sur_create(64, flat(_params(7)))
+        loss = wo.wo_sur_train(s, z, dd, epochs=2, batch=128, lr=1e-3, seed=seed)
+        assert np.isfinite(loss) and loss > 0
+        out.append((np.asarray(wo.wo_sur_get_params(s)), loss))
+        s.free()
+    assert np.array_equal(out[0][0], out[1][0]) and out[0][1] == out[1][1]
+    assert not np.array_equal(out[0][0], out[2][0])
