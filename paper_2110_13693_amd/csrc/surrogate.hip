@@ -24,6 +24,7 @@ typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 bf16x8;
 typedef __attribute__((__vector_size__(4 * sizeof(float)))) float floatx4;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float floatx16;
 typedef __attribute__((__vector_size__(4 * sizeof(uint32_t)))) uint32_t u32x4;
+typedef __attribute__((__vector_size__(2 * sizeof(uint32_t)))) uint32_t u32x2;
 
 // fp32 -> bf16, nearest with ties to even (the hardware conversion)
 static __device__ __forceinline__ uint16_t f2bf(float f)
@@ -60,8 +61,8 @@ static __device__ __forceinline__ float gelu_grad_f(float u)
 // step 64, four waves in 2 x 2, each (TM/2)^2 = (TM/32)^2 MFMA tiles of
 // 16 x 16.  The next K step's operands are loaded into registers while the
 // current one's MFMAs run from LDS.  M, N multiples of TM and K a multiple of
-// 64 (the host pads); rows of A at or beyond M_real, and samples of B at or
-// beyond K_real, read as zero when generated from zone bytes.
+// 64 (the host pads); rows of A at or beyond M_real read as zero when
+// generated from zone bytes.
 // ---------------------------------------------------------------------------
 constexpr int GBK = 64, GPAD = 8, GLDK = GBK + GPAD;
 // zone bytes of A rows at a 68-byte stride: the 16 rows of an MFMA tile then
@@ -79,9 +80,8 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
     // operand tiles in two buffers: step k reads buffer k & 1 while the next
     // step's operands are written to the other one
     __shared__ __align__(16) uint16_t As[2][(AMODE == A_BF16) ? TM * GLDK : 8];
-    __shared__ __align__(16) uint16_t Bs[2][(BMODE == B_BF16) ? TM * GLDK : 8];
+    __shared__ __align__(16) uint16_t Bs[2][TM * GLDK];
     __shared__ __align__(16) uint8_t ZsA[(AMODE == A_ONEHOT) ? TM * ZLD : 16];
-    __shared__ __align__(16) uint8_t ZsB[2][(BMODE == B_ONEHOT_T) ? GBK * 64 : 16];
     // one-hot fragments: pattern d < 8 holds bf16 1.0 at element d, pattern 8
     // is all zeros
     __shared__ __align__(16) uint32_t OneHot[(AMODE == A_ONEHOT) ? 9 * 4 : 4];
@@ -123,7 +123,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
         }
     }
 
-    u32x4 ra[NLD], rbv[NLD], rz;   // native vectors, so that they stay in registers
+    u32x4 ra[NLD], rbv[NLD];   // native vectors, so that they stay in registers
 #define WO_LOAD_TILE(k0_)                                                                                        \
     do {                                                                                                         \
         if (AMODE == A_BF16) {                                                                                   \
@@ -132,15 +132,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                 ra[i] = *(const u32x4 *)(g.A + (int64_t)(m0 + r) * g.lda + (k0_) + part * 8);                    \
             }                                                                                                    \
         }                                                                                                        \
-        if (BMODE == B_BF16) {                                                                                   \
-            _Pragma("unroll") for (int i = 0; i < NLD; i++) {                                                    \
-                const int c = tid + i * 256, r = c >> 3, part = c & 7;                                           \
-                rbv[i] = *(const u32x4 *)(g.B + (int64_t)(n0 + r) * g.ldb + (k0_) + part * 8);                   \
-            }                                                                                                    \
-        } else {                                                                                                 \
-            const int r = tid >> 2, part = tid & 3;                                                              \
-            rz = u32x4{0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu, 0xFFFFFFFFu};                                 \
-            if ((k0_) + r < g.K_real) rz = *(const u32x4 *)(g.zoneB + (int64_t)((k0_) + r) * 64 + part * 16);    \
+        _Pragma("unroll") for (int i = 0; i < NLD; i++) {                                                        \
+            const int c = tid + i * 256, r = c >> 3, part = c & 7;                                               \
+            rbv[i] = *(const u32x4 *)(g.B + (int64_t)(n0 + r) * g.ldb + (k0_) + part * 8);                       \
         }                                                                                                        \
     } while (0)
 #define WO_STORE_TILE(buf)                                                                                       \
@@ -151,13 +145,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                 *(u32x4 *)(&As[buf][r * GLDK + part * 8]) = ra[i];                                               \
             }                                                                                                    \
         }                                                                                                        \
-        if (BMODE == B_BF16) {                                                                                   \
-            _Pragma("unroll") for (int i = 0; i < NLD; i++) {                                                    \
-                const int c = tid + i * 256, r = c >> 3, part = c & 7;                                           \
-                *(u32x4 *)(&Bs[buf][r * GLDK + part * 8]) = rbv[i];                                              \
-            }                                                                                                    \
-        } else {                                                                                                 \
-            *(u32x4 *)(&ZsB[buf][(tid >> 2) * 64 + (tid & 3) * 16]) = rz;                                         \
+        _Pragma("unroll") for (int i = 0; i < NLD; i++) {                                                        \
+            const int c = tid + i * 256, r = c >> 3, part = c & 7;                                               \
+            *(u32x4 *)(&Bs[buf][r * GLDK + part * 8]) = rbv[i];                                                  \
         }                                                                                                        \
     } while (0)
 
@@ -192,21 +182,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 #pragma unroll
             for (int tj = 0; tj < FT; tj++) {
                 const int col = wn * WT + tj * MS + fr;
-                if (BMODE == B_BF16) {
-                    bfr[tj] = *(const bf16x8 *)(&Bs[cur][col * GLDK + ks + fk]);
-                } else {
-                    const int n = n0 + col;                 // input feature = category*64 + zone
-                    const int cc = n >> 6;
-                    const uint8_t zz = cc < g.n_cat ? (uint8_t)(n & 63) : (uint8_t)0xFE;   // 0xFE matches no zone
-                    u32x4 wv;
-#pragma unroll
-                    for (int e = 0; e < 4; e++) {
-                        const uint32_t lo = ZsB[cur][(ks + fk + 2 * e) * 64 + cc] == zz ? 0x3F80u : 0u;
-                        const uint32_t hi = ZsB[cur][(ks + fk + 2 * e + 1) * 64 + cc] == zz ? 0x3F800000u : 0u;
-                        wv[e] = lo | hi;
-                    }
-                    bfr[tj] = __builtin_bit_cast(bf16x8, wv);
-                }
+                bfr[tj] = *(const bf16x8 *)(&Bs[cur][col * GLDK + ks + fk]);
             }
 #pragma unroll
             for (int ti = 0; ti < FT; ti++)
@@ -254,7 +230,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                                               (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
                         *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pk;
                     }
-                } else {   // EPI_GELU_GRAD_T: v = acc * gelu'(U), stored transposed in bf16
+                } else {   // EPI_GELU_GRAD_T: v = acc * gelu'(U) in bf16, transposed (and row-major)
                     uint16_t hv[4];
 #pragma unroll
                     for (int r = 0; r < 4; r++) {
@@ -264,6 +240,24 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                     uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
                                           (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
                     *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pk;
+                    if (g.H) {
+                        // and in column slices, [N / DU1_SLICE][M][DU1_SLICE]: a
+                        // 4 x 4 transpose within each quad of lanes (4
+                        // consecutive columns), after which lane t holds row
+                        // rb + t of the quad's columns
+                        const int t = lane & 3;
+                        const uint32_t snd = t < 2 ? pk.y : pk.x;
+                        const uint32_t rcv = (uint32_t)__shfl_xor((int)snd, 2, 64);
+                        const uint32_t a = t < 2 ? pk.x : rcv, b = t < 2 ? rcv : pk.y;   // rows of columns t & 1, + 2
+                        const uint32_t s1 = (t & 1) ? ((a & 0xFFFFu) | (b << 16)) : ((a >> 16) | (b & 0xFFFF0000u));
+                        const uint32_t r1 = (uint32_t)__shfl_xor((int)s1, 1, 64);
+                        const uint2 row = (t & 1) ? make_uint2((r1 & 0xFFFFu) | (a & 0xFFFF0000u),
+                                                               (r1 >> 16) | (b & 0xFFFF0000u))
+                                                  : make_uint2((a & 0xFFFFu) | (r1 << 16),
+                                                               (b & 0xFFFFu) | (r1 & 0xFFFF0000u));
+                        *(uint2 *)(g.H + (uint32_t)((col / DU1_SLICE) * g.M * DU1_SLICE + (rb + t) * DU1_SLICE +
+                                                    (col - t) % DU1_SLICE)) = row;
+                    }
                 }
             }
         }
@@ -319,7 +313,7 @@ __global__ __launch_bounds__(256) void layer3_kernel(L3Args a)
 //   [0, W3_SLICES): gW3 over a slice of the batch, one thread per output
 //     (rows of h2 read whole); the last of them to finish adds the slices;
 //   then one wave per output of gb3, gb2, gb1 and the loss;
-//   then 1,024 outputs of gW2 per workgroup (if split), then of gW1 (if split).
+//   then 1,024 outputs of gW2 per workgroup (if split).
 __global__ __launch_bounds__(256) void batch_sums_kernel(SumArgs a)
 {
     const int tid = threadIdx.x, lane = tid & 63;
@@ -381,30 +375,219 @@ __global__ __launch_bounds__(256) void batch_sums_kernel(SumArgs a)
         return;
     }
     blk -= row_blocks;
-    const float *part = a.w2part;
-    int splits = a.w2_splits;
-    int64_t stride = a.w2_stride;
-    float *out = a.gW2;
-    const int w2_blocks = a.w2part ? N_H2 * N_H1 / 1024 : 0;
-    if (blk >= w2_blocks) {
-        blk -= w2_blocks;
-        part = a.w1part;
-        splits = a.w1_splits;
-        stride = a.w1_stride;
-        out = a.gW1;
-    }
     const int64_t i = ((int64_t)blk * 256 + tid) * 4;
-    if (part) {
-        float4 t = *(const float4 *)(part + i);
-        for (int k = 1; k < splits; k++) {
-            const float4 u = *(const float4 *)(part + k * stride + i);
+    if (a.w2part) {
+        float4 t = *(const float4 *)(a.w2part + i);
+        for (int k = 1; k < a.w2_splits; k++) {
+            const float4 u = *(const float4 *)(a.w2part + k * a.w2_stride + i);
             t.x += u.x;
             t.y += u.y;
             t.z += u.z;
             t.w += u.w;
         }
-        *(float4 *)(out + i) = t;
+        *(float4 *)(a.gW2 + i) = t;
     }
+}
+
+// ---------------------------------------------------------------------------
+// dW1 without the product.  The input is one-hot per category, so
+//   dW1[h][c * 64 + z] = sum of du1[s][h] over the samples s whose category c
+//   lies in zone z:
+// one sum of du1 rows per (category, zone) bin, 1/64 of the arithmetic of the
+// dense product.  du1 comes in column slices of 128 hidden units, [8][n][128].
+// Workgroup b takes category c = b / 8 and slice b % 8, two units per lane;
+// consecutive workgroups go to different XCDs, so that each XCD reads one
+// slice, a contiguous 256 KB per 1,024 samples that its L2 holds.
+//   1. The batch's samples are sorted by their zone of category c, stably
+//      (ties in sample order), into LDS: so every sum runs in a fixed order.
+//      A sample's rank among the earlier samples of its group of 64 in its
+//      bin comes from ballots (one per bit of the bin), its wave's running
+//      count per bin from LDS.
+//   2. The eight waves take equal shares of the sorted positions and add each
+//      bin's rows in fp32 in list order; a bin that crosses into a wave's
+//      share from an earlier one is finished there, and its parts are added
+//      in wave order.
+// Categories at or beyond n_cat get zeros; zone bytes of 64 or more fall in
+// no bin.
+// ---------------------------------------------------------------------------
+constexpr int W1_SLICE = DU1_SLICE;
+constexpr int W1_UNITS = W1_SLICE / 64;                      // hidden units per lane
+constexpr int W1_SLICES = N_H1 / W1_SLICE;
+constexpr int W1_WAVES = 16;
+static_assert(W1_UNITS == 4, "four units per lane, one 8-byte load");
+static_assert(8 % W1_SLICES == 0, "slices spread evenly over 8 XCDs");
+constexpr int W1_GROUPS = MAX_GRAD_ROWS / (64 * W1_WAVES);   // groups of 64 samples per wave when sorting
+
+__global__ __launch_bounds__(64 * W1_WAVES) void w1_grad_kernel(const uint16_t *du1, const uint8_t *zt, int n,
+                                                                int n_cat, float *gW1)
+{
+    __shared__ float out[W1_SLICE][65];
+    __shared__ float head[W1_WAVES][W1_SLICE];
+    __shared__ int headz[W1_WAVES];
+    __shared__ uint32_t cnt[W1_WAVES][64];      // per wave: samples per bin, then its first position per bin
+    __shared__ __align__(16) uint32_t sidx[MAX_GRAD_ROWS];   // sorted samples, as byte offsets of their rows
+    __shared__ int32_t soff[65];
+    const int tid = threadIdx.x, lane = tid & 63;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);   // uniform, so that the loops run on scalars
+    // XCD x = b % 8 serves slice x / (8 / W1_SLICES)
+    constexpr int XPS = 8 / W1_SLICES;                       // XCDs per slice
+    const int x = (int)blockIdx.x & 7;
+    const int c = ((int)blockIdx.x >> 3) * XPS + x % XPS, sl = x / XPS, h0 = sl * W1_SLICE;
+    for (int k = tid; k < W1_SLICE * 65; k += 64 * W1_WAVES) (&out[0][0])[k] = 0.f;
+    if (tid < W1_WAVES) headz[tid] = -1;
+    const int per_s = (n + 64 * W1_WAVES - 1) / (64 * W1_WAVES) * 64;   // samples per wave, whole groups
+    uint32_t zr[W1_GROUPS];                     // bin | rank << 8
+    if (c < n_cat) {
+        cnt[w][lane] = 0u;
+#pragma unroll
+        for (int g = 0; g < W1_GROUPS; g++) {
+            const int sm = w * per_s + g * 64 + lane;
+            zr[g] = g * 64 < per_s && sm < n ? min((uint32_t)zt[(int64_t)c * n + sm], 64u) : 64u;
+        }
+#pragma unroll
+        for (int g = 0; g < W1_GROUPS; g++) {
+            const uint32_t z = zr[g];
+            uint64_t m = ~0ull;                 // the lanes that share this lane's bin
+#pragma unroll
+            for (int b = 0; b < 7; b++) {
+                const uint64_t bb = __ballot((z >> b) & 1u);
+                m &= ((z >> b) & 1u) ? bb : ~bb;
+            }
+            const uint32_t below = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+            const uint32_t base = z < 64u ? cnt[w][z] : 0u;
+            zr[g] = z | ((base + below) << 8);
+            // the highest lane of each bin advances the bin's count
+            if (z < 64u && (m >> lane) == 1ull) cnt[w][z] = base + (uint32_t)__popcll(m);
+        }
+    }
+    __syncthreads();
+    if (c < n_cat && w == 0) {
+        // bins in order and, within a bin, the waves in order (sample order)
+        uint32_t t[W1_WAVES], tot = 0;
+#pragma unroll
+        for (int k = 0; k < W1_WAVES; k++) {
+            t[k] = cnt[k][lane];
+            tot += t[k];
+        }
+        uint32_t inc = tot;
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const uint32_t u = __shfl_up(inc, d, 64);
+            if (lane >= d) inc += u;
+        }
+        uint32_t run = inc - tot;
+        soff[lane] = (int32_t)run;
+        if (lane == 63) soff[64] = (int32_t)inc;
+#pragma unroll
+        for (int k = 0; k < W1_WAVES; k++) {
+            cnt[k][lane] = run;
+            run += t[k];
+        }
+    }
+    __syncthreads();
+    if (c < n_cat) {
+#pragma unroll
+        for (int g = 0; g < W1_GROUPS; g++) {
+            const uint32_t z = zr[g] & 0xFFu;
+            if (z < 64u) sidx[cnt[w][z] + (zr[g] >> 8)] = (uint32_t)(w * per_s + g * 64 + lane) * (2u * W1_SLICE);
+        }
+        // the last block of a share may read up to 15 positions past the
+        // sorted ones: they name row 0 (and are not added)
+        const int nv = soff[64];
+        if (tid < 16 && nv + tid < MAX_GRAD_ROWS) sidx[nv + tid] = 0u;
+    }
+    __syncthreads();
+    if (c < n_cat) {
+        const int nv = __builtin_amdgcn_readfirstlane(soff[64]);
+        const int per = (nv + 16 * W1_WAVES - 1) / (16 * W1_WAVES) * 16;   // positions per wave, whole blocks of 16
+        const int i0 = min(nv, w * per), i1 = min(nv, i0 + per);
+        if (i0 < i1) {
+            int z = 0;
+            while (soff[z + 1] <= i0) z++;
+            z = __builtin_amdgcn_readfirstlane(z);
+            int zend = __builtin_amdgcn_readfirstlane(soff[z + 1]);
+            bool first = __builtin_amdgcn_readfirstlane(soff[z]) < i0;   // the bin began in an earlier share
+            float a[W1_UNITS];
+#pragma unroll
+            for (int u = 0; u < W1_UNITS; u++) a[u] = 0.f;
+            // the slice as a buffer: a position's row offset is uniform and
+            // goes in a scalar register, the lane's units are the vector offset
+            const __amdgpu_buffer_rsrc_t slice = __builtin_amdgcn_make_buffer_rsrc(
+                (void *)(du1 + (int64_t)sl * n * W1_SLICE), 0, n * 2 * W1_SLICE, 0x00020000);
+            const int lane_off = 2 * W1_UNITS * lane;
+            using Row = u32x2;
+            auto ld = [&](int so) -> Row { return __builtin_amdgcn_raw_buffer_load_b64(slice, lane_off, so, 0); };
+            auto add = [&](const Row &r) {
+                a[0] += __uint_as_float(r[0] << 16);
+                a[1] += __uint_as_float(r[0] & 0xFFFF0000u);
+                a[2] += __uint_as_float(r[1] << 16);
+                a[3] += __uint_as_float(r[1] & 0xFFFF0000u);
+            };
+            auto flush = [&](bool to_head) {
+#pragma unroll
+                for (int u = 0; u < W1_UNITS; u++) {
+                    if (to_head) head[w][W1_UNITS * lane + u] = a[u];
+                    else out[W1_UNITS * lane + u][z] = a[u];
+                    a[u] = 0.f;
+                }
+                if (to_head && lane == 0) headz[w] = z;
+            };
+            // the rows of block i + 16 load while block i is added; a block's
+            // positions past i1 read a row that is not added
+            Row v[16], nx[16];
+            auto load16 = [&](int i, Row *dst) {
+#pragma unroll
+                for (int k4 = 0; k4 < 4; k4++) {
+                    const uint4 q = *(const uint4 *)&sidx[i + 4 * k4];
+                    const uint32_t qw[4] = {q.x, q.y, q.z, q.w};
+#pragma unroll
+                    for (int k = 0; k < 4; k++) dst[4 * k4 + k] = ld(__builtin_amdgcn_readfirstlane((int)qw[k]));
+                }
+            };
+            load16(i0, nx);
+            for (int i = i0; i < i1; i += 16) {
+#pragma unroll
+                for (int k = 0; k < 16; k++) v[k] = nx[k];
+                if (i + 16 < i1) load16(i + 16, nx);
+                if (i + 16 <= min(zend, i1)) {
+                    // the whole block lies in bin z
+#pragma unroll
+                    for (int k = 0; k < 16; k++) add(v[k]);
+                    continue;
+                }
+#pragma unroll
+                for (int k = 0; k < 16; k++) {
+                    if (i + k >= i1) break;
+                    while (i + k == zend) {                // leave bin z
+                        flush(first);
+                        first = false;
+                        z++;
+                        zend = __builtin_amdgcn_readfirstlane(soff[z + 1]);
+                    }
+                    add(v[k]);
+                }
+            }
+            flush(first);
+        }
+    }
+    __syncthreads();
+    if (tid < W1_SLICE) {
+#pragma unroll
+        for (int k = 1; k < W1_WAVES; k++)
+            if (headz[k] >= 0) out[tid][headz[k]] += head[k][tid];
+    }
+    __syncthreads();
+    for (int k = tid; k < W1_SLICE * 64; k += 64 * W1_WAVES) {
+        const int r = k >> 6, j = k & 63;
+        gW1[(int64_t)(h0 + r) * N_IN + c * 64 + j] = out[r][j];
+    }
+}
+
+// Zone bytes by category: zt[c * n + b] = zb[b * 64 + c], one wave per sample.
+__global__ __launch_bounds__(256) void zone_cols_kernel(const uint8_t *zb, int n, uint8_t *zt)
+{
+    const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+    if (b < n) zt[(int64_t)lane * n + b] = zb[(int64_t)b * 64 + lane];
 }
 
 // Adam over the flat fp32 parameter vector (Kingma & Ba 2015, bias-corrected).
@@ -484,12 +667,14 @@ __device__ __forceinline__ uint64_t feistel_perm(uint64_t x, uint64_t n, int h, 
 
 __global__ __launch_bounds__(256) void gather_batch_kernel(const uint8_t *zone, const int32_t *dist, int64_t n_all,
                                                            int h, uint64_t key, int64_t first, int n, double mean,
-                                                           double inv_std, uint8_t *zb, float *tb)
+                                                           double inv_std, uint8_t *zb, uint8_t *zt, float *tb)
 {
     const int b = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
     if (b >= n) return;
     const int64_t s = (int64_t)feistel_perm((uint64_t)(first + b), (uint64_t)n_all, h, key);
-    zb[(int64_t)b * 64 + lane] = zone[s * 64 + lane];
+    const uint8_t zv = zone[s * 64 + lane];
+    zb[(int64_t)b * 64 + lane] = zv;
+    zt[(int64_t)lane * n + b] = zv;
     if (lane == 0) tb[b] = (float)(((double)dist[s] - mean) * inv_std);
 }
 
@@ -668,7 +853,6 @@ hipError_t launch_gemm(int amode, int bmode, int epi, const GemmArgs &g, hipStre
     if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_BIAS_GELU) return launch_gemm_t<A_BF16, B_BF16, EPI_BIAS_GELU>(g, s);
     if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_STORE) return launch_gemm_t<A_BF16, B_BF16, EPI_STORE>(g, s);
     if (amode == A_BF16 && bmode == B_BF16 && epi == EPI_GELU_GRAD_T) return launch_gemm_t<A_BF16, B_BF16, EPI_GELU_GRAD_T>(g, s);
-    if (amode == A_BF16 && bmode == B_ONEHOT_T && epi == EPI_STORE) return launch_gemm_t<A_BF16, B_ONEHOT_T, EPI_STORE>(g, s);
     return hipErrorInvalidValue;
 }
 
@@ -681,8 +865,7 @@ hipError_t launch_layer3(const L3Args &a, hipStream_t s)
 hipError_t launch_batch_sums(const SumArgs &a, hipStream_t s)
 {
     const int n_rows = 1 + N_H2 + N_H1 + 1;
-    const int blocks = W3_SLICES + (n_rows + 3) / 4 + (a.w2part ? N_H2 * N_H1 / 1024 : 0) +
-                       (a.w1part ? N_H1 * N_IN / 1024 : 0);
+    const int blocks = W3_SLICES + (n_rows + 3) / 4 + (a.w2part ? N_H2 * N_H1 / 1024 : 0);
     hipLaunchKernelGGL(batch_sums_kernel, dim3(blocks), dim3(256), 0, s, a);
     return hipGetLastError();
 }
@@ -704,11 +887,26 @@ hipError_t launch_refresh_bf16(const float *W1t, const float *W2t, uint16_t *W1b
     return hipGetLastError();
 }
 
+hipError_t launch_zone_cols(const uint8_t *zb, int n, uint8_t *zt, hipStream_t s)
+{
+    hipLaunchKernelGGL(zone_cols_kernel, dim3((n + 3) / 4), dim3(256), 0, s, zb, n, zt);
+    return hipGetLastError();
+}
+
+hipError_t launch_w1_grad(const uint16_t *du1, const uint8_t *zt, int n, int n_cat, float *gW1, hipStream_t s)
+{
+    if (n < 1 || n > MAX_GRAD_ROWS || n_cat < 1 || n_cat > 64) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(w1_grad_kernel, dim3(64 * W1_SLICES), dim3(64 * W1_WAVES), 0, s, du1, zt, n, n_cat,
+                       gW1);
+    return hipGetLastError();
+}
+
 hipError_t launch_gather_batch(const uint8_t *zone, const int32_t *dist, int64_t n_all, int h, uint64_t key,
-                               int64_t first, int n, double mean, double inv_std, uint8_t *zb, float *tb, hipStream_t s)
+                               int64_t first, int n, double mean, double inv_std, uint8_t *zb, uint8_t *zt,
+                               float *tb, hipStream_t s)
 {
     hipLaunchKernelGGL(gather_batch_kernel, dim3((n + 3) / 4), dim3(256), 0, s, zone, dist, n_all, h, key, first, n,
-                       mean, inv_std, zb, tb);
+                       mean, inv_std, zb, zt, tb);
     return hipGetLastError();
 }
 

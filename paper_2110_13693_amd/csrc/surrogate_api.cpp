@@ -21,7 +21,7 @@ using namespace wo;
 namespace {
 
 constexpr int PRED_CHUNK = 65536;    // rows per inference pass (enough workgroups to fill the GPU)
-constexpr int MAX_BATCH = 4096;      // training rows per step
+constexpr int MAX_BATCH = MAX_GRAD_ROWS;   // training rows per step
 constexpr int WORK_ROWS = PRED_CHUNK > MAX_BATCH ? PRED_CHUNK : MAX_BATCH;
 
 uint64_t splitmix64(uint64_t x)
@@ -49,6 +49,7 @@ struct wo_sur {
     double *d_mom = nullptr;
     float *d_loss = nullptr;
     float *d_red = nullptr;             // gW3 slice sums, then the slices' counter (zero between calls)
+    uint8_t *d_zt = nullptr;            // a training batch's zone bytes by category [64][batch]
     double mean = 0.0, std = 1.0;
     bool scaled = false;
     int step = 0;                       // Adam steps taken
@@ -107,8 +108,8 @@ wo_status forward(wo_sur *s, const uint8_t *zone, int rows_real, int rows, bool 
 }
 
 // forward + backward of one batch of `rows` (multiple of 128) whose zone rows
-// are d_zb and standardised targets d_tb; gradients into d_g, loss into
-// loss_out (null: d_loss).
+// are d_zb (by category in d_zt) and standardised targets d_tb; gradients into
+// d_g, loss into loss_out (null: d_loss).
 wo_status gradients(wo_sur *s, int rows, hipStream_t st, float *loss_out = nullptr)
 {
     wo_status r = forward(s, s->d_zb, rows, rows, true, st);
@@ -140,6 +141,7 @@ wo_status gradients(wo_sur *s, int rows, hipStream_t st, float *loss_out = nullp
     g1.Uin = s->d_U1;
     g1.HT = s->d_DU1T;
     g1.ldt = rows;
+    g1.H = s->d_H1;   // du1 in column slices as well, in h1's buffer (free after layer 2)
     WO_HIP(launch_gemm(A_BF16, B_BF16, EPI_GELU_GRAD_T, g1, st));
     // gW2^T [256][1024] = du2^T [256][b] . (h1^T [1024][b])^T: a long K over
     // few outputs, so K is split in parts (into u1's buffer, free now) that
@@ -159,27 +161,9 @@ wo_status gradients(wo_sur *s, int rows, hipStream_t st, float *loss_out = nullp
     g2.ksplit = ks;
     g2.c_split = (int64_t)N_H2 * N_H1;
     WO_HIP(launch_gemm(A_BF16, B_BF16, EPI_STORE, g2, st));
-    // gW1^T [1024][4096] = du1^T [1024][b] . (x^T [4096][b])^T, x one-hot:
-    // one workgroup per CU unsplit, so K is split in parts as well (after
-    // gW2's parts in u1's buffer), each part's loads then overlapping
-    // another's products
-    int ks1 = 2;
-    while (ks1 > 1 && rows % (ks1 * 64)) ks1 >>= 1;
-    float *w1part = s->d_U1 + (int64_t)8 * N_H2 * N_H1;
-    GemmArgs g0{};
-    g0.M = N_H1;
-    g0.N = N_IN;
-    g0.K = rows;
-    g0.K_real = rows;
-    g0.n_cat = s->n_cat;
-    g0.A = s->d_DU1T;
-    g0.lda = rows;
-    g0.zoneB = s->d_zb;
-    g0.C = ks1 > 1 ? w1part : s->d_g + P_W1;
-    g0.ldc = N_IN;
-    g0.ksplit = ks1;
-    g0.c_split = (int64_t)N_H1 * N_IN;
-    WO_HIP(launch_gemm(A_BF16, B_ONEHOT_T, EPI_STORE, g0, st));
+    // gW1 [1024][4096] = du1^T . x with x one-hot: sums of du1 rows per
+    // (category, zone) bin
+    WO_HIP(launch_w1_grad(s->d_H1, s->d_zt, rows, s->n_cat, s->d_g + P_W1, st));
     SumArgs sm{};
     sm.n = rows;
     sm.H2 = s->d_H2;
@@ -199,10 +183,6 @@ wo_status gradients(wo_sur *s, int rows, hipStream_t st, float *loss_out = nullp
     sm.w2_splits = ks;
     sm.w2_stride = (int64_t)N_H2 * N_H1;
     sm.gW2 = s->d_g + P_W2;
-    sm.w1part = ks1 > 1 ? w1part : nullptr;
-    sm.w1_splits = ks1;
-    sm.w1_stride = (int64_t)N_H1 * N_IN;
-    sm.gW1 = s->d_g + P_W1;
     WO_HIP(launch_batch_sums(sm, st));
     return WO_OK;
 }
@@ -320,7 +300,8 @@ extern "C" wo_status wo_sur_create(int32_t n_categories, const float *h_init, ui
         (r = alloc(&s->d_sq, WORK_ROWS)) || (r = alloc(&s->d_H1, (size_t)WORK_ROWS * N_H1)) ||
         (r = alloc(&s->d_H1T, (size_t)WORK_ROWS * N_H1)) || (r = alloc(&s->d_DU2, (size_t)WORK_ROWS * N_H2)) ||
         (r = alloc(&s->d_DU2T, (size_t)WORK_ROWS * N_H2)) || (r = alloc(&s->d_DU1T, (size_t)WORK_ROWS * N_H1)) ||
-        (r = alloc(&s->d_mom, 2)) || (r = alloc(&s->d_loss, 1)) || (r = alloc(&s->d_red, W3_SLICES * N_H2 + 16)))
+        (r = alloc(&s->d_mom, 2)) || (r = alloc(&s->d_loss, 1)) || (r = alloc(&s->d_red, W3_SLICES * N_H2 + 16)) ||
+        (r = alloc(&s->d_zt, (size_t)64 * MAX_GRAD_ROWS)))
         return r;
     std::vector<float> host, dev;
     if (h_init) {
@@ -349,7 +330,8 @@ extern "C" wo_status wo_sur_free(wo_sur *s)
     (void)hipDeviceSynchronize();
     void *bufs[] = {s->d_p,  s->d_g,   s->d_m,  s->d_v,   s->d_W1b, s->d_W2b,  s->d_W2kn, s->d_zb,   s->d_tb,
                     s->d_U1, s->d_U2,  s->d_H2, s->d_dy,  s->d_sq,  s->d_H1,   s->d_H1T,  s->d_DU2,  s->d_DU2T,
-                    s->d_DU1T, s->d_pred, s->d_losses, s->d_mom, s->d_loss, s->d_red};
+                    s->d_DU1T, s->d_pred, s->d_losses, s->d_mom, s->d_loss, s->d_red,
+                    s->d_zt};
     for (void *b : bufs)
         if (b) (void)hipFree(b);
     delete s;
@@ -400,6 +382,7 @@ extern "C" wo_status wo_sur_gradients(wo_sur *s, int32_t n, const uint8_t *d_zon
     hipStream_t st = (hipStream_t)stream;
     WO_HIP(hipMemcpyAsync(s->d_zb, d_zone_of, (size_t)n * 64, hipMemcpyDeviceToDevice, st));
     WO_HIP(hipMemcpyAsync(s->d_tb, d_target, sizeof(float) * n, hipMemcpyDeviceToDevice, st));
+    WO_HIP(launch_zone_cols(s->d_zb, n, s->d_zt, st));
     wo_status r = gradients(s, n, st);
     if (r) return r;
     std::vector<float> dev(P_TOTAL);
@@ -458,7 +441,7 @@ extern "C" wo_status wo_sur_train(wo_sur *s, int64_t n, const uint8_t *d_zone_of
         const bool last = ep == epochs - 1;
         for (int64_t b = 0; b < n_batches; b++) {
             WO_HIP(launch_gather_batch(d_zone_of, d_dist, n, h, key, b * batch, batch, s->mean, 1.0 / s->std,
-                                       s->d_zb, s->d_tb, st));
+                                       s->d_zb, s->d_zt, s->d_tb, st));
             wo_status r = gradients(s, batch, st, last && h_last_loss ? s->d_losses + b : nullptr);
             if (r) return r;
             s->step++;

@@ -10,6 +10,8 @@ constexpr int N_IN = 4096;   // 64 categories x 64 zones, one-hot
 constexpr int N_H1 = 1024;
 constexpr int N_H2 = 256;
 constexpr int TOPK_MAX = 4096;
+constexpr int MAX_GRAD_ROWS = 4096;   // samples per training batch
+constexpr int DU1_SLICE = 256;        // du1 for the dW1 bins: column slices of this many hidden units
 
 // flat parameter vector, [out][in] weight layout
 constexpr int64_t P_W1 = 0;
@@ -21,24 +23,23 @@ constexpr int64_t P_B3 = P_W3 + N_H2;
 constexpr int64_t P_TOTAL = P_B3 + 1;
 
 enum { A_BF16 = 0, A_ONEHOT = 1 };
-enum { B_BF16 = 0, B_ONEHOT_T = 1 };
+enum { B_BF16 = 0 };
 enum { EPI_STORE = 0, EPI_BIAS_GELU = 1, EPI_GELU_GRAD_T = 2 };
 
 struct GemmArgs {
     int M, N, K;              // padded sizes (M, N multiples of 128, K of 64)
-    int M_real, K_real;       // rows of the zone operand that exist
+    int M_real;               // rows of the zone operand that exist
     int n_cat;                // categories that exist: zone bytes of higher ones are ignored
     const uint16_t *A;        // A_BF16: [M][lda]
     int lda;
     const uint8_t *zoneA;     // A_ONEHOT: zone rows [M_real][64]
     const uint16_t *B;        // B_BF16: [N][ldb]
     int ldb;
-    const uint8_t *zoneB;     // B_ONEHOT_T: zone rows of the K samples [K_real][64]
     float *C;                 // EPI_STORE: [M][ldc]
     int ldc;
     const float *bias;        // EPI_BIAS_GELU
     float *U;                 // EPI_BIAS_GELU: pre-activation [M][ldc] (may be null)
-    uint16_t *H;              // EPI_BIAS_GELU: bf16 activation [M][ldc] (may be null)
+    uint16_t *H;              // bf16 result (may be null): EPI_BIAS_GELU [M][ldc], EPI_GELU_GRAD_T [N / DU1_SLICE][M][DU1_SLICE]
     uint16_t *HT;             // EPI_BIAS_GELU / EPI_GELU_GRAD_T: bf16 transposed [N][ldt]
     int ldt;
     const float *Uin;         // EPI_GELU_GRAD_T: pre-activation [M][ldc]
@@ -76,14 +77,15 @@ struct SumArgs {
     int w2_splits;
     int64_t w2_stride;
     float *gW2;
-    const float *w1part;      // the same for gW1
-    int w1_splits;
-    int64_t w1_stride;
-    float *gW1;
 };
 
 hipError_t launch_gemm(int amode, int bmode, int epi, const GemmArgs &g, hipStream_t s);
 hipError_t launch_layer3(const L3Args &a, hipStream_t s);
+// zone bytes by category: zt [64][n] from the zone rows zb [n][64]
+hipError_t launch_zone_cols(const uint8_t *zb, int n, uint8_t *zt, hipStream_t s);
+// gW1 [1024][4096] of a batch of n samples (at most MAX_GRAD_ROWS) from its
+// zone bytes by category zt [64][n] and du1 in column slices [N_H1 / DU1_SLICE][n][DU1_SLICE] (bf16)
+hipError_t launch_w1_grad(const uint16_t *du1, const uint8_t *zt, int n, int n_cat, float *gW1, hipStream_t s);
 hipError_t launch_batch_sums(const SumArgs &a, hipStream_t s);
 // Adam step; when W1b is non-null the updated W1 and W2 are also written to
 // their bf16 copies (W2 as stored and transposed), as launch_refresh_bf16 does
@@ -92,7 +94,8 @@ hipError_t launch_adam(float *p, const float *g, float *m, float *v, int64_t n, 
 hipError_t launch_refresh_bf16(const float *W1t, const float *W2t, uint16_t *W1b, uint16_t *W2b, uint16_t *W2kn,
                                hipStream_t s);
 hipError_t launch_gather_batch(const uint8_t *zone, const int32_t *dist, int64_t n_all, int h, uint64_t key,
-                               int64_t first, int n, double mean, double inv_std, uint8_t *zb, float *tb, hipStream_t s);
+                               int64_t first, int n, double mean, double inv_std, uint8_t *zb, uint8_t *zt,
+                               float *tb, hipStream_t s);
 hipError_t launch_moments(const int32_t *d, int64_t n, double *out, hipStream_t s);
 hipError_t launch_topk(const float *pred, int n, int k, int32_t *out, hipStream_t s);
 hipError_t launch_worst(const int32_t *dist, int n, int k, int32_t *out, hipStream_t s);

@@ -266,6 +266,36 @@ def test_gradients_match_reference(n):
     s.free()
 
 
+@pytest.mark.parametrize("n,n_cat", [(4096, 64), (384, 20)])
+def test_gradients_with_crowded_zone_bins(n, n_cat):
+    """dW1 is summed per (category, zone) bin over a batch sorted by zone; a
+    bin may hold the whole batch, or cross the shares of several waves."""
+    import torch
+    wo = _wo()
+    p = _params(7)
+    s = wo.wo_sur_create(n_cat, flat(p))
+    rng = np.random.default_rng(8)
+    Z = rng.integers(0, 64, size=(n, 64)).astype(np.uint8)
+    Z[:, 0] = 5                                   # one bin of n samples
+    Z[:, 1] = 63
+    Z[:, 2] = (np.arange(n) * 3 // n).astype(np.uint8)          # three long bins
+    Z[:, 3] = (np.arange(n) * 3 // n * 21).astype(np.uint8)     # the same, empty bins between them
+    Z[:, 4] = np.where(np.arange(n) % 7 == 0, 9, 40).astype(np.uint8)
+    t = rng.normal(0, 1, n).astype(np.float32)
+    g, _ = wo.wo_sur_gradients(s, torch.from_numpy(Z).cuda(), torch.from_numpy(t).cuda())
+    q = _ref_params(p)
+    tt = t.astype(np.float64)
+    y, cache = S.forward(q, S.one_hot(Z, n_cat))
+    ref = S.backward(q, cache, y, tt)
+    model = device_error_model(q, cache, y, tt)
+    got = unflat(g)
+    for k, _ in SHAPES:
+        assert_within(got[k], ref[k], model["grads"][k], k, floor=1e-9 * float(np.abs(ref[k]).max()))
+    # inputs of absent categories are zero, and so is their gradient
+    assert not np.any(got["W1"].reshape(64, 64, -1)[n_cat:])
+    s.free()
+
+
 def test_screen_orders_by_prediction_then_index():
     import torch
     wo = _wo()
