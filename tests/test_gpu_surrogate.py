@@ -266,7 +266,7 @@ def test_gradients_match_reference(n):
     s.free()
 
 
-@pytest.mark.parametrize("n,n_cat", [(4096, 64), (384, 20)])
+@pytest.mark.parametrize("n,n_cat", [(4096, 64), (384, 20), (128, 1)])
 def test_gradients_with_crowded_zone_bins(n, n_cat):
     """dW1 is summed per (category, zone) bin over a batch sorted by zone; a
     bin may hold the whole batch, or cross the shares of several waves."""
