@@ -834,7 +834,11 @@ static hipError_t launch_gemm_t(const GemmArgs &g, hipStream_t s)
 {
     const int ks = g.ksplit > 1 ? g.ksplit : 1;
     const int64_t t128 = (int64_t)(g.N / 128) * (g.M / 128) * ks;
-    if (t128 >= 1024) {
+    // a short K (dU1: 256) leaves the epilogue most of a workgroup's time:
+    // 64 x 64 tiles, so that four workgroups per CU overlap their epilogues
+    if (g.K <= 256 && t128 < 1024) {
+        hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 64, 32>), dim3(g.N / 64, g.M / 64, ks), dim3(256), 0, s, g);
+    } else if (t128 >= 1024) {
         hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 128, 16>), dim3(g.N / 128, g.M / 128, ks), dim3(256), 0, s, g);
     } else if (t128 >= 256) {
         hipLaunchKernelGGL((gemm_kernel<AM, BM, EP, 128, 32>), dim3(g.N / 128, g.M / 128, ks), dim3(256), 0, s, g);
