@@ -265,44 +265,67 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 }
 
 // ---------------------------------------------------------------------------
-// Layer 3 and the loss.  One wave per sample: h2 = GELU(u2) in fp32,
-// y = h2 . W3 + b3.  Training also forms dy = 2 (y - t) / n and
-// du2 = dy * W3 * GELU'(u2) (bf16, row-major and transposed).
+// Layer 3 and the loss.  One wave per sample, L3_ROWS samples per workgroup:
+// h2 = GELU(u2) in fp32, y = h2 . W3 + b3.  Training also forms
+// dy = 2 (y - t) / n and du2 = dy * W3 * GELU'(u2) (bf16, row-major and
+// transposed; the transposed rows of the workgroup's samples go out through
+// LDS, 32 contiguous bytes per output).
 // ---------------------------------------------------------------------------
+constexpr int L3_ROWS = 16;
+static_assert(L3_ROWS == 16 && N_H2 == 256, "a thread per output writes two 16-byte pieces");
 __global__ __launch_bounds__(256) void layer3_kernel(L3Args a)
 {
-    const int lane = threadIdx.x & 63;
-    const int b = blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (b >= a.n) return;
-    float u[4], h[4], s = 0.f;
+    __shared__ __align__(16) uint16_t t2[L3_ROWS][N_H2];   // du2 of the workgroup's samples
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int base = blockIdx.x * L3_ROWS;
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const int j = lane + 64 * q;
-        u[q] = a.U2[(int64_t)b * N_H2 + j];
-        h[q] = gelu_f(u[q]);
-        s += h[q] * a.W3[j];
-    }
+    for (int r = w; r < L3_ROWS; r += 4) {
+        const int b = base + r;
+        if (b >= a.n) break;
+        float u[4], h[4], s = 0.f;
 #pragma unroll
-    for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
-    const float y = s + a.b3[0];
-    if (a.target == nullptr) {
-        if (lane == 0) a.pred[b] = y * a.std + a.mean;
-        return;
-    }
-    const float t = a.target[b];
-    const float dy = 2.0f * (y - t) / (float)a.n_batch;
-    if (lane == 0) {
-        a.dy[b] = dy;
-        a.sq[b] = (y - t) * (y - t);
-        if (a.pred) a.pred[b] = y;
-    }
+        for (int q = 0; q < 4; q++) {
+            const int j = lane + 64 * q;
+            u[q] = a.U2[(int64_t)b * N_H2 + j];
+            h[q] = gelu_f(u[q]);
+            s += h[q] * a.W3[j];
+        }
 #pragma unroll
-    for (int q = 0; q < 4; q++) {
-        const int j = lane + 64 * q;
-        a.H2[(int64_t)b * N_H2 + j] = h[q];
-        const uint16_t v = f2bf(dy * a.W3[j] * gelu_grad_f(u[q]));
-        a.DU2[(int64_t)b * N_H2 + j] = v;
-        a.DU2T[(int64_t)j * a.ld_t + b] = v;
+        for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d, 64);
+        const float y = s + a.b3[0];
+        if (a.target == nullptr) {
+            if (lane == 0) a.pred[b] = y * a.std + a.mean;
+            continue;
+        }
+        const float t = a.target[b];
+        const float dy = 2.0f * (y - t) / (float)a.n_batch;
+        if (lane == 0) {
+            a.dy[b] = dy;
+            a.sq[b] = (y - t) * (y - t);
+            if (a.pred) a.pred[b] = y;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; q++) {
+            const int j = lane + 64 * q;
+            a.H2[(int64_t)b * N_H2 + j] = h[q];
+            const uint16_t v = f2bf(dy * a.W3[j] * gelu_grad_f(u[q]));
+            a.DU2[(int64_t)b * N_H2 + j] = v;
+            t2[r][j] = v;
+        }
+    }
+    if (a.target == nullptr) return;             // the same for the whole grid
+    __syncthreads();
+    // du2 transposed: output j = thread, the workgroup's samples
+    const int j = threadIdx.x;
+    uint16_t *dst = a.DU2T + (int64_t)j * a.ld_t + base;
+    if (base + L3_ROWS <= a.n) {
+        uint32_t wv[L3_ROWS / 2];
+#pragma unroll
+        for (int r = 0; r < L3_ROWS; r += 2) wv[r / 2] = (uint32_t)t2[r][j] | ((uint32_t)t2[r + 1][j] << 16);
+        ((uint4 *)dst)[0] = make_uint4(wv[0], wv[1], wv[2], wv[3]);
+        ((uint4 *)dst)[1] = make_uint4(wv[4], wv[5], wv[6], wv[7]);
+    } else {
+        for (int r = 0; base + r < a.n; r++) dst[r] = t2[r][j];
     }
 }
 
@@ -862,7 +885,8 @@ hipError_t launch_gemm(int amode, int bmode, int epi, const GemmArgs &g, hipStre
 
 hipError_t launch_layer3(const L3Args &a, hipStream_t s)
 {
-    hipLaunchKernelGGL(layer3_kernel, dim3((a.n + 3) / 4), dim3(256), 0, s, a);
+    if (a.target && (a.ld_t % 8 || a.n > a.ld_t)) return hipErrorInvalidValue;   // 16-byte rows of du2^T
+    hipLaunchKernelGGL(layer3_kernel, dim3((a.n + L3_ROWS - 1) / L3_ROWS), dim3(256), 0, s, a);
     return hipGetLastError();
 }
 
