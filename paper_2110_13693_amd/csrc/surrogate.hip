@@ -208,6 +208,7 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
 #pragma unroll
         for (int tj = 0; tj < FT; tj++) {
             const int col = n0 + wn * WT + tj * MS + fr;
+            uint2 pkq[QN];                           // the transposed copy's 4-row pieces
 #pragma unroll
             for (int q = 0; q < QN; q++) {
                 const int rb = m0 + wm * WT + ti * MS + 8 * q + (lane / MS) * 4;
@@ -226,9 +227,9 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                         if (g.H) g.H[(uint32_t)((rb + r) * g.ldc + col)] = hv[r];
                     }
                     if (g.HT) {
-                        uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
-                                              (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
-                        *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pk;
+                        pkq[q] = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
+                                            (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
+                        if (MS != 32) *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pkq[q];
                     }
                 } else {   // EPI_GELU_GRAD_T: v = acc * gelu'(U) in bf16, transposed (and row-major)
                     uint16_t hv[4];
@@ -237,9 +238,10 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                         const float u = g.Uin[(uint32_t)((rb + r) * g.ldc + col)];
                         hv[r] = f2bf(acc[ti][tj][4 * q + r] * gelu_grad_f(u));
                     }
-                    uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
-                                          (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
-                    *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pk;
+                    const uint2 pk = make_uint2((uint32_t)hv[0] | ((uint32_t)hv[1] << 16),
+                                                (uint32_t)hv[2] | ((uint32_t)hv[3] << 16));
+                    pkq[q] = pk;
+                    if (MS != 32) *(uint2 *)(g.HT + (int64_t)col * g.ldt + rb) = pk;
                     if (g.H) {
                         // and in column slices, [N / DU1_SLICE][M][DU1_SLICE]: a
                         // 4 x 4 transpose within each quad of lanes (4
@@ -259,6 +261,23 @@ __global__ __launch_bounds__(256) void gemm_kernel(GemmArgs g)
                                                     (col - t) % DU1_SLICE)) = row;
                     }
                 }
+            }
+            if (MS == 32 && EPI != EPI_STORE && g.HT) {
+                // the transposed copy in 16-byte pieces: lanes l and l + 32
+                // hold rows 8 q .. 8 q + 3 and 8 q + 4 .. 8 q + 7 of a column;
+                // they swap halves so that lane l writes rows 0 .. 15 and
+                // lane l + 32 rows 16 .. 31 of the tile, 8 at a time
+                const bool lo = lane < 32;
+                const uint2 s0 = lo ? pkq[2 % QN] : pkq[0], s1 = lo ? pkq[3 % QN] : pkq[1 % QN];
+                const uint2 r0 = make_uint2((uint32_t)__shfl_xor((int)s0.x, 32, 64), (uint32_t)__shfl_xor((int)s0.y, 32, 64));
+                const uint2 r1 = make_uint2((uint32_t)__shfl_xor((int)s1.x, 32, 64), (uint32_t)__shfl_xor((int)s1.y, 32, 64));
+                const uint4 w0 = lo ? make_uint4(pkq[0].x, pkq[0].y, r0.x, r0.y)
+                                    : make_uint4(r0.x, r0.y, pkq[2 % QN].x, pkq[2 % QN].y);
+                const uint4 w1 = lo ? make_uint4(pkq[1 % QN].x, pkq[1 % QN].y, r1.x, r1.y)
+                                    : make_uint4(r1.x, r1.y, pkq[3 % QN].x, pkq[3 % QN].y);
+                uint16_t *ht = g.HT + (int64_t)col * g.ldt + m0 + wm * WT + ti * MS + (lo ? 0 : 16);
+                *(uint4 *)ht = w0;
+                *(uint4 *)(ht + 8) = w1;
             }
         }
     }
