@@ -8,11 +8,13 @@
 //   h2  = GELU(h1 W2 + b2)     256
 //   y   = h2 W3 + b3           (standardised distance)
 //
-// GEMMs run on MFMA (v_mfma_f32_32x32x16_bf16: bf16 operands, fp32
-// accumulation).  Weights are kept as fp32 masters in [out][in] layout with
-// bf16 working copies; the one-hot operand is generated in registers from the
-// zone bytes and never stored.  Every GEMM here is C[M][N] = A[M][K] . B[N][K]^T
-// with both operands K-contiguous.
+// GEMMs run on MFMA (v_mfma_f32_32x32x16_bf16 or v_mfma_f32_16x16x32_bf16:
+// bf16 operands, fp32 accumulation).  Weights are kept as fp32 masters in
+// [out][in] layout with bf16 working copies; the one-hot operand of the
+// forward products is generated in registers from the zone bytes and never
+// stored.  Every GEMM here is C[M][N] = A[M][K] . B[N][K]^T with both operands
+// K-contiguous.  The gradient of W1 is not a product: with a one-hot input it
+// is a sum of du1 rows per (category, zone) bin (w1_grad_kernel).
 #include <type_traits>
 
 #include "wo_internal.h"
