@@ -803,7 +803,8 @@ def main(argv=None):
     out["peaks_measured"] = {"int_valu_Tops": peaks["int_ops_per_s"] / 1e12,
                              "lds_read_TBps": peaks["lds_bytes_per_s"] / 1e12,
                              "hbm_read_TBps": peaks["hbm_read_bytes_per_s"] / 1e12,
-                             "bf16_mfma_TFLOPs": peaks["bf16_flops_per_s"] / 1e12}
+                             "bf16_mfma_TFLOPs": peaks["bf16_flops_per_s"] / 1e12,
+                             "l2_read_TBps": peaks["l2_read_bytes_per_s"] / 1e12}
     d_host = dist.cpu().numpy()
     t_host = thr.cpu().numpy()
     out["check"] = {"dist_min": int(d_host.min()), "dist_max": int(d_host.max())}

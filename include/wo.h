@@ -624,7 +624,9 @@ wo_status wo_measure_int_peak(int32_t reps, double *ops_per_s, void *stream);
  * as wo_measure_int_peak gives it; the LDS read bandwidth (every wave reads
  * 1 KB per instruction, without bank conflicts); the HBM read bandwidth (a
  * 1 GiB buffer read once with 16-byte loads); the dense BF16 MFMA rate
- * (four independent 32 x 32 x 16 products per wave).  Each is the best of
+ * (four independent 32 x 32 x 16 products per wave); the L2 read bandwidth
+ * (each XCD re-reads a 2 MB slice of its own, 64 times, with 16-byte loads;
+ * workgroup b is taken to run on XCD b % 8).  Each is the best of
  * `reps` (1 .. 100) timed launches.  Synchronous; allocates 1 GiB and small
  * output buffers for the call. */
 typedef struct {
@@ -632,6 +634,7 @@ typedef struct {
     double lds_bytes_per_s;
     double hbm_read_bytes_per_s;
     double bf16_flops_per_s;
+    double l2_read_bytes_per_s;
 } wo_peaks;
 wo_status wo_measure_peaks(int32_t reps, wo_peaks *out, void *stream);
 

@@ -71,6 +71,23 @@ __global__ __launch_bounds__(256) void hbm_read_kernel(const pk_u32x4 *buf, int6
     out[blockIdx.x * blockDim.x + threadIdx.x] = x;
 }
 
+// L2: each XCD re-reads a 2 MB slice of its own (workgroups go to the XCDs in
+// turn, so workgroup b reads slice b % 8), small enough to stay in its L2,
+// with 16-byte loads; passes x 8 slices are read in all
+constexpr int64_t L2_SLICE16 = (int64_t)(2 << 20) / 16;   // 16-byte elements per slice (a power of 2)
+__global__ __launch_bounds__(256) void l2_read_kernel(const pk_u32x4 *buf, int32_t passes, uint32_t *out)
+{
+    const pk_u32x4 *sl = buf + (int64_t)(blockIdx.x & 7) * L2_SLICE16;
+    const int64_t stride = (int64_t)(gridDim.x >> 3) * blockDim.x, end = (int64_t)passes * L2_SLICE16;
+    uint32_t x = 0;
+#pragma unroll 8
+    for (int64_t e = (int64_t)(blockIdx.x >> 3) * blockDim.x + threadIdx.x; e < end; e += stride) {
+        const pk_u32x4 v = sl[e & (L2_SLICE16 - 1)];
+        x ^= v[0] ^ v[1] ^ v[2] ^ v[3];
+    }
+    out[blockIdx.x * blockDim.x + threadIdx.x] = x;
+}
+
 typedef __attribute__((__vector_size__(8 * sizeof(__bf16)))) __bf16 pk_bf16x8;
 typedef __attribute__((__vector_size__(16 * sizeof(float)))) float pk_floatx16;
 constexpr int PK_MFMA_CHAINS = 4;
@@ -171,6 +188,12 @@ extern "C" wo_status wo_measure_peaks(int32_t reps, wo_peaks *out, void *stream)
             hipLaunchKernelGGL(hbm_read_kernel, dim3(grid_hbm), dim3(256), 0, s, buf, hbm_bytes / 16, o32);
         }, &ms);
     if (!st) out->hbm_read_bytes_per_s = (double)hbm_bytes / (ms * 1e-3);
+    const int32_t l2_passes = 64;
+    if (!st)
+        st = best_ms(s, reps, [&] {
+            hipLaunchKernelGGL(l2_read_kernel, dim3(grid_small), dim3(256), 0, s, buf, l2_passes, o32);
+        }, &ms);
+    if (!st) out->l2_read_bytes_per_s = 8.0 * 16.0 * (double)L2_SLICE16 * l2_passes / (ms * 1e-3);
     if (!st)
         st = best_ms(s, reps, [&] {
             hipLaunchKernelGGL(mfma_bf16_kernel, dim3(grid_small), dim3(256), 0, s, of, mfma_steps);

@@ -67,7 +67,8 @@ class wo_aisle_params(ctypes.Structure):
 
 class wo_peaks(ctypes.Structure):
     _fields_ = [("int_ops_per_s", ctypes.c_double), ("lds_bytes_per_s", ctypes.c_double),
-                ("hbm_read_bytes_per_s", ctypes.c_double), ("bf16_flops_per_s", ctypes.c_double)]
+                ("hbm_read_bytes_per_s", ctypes.c_double), ("bf16_flops_per_s", ctypes.c_double),
+                ("l2_read_bytes_per_s", ctypes.c_double)]
 
 
 class wo_aisle_result(ctypes.Structure):
@@ -502,7 +503,8 @@ def wo_measure_peaks(reps: int = 3, stream=None) -> dict:
     p = wo_peaks()
     _check(lib().wo_measure_peaks(int(reps), ctypes.byref(p), ctypes.c_void_p(_stream_handle(stream))))
     return {"int_ops_per_s": p.int_ops_per_s, "lds_bytes_per_s": p.lds_bytes_per_s,
-            "hbm_read_bytes_per_s": p.hbm_read_bytes_per_s, "bf16_flops_per_s": p.bf16_flops_per_s}
+            "hbm_read_bytes_per_s": p.hbm_read_bytes_per_s, "bf16_flops_per_s": p.bf16_flops_per_s,
+            "l2_read_bytes_per_s": p.l2_read_bytes_per_s}
 
 
 def wo_measure_int_peak(reps: int = 5, stream=None) -> float:
